@@ -1,0 +1,237 @@
+"""FP64 CPU oracle of the contact-manifold hot path.
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import this package.  The product path
+(``paper_2604_17538_amd``) never imports, links or runs anything here, and this
+package imports nothing from it except the seeded input generators' data
+classes, which hold no arithmetic of the method.
+
+The numerical core is ``oracle.cpp`` (plain FP64 C++, templated on the scalar so
+hyper-dual numbers give exact gradients and Hessian-vector products); the hull of
+a piece is qhull via ``oracle.geometry``.  ``build()`` compiles the core with g++.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Optional
+
+import numpy as np
+
+from . import geometry
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.cpp into liboracle.so (g++, FP64, OpenMP)."""
+    src = os.path.join(_HERE, "oracle.cpp")
+    if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(src):
+        tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+        subprocess.check_call(["g++", "-O2", "-std=c++17", "-fopenmp", "-shared", "-fPIC",
+                               src, "-o", tmp])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+class Params(ctypes.Structure):
+    """Method constants (all lengths in metres).  Mirrors the oracle's C struct."""
+    _fields_ = [(n, ctypes.c_double) for n in
+                ("tau_cap", "tau_cup", "tau_st", "tau_clip", "tau_blend", "d_max", "eps_t", "eps_n",
+                 "grid_margin", "grid_margin_rel")] + \
+               [(n, ctypes.c_int32) for n in ("st_iters", "grid_res", "broad_phase", "edge_bound")]
+
+
+def default_params(L_ref: float = 0.1, broad_phase: bool = True, **kw) -> Params:
+    """Constants scaled with the workload's length scale L_ref.
+
+    tau = 0.01 L_ref for the intersection, union, trace gate and softclip;
+    tau_b = 0.02 L_ref; d_max = 0.05 L_ref; eps_t = 0.025 L_ref; eps_n = 1e-6;
+    K = 3 sphere-trace steps; 32^3 voxel grid over the vertex AABB grown by
+    0.1 L_ref + 1.0 * (object radius); the paper's min-form edge bound.
+    """
+    p = Params(tau_cap=0.01 * L_ref, tau_cup=0.01 * L_ref, tau_st=0.01 * L_ref, tau_clip=0.01 * L_ref,
+               tau_blend=0.02 * L_ref, d_max=0.05 * L_ref, eps_t=0.025 * L_ref, eps_n=1e-6,
+               grid_margin=0.1 * L_ref, grid_margin_rel=1.0, st_iters=3, grid_res=32,
+               broad_phase=int(broad_phase), edge_bound=0)
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build(force=False)
+        L = ctypes.CDLL(_LIB_PATH)
+        P, I32, I64, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+        L.orc_object_create.restype = I32
+        L.orc_object_create.argtypes = [I32, P, P, P, P, P, P]
+        L.orc_object_free.argtypes = [I32]
+        L.orc_build_grid.argtypes = [I32, P]
+        L.orc_grid.argtypes = [I32, P, P]
+        L.orc_lower_bound.restype = D
+        L.orc_lower_bound.argtypes = [I32, P]
+        L.orc_sdf.argtypes = [I32, P, I64, P, P, P, P]
+        L.orc_edge_point_sphere.argtypes = [P, P, D, P, P, P, P, P]
+        L.orc_edge_point.argtypes = [I32, P, P, P, P]
+        L.orc_transition.argtypes = [P, D, P]
+        L.orc_softclip.argtypes = [D, D, D, D, P]
+        L.orc_n_groups.restype = I64
+        L.orc_n_groups.argtypes = [I32, I32]
+        L.orc_n_contacts.restype = I64
+        L.orc_n_contacts.argtypes = [I32, I32]
+        L.orc_contacts.argtypes = [P, I64, P, P, P, P, P, P, P, I32]
+        L.orc_groups_at_xi.argtypes = [P, I32, I32, P, P, P]
+        L.orc_grad_hvp.argtypes = [P, I64, P, P, P, P, P, P, P, P, I32]
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.c_void_p) if a is not None else None
+
+
+def _c(a, dt):
+    return np.ascontiguousarray(a, dtype=dt)
+
+
+class Obj:
+    """An object registered with the oracle (FP64 pieces + optional voxel grid)."""
+
+    def __init__(self, plane_off, planes, vert_off, verts, edge_off, edges):
+        self.plane_off = _c(plane_off, np.int64)
+        self.planes = _c(planes, np.float64).reshape(-1, 4)
+        self.vert_off = _c(vert_off, np.int64)
+        self.verts = _c(verts, np.float64).reshape(-1, 3)
+        self.edge_off = _c(edge_off, np.int64)
+        self.edges = _c(edges, np.int32).reshape(-1, 2)
+        self.h = lib().orc_object_create(len(self.plane_off) - 1, _p(self.plane_off), _p(self.planes),
+                                         _p(self.vert_off), _p(self.verts), _p(self.edge_off),
+                                         _p(self.edges))
+
+    @property
+    def n_pieces(self):
+        return len(self.plane_off) - 1
+
+    def n_contacts(self):
+        return len(self.verts) + len(self.edges)
+
+    def radius(self):
+        return float(np.sqrt((self.verts ** 2).sum(1)).max())
+
+    def build_grid(self, prm: Params):
+        lib().orc_build_grid(self.h, ctypes.byref(prm))
+
+    def grid(self):
+        meta = np.zeros(8)
+        lib().orc_grid(self.h, None, _p(meta))
+        n = int(meta[7])
+        G = np.zeros(n ** 3)
+        lib().orc_grid(self.h, _p(G), _p(meta))
+        return G.reshape(n, n, n), meta[:3].copy(), meta[3:6].copy(), float(meta[6])
+
+    def lower_bound(self, x):
+        x = _c(x, np.float64)
+        return lib().orc_lower_bound(self.h, _p(x))
+
+    def sdf(self, prm: Params, x):
+        x = _c(x, np.float64).reshape(-1, 3)
+        n = len(x)
+        phi, g, H = np.zeros(n), np.zeros((n, 3)), np.zeros((n, 9))
+        lib().orc_sdf(self.h, ctypes.byref(prm), n, _p(x), _p(phi), _p(g), _p(H))
+        return phi, g, H.reshape(n, 3, 3)
+
+    def edge_point(self, prm: Params, xI, xII):
+        pe = np.zeros(3)
+        lib().orc_edge_point(self.h, ctypes.byref(prm), _p(_c(xI, np.float64)), _p(_c(xII, np.float64)),
+                             _p(pe))
+        return pe
+
+    def __del__(self):
+        try:
+            lib().orc_object_free(self.h)
+        except Exception:
+            pass
+
+
+def from_points(offsets, points) -> Obj:
+    return Obj(*geometry.object_geometry(np.asarray(offsets), np.asarray(points, np.float64)))
+
+
+def from_workload_object(o) -> Obj:
+    """Oracle object from a generator object (point clouds or explicit pieces)."""
+    if hasattr(o, "points"):
+        return from_points(o.offsets, o.points)
+    return Obj(o.plane_off, o.planes, o.vert_off, o.verts, o.edge_off, o.edges)
+
+
+def edge_point_sphere(prm: Params, c, R, xI, xII):
+    pe, a, b = np.zeros(3), ctypes.c_double(), ctypes.c_double()
+    lib().orc_edge_point_sphere(ctypes.byref(prm), _p(_c(c, np.float64)), float(R), _p(_c(xI, np.float64)),
+                                _p(_c(xII, np.float64)), _p(pe), ctypes.byref(a), ctypes.byref(b))
+    return pe, a.value, b.value
+
+
+def transition(prm: Params, phi: float):
+    """(f_t, f_t', f_t'') at phi."""
+    out = np.zeros(3)
+    lib().orc_transition(ctypes.byref(prm), float(phi), _p(out))
+    return out
+
+
+def softclip(x: float, a: float, b: float, tau: float):
+    """(s_clip(x, a, b), d s_clip / dx)."""
+    out = np.zeros(2)
+    lib().orc_softclip(float(x), float(a), float(b), float(tau), _p(out))
+    return out
+
+
+def layout(objs, qa, qb):
+    """Group and contact offsets of a batch (queries in order, A's side first)."""
+    ng = np.array([objs[a].n_pieces + objs[b].n_pieces for a, b in zip(qa, qb)], np.int64)
+    nc = np.array([objs[a].n_contacts() + objs[b].n_contacts() for a, b in zip(qa, qb)], np.int64)
+    return np.concatenate([[0], np.cumsum(ng)]), np.concatenate([[0], np.cumsum(nc)])
+
+
+def contacts(prm: Params, objs, qa, qb, poses, want_contacts=False, threads: int = 0):
+    """Group records [G,12] (p, n, d, q, W, logZ) and optional per-contact records [C,13]."""
+    qa_h = _c([objs[i].h for i in qa], np.int32)
+    qb_h = _c([objs[i].h for i in qb], np.int32)
+    poses = _c(poses, np.float64).reshape(-1, 14)
+    goff, coff = layout(objs, qa, qb)
+    groups = np.zeros((goff[-1], 12))
+    cts = np.zeros((coff[-1], 13)) if want_contacts else None
+    lib().orc_contacts(ctypes.byref(prm), len(qa_h), _p(qa_h), _p(qb_h), _p(poses), _p(goff), _p(coff),
+                       _p(groups), _p(cts), int(threads))
+    return (groups, cts, goff, coff) if want_contacts else (groups, goff)
+
+
+def groups_at_xi(prm: Params, A: Obj, B: Obj, pose, xi):
+    """Group records of one query at the perturbed poses T(xi) (Rodrigues)."""
+    out = np.zeros((A.n_pieces + B.n_pieces, 12))
+    lib().orc_groups_at_xi(ctypes.byref(prm), A.h, B.h, _p(_c(pose, np.float64)), _p(_c(xi, np.float64)),
+                           _p(out))
+    return out
+
+
+def grad_hvp(prm: Params, objs, qa, qb, poses, cot, direction: Optional[np.ndarray] = None, threads: int = 0):
+    """Gradient [n,12] of <cot, groups> w.r.t. (w_A, v_A, w_B, v_B) and, if a
+    direction [n,12] is given, the Hessian-vector product [n,12]."""
+    qa_h = _c([objs[i].h for i in qa], np.int32)
+    qb_h = _c([objs[i].h for i in qb], np.int32)
+    poses = _c(poses, np.float64).reshape(-1, 14)
+    goff, _ = layout(objs, qa, qb)
+    cot = _c(cot, np.float64).reshape(-1, 12)
+    assert len(cot) == goff[-1]
+    n = len(qa_h)
+    grad = np.zeros((n, 12))
+    hv = np.zeros((n, 12)) if direction is not None else None
+    d = _c(direction, np.float64).reshape(-1, 12) if direction is not None else None
+    lib().orc_grad_hvp(ctypes.byref(prm), n, _p(qa_h), _p(qb_h), _p(poses), _p(goff), _p(cot), _p(d),
+                       _p(grad), _p(hv), int(threads))
+    return (grad, hv) if direction is not None else grad

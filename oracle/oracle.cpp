@@ -1,0 +1,698 @@
+// FP64 CPU oracle for the differentiable contact-manifold hot path.
+//
+// TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the
+// CPU-baseline leg of the benchmark may load this library.  It shares no code,
+// header, table or helper with the HIP path: it is an independent, plain,
+// slow and obviously-correct restatement of the paper's definitions.
+//
+// Paper: Beker, Geist, Paulus, Martius, "Novel Algorithms for Smoothly
+// Differentiable and Efficiently Vectorizable Contact Manifold Construction".
+//
+// Every routine is templated on the scalar type so the same code runs in
+// double (values) and in forward-mode dual numbers (exact first and second
+// derivatives with respect to the two 6-DoF poses).  Discrete decisions (the
+// stabilising shifts of log-sum-exp, voxel indices, broad-phase filtering and
+// the branches of the transition function) use the real part only.
+//
+// Steps (section of the paper in brackets):
+//   O2  piece SDF: smooth intersection of facet half-spaces   [Sec. III-A.2/3, eq. smooth-intersection]
+//   O3  object SDF: smooth union of its pieces                  [Sec. III-A.2, eq. soft_union]
+//       normal n = grad / sqrt(|grad|^2 + eps_n^2)              (reading of the paper, see DESIGN)
+//   O4  voxel grid of phi at voxel centres, vertex/edge filter  [Sec. IV-C.2]
+//   O5  vertex-SDF contacts                                     [Sec. IV-B]
+//   O6  edge-SDF contacts by sphere tracing + softclip          [Sec. IV-B.2, Fig. e_s]
+//   O7  mollification with a C2 transition f_t                  [Sec. IV-C.1]
+//   O8  softmax blending per convex piece                       [Sec. IV-D.1-3]
+//   O9  both directions (SDF and mesh roles swapped)            [Sec. III, first paragraph]
+//   O10 derivatives w.r.t. world-frame pose perturbations       (project addition)
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <limits>
+#include <mutex>
+#include <vector>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+namespace orc {
+
+// ---------------------------------------------------------------- scalars --
+inline double val(double x) { return x; }
+
+// Forward-mode dual number with N tangent slots; T may itself be a Dual,
+// which gives second derivatives (hyper-dual numbers).
+template <class T, int N>
+struct Dual {
+  T v;
+  T d[N];
+  Dual() : v(0.0) { for (int i = 0; i < N; ++i) d[i] = T(0.0); }
+  Dual(double c) : v(c) { for (int i = 0; i < N; ++i) d[i] = T(0.0); }
+  explicit Dual(const T& c, int) : v(c) { for (int i = 0; i < N; ++i) d[i] = T(0.0); }
+};
+template <class T, int N> inline double val(const Dual<T, N>& x) { return val(x.v); }
+
+#define ORC_DUAL template <class T, int N>
+ORC_DUAL inline Dual<T, N> operator+(const Dual<T, N>& a, const Dual<T, N>& b) {
+  Dual<T, N> r; r.v = a.v + b.v; for (int i = 0; i < N; ++i) r.d[i] = a.d[i] + b.d[i]; return r; }
+ORC_DUAL inline Dual<T, N> operator-(const Dual<T, N>& a, const Dual<T, N>& b) {
+  Dual<T, N> r; r.v = a.v - b.v; for (int i = 0; i < N; ++i) r.d[i] = a.d[i] - b.d[i]; return r; }
+ORC_DUAL inline Dual<T, N> operator-(const Dual<T, N>& a) {
+  Dual<T, N> r; r.v = -a.v; for (int i = 0; i < N; ++i) r.d[i] = -a.d[i]; return r; }
+ORC_DUAL inline Dual<T, N> operator*(const Dual<T, N>& a, const Dual<T, N>& b) {
+  Dual<T, N> r; r.v = a.v * b.v; for (int i = 0; i < N; ++i) r.d[i] = a.v * b.d[i] + a.d[i] * b.v; return r; }
+ORC_DUAL inline Dual<T, N> operator/(const Dual<T, N>& a, const Dual<T, N>& b) {
+  Dual<T, N> r; T inv = T(1.0) / b.v; r.v = a.v * inv;
+  for (int i = 0; i < N; ++i) r.d[i] = (a.d[i] - r.v * b.d[i]) * inv;
+  return r; }
+ORC_DUAL inline Dual<T, N> operator+(const Dual<T, N>& a, double b) { Dual<T, N> r = a; r.v = r.v + b; return r; }
+ORC_DUAL inline Dual<T, N> operator+(double b, const Dual<T, N>& a) { return a + b; }
+ORC_DUAL inline Dual<T, N> operator-(const Dual<T, N>& a, double b) { Dual<T, N> r = a; r.v = r.v - b; return r; }
+ORC_DUAL inline Dual<T, N> operator-(double b, const Dual<T, N>& a) { return (-a) + b; }
+ORC_DUAL inline Dual<T, N> operator*(const Dual<T, N>& a, double b) {
+  Dual<T, N> r; r.v = a.v * b; for (int i = 0; i < N; ++i) r.d[i] = a.d[i] * b; return r; }
+ORC_DUAL inline Dual<T, N> operator*(double b, const Dual<T, N>& a) { return a * b; }
+ORC_DUAL inline Dual<T, N> operator/(const Dual<T, N>& a, double b) { return a * (1.0 / b); }
+ORC_DUAL inline Dual<T, N> operator/(double a, const Dual<T, N>& b) { return Dual<T, N>(a) / b; }
+ORC_DUAL inline Dual<T, N>& operator+=(Dual<T, N>& a, const Dual<T, N>& b) { a = a + b; return a; }
+ORC_DUAL inline Dual<T, N>& operator-=(Dual<T, N>& a, const Dual<T, N>& b) { a = a - b; return a; }
+
+using std::exp; using std::log; using std::log1p; using std::sqrt;
+// f(x) = f(v) + f'(v) dx
+ORC_DUAL inline Dual<T, N> exp(const Dual<T, N>& a) {
+  Dual<T, N> r; r.v = exp(a.v); for (int i = 0; i < N; ++i) r.d[i] = a.d[i] * r.v; return r; }
+ORC_DUAL inline Dual<T, N> log(const Dual<T, N>& a) {
+  Dual<T, N> r; r.v = log(a.v); T inv = T(1.0) / a.v; for (int i = 0; i < N; ++i) r.d[i] = a.d[i] * inv; return r; }
+ORC_DUAL inline Dual<T, N> log1p(const Dual<T, N>& a) {
+  Dual<T, N> r; r.v = log1p(a.v); T inv = T(1.0) / (a.v + 1.0); for (int i = 0; i < N; ++i) r.d[i] = a.d[i] * inv; return r; }
+ORC_DUAL inline Dual<T, N> sqrt(const Dual<T, N>& a) {
+  Dual<T, N> r; r.v = sqrt(a.v); T inv = T(0.5) / r.v; for (int i = 0; i < N; ++i) r.d[i] = a.d[i] * inv; return r; }
+
+// ----------------------------------------------------------------- vectors --
+template <class T> struct V3 { T x, y, z; };
+template <class T> inline V3<T> mk(T x, T y, T z) { return V3<T>{x, y, z}; }
+template <class T> inline V3<T> operator+(const V3<T>& a, const V3<T>& b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
+template <class T> inline V3<T> operator-(const V3<T>& a, const V3<T>& b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+template <class T, class S> inline V3<T> operator*(const V3<T>& a, const S& s) { return {a.x * s, a.y * s, a.z * s}; }
+template <class T> inline T dot(const V3<T>& a, const V3<T>& b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+template <class T> inline V3<T> cvt(const double* p) { return {T(p[0]), T(p[1]), T(p[2])}; }
+template <class T> inline V3<double> vval(const V3<T>& a) { return {val(a.x), val(a.y), val(a.z)}; }
+
+// 3x3 matrix, row-major.
+template <class T> struct M3 { T m[3][3]; };
+template <class T> inline V3<T> mul(const M3<T>& R, const V3<T>& v) {
+  return {R.m[0][0] * v.x + R.m[0][1] * v.y + R.m[0][2] * v.z,
+          R.m[1][0] * v.x + R.m[1][1] * v.y + R.m[1][2] * v.z,
+          R.m[2][0] * v.x + R.m[2][1] * v.y + R.m[2][2] * v.z}; }
+template <class T> inline V3<T> mulT(const M3<T>& R, const V3<T>& v) {
+  return {R.m[0][0] * v.x + R.m[1][0] * v.y + R.m[2][0] * v.z,
+          R.m[0][1] * v.x + R.m[1][1] * v.y + R.m[2][1] * v.z,
+          R.m[0][2] * v.x + R.m[1][2] * v.y + R.m[2][2] * v.z}; }
+template <class T> inline M3<T> matmul(const M3<T>& A, const M3<T>& B) {
+  M3<T> C; for (int i = 0; i < 3; ++i) for (int j = 0; j < 3; ++j) {
+    T s = A.m[i][0] * B.m[0][j]; s = s + A.m[i][1] * B.m[1][j]; s = s + A.m[i][2] * B.m[2][j]; C.m[i][j] = s; }
+  return C; }
+
+// Rotation matrix of a quaternion (w, x, y, z), normalised first.
+inline M3<double> quat_to_R(const double* q) {
+  double n = std::sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+  double w = q[0] / n, x = q[1] / n, y = q[2] / n, z = q[3] / n;
+  M3<double> R;
+  R.m[0][0] = 1 - 2 * (y * y + z * z); R.m[0][1] = 2 * (x * y - w * z);     R.m[0][2] = 2 * (x * z + w * y);
+  R.m[1][0] = 2 * (x * y + w * z);     R.m[1][1] = 1 - 2 * (x * x + z * z); R.m[1][2] = 2 * (y * z - w * x);
+  R.m[2][0] = 2 * (x * z - w * y);     R.m[2][1] = 2 * (y * z + w * x);     R.m[2][2] = 1 - 2 * (x * x + y * y);
+  return R;
+}
+
+// ------------------------------------------------------------- parameters --
+struct Params {
+  double tau_cap, tau_cup, tau_st, tau_clip, tau_blend, d_max, eps_t, eps_n;
+  double grid_margin, grid_margin_rel;  // grid = vertex AABB grown by margin + margin_rel * radius
+  int32_t st_iters, grid_res, broad_phase, edge_bound;  // edge_bound: 0 paper's min form, 1 tight form
+};
+
+// --------------------------------------------------------------- geometry --
+struct Piece {
+  std::vector<double> planes;  // 4 per plane: (n_x, n_y, n_z, h); inside where n.x + h <= 0
+  std::vector<double> verts;   // 3 per vertex, object frame
+  std::vector<int32_t> edges;  // 2 per edge, piece-local vertex indices
+  size_t n_planes() const { return planes.size() / 4; }
+  size_t n_verts() const { return verts.size() / 3; }
+  size_t n_edges() const { return edges.size() / 2; }
+};
+struct Grid {
+  int n = 0;
+  double origin[3] = {0, 0, 0}, h[3] = {0, 0, 0}, r = 0;
+  std::vector<double> G;  // phi at voxel centres, index (i * n + j) * n + k
+};
+struct Object {
+  std::vector<Piece> pieces;
+  Grid grid;
+};
+
+std::mutex g_mu;
+std::vector<Object*> g_objects;
+
+inline const Object& obj(int h) { return *g_objects.at(size_t(h)); }
+
+// ---------------------------------------------------------------- O2 / O3 --
+// Smooth intersection of the piece's half-spaces, phi_k = LSE_j(n_j.x + h_j) with
+// temperature tau (Sec. II LSE; Sec. III-A.2 smooth intersection; Sec. III-A.3
+// half-space SDF).  Also returns grad phi_k = sum_j softmax_j n_j.
+template <class T>
+void piece_sdf(const Piece& pc, const V3<T>& x, double tau, T& phi, V3<T>& grad) {
+  const size_t P = pc.n_planes();
+  double m = -std::numeric_limits<double>::infinity();
+  for (size_t j = 0; j < P; ++j) {
+    const double* p = &pc.planes[4 * j];
+    m = std::max(m, val(x.x * p[0] + x.y * p[1] + x.z * p[2] + p[3]));
+  }
+  T s(0.0);
+  V3<T> G{T(0.0), T(0.0), T(0.0)};
+  for (size_t j = 0; j < P; ++j) {
+    const double* p = &pc.planes[4 * j];
+    T a = x.x * p[0] + x.y * p[1] + x.z * p[2] + p[3];
+    T w = exp((a - m) / tau);
+    s += w;
+    G.x += w * p[0]; G.y += w * p[1]; G.z += w * p[2];
+  }
+  phi = m + tau * log(s);
+  grad = G * (1.0 / s);
+}
+
+// Smooth union of the object's pieces, phi = -LSE_k(-phi_k) (eq. soft_union).
+template <class T>
+void object_sdf(const Object& o, const V3<T>& x, const Params& prm, T& phi, V3<T>& grad) {
+  const size_t K = o.pieces.size();
+  std::vector<T> pk(K);
+  std::vector<V3<T>> gk(K);
+  double M = std::numeric_limits<double>::infinity();
+  for (size_t k = 0; k < K; ++k) {
+    piece_sdf(o.pieces[k], x, prm.tau_cap, pk[k], gk[k]);
+    M = std::min(M, val(pk[k]));
+  }
+  T S(0.0);
+  V3<T> G{T(0.0), T(0.0), T(0.0)};
+  for (size_t k = 0; k < K; ++k) {
+    T u = exp((M - pk[k]) / prm.tau_cup);
+    S += u;
+    G.x += u * gk[k].x; G.y += u * gk[k].y; G.z += u * gk[k].z;
+  }
+  phi = M - prm.tau_cup * log(S);
+  grad = G * (1.0 / S);
+}
+
+template <class T>
+V3<T> normal_of(const V3<T>& g, const Params& prm) {
+  T s = sqrt(dot(g, g) + prm.eps_n * prm.eps_n);
+  return g * (1.0 / s);
+}
+
+// ---------------------------------------------------------- smooth helpers --
+// Sec. II: sigma(x) = 1 / (1 + exp(-x)), evaluated without overflow.
+template <class T> T sigmoid(const T& z) {
+  if (val(z) >= 0) return 1.0 / (1.0 + exp(-z));
+  T e = exp(z);
+  return e / (1.0 + e);
+}
+// Sec. II: s_+(x) = tau log(1 + exp(x / tau)), written as max(x,0) + tau log1p(exp(-|x|/tau)).
+template <class T> T softplus(const T& x, double tau) {
+  if (val(x) >= 0) return x + tau * log1p(exp(-x / tau));
+  return tau * log1p(exp(x / tau));
+}
+// Sec. II: s_clip(x, a, b) = a + s_+(x - a) - s_+(x - b).
+template <class T> T softclip(const T& x, const T& a, const T& b, double tau) {
+  return a + softplus(x - a, tau) - softplus(x - b, tau);
+}
+
+// ------------------------------------------------------------------ O4 grid --
+void build_grid(Object& o, const Params& prm) {
+  double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+  for (const Piece& pc : o.pieces)
+    for (size_t i = 0; i < pc.n_verts(); ++i)
+      for (int a = 0; a < 3; ++a) {
+        lo[a] = std::min(lo[a], pc.verts[3 * i + a]);
+        hi[a] = std::max(hi[a], pc.verts[3 * i + a]);
+      }
+  double rad = 0;  // bounding radius about the object origin
+  for (const Piece& pc : o.pieces)
+    for (size_t i = 0; i < pc.n_verts(); ++i)
+      rad = std::max(rad, std::sqrt(pc.verts[3 * i] * pc.verts[3 * i] + pc.verts[3 * i + 1] * pc.verts[3 * i + 1] +
+                                    pc.verts[3 * i + 2] * pc.verts[3 * i + 2]));
+  const double margin = prm.grid_margin + prm.grid_margin_rel * rad;
+  Grid& g = o.grid;
+  g.n = prm.grid_res;
+  double r2 = 0;
+  for (int a = 0; a < 3; ++a) {
+    g.origin[a] = lo[a] - margin;
+    g.h[a] = (hi[a] - lo[a] + 2 * margin) / g.n;
+    r2 += g.h[a] * g.h[a];
+  }
+  g.r = 0.5 * std::sqrt(r2);  // circumradius of a voxel
+  g.G.assign(size_t(g.n) * g.n * g.n, 0.0);
+  for (int i = 0; i < g.n; ++i)
+    for (int j = 0; j < g.n; ++j)
+      for (int k = 0; k < g.n; ++k) {
+        V3<double> c{g.origin[0] + (i + 0.5) * g.h[0], g.origin[1] + (j + 0.5) * g.h[1],
+                     g.origin[2] + (k + 0.5) * g.h[2]};
+        double phi; V3<double> gr;
+        object_sdf(o, c, prm, phi, gr);
+        g.G[(size_t(i) * g.n + j) * g.n + k] = phi;
+      }
+}
+
+// Lower bound of phi at x (SDF-object frame): phi(p_c) minus the distance bound,
+// max(r, |x - p_c|), which is the circumradius inside the grid and the
+// 1-Lipschitz extension for points clamped from outside it (Sec. IV-C.2, Fig. broadphase1).
+inline double lower_bound(const Grid& g, const V3<double>& x) {
+  const double xs[3] = {x.x, x.y, x.z};
+  int idx[3];
+  double d2 = 0;
+  for (int a = 0; a < 3; ++a) {
+    double u = (xs[a] - g.origin[a]) / g.h[a];
+    int i = int(std::floor(u));
+    i = std::min(std::max(i, 0), g.n - 1);
+    idx[a] = i;
+    double c = g.origin[a] + (i + 0.5) * g.h[a];
+    d2 += (xs[a] - c) * (xs[a] - c);
+  }
+  double Gc = g.G[(size_t(idx[0]) * g.n + idx[1]) * g.n + idx[2]];
+  return Gc - std::max(g.r, std::sqrt(d2));
+}
+
+// ------------------------------------------------------------- O6 E-SDF --
+// Sphere trace both corners towards each other with the soft-gated step
+// sigma(phi/tau_s) * phi (Sec. IV-B.2; Fig. e_s), K iterations, then softclip
+// both arc lengths to [0, L] and return the midpoint (SDF-object frame).
+template <class T, class Sdf>
+V3<T> edge_point(const Sdf& sdf, const V3<T>& xI, const V3<T>& xII, const Params& prm,
+                 T* alpha_out = nullptr, T* beta_out = nullptr) {
+  V3<T> dvec = xII - xI;
+  T L = sqrt(dot(dvec, dvec));
+  V3<T> e = dvec * (1.0 / L);
+  T alpha(0.0), beta(0.0);
+  for (int k = 0; k < prm.st_iters; ++k) {
+    T pa = sdf(xI + e * alpha);
+    T pb = sdf(xII - e * beta);
+    alpha = alpha + sigmoid(pa * (1.0 / prm.tau_st)) * pa;
+    beta = beta + sigmoid(pb * (1.0 / prm.tau_st)) * pb;
+  }
+  T zero(0.0);
+  T ac = softclip(alpha, zero, L, prm.tau_clip);
+  T bc = softclip(beta, zero, L, prm.tau_clip);
+  if (alpha_out) *alpha_out = ac;
+  if (beta_out) *beta_out = bc;
+  return (xI + e * ac + xII - e * bc) * 0.5;
+}
+
+// ----------------------------------------------------------- O7 mollify --
+// C2 transition: quintic smoothstep of s = (d_max - phi)/eps_t clamped to [0,1];
+// non-increasing in phi, 0 for phi >= d_max, 1 for phi <= d_max - eps_t (Sec. IV-C.1).
+template <class T> T transition(const T& phi, const Params& prm) {
+  T s = (prm.d_max - phi) * (1.0 / prm.eps_t);
+  if (val(s) <= 0) return T(0.0);
+  if (val(s) >= 1) return T(1.0);
+  return s * s * s * (10.0 - 15.0 * s + 6.0 * s * s);
+}
+
+template <class T> struct Contact {
+  T d, f;            // mollified depth d_c and transition value f
+  V3<T> pc, nc, fp;  // mollified point, mollified world normal, f * raw point
+  double raw_phi;    // unmollified phi (NaN when filtered)
+  int mask;          // 1 = survived the broad phase
+  int kind;          // 0 vertex, 1 edge
+};
+
+template <class T>
+Contact<T> mollify(const T& phi, const V3<T>& Nw, const V3<T>& p, const V3<T>& p_rest, const Params& prm) {
+  Contact<T> c;
+  T f = transition(phi, prm);
+  c.f = f;
+  c.d = f * phi + (1.0 - f) * prm.d_max;
+  c.nc = Nw * f;
+  c.pc = p * f + p_rest * (1.0 - f);
+  c.fp = p * f;
+  c.raw_phi = val(phi);
+  c.mask = 1;
+  return c;
+}
+
+template <class T>
+Contact<T> filtered(const V3<T>& p_rest, const Params& prm) {
+  Contact<T> c;
+  c.f = T(0.0);
+  c.d = T(prm.d_max);
+  c.nc = V3<T>{T(0.0), T(0.0), T(0.0)};
+  c.pc = p_rest;
+  c.fp = V3<T>{T(0.0), T(0.0), T(0.0)};
+  c.raw_phi = std::numeric_limits<double>::quiet_NaN();
+  c.mask = 0;
+  return c;
+}
+
+// ------------------------------------------------------------- O8 blend --
+template <class T> struct GroupOut {
+  V3<T> p, n; T d; V3<T> q; T W, logZ;
+};
+
+// Softmax over l_i = -d_c,i / tau_b (deeper contacts weigh more), then blend
+// depth, normal (renormalised), point and the Jacobian moments q = sum w f p,
+// W = sum w f (Sec. IV-D.2-3).
+template <class T>
+GroupOut<T> blend(const std::vector<Contact<T>>& cs, const Params& prm, std::vector<double>* w_out) {
+  double Lam = -std::numeric_limits<double>::infinity();
+  std::vector<T> l(cs.size());
+  for (size_t i = 0; i < cs.size(); ++i) { l[i] = cs[i].d * (-1.0 / prm.tau_blend); Lam = std::max(Lam, val(l[i])); }
+  T Z(0.0);
+  std::vector<T> e(cs.size());
+  for (size_t i = 0; i < cs.size(); ++i) { e[i] = exp(l[i] - Lam); Z += e[i]; }
+  GroupOut<T> g;
+  T zero(0.0);
+  g.p = g.n = g.q = V3<T>{zero, zero, zero};
+  g.d = g.W = zero;
+  V3<T> m{zero, zero, zero};
+  for (size_t i = 0; i < cs.size(); ++i) {
+    T w = e[i] / Z;
+    if (w_out) w_out->push_back(val(w));
+    g.d += w * cs[i].d;
+    m = m + cs[i].nc * w;
+    g.p = g.p + cs[i].pc * w;
+    g.q = g.q + cs[i].fp * w;
+    g.W += w * cs[i].f;
+  }
+  g.n = normal_of(m, prm);
+  g.logZ = Lam + log(Z);
+  return g;
+}
+
+// ---------------------------------------------------------- O5-O9 query --
+template <class T> struct Pose { M3<T> R; V3<T> t; };
+
+template <class T> struct SdfFn {
+  const Object* o; const Params* prm;
+  T operator()(const V3<T>& x) const { T phi; V3<T> g; object_sdf(*o, x, *prm, phi, g); return phi; }
+};
+
+// One direction: vertices and edges of `mesh` against the SDF of `sdf`.
+template <class T>
+void direction(const Object& mesh, const Object& sdf, const Pose<T>& PM, const Pose<T>& PS,
+               const Params& prm, std::vector<GroupOut<T>>& out, std::vector<double>* dbg) {
+  const bool bp = prm.broad_phase != 0 && sdf.grid.n > 0;
+  SdfFn<T> fn{&sdf, &prm};
+  for (const Piece& pc : mesh.pieces) {
+    std::vector<Contact<T>> cs;
+    const size_t V = pc.n_verts();
+    std::vector<V3<T>> Pw(V), xs(V);
+    for (size_t i = 0; i < V; ++i) {
+      Pw[i] = mul(PM.R, cvt<T>(&pc.verts[3 * i])) + PM.t;  // world position of the vertex
+      xs[i] = mulT(PS.R, Pw[i] - PS.t);                       // in the SDF object's frame
+    }
+    // O5: vertex-SDF contacts (Sec. IV-B).
+    for (size_t i = 0; i < V; ++i) {
+      if (bp && lower_bound(sdf.grid, vval(xs[i])) >= prm.d_max) {
+        cs.push_back(filtered(Pw[i], prm)); cs.back().kind = 0; continue;
+      }
+      T phi; V3<T> g;
+      object_sdf(sdf, xs[i], prm, phi, g);
+      V3<T> Nw = mul(PS.R, normal_of(g, prm));
+      cs.push_back(mollify(phi, Nw, Pw[i], Pw[i], prm)); cs.back().kind = 0;
+    }
+    // O6: edge-SDF contacts (Sec. IV-B.2).
+    for (size_t k = 0; k < pc.n_edges(); ++k) {
+      const int i0 = pc.edges[2 * k], i1 = pc.edges[2 * k + 1];
+      V3<T> rest = (Pw[i0] + Pw[i1]) * 0.5;
+      if (bp) {
+        V3<double> a = vval(xs[i0]), b = vval(xs[i1]);
+        V3<double> dv = b - a;
+        double L = std::sqrt(dot(dv, dv));
+        double la = lower_bound(sdf.grid, a), lbb = lower_bound(sdf.grid, b);
+        // Any edge point is within s of one end and L - s of the other, so
+        // phi >= min(la, lb) - L (the paper's form) and, tighter,
+        // phi >= max(max(la, lb) - L, (la + lb - L) / 2).
+        double lb = prm.edge_bound == 0 ? std::min(la, lbb) - L
+                                        : std::max(std::max(la, lbb) - L, 0.5 * (la + lbb - L));
+        if (lb >= prm.d_max) { cs.push_back(filtered(rest, prm)); cs.back().kind = 1; continue; }
+      }
+      V3<T> pe = edge_point(fn, xs[i0], xs[i1], prm);
+      T phi; V3<T> g;
+      object_sdf(sdf, pe, prm, phi, g);
+      V3<T> Nw = mul(PS.R, normal_of(g, prm));
+      V3<T> pw = mul(PS.R, pe) + PS.t;
+      cs.push_back(mollify(phi, Nw, pw, rest, prm)); cs.back().kind = 1;
+    }
+    std::vector<double> w;
+    out.push_back(blend(cs, prm, dbg ? &w : nullptr));
+    if (dbg) {
+      for (size_t i = 0; i < cs.size(); ++i) {
+        const Contact<T>& c = cs[i];
+        double rec[13] = {double(c.mask), val(c.d), val(c.f), w[i],
+                          val(c.pc.x), val(c.pc.y), val(c.pc.z),
+                          val(c.nc.x), val(c.nc.y), val(c.nc.z), c.raw_phi, double(c.kind), 0.0};
+        dbg->insert(dbg->end(), rec, rec + 13);
+      }
+    }
+  }
+}
+
+template <class T>
+void query(const Object& A, const Object& B, const Pose<T>& PA, const Pose<T>& PB, const Params& prm,
+           std::vector<GroupOut<T>>& out, std::vector<double>* dbg) {
+  direction(A, B, PA, PB, prm, out, dbg);  // A's mesh against B's SDF
+  direction(B, A, PB, PA, prm, out, dbg);  // roles swapped (Sec. III)
+}
+
+template <class T> inline void put(const GroupOut<T>& g, double* o) {
+  const T* v[12] = {&g.p.x, &g.p.y, &g.p.z, &g.n.x, &g.n.y, &g.n.z, &g.d, &g.q.x, &g.q.y, &g.q.z, &g.W, &g.logZ};
+  for (int i = 0; i < 12; ++i) o[i] = val(*v[i]);
+}
+template <class T> inline const T& comp(const GroupOut<T>& g, int i) {
+  const T* v[12] = {&g.p.x, &g.p.y, &g.p.z, &g.n.x, &g.n.y, &g.n.z, &g.d, &g.q.x, &g.q.y, &g.q.z, &g.W, &g.logZ};
+  return *v[i];
+}
+
+// ----------------------------------------------------- O10 perturbed pose --
+// T_X(xi) = (exp([w_X]x) R_X, t_X + v_X).  `second_order` uses I + W + W^2/2,
+// whose first and second derivatives at xi = 0 equal those of the exponential;
+// otherwise Rodrigues' formula (used for finite differences at +-h).
+template <class T>
+Pose<T> perturbed(const M3<double>& R0, const double* t0, const T* w, const T* v, bool second_order) {
+  M3<T> E;
+  T zero(0.0), one(1.0);
+  if (second_order) {
+    // W = [w]x
+    M3<T> W;
+    W.m[0][0] = zero; W.m[0][1] = -w[2]; W.m[0][2] = w[1];
+    W.m[1][0] = w[2]; W.m[1][1] = zero; W.m[1][2] = -w[0];
+    W.m[2][0] = -w[1]; W.m[2][1] = w[0]; W.m[2][2] = zero;
+    M3<T> W2 = matmul(W, W);
+    for (int i = 0; i < 3; ++i) for (int j = 0; j < 3; ++j)
+      E.m[i][j] = (i == j ? one : zero) + W.m[i][j] + W2.m[i][j] * 0.5;
+  } else {
+    double wx = val(w[0]), wy = val(w[1]), wz = val(w[2]);
+    double th = std::sqrt(wx * wx + wy * wy + wz * wz);
+    double K[3][3] = {{0, -wz, wy}, {wz, 0, -wx}, {-wy, wx, 0}};
+    double K2[3][3];
+    for (int i = 0; i < 3; ++i) for (int j = 0; j < 3; ++j) {
+      K2[i][j] = 0; for (int l = 0; l < 3; ++l) K2[i][j] += K[i][l] * K[l][j]; }
+    double a = th > 1e-300 ? std::sin(th) / th : 1.0;
+    double b = th > 1e-300 ? (1 - std::cos(th)) / (th * th) : 0.5;
+    for (int i = 0; i < 3; ++i) for (int j = 0; j < 3; ++j)
+      E.m[i][j] = T((i == j ? 1.0 : 0.0) + a * K[i][j] + b * K2[i][j]);
+  }
+  M3<T> R0T;
+  for (int i = 0; i < 3; ++i) for (int j = 0; j < 3; ++j) R0T.m[i][j] = T(R0.m[i][j]);
+  Pose<T> P;
+  P.R = matmul(E, R0T);
+  P.t = V3<T>{T(t0[0]) + v[0], T(t0[1]) + v[1], T(t0[2]) + v[2]};
+  return P;
+}
+
+size_t n_groups(const Object& A, const Object& B) { return A.pieces.size() + B.pieces.size(); }
+size_t n_contacts(const Object& o) {
+  size_t c = 0;
+  for (const Piece& p : o.pieces) c += p.n_verts() + p.n_edges();
+  return c;
+}
+
+}  // namespace orc
+
+using namespace orc;
+
+extern "C" {
+
+// Registers an object given explicitly as pieces; returns its handle.
+int orc_object_create(int32_t n_pieces, const int64_t* plane_off, const double* planes,
+                      const int64_t* vert_off, const double* verts,
+                      const int64_t* edge_off, const int32_t* edges) {
+  Object* o = new Object;
+  o->pieces.resize(size_t(n_pieces));
+  for (int k = 0; k < n_pieces; ++k) {
+    Piece& p = o->pieces[size_t(k)];
+    p.planes.assign(planes + 4 * plane_off[k], planes + 4 * plane_off[k + 1]);
+    p.verts.assign(verts + 3 * vert_off[k], verts + 3 * vert_off[k + 1]);
+    p.edges.assign(edges + 2 * edge_off[k], edges + 2 * edge_off[k + 1]);
+  }
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_objects.push_back(o);
+  return int(g_objects.size() - 1);
+}
+
+void orc_object_free(int32_t h) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  delete g_objects.at(size_t(h));
+  g_objects[size_t(h)] = nullptr;
+}
+
+void orc_build_grid(int32_t h, const Params* prm) { build_grid(*g_objects.at(size_t(h)), *prm); }
+
+// meta: origin[3], h[3], r, n.  G may be null.
+void orc_grid(int32_t h, double* G, double* meta) {
+  const Grid& g = obj(h).grid;
+  for (int a = 0; a < 3; ++a) { meta[a] = g.origin[a]; meta[3 + a] = g.h[a]; }
+  meta[6] = g.r; meta[7] = g.n;
+  if (G) std::copy(g.G.begin(), g.G.end(), G);
+}
+
+double orc_lower_bound(int32_t h, const double* x) { return lower_bound(obj(h).grid, V3<double>{x[0], x[1], x[2]}); }
+
+// phi, grad (n x 3) and Hessian (n x 9) of the object SDF at n points.
+void orc_sdf(int32_t h, const Params* prm, int64_t n, const double* x, double* phi, double* grad, double* hess) {
+  const Object& o = obj(h);
+  for (int64_t i = 0; i < n; ++i) {
+    typedef Dual<double, 3> D3;
+    V3<D3> xd{D3(x[3 * i]), D3(x[3 * i + 1]), D3(x[3 * i + 2])};
+    xd.x.d[0] = 1; xd.y.d[1] = 1; xd.z.d[2] = 1;
+    D3 p; V3<D3> g;
+    object_sdf(o, xd, *prm, p, g);
+    phi[i] = p.v;
+    if (grad) { grad[3 * i] = g.x.v; grad[3 * i + 1] = g.y.v; grad[3 * i + 2] = g.z.v; }
+    if (hess) {
+      const D3* gg[3] = {&g.x, &g.y, &g.z};
+      for (int a = 0; a < 3; ++a) for (int b = 0; b < 3; ++b) hess[9 * i + 3 * a + b] = gg[a]->d[b];
+    }
+  }
+}
+
+// E-SDF of an edge against the sphere SDF |x - c| - R (generic-SDF check of O6).
+void orc_edge_point_sphere(const Params* prm, const double* c, double R, const double* xI, const double* xII,
+                           double* pe, double* alpha, double* beta) {
+  struct Sphere { V3<double> c; double R;
+    double operator()(const V3<double>& x) const { V3<double> d = x - c; return std::sqrt(dot(d, d)) - R; } };
+  Sphere s{V3<double>{c[0], c[1], c[2]}, R};
+  double a, b;
+  V3<double> p = edge_point(s, cvt<double>(xI), cvt<double>(xII), *prm, &a, &b);
+  pe[0] = p.x; pe[1] = p.y; pe[2] = p.z; *alpha = a; *beta = b;
+}
+
+// E-SDF point of an edge against an object's SDF (object frame).
+void orc_edge_point(int32_t h, const Params* prm, const double* xI, const double* xII, double* pe) {
+  SdfFn<double> fn{&obj(h), prm};
+  V3<double> p = edge_point(fn, cvt<double>(xI), cvt<double>(xII), *prm);
+  pe[0] = p.x; pe[1] = p.y; pe[2] = p.z;
+}
+
+// Transition f_t and its first two derivatives at phi (hyper-dual).
+void orc_transition(const Params* prm, double phi, double* out3) {
+  typedef Dual<double, 1> In; typedef Dual<In, 1> HD;
+  HD x(0.0); x.v = In(phi); x.v.d[0] = 1.0; x.d[0] = In(1.0);
+  HD f = transition(x, *prm);
+  out3[0] = f.v.v; out3[1] = f.d[0].v; out3[2] = f.d[0].d[0];
+}
+// Softclip s_clip(x, a, b) with temperature tau and its derivative in x.
+void orc_softclip(double x, double a, double b, double tau, double* out2) {
+  typedef Dual<double, 1> D;
+  D xd(x); xd.d[0] = 1.0;
+  D r = softclip(xd, D(a), D(b), tau);
+  out2[0] = r.v; out2[1] = r.d[0];
+}
+
+int64_t orc_n_groups(int32_t a, int32_t b) { return int64_t(n_groups(obj(a), obj(b))); }
+int64_t orc_n_contacts(int32_t a, int32_t b) { return int64_t(n_contacts(obj(a)) + n_contacts(obj(b))); }
+
+// Forward pass for n pair-queries.  poses: n x 14 = qa(w,x,y,z) ta qb tb.
+// groups: [sum groups][12] = p(3) n(3) d q(3) W logZ, queries in order, A's
+// pieces first.  contacts (nullable): [sum contacts][13] = mask d_c f w p_c(3)
+// n_c(3) phi kind pad, in the same order (A's mesh first; per piece vertices
+// then edges).
+void orc_contacts(const Params* prm, int64_t n, const int32_t* qa, const int32_t* qb, const double* poses,
+                  const int64_t* group_off, const int64_t* contact_off,
+                  double* groups, double* contacts, int32_t n_threads) {
+#ifdef _OPENMP
+  if (n_threads > 0) omp_set_num_threads(n_threads);
+#pragma omp parallel for schedule(dynamic, 1)
+#endif
+  for (int64_t i = 0; i < n; ++i) {
+    const double* ps = poses + 14 * i;
+    Pose<double> PA{quat_to_R(ps), V3<double>{ps[4], ps[5], ps[6]}};
+    Pose<double> PB{quat_to_R(ps + 7), V3<double>{ps[11], ps[12], ps[13]}};
+    std::vector<GroupOut<double>> out;
+    std::vector<double> dbg;
+    query(obj(qa[i]), obj(qb[i]), PA, PB, *prm, out, contacts ? &dbg : nullptr);
+    for (size_t g = 0; g < out.size(); ++g) put(out[g], groups + 12 * (group_off[i] + int64_t(g)));
+    if (contacts) std::copy(dbg.begin(), dbg.end(), contacts + 13 * contact_off[i]);
+  }
+}
+
+// Group outputs of one query at the perturbed pose T(xi) (Rodrigues), for
+// finite differences.
+void orc_groups_at_xi(const Params* prm, int32_t a, int32_t b, const double* pose, const double* xi, double* groups) {
+  M3<double> RA = quat_to_R(pose), RB = quat_to_R(pose + 7);
+  Pose<double> PA = perturbed<double>(RA, pose + 4, xi, xi + 3, false);
+  Pose<double> PB = perturbed<double>(RB, pose + 11, xi + 6, xi + 9, false);
+  std::vector<GroupOut<double>> out;
+  query(obj(a), obj(b), PA, PB, *prm, out, nullptr);
+  for (size_t g = 0; g < out.size(); ++g) put(out[g], groups + 12 * g);
+}
+
+// Gradient of L = <c, y> w.r.t. xi = (w_A, v_A, w_B, v_B) at xi = 0 and,
+// when dir != null, the Hessian-vector product H dir, by hyper-dual numbers.
+void orc_grad_hvp(const Params* prm, int64_t n, const int32_t* qa, const int32_t* qb, const double* poses,
+                  const int64_t* group_off, const double* cot, const double* dir,
+                  double* grad, double* hv, int32_t n_threads) {
+#ifdef _OPENMP
+  if (n_threads > 0) omp_set_num_threads(n_threads);
+#pragma omp parallel for schedule(dynamic, 1)
+#endif
+  for (int64_t i = 0; i < n; ++i) {
+    const double* ps = poses + 14 * i;
+    M3<double> RA = quat_to_R(ps), RB = quat_to_R(ps + 7);
+    const double* c = cot + 12 * group_off[i];
+    if (dir) {
+      typedef Dual<double, 1> In;
+      typedef Dual<In, 12> HD;
+      HD xi[12];
+      for (int k = 0; k < 12; ++k) {
+        xi[k] = HD(0.0);
+        xi[k].v.d[0] = dir[12 * i + k];
+        xi[k].d[k] = In(1.0);
+      }
+      Pose<HD> PA = perturbed<HD>(RA, ps + 4, xi, xi + 3, true);
+      Pose<HD> PB = perturbed<HD>(RB, ps + 11, xi + 6, xi + 9, true);
+      std::vector<GroupOut<HD>> out;
+      query(obj(qa[i]), obj(qb[i]), PA, PB, *prm, out, nullptr);
+      HD L(0.0);
+      for (size_t g = 0; g < out.size(); ++g)
+        for (int k = 0; k < 12; ++k) L += comp(out[g], k) * c[12 * g + k];
+      for (int k = 0; k < 12; ++k) {
+        grad[12 * i + k] = L.d[k].v;
+        hv[12 * i + k] = L.d[k].d[0];
+      }
+    } else {
+      typedef Dual<double, 12> D;
+      D xi[12];
+      for (int k = 0; k < 12; ++k) { xi[k] = D(0.0); xi[k].d[k] = 1.0; }
+      Pose<D> PA = perturbed<D>(RA, ps + 4, xi, xi + 3, true);
+      Pose<D> PB = perturbed<D>(RB, ps + 11, xi + 6, xi + 9, true);
+      std::vector<GroupOut<D>> out;
+      query(obj(qa[i]), obj(qb[i]), PA, PB, *prm, out, nullptr);
+      D L(0.0);
+      for (size_t g = 0; g < out.size(); ++g)
+        for (int k = 0; k < 12; ++k) L += comp(out[g], k) * c[12 * g + k];
+      for (int k = 0; k < 12; ++k) grad[12 * i + k] = L.d[k];
+    }
+  }
+}
+
+}  // extern "C"

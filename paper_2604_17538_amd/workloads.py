@@ -1,0 +1,258 @@
+"""Seeded synthetic inputs for the contact-manifold workloads.
+
+This module only draws random numbers: point clouds of convex pieces, explicit
+box geometry, poses, cotangents and directions.  It holds none of the method's
+arithmetic (no hull, no SDF, no contact, no blending), so both the HIP path and
+the FP64 oracle consume exactly the same inputs.
+
+The paper evaluates on armadillo/cup meshes and random configurations
+(Sec. V.3-V.4); those assets are not available, so these generators stand in for
+them with unions of convex pieces of comparable primitive counts.
+
+Recipes (all draws from ``numpy.random.Generator(PCG64(seed))`` in the order
+written below):
+
+* ellipsoid points: ``a * normalize(N(0, I3))``; radial noise multiplies by
+  ``1 + U[-noise, noise]``;
+* log-uniform integer in [lo, hi]: ``floor(exp(U[ln lo, ln(hi + 1))))``;
+* poses: ``T_A`` is the identity, ``q_B = normalize(N(0, I4))``,
+  ``dir = normalize(N(0, I3))``, ``t_B = dist * dir`` with
+  ``dist = (r_A + r_B) * U[0.6, 1.05]`` where ``r_X`` is the largest point norm of
+  object X in its own frame.
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import List, Optional
+
+import numpy as np
+
+SEED_BASE = 17538
+
+
+@dataclasses.dataclass
+class PointObject:
+    """An object given as point clouds, one per convex piece (object frame)."""
+    offsets: np.ndarray  # int64 [n_pieces + 1], indices into points
+    points: np.ndarray   # float64 [n_points, 3]
+
+    @property
+    def n_pieces(self) -> int:
+        return len(self.offsets) - 1
+
+    def piece(self, k: int) -> np.ndarray:
+        return self.points[self.offsets[k]:self.offsets[k + 1]]
+
+    def radius(self) -> float:
+        return float(np.sqrt((self.points ** 2).sum(1)).max())
+
+
+@dataclasses.dataclass
+class RawObject:
+    """An object given explicitly: planes (n, h), vertices and edges per piece."""
+    plane_off: np.ndarray  # int64 [n_pieces + 1]
+    planes: np.ndarray     # float64 [P, 4]  (n_x, n_y, n_z, h), inside: n.x + h <= 0
+    vert_off: np.ndarray   # int64 [n_pieces + 1]
+    verts: np.ndarray      # float64 [V, 3]
+    edge_off: np.ndarray   # int64 [n_pieces + 1]
+    edges: np.ndarray      # int32 [E, 2], piece-local vertex indices
+
+    @property
+    def n_pieces(self) -> int:
+        return len(self.plane_off) - 1
+
+    def radius(self) -> float:
+        return float(np.sqrt((self.verts ** 2).sum(1)).max())
+
+
+@dataclasses.dataclass
+class Workload:
+    name: str
+    objects: list                 # PointObject | RawObject
+    qa: np.ndarray                # int32 [n] object index of A
+    qb: np.ndarray                # int32 [n] object index of B
+    poses: np.ndarray             # float64 [n, 14]: qa(w,x,y,z) ta(3) qb(w,x,y,z) tb(3)
+    L_ref: float                  # length scale of the workload (m)
+    cot_seed: Optional[int] = None
+
+    @property
+    def n(self) -> int:
+        return len(self.qa)
+
+
+def unit_box(side: float = 1.0) -> RawObject:
+    """Axis-aligned box [-side/2, side/2]^3: 8 vertices, 12 edges, 6 planes."""
+    b = 0.5 * side
+    planes = np.array([[1, 0, 0, -b], [-1, 0, 0, -b], [0, 1, 0, -b],
+                       [0, -1, 0, -b], [0, 0, 1, -b], [0, 0, -1, -b]], np.float64)
+    verts = np.array([[sx * b, sy * b, sz * b] for sx in (-1, 1) for sy in (-1, 1)
+                      for sz in (-1, 1)], np.float64)
+    edges = []
+    for i in range(8):
+        for j in range(i + 1, 8):
+            if np.count_nonzero(verts[i] != verts[j]) == 1:
+                edges.append((i, j))
+    edges = np.array(edges, np.int32)
+    z = np.array([0, 0], np.int64)
+    return RawObject(np.array([0, 6], np.int64), planes, np.array([0, 8], np.int64), verts,
+                     np.array([0, len(edges)], np.int64), edges)
+
+
+def _unit_gauss(rng, n, d):
+    x = rng.standard_normal((n, d))
+    return x / np.linalg.norm(x, axis=1, keepdims=True)
+
+
+def ellipsoid_points(rng, n, axes, noise=0.0):
+    p = np.asarray(axes)[None, :] * _unit_gauss(rng, n, 3)
+    if noise > 0:
+        p = p * (1.0 + rng.uniform(-noise, noise, size=(n, 1)))
+    return p
+
+
+def log_uniform_int(rng, lo, hi, size=None):
+    return np.floor(np.exp(rng.uniform(np.log(lo), np.log(hi + 1), size=size))).astype(np.int64)
+
+
+def random_poses(rng, radii_a, radii_b, lo=0.6, hi=1.05):
+    """T_A = identity, q_B uniform on SO(3), t_B at distance (r_A + r_B) * U[lo, hi]."""
+    n = len(radii_a)
+    poses = np.zeros((n, 14))
+    poses[:, 0] = 1.0
+    qb = _unit_gauss(rng, n, 4)
+    d = _unit_gauss(rng, n, 3)
+    dist = (np.asarray(radii_a) + np.asarray(radii_b)) * rng.uniform(lo, hi, size=n)
+    poses[:, 7:11] = qb
+    poses[:, 11:14] = d * dist[:, None]
+    return poses
+
+
+def multi_piece_object(rng, n_pieces, counts, axes_lo=0.02, axes_hi=0.2, centre=0.1,
+                       noise=0.0) -> PointObject:
+    pts, off = [], [0]
+    for k in range(n_pieces):
+        axes = rng.uniform(axes_lo, axes_hi, size=3)
+        c = rng.uniform(-centre, centre, size=3)
+        p = ellipsoid_points(rng, int(counts[k]), axes, noise) + c[None, :]
+        pts.append(p)
+        off.append(off[-1] + len(p))
+    return PointObject(np.array(off, np.int64), np.concatenate(pts, 0))
+
+
+def config0(seed: int = SEED_BASE + 0, n_poses: int = 256) -> Workload:
+    """Two unit boxes (explicit geometry) + two hulls of 64 ellipsoid points."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    box = unit_box(1.0)
+    e1 = PointObject(np.array([0, 64], np.int64),
+                     ellipsoid_points(rng, 64, rng.uniform(0.5, 1.0, size=3)))
+    e2 = PointObject(np.array([0, 64], np.int64),
+                     ellipsoid_points(rng, 64, rng.uniform(0.5, 1.0, size=3)))
+    objects = [box, box, e1, e2]
+    p_box = random_poses(rng, [box.radius()] * n_poses, [box.radius()] * n_poses)
+    p_ell = random_poses(rng, [e1.radius()] * n_poses, [e2.radius()] * n_poses)
+    qa = np.array([0] * n_poses + [2] * n_poses, np.int32)
+    qb = np.array([1] * n_poses + [3] * n_poses, np.int32)
+    return Workload("c0", objects, qa, qb, np.concatenate([p_box, p_ell]), 1.0)
+
+
+def config1(seed: int = SEED_BASE + 1, n_envs: int = 4096) -> Workload:
+    """n_envs pairs of 8-piece objects; pieces are hulls of U{32..128} noisy ellipsoid points."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    objects = []
+    for _ in range(2 * n_envs):
+        counts = rng.integers(32, 129, size=8)
+        objects.append(multi_piece_object(rng, 8, counts, noise=0.05))
+    radii = np.array([o.radius() for o in objects])
+    qa = np.arange(0, 2 * n_envs, 2, dtype=np.int32)
+    qb = qa + 1
+    poses = random_poses(rng, radii[qa], radii[qb])
+    return Workload("c1", objects, qa, qb, poses, 0.1)
+
+
+def _c2_object(rng, vlo=8, vhi=512, plo=1, phi=32):
+    n_pieces = int(log_uniform_int(rng, plo, phi))
+    counts = log_uniform_int(rng, vlo, vhi, size=n_pieces)
+    return multi_piece_object(rng, n_pieces, counts, noise=0.0)
+
+
+def config2(seed: int = SEED_BASE + 2, n_pairs: int = 16384) -> Workload:
+    """Pairs with log-uniform piece counts [1,32] and vertex counts [8,512]."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    objects = [_c2_object(rng) for _ in range(2 * n_pairs)]
+    radii = np.array([o.radius() for o in objects])
+    qa = np.arange(0, 2 * n_pairs, 2, dtype=np.int32)
+    qb = qa + 1
+    poses = random_poses(rng, radii[qa], radii[qb])
+    return Workload("c2", objects, qa, qb, poses, 0.1, cot_seed=seed + 1000)
+
+
+def config4(seed: int = SEED_BASE + 4, n_envs: int = 65536, library: Optional[int] = None) -> Workload:
+    """Pairs of 32-piece objects with log-uniform [64,1024] points per piece.
+
+    ``library`` draws the objects from a library of that many distinct objects
+    (pair objects picked uniformly) instead of 2 * n_envs distinct ones.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    n_obj = 2 * n_envs if library is None else library
+    objects = [_c2_object(rng, 64, 1024, 32, 32) for _ in range(n_obj)]
+    radii = np.array([o.radius() for o in objects])
+    if library is None:
+        qa = np.arange(0, 2 * n_envs, 2, dtype=np.int32)
+        qb = qa + 1
+    else:
+        qa = rng.integers(0, n_obj, size=n_envs).astype(np.int32)
+        qb = rng.integers(0, n_obj, size=n_envs).astype(np.int32)
+    poses = random_poses(rng, radii[qa], radii[qb])
+    return Workload("c4", objects, qa, qb, poses, 0.1, cot_seed=seed + 1000)
+
+
+def cotangents(seed: int, n_groups: int) -> np.ndarray:
+    """Cotangent c ~ N(0, 1) for every group output (12 per group)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return rng.standard_normal((n_groups, 12))
+
+
+def directions(seed: int, n: int) -> np.ndarray:
+    """Unit Gaussian direction in R^12 per pair-query."""
+    rng = np.random.Generator(np.random.PCG64(seed + 1))
+    return _unit_gauss(rng, n, 12)
+
+
+@dataclasses.dataclass
+class ServingTrace:
+    """Poisson request stream over a library of objects."""
+    arrival_s: np.ndarray      # float64 [R] arrival times
+    n_pairs: np.ndarray        # int32 [R] pairs per request (U{1..64})
+    want_grad: np.ndarray      # bool [R] (30 % forward+gradient)
+    pair_a: List[np.ndarray]   # per request: object indices A
+    pair_b: List[np.ndarray]
+    poses: List[np.ndarray]    # per request: [n_pairs, 14]
+
+
+def serving_trace(library: list, rate_hz: float, duration_s: float,
+                  seed: int = SEED_BASE + 3, max_pairs: int = 64,
+                  grad_fraction: float = 0.3) -> ServingTrace:
+    rng = np.random.Generator(np.random.PCG64(seed))
+    radii = np.array([o.radius() for o in library])
+    t, arr = 0.0, []
+    while True:
+        t += rng.exponential(1.0 / rate_hz)
+        if t >= duration_s:
+            break
+        arr.append(t)
+    R = len(arr)
+    n_pairs = rng.integers(1, max_pairs + 1, size=R).astype(np.int32)
+    want_grad = rng.uniform(size=R) < grad_fraction
+    pa, pb, ps = [], [], []
+    for r in range(R):
+        a = rng.integers(0, len(library), size=n_pairs[r]).astype(np.int32)
+        b = rng.integers(0, len(library), size=n_pairs[r]).astype(np.int32)
+        pa.append(a)
+        pb.append(b)
+        ps.append(random_poses(rng, radii[a], radii[b]))
+    return ServingTrace(np.array(arr), n_pairs, want_grad, pa, pb, ps)
+
+
+def library_objects(n: int = 2048, seed: int = SEED_BASE + 3) -> list:
+    rng = np.random.Generator(np.random.PCG64(seed + 7))
+    return [_c2_object(rng) for _ in range(n)]

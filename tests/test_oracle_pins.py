@@ -1,0 +1,512 @@
+"""Pins of the FP64 oracle against what the paper and mathematics fix.
+
+Each test checks the oracle against something other than itself: closed forms,
+textbook bounds of log-sum-exp, brute-force exact distances, finite differences,
+and invariants the paper states (symmetry by swapping roles, weights summing to
+one, the blended point staying in the convex hull, filtered contacts giving
+(d_max, 0, 0)).  All CPU.
+"""
+import numpy as np
+import pytest
+from scipy.spatial import ConvexHull
+
+from paper_2604_17538_amd import workloads as W
+
+pytestmark = pytest.mark.filterwarnings("ignore")
+
+
+# ------------------------------------------------------------------ helpers --
+def point_segment_dist(p, a, b):
+    ab = b - a
+    t = np.clip(np.dot(p - a, ab) / np.dot(ab, ab), 0.0, 1.0)
+    return np.linalg.norm(p - (a + t * ab))
+
+
+def point_triangle_dist(p, a, b, c):
+    n = np.cross(b - a, c - a)
+    n = n / np.linalg.norm(n)
+    d = np.dot(p - a, n)
+    q = p - d * n
+    # barycentric test of the projection
+    v0, v1, v2 = b - a, c - a, q - a
+    d00, d01, d11 = v0 @ v0, v0 @ v1, v1 @ v1
+    d20, d21 = v2 @ v0, v2 @ v1
+    den = d00 * d11 - d01 * d01
+    v = (d11 * d20 - d01 * d21) / den
+    w = (d00 * d21 - d01 * d20) / den
+    if v >= 0 and w >= 0 and v + w <= 1:
+        return abs(d)
+    return min(point_segment_dist(p, a, b), point_segment_dist(p, b, c), point_segment_dist(p, c, a))
+
+
+def exact_hull_sdf(points, x):
+    """Brute-force exact signed distance to the convex hull of points."""
+    h = ConvexHull(points)
+    inside = np.all(h.equations[:, :3] @ x + h.equations[:, 3] <= 0)
+    d = min(point_triangle_dist(x, *points[s]) for s in h.simplices)
+    return -d if inside else d
+
+
+def fibonacci_sphere(n, R):
+    i = np.arange(n) + 0.5
+    phi = np.arccos(1 - 2 * i / n)
+    th = np.pi * (1 + 5 ** 0.5) * i
+    return R * np.stack([np.cos(th) * np.sin(phi), np.sin(th) * np.sin(phi), np.cos(phi)], 1)
+
+
+def one_piece(O, pts):
+    return O.from_points(np.array([0, len(pts)]), pts)
+
+
+# ------------------------------------------------------------ O2/O3 the SDF --
+def test_box_sdf_small_tau_is_exact_box_sdf(oracle_mod):
+    """tau -> 0: inside, phi -> max_i(|x_i| - 1/2); outside in a face region,
+    phi -> the Euclidean distance to that face (textbook box SDF)."""
+    O = oracle_mod
+    b = W.unit_box()
+    box = O.Obj(b.plane_off, b.planes, b.vert_off, b.verts, b.edge_off, b.edges)
+    prm = O.default_params(1.0, tau_cap=1e-5, tau_cup=1e-5)
+    rng = np.random.default_rng(0)
+    xin = rng.uniform(-0.45, 0.45, size=(200, 3))
+    phi, g, _ = box.sdf(prm, xin)
+    ref = np.max(np.abs(xin) - 0.5, axis=1)
+    assert np.allclose(phi, ref, atol=2e-5)
+    # face region of +x: x > 1/2, |y|,|z| < 1/2
+    xout = np.c_[rng.uniform(0.55, 2.0, 100), rng.uniform(-0.4, 0.4, (100, 2))]
+    phi, g, _ = box.sdf(prm, xout)
+    assert np.allclose(phi, xout[:, 0] - 0.5, atol=2e-5)
+    assert np.allclose(g, [[1, 0, 0]] * 100, atol=1e-6)
+
+
+def test_piece_lse_bounds_vs_bruteforce_hull_distance(oracle_mod):
+    """0 <= phi_LSE - max_j a_j <= tau log P (textbook LSE bound), and
+    max_j a_j equals the exact hull SDF inside and in face regions and is
+    <= it everywhere (brute force over the hull's triangles)."""
+    O = oracle_mod
+    rng = np.random.default_rng(1)
+    pts = W.ellipsoid_points(rng, 40, [0.6, 0.8, 1.0])
+    obj = one_piece(O, pts)
+    P = len(obj.planes)
+    tau = 0.02
+    prm = O.default_params(1.0, tau_cap=tau, tau_cup=tau)
+    xs = rng.uniform(-1.6, 1.6, size=(60, 3))
+    phi, _, _ = obj.sdf(prm, xs)
+    amax = np.max(xs @ obj.planes[:, :3].T + obj.planes[:, 3], axis=1)
+    assert np.all(phi - amax >= -1e-12)
+    assert np.all(phi - amax <= tau * np.log(P) + 1e-12)
+    for x, a in zip(xs, amax):
+        ex = exact_hull_sdf(pts, x)
+        assert a <= ex + 1e-9
+        if ex <= 0:
+            assert abs(a - ex) < 1e-9  # interior: polytope SDF is exactly max_j a_j
+
+
+def test_union_bounds(oracle_mod):
+    """min_k phi_k - tau_u log K <= phi_union <= min_k phi_k (textbook LSE)."""
+    O = oracle_mod
+    rng = np.random.default_rng(2)
+    w = W.multi_piece_object(rng, 5, [30] * 5)
+    obj = O.from_points(w.offsets, w.points)
+    singles = [one_piece(O, w.piece(k)) for k in range(5)]
+    prm = O.default_params(0.1)
+    xs = rng.uniform(-0.3, 0.3, size=(100, 3))
+    phi, _, _ = obj.sdf(prm, xs)
+    pk = np.stack([s.sdf(prm, xs)[0] for s in singles], 1)
+    m = pk.min(1)
+    assert np.all(phi <= m + 1e-12)
+    assert np.all(phi >= m - prm.tau_cup * np.log(5) - 1e-12)
+
+
+def test_sphere_hull_converges_to_sphere_sdf(oracle_mod):
+    """Hull of 1000 Fibonacci points on a radius-R sphere: with small tau, phi is
+    within [|x| cos(t) - R, |x| - R cos(t)] outside, t the largest facet angle."""
+    O = oracle_mod
+    R = 0.5
+    pts = fibonacci_sphere(1000, R)
+    obj = one_piece(O, pts)
+    prm = O.default_params(1.0, tau_cap=1e-6, tau_cup=1e-6)
+    ct = np.min(-obj.planes[:, 3]) / R  # cos of the largest angular facet radius
+    assert ct > 0.99
+    rng = np.random.default_rng(3)
+    d = rng.standard_normal((50, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    xs = d * rng.uniform(0.6, 2.0, (50, 1))
+    phi, g, _ = obj.sdf(prm, xs)
+    r = np.linalg.norm(xs, axis=1)
+    assert np.all(phi >= r * ct - R - 1e-9)
+    assert np.all(phi <= r - R * ct + 1e-9)
+    assert np.all(np.abs(phi - (r - R)) < R * (1 - ct) * r / R + 1e-6)
+
+
+def test_gradient_and_hessian_match_finite_differences(oracle_mod):
+    O = oracle_mod
+    rng = np.random.default_rng(4)
+    w = W.multi_piece_object(rng, 4, [40] * 4)
+    obj = O.from_points(w.offsets, w.points)
+    prm = O.default_params(0.1)
+    xs = rng.uniform(-0.25, 0.25, size=(20, 3))
+    phi, g, H = obj.sdf(prm, xs)
+    h = 1e-6
+    for a in range(3):
+        e = np.zeros(3); e[a] = h
+        pp, gp, _ = obj.sdf(prm, xs + e)
+        pm, gm, _ = obj.sdf(prm, xs - e)
+        assert np.allclose((pp - pm) / (2 * h), g[:, a], rtol=1e-6, atol=1e-8)
+        assert np.allclose((gp - gm) / (2 * h), H[:, :, a], rtol=1e-4, atol=1e-4)
+    assert np.allclose(H, np.transpose(H, (0, 2, 1)), atol=1e-9)
+
+
+def test_one_lipschitz(oracle_mod):
+    """|phi(x) - phi(y)| <= |x - y| and |grad phi| <= 1 (LSE of unit-normal planes)."""
+    O = oracle_mod
+    rng = np.random.default_rng(5)
+    w = W.multi_piece_object(rng, 6, [25] * 6)
+    obj = O.from_points(w.offsets, w.points)
+    prm = O.default_params(0.1)
+    x = rng.uniform(-0.4, 0.4, (300, 3))
+    y = x + rng.normal(0, 0.05, (300, 3))
+    px, gx, _ = obj.sdf(prm, x)
+    py, _, _ = obj.sdf(prm, y)
+    assert np.all(np.abs(px - py) <= np.linalg.norm(x - y, axis=1) + 1e-12)
+    assert np.all(np.linalg.norm(gx, axis=1) <= 1 + 1e-12)
+
+
+# ------------------------------------------------------------------ O6 E-SDF --
+def test_esdf_sphere_chord_midpoint(oracle_mod):
+    """Sphere SDF, many trace steps, sharp gates: an edge crossing the sphere
+    gives the chord midpoint, i.e. the foot of the perpendicular from the centre."""
+    O = oracle_mod
+    prm = O.default_params(1.0, tau_st=1e-7, tau_clip=1e-7, st_iters=200)
+    rng = np.random.default_rng(6)
+    c, R = np.array([0.1, -0.2, 0.3]), 0.7
+    for _ in range(20):
+        u = rng.standard_normal(3); u /= np.linalg.norm(u)
+        off = rng.standard_normal(3); off -= off @ u * u
+        off *= rng.uniform(0, 0.6) / np.linalg.norm(off)
+        foot = c + off
+        xI, xII = foot - 1.5 * u, foot + 1.3 * u
+        pe, a, b = O.edge_point_sphere(prm, c, R, xI, xII)
+        assert np.allclose(pe, foot, atol=1e-5)
+        assert abs(np.linalg.norm(pe - c) - R - (np.linalg.norm(off) - R)) < 1e-5
+
+
+def test_esdf_no_move_inside_and_single_crossing(oracle_mod):
+    O = oracle_mod
+    prm = O.default_params(1.0, tau_st=1e-7, tau_clip=1e-7, st_iters=200)
+    c, R = np.zeros(3), 1.0
+    # both corners inside: no motion, p^e = midpoint (Fig. e_s caption)
+    xI, xII = np.array([-0.3, 0.1, 0.0]), np.array([0.5, -0.2, 0.1])
+    pe, a, b = O.edge_point_sphere(prm, c, R, xI, xII)
+    assert np.allclose(pe, 0.5 * (xI + xII), atol=1e-6)
+    assert a < 1e-5 and b < 1e-5
+    # single crossing: trace from the outside corner stops at the surface
+    xI, xII = np.array([0.2, 0.1, 0.0]), np.array([2.0, 0.3, -0.4])
+    pe, a, b = O.edge_point_sphere(prm, c, R, xI, xII)
+    # bisection for the crossing on the segment
+    lo, hi = 0.0, 1.0
+    for _ in range(80):
+        mid = 0.5 * (lo + hi)
+        if np.linalg.norm(xI + mid * (xII - xI)) < R:
+            lo = mid
+        else:
+            hi = mid
+    cross = xI + lo * (xII - xI)
+    assert np.allclose(pe, 0.5 * (xI + cross), atol=1e-6)
+    # edge missing the sphere: both traces run to the far end, p^e = midpoint
+    xI, xII = np.array([1.5, -1.0, 0.2]), np.array([1.5, 1.0, 0.2])
+    pe, _, _ = O.edge_point_sphere(prm, c, R, xI, xII)
+    assert np.allclose(pe, 0.5 * (xI + xII), atol=1e-6)
+
+
+def test_softclip_properties(oracle_mod):
+    """s_clip stays strictly inside (a, b), is increasing, and tends to the hard clip."""
+    O = oracle_mod
+    xs = np.linspace(-2, 3, 101)
+    vals = np.array([O.softclip(x, 0.0, 1.0, 0.05) for x in xs])
+    assert np.all(vals[:, 0] >= 0) and np.all(vals[:, 0] <= 1)
+    mid = (xs > -0.5) & (xs < 1.5)  # away from where FP64 rounds to the bounds
+    assert np.all(vals[mid, 0] > 0) and np.all(vals[mid, 0] < 1)
+    assert np.all(vals[:, 1] >= 0) and np.all(vals[mid, 1] > 0) and np.all(np.diff(vals[mid, 0]) > 0)
+    hard = np.clip(xs, 0, 1)
+    sharp = np.array([O.softclip(x, 0.0, 1.0, 1e-6)[0] for x in xs])
+    assert np.allclose(sharp, hard, atol=1e-5)
+
+
+# --------------------------------------------------------------- O7 mollify --
+def test_transition_is_c2_monotone_and_saturates(oracle_mod):
+    O = oracle_mod
+    prm = O.default_params(1.0)
+    dm, eps = prm.d_max, prm.eps_t
+    assert np.allclose(O.transition(prm, dm + 0.01), [0, 0, 0])
+    assert np.allclose(O.transition(prm, dm - eps - 0.01), [1, 0, 0])
+    assert abs(O.transition(prm, dm - eps / 2)[0] - 0.5) < 1e-12
+    phis = np.linspace(dm - eps - 0.005, dm + 0.005, 401)
+    vals = np.array([O.transition(prm, p) for p in phis])
+    assert np.all(np.diff(vals[:, 0]) <= 1e-15)
+    # derivatives vanish at both ends (C2) and match finite differences inside
+    for end in (dm, dm - eps):
+        l, r = O.transition(prm, end - 1e-12), O.transition(prm, end + 1e-12)
+        assert np.all(np.abs(l[1:]) < 1e-4) and np.all(np.abs(r[1:]) < 1e-4)
+    h = 1e-7
+    for p in np.linspace(dm - eps + 1e-3, dm - 1e-3, 7):
+        f0, f1, f2 = O.transition(prm, p)
+        assert abs((O.transition(prm, p + h)[0] - O.transition(prm, p - h)[0]) / (2 * h) - f1) < 1e-5
+        assert abs((O.transition(prm, p + h)[1] - O.transition(prm, p - h)[1]) / (2 * h) - f2) < 1e-2 * max(1, abs(f2))
+
+
+# ------------------------------------------------------ contacts end to end --
+def _c0_objs(O, prm, n=None):
+    w = W.config0()
+    objs = [O.from_workload_object(o) for o in w.objects]
+    for o in objs:
+        o.build_grid(prm)
+    return w, objs
+
+
+def test_box_on_box_face_contact_closed_form(oracle_mod):
+    """Unit box A at the origin, unit box B at (1/4, 1/4, 1 - delta): the deepest
+    contacts tie at depth -delta; with sharp temperatures the groups give
+    d -> -delta, normals +z (B on A) and -z (A on B), and points at the mean of
+    the tied contacts: (-1/8, -1/8, 1/2 - delta) and (3/8, 3/8, 1/2)."""
+    O = oracle_mod
+    b = W.unit_box()
+    A = O.Obj(b.plane_off, b.planes, b.vert_off, b.verts, b.edge_off, b.edges)
+    B = O.Obj(b.plane_off, b.planes, b.vert_off, b.verts, b.edge_off, b.edges)
+    delta = 0.1
+    prm = O.default_params(1.0, tau_cap=1e-5, tau_cup=1e-5, tau_st=1e-5, tau_clip=1e-5, tau_blend=1e-4,
+                           eps_t=0.02, st_iters=3)
+    for o in (A, B):
+        o.build_grid(prm)
+    pose = np.array([1, 0, 0, 0, 0, 0, 0, 1, 0, 0, 0, 0.25, 0.25, 1 - delta])
+    g, c, goff, coff = O.contacts(prm, [A, B], [0], [1], pose[None], want_contacts=True)
+    gA, gB = g[0], g[1]  # A's mesh vs B's SDF, then B's mesh vs A's SDF
+    assert abs(gA[6] + delta) < 1e-4 and abs(gB[6] + delta) < 1e-4
+    assert np.allclose(gA[3:6], [0, 0, -1], atol=1e-6)
+    assert np.allclose(gB[3:6], [0, 0, 1], atol=1e-6)
+    assert np.allclose(gB[0:3], [-1 / 8, -1 / 8, 0.5 - delta], atol=1e-3)
+    assert np.allclose(gA[0:3], [3 / 8, 3 / 8, 0.5], atol=1e-3)
+    # the blended Jacobian moments: q = W p for fully active contacts
+    assert abs(gB[10] - 1) < 1e-6 and np.allclose(gB[7:10], gB[0:3], atol=1e-3)
+    # closed-form gradients: d(d_g)/d t_Bz -> +1 and d(d_g)/d t_Bx -> 0 for both groups
+    cot = np.zeros((2, 12)); cot[1, 6] = 1.0
+    grad = O.grad_hvp(prm, [A, B], [0], [1], pose[None], cot)
+    assert abs(grad[0, 11] - 1) < 1e-3 and abs(grad[0, 9]) < 1e-3 and abs(grad[0, 5] + 1) < 1e-3
+
+
+def test_broad_phase_on_equals_off(oracle_mod):
+    """Filtered contacts get (d_max, 0, 0) exactly as the narrow phase would
+    (f_t vanishes with its derivatives above d_max), so outputs are unchanged."""
+    O = oracle_mod
+    prm = O.default_params(1.0)
+    w, objs = _c0_objs(O, prm)
+    sel = np.r_[0:32, 256:288]
+    g1, c1, _, _ = O.contacts(prm, objs, w.qa[sel], w.qb[sel], w.poses[sel], want_contacts=True)
+    prm0 = O.default_params(1.0, broad_phase=False)
+    g0, c0, _, _ = O.contacts(prm0, objs, w.qa[sel], w.qb[sel], w.poses[sel], want_contacts=True)
+    assert c1[:, 0].mean() < 0.9  # the broad phase does filter
+    assert np.array_equal(g1, g0)
+    prm1 = O.default_params(1.0, edge_bound=1)
+    g2, c2, _, _ = O.contacts(prm1, objs, w.qa[sel], w.qb[sel], w.poses[sel], want_contacts=True)
+    assert np.array_equal(g2, g0)
+    assert c2[:, 0].sum() <= c1[:, 0].sum()
+
+
+def test_filtered_contacts_have_no_false_negatives(oracle_mod):
+    """Dense sampling along every filtered edge and at every filtered vertex
+    shows phi >= d_max (Lipschitz argument of Fig. broadphase1)."""
+    O = oracle_mod
+    prm = O.default_params(1.0)
+    w, objs = _c0_objs(O, prm)
+    A, B = objs[2], objs[3]
+    rng = np.random.default_rng(7)
+    for i in rng.choice(np.arange(256, 512), 6, replace=False):
+        pose = w.poses[i]
+        from scipy.spatial.transform import Rotation
+        RB = Rotation.from_quat(np.r_[pose[8:11], pose[7]]).as_matrix()
+        tB = pose[11:14]
+        # A's mesh (identity pose) in B's frame
+        xa = (A.verts - tB) @ RB
+        for e in A.edges:
+            xI, xII = xa[e[0]], xa[e[1]]
+            L = np.linalg.norm(xII - xI)
+            lb = min(B.lower_bound(xI), B.lower_bound(xII)) - L
+            if lb >= prm.d_max:
+                s = np.linspace(0, 1, 1000)[:, None]
+                phi, _, _ = B.sdf(prm, xI + s * (xII - xI))
+                assert phi.min() >= prm.d_max
+        for v in xa:
+            if B.lower_bound(v) >= prm.d_max:
+                assert B.sdf(prm, v)[0][0] >= prm.d_max
+
+
+def test_voxel_lower_bound_holds_inside_voxels(oracle_mod):
+    O = oracle_mod
+    prm = O.default_params(1.0)
+    w, objs = _c0_objs(O, prm)
+    obj = objs[2]
+    G, org, h, r = obj.grid()
+    rng = np.random.default_rng(8)
+    n = G.shape[0]
+    for _ in range(20):
+        idx = rng.integers(0, n, 3)
+        pts = org + (idx + rng.uniform(0, 1, (1000, 3))) * h
+        phi, _, _ = obj.sdf(prm, pts)
+        assert np.all(phi >= G[tuple(idx)] - r - 1e-12)
+
+
+def test_blend_invariants_and_filtered_group(oracle_mod):
+    O = oracle_mod
+    prm = O.default_params(1.0)
+    w, objs = _c0_objs(O, prm)
+    g, c, goff, coff = O.contacts(prm, objs, w.qa, w.qb, w.poses, want_contacts=True)
+    tb = prm.tau_blend
+    for q in range(0, 512, 37):
+        lg = 0
+        base = coff[q]
+        for side, (mo, so) in enumerate([(w.qa[q], w.qb[q]), (w.qb[q], w.qa[q])]):
+            o = objs[mo]
+            for k in range(o.n_pieces):
+                nv = o.vert_off[k + 1] - o.vert_off[k]
+                ne = o.edge_off[k + 1] - o.edge_off[k]
+                cs = c[base:base + nv + ne]
+                base += nv + ne
+                gg = g[goff[q] + lg]
+                lg += 1
+                wts = cs[:, 3]
+                assert abs(wts.sum() - 1) < 1e-12
+                assert np.allclose(wts, np.exp(-cs[:, 1] / tb - gg[11]), rtol=1e-10)
+                # blended point is the weighted mean of the contact points
+                assert np.allclose(gg[0:3], wts @ cs[:, 4:7], atol=1e-12)
+                assert abs(gg[6] - wts @ cs[:, 1]) < 1e-12
+                if cs[:, 0].sum() == 0:  # every contact filtered
+                    assert gg[6] == prm.d_max and np.all(gg[3:6] == 0) and gg[10] == 0
+                # filtered contacts: (d_max, 0, 0)
+                f = cs[:, 0] == 0
+                assert np.all(cs[f, 1] == prm.d_max) and np.all(cs[f, 7:10] == 0) and np.all(cs[f, 2] == 0)
+
+
+def test_two_contact_group_weights_are_a_sigmoid(oracle_mod):
+    """A mesh piece with two vertices and no edges: w_1 = sigma((d_2 - d_1)/tau_b)."""
+    O = oracle_mod
+    b = W.unit_box()
+    box = O.Obj(b.plane_off, b.planes, b.vert_off, b.verts, b.edge_off, b.edges)
+    two = O.Obj([0, 6], b.planes, [0, 2], np.array([[0.0, 0.0, 0.55], [0.1, 0.0, 0.48]]), [0, 0],
+                np.zeros((0, 2), np.int32))
+    prm = O.default_params(1.0)
+    for o in (box, two):
+        o.build_grid(prm)
+    pose = np.array([1, 0, 0, 0, 0, 0, 0, 1, 0, 0, 0, 0, 0, 0.0])
+    g, c, goff, coff = O.contacts(prm, [two, box], [0], [1], pose[None], want_contacts=True)
+    d1, d2 = c[0, 1], c[1, 1]
+    w1 = 1 / (1 + np.exp(-(d2 - d1) / prm.tau_blend))
+    assert abs(c[0, 3] - w1) < 1e-12
+    assert abs(g[0, 11] - (-prm.tau_blend * 0 + np.logaddexp(-d1 / prm.tau_blend, -d2 / prm.tau_blend))) < 1e-10
+
+
+def test_frame_invariance_and_swap_symmetry(oracle_mod):
+    O = oracle_mod
+    from scipy.spatial.transform import Rotation
+    prm = O.default_params(1.0)
+    w, objs = _c0_objs(O, prm)
+    sel = np.r_[256:272]
+    g, _ = O.contacts(prm, objs, w.qa[sel], w.qb[sel], w.poses[sel])
+    rng = np.random.default_rng(9)
+    Gq = rng.standard_normal(4); Gq /= np.linalg.norm(Gq)
+    RG = Rotation.from_quat(np.r_[Gq[1:], Gq[0]]).as_matrix()
+    tG = rng.uniform(-2, 2, 3)
+    poses2 = w.poses[sel].copy()
+    for i in range(len(sel)):
+        for o in (0, 7):
+            q = poses2[i, o:o + 4]
+            R = Rotation.from_quat(np.r_[q[1:], q[0]])
+            R2 = (Rotation.from_matrix(RG) * R).as_quat()
+            poses2[i, o:o + 4] = np.r_[R2[3], R2[:3]]
+            poses2[i, o + 4:o + 7] = RG @ poses2[i, o + 4:o + 7] + tG
+    g2, _ = O.contacts(prm, objs, w.qa[sel], w.qb[sel], poses2)
+    W_ = g[:, 10:11]
+    assert np.allclose(g2[:, 0:3], g[:, 0:3] @ RG.T + tG, atol=1e-9)
+    assert np.allclose(g2[:, 3:6], g[:, 3:6] @ RG.T, atol=1e-9)
+    assert np.allclose(g2[:, 7:10], g[:, 7:10] @ RG.T + W_ * tG, atol=1e-9)
+    assert np.allclose(g2[:, [6, 10, 11]], g[:, [6, 10, 11]], atol=1e-9)
+    # swap A and B: the two blocks of groups trade places
+    ps = w.poses[sel]
+    sw = np.concatenate([ps[:, 7:14], ps[:, 0:7]], 1)
+    g3, goff3 = O.contacts(prm, objs, w.qb[sel], w.qa[sel], sw)
+    for i in range(len(sel)):
+        na, nb = objs[w.qa[sel][i]].n_pieces, objs[w.qb[sel][i]].n_pieces
+        blk = g[i * (na + nb):(i + 1) * (na + nb)]
+        blk3 = g3[i * (na + nb):(i + 1) * (na + nb)]
+        assert np.allclose(blk3[:nb], blk[na:], atol=1e-12)
+        assert np.allclose(blk3[nb:], blk[:na], atol=1e-12)
+
+
+# ----------------------------------------------------------- O10 derivatives --
+def _deriv_case(O):
+    prm = O.default_params(1.0)
+    w, objs = _c0_objs(O, prm)
+    g, goff = O.contacts(prm, objs, w.qa, w.qb, w.poses)
+    # pick penetrating ellipsoid queries and box queries
+    d = g[:, 6]
+    q_pen = [q for q in range(512) if (d[goff[q]:goff[q + 1]] < prm.d_max - 1e-3).any()]
+    sel = np.array([q for q in q_pen if q >= 256][:3] + [q for q in q_pen if q < 256][:2])
+    return prm, w, objs, sel
+
+
+def test_gradient_matches_central_differences(oracle_mod):
+    O = oracle_mod
+    prm, w, objs, sel = _deriv_case(O)
+    goff, _ = O.layout(objs, w.qa[sel], w.qb[sel])
+    cot = W.cotangents(5, goff[-1])
+    grad = O.grad_hvp(prm, objs, w.qa[sel], w.qb[sel], w.poses[sel], cot)
+    h = 1e-6
+    for i, q in enumerate(sel):
+        A, B = objs[w.qa[q]], objs[w.qb[q]]
+        c = cot[goff[i]:goff[i + 1]]
+        fd = np.zeros(12)
+        for k in range(12):
+            e = np.zeros(12); e[k] = h
+            fd[k] = ((O.groups_at_xi(prm, A, B, w.poses[q], e) * c).sum()
+                     - (O.groups_at_xi(prm, A, B, w.poses[q], -e) * c).sum()) / (2 * h)
+        assert np.linalg.norm(fd - grad[i]) <= 1e-6 * np.linalg.norm(grad[i]) + 1e-9
+
+
+def test_hvp_matches_second_differences_and_is_symmetric(oracle_mod):
+    O = oracle_mod
+    prm, w, objs, sel = _deriv_case(O)
+    sel = sel[:3]
+    goff, _ = O.layout(objs, w.qa[sel], w.qb[sel])
+    cot = W.cotangents(6, goff[-1])
+    v = W.directions(6, len(sel))
+    u = W.directions(7, len(sel))
+    grad, Hv = O.grad_hvp(prm, objs, w.qa[sel], w.qb[sel], w.poses[sel], cot, v)
+    grad2, Hu = O.grad_hvp(prm, objs, w.qa[sel], w.qb[sel], w.poses[sel], cot, u)
+    assert np.allclose(grad, grad2)
+    h = 1e-4
+    for i, q in enumerate(sel):
+        A, B = objs[w.qa[q]], objs[w.qb[q]]
+        c = cot[goff[i]:goff[i + 1]]
+
+        def L(xi):
+            return (O.groups_at_xi(prm, A, B, w.poses[q], xi) * c).sum()
+        fd = np.zeros(12)
+        for k in range(12):
+            e = np.zeros(12); e[k] = h
+            fd[k] = (L(e + h * v[i]) - L(e - h * v[i]) - L(-e + h * v[i]) + L(-e - h * v[i])) / (4 * h * h)
+        assert np.linalg.norm(fd - Hv[i]) <= 2e-4 * np.linalg.norm(Hv[i]) + 1e-6
+        assert abs(u[i] @ Hv[i] - v[i] @ Hu[i]) <= 1e-8 * (np.abs(Hv[i]).sum() + 1)
+
+
+def test_gradient_of_invariant_outputs_is_orthogonal_to_global_twists(oracle_mod):
+    O = oracle_mod
+    prm, w, objs, sel = _deriv_case(O)
+    goff, _ = O.layout(objs, w.qa[sel], w.qb[sel])
+    cot = W.cotangents(8, goff[-1])
+    cot[:, [0, 1, 2, 3, 4, 5, 7, 8, 9]] = 0.0  # only d, W, logZ: frame invariant
+    grad = O.grad_hvp(prm, objs, w.qa[sel], w.qb[sel], w.poses[sel], cot)
+    rng = np.random.default_rng(10)
+    for i, q in enumerate(sel):
+        tA, tB = w.poses[q, 4:7], w.poses[q, 11:14]
+        for _ in range(3):
+            om, t = rng.standard_normal(3), rng.standard_normal(3)
+            xi = np.r_[om, np.cross(om, tA) + t, om, np.cross(om, tB) + t]
+            assert abs(grad[i] @ xi) <= 1e-9 * (np.abs(grad[i]).sum() * np.abs(xi).sum() + 1)
