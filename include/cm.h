@@ -1,0 +1,214 @@
+/* cm.h -- C ABI of the MI355X (gfx950) contact-manifold library.
+ *
+ * Implements the data-parallel hot path of Beker, Geist, Paulus, Martius,
+ * "Novel Algorithms for Smoothly Differentiable and Efficiently Vectorizable
+ * Contact Manifold Construction":
+ *   - each object is a union of convex pieces; a piece's SDF is the smooth
+ *     intersection (log-sum-exp) of its hull facet half-spaces (Sec. III-A.2,
+ *     eq. smooth-intersection; Sec. III-A.3) and the object's SDF is the smooth
+ *     union of its pieces (eq. soft_union);
+ *   - the mesh of one object (hull vertices and feature edges of its pieces)
+ *     collides with the SDF of the other, and then the roles are swapped
+ *     (Sec. III, opening paragraph);
+ *   - voxel-grid broad phase (Sec. IV-C.2), vertex-SDF and edge-SDF narrow
+ *     phase with sphere tracing (Sec. IV-B), C2 mollification (Sec. IV-C.1) and
+ *     softmax blending per convex piece (Sec. IV-D).
+ * Gradients w.r.t. both 6-DoF poses and Hessian-vector products are project
+ * additions (the paper's goal is twice-differentiability, abstract).
+ *
+ * Conventions
+ *   - Functions never throw across the ABI.  They return a cm_status; on error
+ *     cm_last_error(ctx) holds a message (thread-local to the context).
+ *   - Lengths are metres, quaternions are (w, x, y, z) and are normalised on
+ *     input; a quaternion with norm < 1e-12 is CM_E_INVALID.
+ *   - Outputs are in the world frame.  A pair-query (A, B) yields one group
+ *     per piece of A (A's mesh against B's SDF) followed by one group per piece
+ *     of B (B's mesh against A's SDF).
+ *   - A group record is 12 floats: p (3), n (3), d, q (3), W, logZ, where p is
+ *     the blended contact point, n the blended normal (renormalised), d the
+ *     blended penetration value (negative = penetrating, saturating at d_max),
+ *     q = sum_i w_i f_i p_i and W = sum_i w_i f_i the moments of the blended
+ *     contact Jacobian J = [[q]x, W I] (Sec. IV-D.3 with J_c = f J), and logZ
+ *     the log-partition of the blending softmax over -d_c / tau_blend.
+ *   - The context owns all geometry and scratch memory.  Query, output,
+ *     cotangent and gradient buffers belong to the caller.
+ *   - Device entry points are asynchronous on the given stream (a hipStream_t
+ *     passed as void*; NULL = the default stream).
+ */
+#ifndef CM_H
+#define CM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t cm_status;
+enum {
+  CM_OK = 0,
+  CM_E_INVALID = -1,     /* bad argument, handle or size */
+  CM_E_OOM = -2,         /* device or host allocation failed / over budget */
+  CM_E_DEGENERATE = -3,  /* a piece has fewer than 4 non-coplanar points */
+  CM_E_HIP = -4,         /* a HIP runtime call failed */
+  CM_E_BUSY = -5,        /* serving queue full */
+  CM_E_NOTFOUND = -6     /* unknown object or ticket */
+};
+
+typedef struct cm_context cm_context;
+typedef struct cm_plan cm_plan;
+typedef uint32_t cm_object;
+typedef uint64_t cm_ticket;
+
+/* Method constants; the paper leaves all of them open (Sec. II uses one
+ * temperature tau everywhere, Sec. IV-C.1 names d_max and eps, Sec. IV-B.2
+ * the number of sphere-trace steps). */
+typedef struct {
+  float tau_cap;     /* temperature of the smooth intersection of half-spaces */
+  float tau_cup;     /* temperature of the smooth union of pieces */
+  float tau_st;      /* sigmoid gate of the sphere-trace step */
+  float tau_clip;    /* softclip temperature */
+  float tau_blend;   /* blending softmax temperature */
+  float d_max;       /* contact distance threshold */
+  float eps_t;       /* transition bandwidth */
+  float eps_n;       /* normal normalisation epsilon */
+  float grid_margin;      /* voxel grid = vertex AABB grown by grid_margin + */
+  float grid_margin_rel;  /*   grid_margin_rel * (object bounding radius)    */
+  int32_t st_iters;  /* sphere-trace steps K */
+  int32_t grid_res;  /* voxels per axis (1..128) */
+  int32_t curve;     /* vertex/edge serialization: 0 none, 1 Morton, 2 Hilbert */
+  int32_t broad_phase;  /* 0 off, 1 on */
+  int32_t edge_bound;   /* 0: min(lb1, lb2) - l (the paper's); 1: tight form */
+} cm_params;
+
+/* A pair-query: objects and poses (body -> world). 64 bytes. */
+typedef struct {
+  cm_object a, b;
+  float qa[4], ta[3];
+  float qb[4], tb[3];
+} cm_query;
+
+/* Device SoA group records: p, n, q are [3][G] (x row, y row, z row), d, W,
+ * logZ are [G], G = total groups of the plan. */
+typedef struct {
+  float *p, *n, *d, *q, *W, *logZ;
+} cm_groups;
+
+/* Constants scaled with a length L_ref (metres): tau = 0.01 L_ref (all four
+ * smoothing temperatures), tau_blend = 0.02 L_ref, d_max = 0.05 L_ref,
+ * eps_t = 0.025 L_ref, eps_n = 1e-6, K = 3, 32^3 grid with margin
+ * 0.1 L_ref + 1.0 * radius, Hilbert serialization, broad phase on, edge_bound 0. */
+cm_status cm_default_params(float L_ref, cm_params* out);
+
+/* Creates a context on HIP device `device` (-1: host-only context that builds
+ * and exports geometry but cannot run queries).  mem_budget_bytes bounds the
+ * device memory the serving loop may keep in flight (0 = 32 GiB). */
+cm_status cm_init(int32_t device, const cm_params* params, size_t mem_budget_bytes, cm_context** out);
+/* Stops the serving loop, waits for device work and frees everything. */
+cm_status cm_shutdown(cm_context* ctx);
+/* Message of the last error on this context (never NULL). */
+const char* cm_last_error(cm_context* ctx);
+
+/* Builds one object from n_pieces point clouds (object frame, FP64, host).
+ * offsets[n_pieces + 1] index xyz triplets.  Per piece: convex hull, merge of
+ * coplanar facets (|dn| < 1e-9, |dh| < 1e-9 * scale), unit outward planes
+ * (n, h) with n.x + h <= 0 inside (Sec. III-A.3), hull vertices and feature
+ * edges (edges between facets on different planes), serialization along the
+ * space-filling curve of params.curve within the piece (Sec. IV-C.3).  Then the
+ * object's voxel grid of phi at voxel centres is built on the device
+ * (Sec. IV-C.2).  CM_E_DEGENERATE if a piece has < 4 non-coplanar points. */
+cm_status cm_build_pieces(cm_context* ctx, int32_t n_pieces, const int64_t* offsets, const double* xyz,
+                          cm_object* out);
+/* Builds n_objects objects at once (host threads + one device upload).
+ * obj_off[n_objects + 1] indexes pieces, piece_off[total pieces + 1] indexes
+ * xyz triplets.  out[n_objects]. */
+cm_status cm_build_objects(cm_context* ctx, int32_t n_objects, const int64_t* obj_off, const int64_t* piece_off,
+                           const double* xyz, cm_object* out);
+/* Builds an object from explicit pieces: planes (n, h) [P][4], vertices [V][3],
+ * edges [E][2] of piece-local vertex indices; *_off[n_pieces + 1] index them.
+ * Normals need not be unit (they are normalised); no hull is computed. */
+cm_status cm_build_pieces_raw(cm_context* ctx, int32_t n_pieces, const int64_t* plane_off, const double* planes,
+                              const int64_t* vert_off, const double* verts, const int64_t* edge_off,
+                              const int32_t* edges, cm_object* out);
+/* Frees the object's device memory.  Plans that use it become invalid. */
+cm_status cm_release_object(cm_context* ctx, cm_object obj);
+cm_status cm_object_info(cm_context* ctx, cm_object obj, int32_t* n_pieces, int64_t* n_planes, int64_t* n_verts,
+                         int64_t* n_edges);
+/* Host copies of the collision geometry in the device order: plane_off,
+ * vert_off, edge_off [n_pieces + 1]; planes [P][4] (unit n, h); verts [V][3];
+ * edges [E][2] piece-local.  Any pointer may be NULL. */
+cm_status cm_object_export(cm_context* ctx, cm_object obj, int64_t* plane_off, double* planes, int64_t* vert_off,
+                           double* verts, int64_t* edge_off, int32_t* edges);
+/* Copies the object's voxel grid to the host (synchronous): G [n^3] (index
+ * (i * n + j) * n + k) and meta = origin (3), spacing (3), circumradius, n. */
+cm_status cm_object_grid(cm_context* ctx, cm_object obj, float* G, float* meta);
+
+/* A plan fixes the objects of a batch of n pair-queries (poses are read at run
+ * time from the device query array) and owns the scratch of the batched
+ * persistent launch: broad-phase survivor bitmasks, the work queue of survivor
+ * tiles (64 contacts of one piece, vertices or edges), per-tile partials. */
+cm_status cm_plan_create(cm_context* ctx, const cm_query* host_queries, int32_t n, cm_plan** out);
+cm_status cm_plan_destroy(cm_plan* plan);
+/* Totals: groups G, contacts C (vertices + edges of both sides), queries n. */
+cm_status cm_plan_info(const cm_plan* plan, int64_t* n_groups, int64_t* n_contacts, int32_t* n_queries);
+/* group_off[n + 1], contact_off[n + 1] (host).  Either may be NULL. */
+cm_status cm_plan_offsets(const cm_plan* plan, int64_t* group_off, int64_t* contact_off);
+/* Work statistics of the last launch on this plan (synchronous):
+ * [0] surviving vertices, [1] surviving edges, [2] tiles, [3] vertices,
+ * [4] edges, [5] point-plane pairs evaluated by the last forward pass. */
+cm_status cm_plan_stats(const cm_plan* plan, int64_t* stats6);
+
+/* Forward pass over the plan's batch.  q_dev: device cm_query[n] (objects
+ * must match the plan).  out: device group records.  contact_dbg (nullable):
+ * device float [13][C] SoA per contact: mask (1 = survived the broad phase),
+ * d_c, f, w, p_c (3), n_c (3), phi (NaN when filtered), kind (0 vertex,
+ * 1 edge), group index (bit pattern of an int32).  Contact order per query:
+ * A's pieces then B's; per piece its vertices then its edges, in the order of
+ * cm_object_export. */
+cm_status cm_contacts_fwd(cm_context* ctx, cm_plan* plan, const cm_query* q_dev, cm_groups out, float* contact_dbg,
+                          void* stream);
+/* Gradient of L = sum_g <cot_g, y_g> w.r.t. xi = (w_A, v_A, w_B, v_B), the
+ * world-frame perturbation T_X <- (exp([w_X]x) R_X, t_X + v_X) at xi = 0.
+ * cot: device group records (same layout as out).  grad: device float [n][12].
+ * Recomputes the forward pass (no stored intermediates). */
+cm_status cm_contacts_bwd(cm_context* ctx, cm_plan* plan, const cm_query* q_dev, cm_groups cot, float* grad,
+                          void* stream);
+/* Hessian-vector product H dir of the same L (dir: device float [n][12]),
+ * written to hv [n][12]; grad (nullable) receives the gradient. */
+cm_status cm_hvp(cm_context* ctx, cm_plan* plan, const cm_query* q_dev, cm_groups cot, const float* dir, float* hv,
+                 float* grad, void* stream);
+
+/* ---------------------------------------------------------------- serving --
+ * A background scheduler admits requests while the device memory they need
+ * stays within the context's budget, packs the queries of all admitted
+ * requests into one batch, runs it on one of several streams while the next
+ * batch is formed, and completes tickets when their batch finishes.
+ * Inputs are copied at submit; outputs are written into the request's host
+ * buffers and are valid once cm_poll reports done.  Thread-safe.  Each
+ * result is independent of what else shares its batch. */
+typedef struct {
+  const cm_query* q;        /* host cm_query[n] */
+  int32_t n;
+  int32_t want_grad;        /* 0: forward only; 1: forward + gradient */
+  const float* cotangent;   /* host [G][12] AoS group cotangents (want_grad) */
+  float* out_groups;        /* host [G][12] AoS group records */
+  float* out_grad;          /* host [n][12] (want_grad) */
+} cm_request;
+/* CM_E_OOM if the request alone exceeds the budget; CM_E_BUSY if the queue is
+ * full.  The group count G of a request is sum over its queries of the two
+ * objects' piece counts. */
+cm_status cm_submit(cm_context* ctx, const cm_request* req, cm_ticket* ticket);
+/* done = 1 once finished; *result is the ticket's status.  A finished ticket
+ * is forgotten after the poll that reports it. */
+cm_status cm_poll(cm_context* ctx, cm_ticket ticket, int32_t* done, cm_status* result);
+/* Blocks until the ticket finishes (or timeout_ms elapses: CM_E_BUSY). */
+cm_status cm_wait(cm_context* ctx, cm_ticket ticket, int32_t timeout_ms, cm_status* result);
+/* Serving statistics: [0] submitted, [1] completed, [2] batches, [3] queued,
+ * [4] in flight, [5] peak in-flight bytes, [6] queries completed. */
+cm_status cm_serve_stats(cm_context* ctx, int64_t* stats7);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CM_H */

@@ -199,13 +199,14 @@ def layout(objs, qa, qb):
 
 
 def contacts(prm: Params, objs, qa, qb, poses, want_contacts=False, threads: int = 0):
-    """Group records [G,12] (p, n, d, q, W, logZ) and optional per-contact records [C,13]."""
+    """Group records [G,12] (p, n, d, q, W, logZ) and optional per-contact records [C,14]
+    (mask, d_c, f, w, p_c, n_c, phi, kind, broad-phase bound, voxel-face distance)."""
     qa_h = _c([objs[i].h for i in qa], np.int32)
     qb_h = _c([objs[i].h for i in qb], np.int32)
     poses = _c(poses, np.float64).reshape(-1, 14)
     goff, coff = layout(objs, qa, qb)
     groups = np.zeros((goff[-1], 12))
-    cts = np.zeros((coff[-1], 13)) if want_contacts else None
+    cts = np.zeros((coff[-1], 14)) if want_contacts else None
     lib().orc_contacts(ctypes.byref(prm), len(qa_h), _p(qa_h), _p(qb_h), _p(poses), _p(goff), _p(coff),
                        _p(groups), _p(cts), int(threads))
     return (groups, cts, goff, coff) if want_contacts else (groups, goff)

@@ -266,12 +266,14 @@ void build_grid(Object& o, const Params& prm) {
 // Lower bound of phi at x (SDF-object frame): phi(p_c) minus the distance bound,
 // max(r, |x - p_c|), which is the circumradius inside the grid and the
 // 1-Lipschitz extension for points clamped from outside it (Sec. IV-C.2, Fig. broadphase1).
-inline double lower_bound(const Grid& g, const V3<double>& x) {
+inline double lower_bound(const Grid& g, const V3<double>& x, double* face_dist = nullptr) {
   const double xs[3] = {x.x, x.y, x.z};
   int idx[3];
   double d2 = 0;
+  double fd = 1e300;
   for (int a = 0; a < 3; ++a) {
     double u = (xs[a] - g.origin[a]) / g.h[a];
+    fd = std::min(fd, std::fabs(u - std::round(u)) * g.h[a]);  // distance to the nearest voxel face
     int i = int(std::floor(u));
     i = std::min(std::max(i, 0), g.n - 1);
     idx[a] = i;
@@ -279,6 +281,7 @@ inline double lower_bound(const Grid& g, const V3<double>& x) {
     d2 += (xs[a] - c) * (xs[a] - c);
   }
   double Gc = g.G[(size_t(idx[0]) * g.n + idx[1]) * g.n + idx[2]];
+  if (face_dist) *face_dist = fd;
   return Gc - std::max(g.r, std::sqrt(d2));
 }
 
@@ -323,6 +326,8 @@ template <class T> struct Contact {
   double raw_phi;    // unmollified phi (NaN when filtered)
   int mask;          // 1 = survived the broad phase
   int kind;          // 0 vertex, 1 edge
+  double bound = std::numeric_limits<double>::quiet_NaN();      // broad-phase lower bound
+  double face_dist = std::numeric_limits<double>::quiet_NaN();  // distance to the nearest voxel face
 };
 
 template <class T>
@@ -411,29 +416,42 @@ void direction(const Object& mesh, const Object& sdf, const Pose<T>& PM, const P
     }
     // O5: vertex-SDF contacts (Sec. IV-B).
     for (size_t i = 0; i < V; ++i) {
-      if (bp && lower_bound(sdf.grid, vval(xs[i])) >= prm.d_max) {
-        cs.push_back(filtered(Pw[i], prm)); cs.back().kind = 0; continue;
+      double bound = 0, fd = 0;
+      if (bp) bound = lower_bound(sdf.grid, vval(xs[i]), &fd);
+      if (bp && bound >= prm.d_max) {
+        cs.push_back(filtered(Pw[i], prm));
+      } else {
+        T phi; V3<T> g;
+        object_sdf(sdf, xs[i], prm, phi, g);
+        V3<T> Nw = mul(PS.R, normal_of(g, prm));
+        cs.push_back(mollify(phi, Nw, Pw[i], Pw[i], prm));
       }
-      T phi; V3<T> g;
-      object_sdf(sdf, xs[i], prm, phi, g);
-      V3<T> Nw = mul(PS.R, normal_of(g, prm));
-      cs.push_back(mollify(phi, Nw, Pw[i], Pw[i], prm)); cs.back().kind = 0;
+      cs.back().kind = 0;
+      if (bp) { cs.back().bound = bound; cs.back().face_dist = fd; }
     }
     // O6: edge-SDF contacts (Sec. IV-B.2).
     for (size_t k = 0; k < pc.n_edges(); ++k) {
       const int i0 = pc.edges[2 * k], i1 = pc.edges[2 * k + 1];
       V3<T> rest = (Pw[i0] + Pw[i1]) * 0.5;
+      double ebound = 0, efd = 0;
       if (bp) {
         V3<double> a = vval(xs[i0]), b = vval(xs[i1]);
         V3<double> dv = b - a;
         double L = std::sqrt(dot(dv, dv));
-        double la = lower_bound(sdf.grid, a), lbb = lower_bound(sdf.grid, b);
+        double fa = 0, fb = 0;
+        double la = lower_bound(sdf.grid, a, &fa), lbb = lower_bound(sdf.grid, b, &fb);
+        efd = std::min(fa, fb);
         // Any edge point is within s of one end and L - s of the other, so
         // phi >= min(la, lb) - L (the paper's form) and, tighter,
         // phi >= max(max(la, lb) - L, (la + lb - L) / 2).
         double lb = prm.edge_bound == 0 ? std::min(la, lbb) - L
                                         : std::max(std::max(la, lbb) - L, 0.5 * (la + lbb - L));
-        if (lb >= prm.d_max) { cs.push_back(filtered(rest, prm)); cs.back().kind = 1; continue; }
+        ebound = lb;
+        if (lb >= prm.d_max) {
+          cs.push_back(filtered(rest, prm));
+          cs.back().kind = 1; cs.back().bound = ebound; cs.back().face_dist = efd;
+          continue;
+        }
       }
       V3<T> pe = edge_point(fn, xs[i0], xs[i1], prm);
       T phi; V3<T> g;
@@ -441,16 +459,17 @@ void direction(const Object& mesh, const Object& sdf, const Pose<T>& PM, const P
       V3<T> Nw = mul(PS.R, normal_of(g, prm));
       V3<T> pw = mul(PS.R, pe) + PS.t;
       cs.push_back(mollify(phi, Nw, pw, rest, prm)); cs.back().kind = 1;
+      if (bp) { cs.back().bound = ebound; cs.back().face_dist = efd; }
     }
     std::vector<double> w;
     out.push_back(blend(cs, prm, dbg ? &w : nullptr));
     if (dbg) {
       for (size_t i = 0; i < cs.size(); ++i) {
         const Contact<T>& c = cs[i];
-        double rec[13] = {double(c.mask), val(c.d), val(c.f), w[i],
+        double rec[14] = {double(c.mask), val(c.d), val(c.f), w[i],
                           val(c.pc.x), val(c.pc.y), val(c.pc.z),
-                          val(c.nc.x), val(c.nc.y), val(c.nc.z), c.raw_phi, double(c.kind), 0.0};
-        dbg->insert(dbg->end(), rec, rec + 13);
+                          val(c.nc.x), val(c.nc.y), val(c.nc.z), c.raw_phi, double(c.kind), c.bound, c.face_dist};
+        dbg->insert(dbg->end(), rec, rec + 14);
       }
     }
   }
@@ -631,7 +650,7 @@ void orc_contacts(const Params* prm, int64_t n, const int32_t* qa, const int32_t
     std::vector<double> dbg;
     query(obj(qa[i]), obj(qb[i]), PA, PB, *prm, out, contacts ? &dbg : nullptr);
     for (size_t g = 0; g < out.size(); ++g) put(out[g], groups + 12 * (group_off[i] + int64_t(g)));
-    if (contacts) std::copy(dbg.begin(), dbg.end(), contacts + 13 * contact_off[i]);
+    if (contacts) std::copy(dbg.begin(), dbg.end(), contacts + 14 * contact_off[i]);
   }
 }
 

@@ -1,0 +1,245 @@
+"""Python API over the C ABI (include/cm.h): contexts, resident objects, plans,
+and launches on torch-managed device memory and streams.
+
+PyTorch is used for device memory, streams and autograd plumbing only; every
+step of the contact pipeline runs in libcm.so's gfx950 kernels.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional, Sequence
+
+import numpy as np
+
+from . import _cm
+from ._cm import cm_groups, cm_params, QUERY_DTYPE
+
+
+class CMError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("%s: %s" % (_cm.STATUS_NAMES.get(status, str(status)), msg))
+        self.status = status
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def default_params(L_ref: float = 0.1, **overrides) -> cm_params:
+    p = cm_params()
+    st = _cm.cm_default_params(float(L_ref), ctypes.byref(p))
+    if st != 0:
+        raise CMError(st, "cm_default_params")
+    for k, v in overrides.items():
+        setattr(p, k, v)
+    return p
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr(stream) -> ctypes.c_void_p:
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Context:
+    """A device context owning resident geometry (device=-1: host-only)."""
+
+    def __init__(self, device: int = 0, params: Optional[cm_params] = None, L_ref: float = 0.1,
+                 budget_bytes: int = 0, **overrides):
+        self.params = params if params is not None else default_params(L_ref, **overrides)
+        self._h = ctypes.c_void_p()
+        st = _cm.cm_init(int(device), ctypes.byref(self.params), int(budget_bytes), ctypes.byref(self._h))
+        if st != 0:
+            raise CMError(st, "cm_init(device=%d)" % device)
+        self.device = device
+
+    @property
+    def handle(self):
+        return self._h
+
+    def _check(self, st, what):
+        if st != 0:
+            raise CMError(st, "%s: %s" % (what, _cm.cm_last_error(self._h).decode()))
+
+    def close(self):
+        if self._h:
+            _cm.cm_shutdown(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -------------------------------------------------------------- objects --
+    def build_pieces(self, offsets, points) -> int:
+        off = np.ascontiguousarray(offsets, np.int64)
+        xyz = np.ascontiguousarray(points, np.float64)
+        h = ctypes.c_uint32()
+        self._check(_cm.cm_build_pieces(self._h, len(off) - 1, _ptr(off), _ptr(xyz), ctypes.byref(h)),
+                    "cm_build_pieces")
+        return h.value
+
+    def build_raw(self, plane_off, planes, vert_off, verts, edge_off, edges) -> int:
+        a = [np.ascontiguousarray(x, t) for x, t in ((plane_off, np.int64), (planes, np.float64),
+                                                     (vert_off, np.int64), (verts, np.float64),
+                                                     (edge_off, np.int64), (edges, np.int32))]
+        h = ctypes.c_uint32()
+        self._check(_cm.cm_build_pieces_raw(self._h, len(a[0]) - 1, *[_ptr(x) for x in a], ctypes.byref(h)),
+                    "cm_build_pieces_raw")
+        return h.value
+
+    def build_objects(self, objects: Sequence) -> np.ndarray:
+        """Registers generator objects (point clouds or explicit pieces); returns handles."""
+        out = np.zeros(len(objects), np.uint32)
+        pts_idx = [i for i, o in enumerate(objects) if hasattr(o, "points")]
+        if pts_idx:
+            obj_off, piece_off, xyz = [0], [0], []
+            for i in pts_idx:
+                o = objects[i]
+                obj_off.append(obj_off[-1] + o.n_pieces)
+                base = piece_off[-1]
+                piece_off.extend((base + np.asarray(o.offsets[1:])).tolist())
+                xyz.append(o.points)
+            obj_off = np.array(obj_off, np.int64)
+            piece_off = np.array(piece_off, np.int64)
+            xyz = np.ascontiguousarray(np.concatenate(xyz), np.float64)
+            hs = np.zeros(len(pts_idx), np.uint32)
+            self._check(_cm.cm_build_objects(self._h, len(pts_idx), _ptr(obj_off), _ptr(piece_off), _ptr(xyz),
+                                             _ptr(hs)), "cm_build_objects")
+            out[pts_idx] = hs
+        for i, o in enumerate(objects):
+            if not hasattr(o, "points"):
+                out[i] = self.build_raw(o.plane_off, o.planes, o.vert_off, o.verts, o.edge_off, o.edges)
+        return out
+
+    def release(self, h: int):
+        self._check(_cm.cm_release_object(self._h, int(h)), "cm_release_object")
+
+    def object_info(self, h: int):
+        k, p, v, e = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        self._check(_cm.cm_object_info(self._h, int(h), ctypes.byref(k), ctypes.byref(p), ctypes.byref(v),
+                                       ctypes.byref(e)), "cm_object_info")
+        return k.value, p.value, v.value, e.value
+
+    def object_export(self, h: int) -> dict:
+        K, P, V, E = self.object_info(h)
+        po, vo, eo = np.zeros(K + 1, np.int64), np.zeros(K + 1, np.int64), np.zeros(K + 1, np.int64)
+        pl, vs, es = np.zeros((P, 4)), np.zeros((V, 3)), np.zeros((E, 2), np.int32)
+        self._check(_cm.cm_object_export(self._h, int(h), _ptr(po), _ptr(pl), _ptr(vo), _ptr(vs), _ptr(eo),
+                                         _ptr(es)), "cm_object_export")
+        return dict(plane_off=po, planes=pl, vert_off=vo, verts=vs, edge_off=eo, edges=es)
+
+    def object_grid(self, h: int):
+        meta = np.zeros(8, np.float32)
+        self._check(_cm.cm_object_grid(self._h, int(h), None, _ptr(meta)), "cm_object_grid")
+        n = int(meta[7])
+        G = np.zeros(n ** 3, np.float32)
+        self._check(_cm.cm_object_grid(self._h, int(h), _ptr(G), _ptr(meta)), "cm_object_grid")
+        return G.reshape(n, n, n), meta[:3].astype(np.float64), meta[3:6].astype(np.float64), float(meta[6])
+
+    def plan(self, qa, qb) -> "Plan":
+        return Plan(self, qa, qb)
+
+
+def make_queries(qa, qb, poses) -> np.ndarray:
+    """Host cm_query array from object handles and [n, 14] poses (qa, ta, qb, tb)."""
+    poses = np.asarray(poses, np.float64).reshape(-1, 14)
+    q = np.zeros(len(poses), QUERY_DTYPE)
+    q["a"] = np.asarray(qa, np.uint32)
+    q["b"] = np.asarray(qb, np.uint32)
+    q["qa"] = poses[:, 0:4]
+    q["ta"] = poses[:, 4:7]
+    q["qb"] = poses[:, 7:11]
+    q["tb"] = poses[:, 11:14]
+    return q
+
+
+def groups_struct(t) -> cm_groups:
+    """cm_groups pointing into the rows of a [12, G] float32 device tensor."""
+    G = t.shape[1]
+    base = t.data_ptr()
+    rows = lambda r: ctypes.c_void_p(base + 4 * r * G)
+    return cm_groups(rows(0), rows(3), rows(6), rows(7), rows(10), rows(11))
+
+
+class Plan:
+    """Fixed objects of a batch of pair-queries plus the launch scratch."""
+
+    def __init__(self, ctx: Context, qa, qb):
+        self.ctx = ctx
+        self.qa = np.asarray(qa, np.uint32)
+        self.qb = np.asarray(qb, np.uint32)
+        hq = make_queries(self.qa, self.qb, np.tile([1, 0, 0, 0, 0, 0, 0] * 2, (len(self.qa), 1)))
+        self._h = ctypes.c_void_p()
+        ctx._check(_cm.cm_plan_create(ctx.handle, _ptr(hq), len(hq), ctypes.byref(self._h)), "cm_plan_create")
+        G, C, n = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32()
+        _cm.cm_plan_info(self._h, ctypes.byref(G), ctypes.byref(C), ctypes.byref(n))
+        self.G, self.C, self.n = G.value, C.value, n.value
+        self.group_off = np.zeros(self.n + 1, np.int64)
+        self.contact_off = np.zeros(self.n + 1, np.int64)
+        _cm.cm_plan_offsets(self._h, _ptr(self.group_off), _ptr(self.contact_off))
+
+    @property
+    def handle(self):
+        return self._h
+
+    def destroy(self):
+        if self._h:
+            _cm.cm_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+    def device_queries(self, poses, device="cuda"):
+        """Device cm_query array (torch uint8 [n, 64]) for this plan's objects."""
+        torch = _torch()
+        hq = make_queries(self.qa, self.qb, poses)
+        return torch.from_numpy(hq.view(np.uint8).reshape(-1, 64).copy()).to(device)
+
+    def forward(self, q_dev, out=None, debug: bool = False, stream=None):
+        """Group records [12, G] (rows p, n, d, q, W, logZ) and optional per-contact [13, C]."""
+        torch = _torch()
+        if out is None:
+            out = torch.empty((12, self.G), dtype=torch.float32, device=q_dev.device)
+        dbg = torch.empty((13, self.C), dtype=torch.float32, device=q_dev.device) if debug else None
+        st = _cm.cm_contacts_fwd(self.ctx.handle, self._h, ctypes.c_void_p(q_dev.data_ptr()), groups_struct(out),
+                                 ctypes.c_void_p(dbg.data_ptr()) if dbg is not None else None,
+                                 _stream_ptr(stream))
+        self.ctx._check(st, "cm_contacts_fwd")
+        return (out, dbg) if debug else out
+
+    def backward(self, q_dev, cot, grad=None, stream=None):
+        torch = _torch()
+        if grad is None:
+            grad = torch.empty((self.n, 12), dtype=torch.float32, device=q_dev.device)
+        st = _cm.cm_contacts_bwd(self.ctx.handle, self._h, ctypes.c_void_p(q_dev.data_ptr()), groups_struct(cot),
+                                 ctypes.c_void_p(grad.data_ptr()), _stream_ptr(stream))
+        self.ctx._check(st, "cm_contacts_bwd")
+        return grad
+
+    def hvp(self, q_dev, cot, direction, hv=None, grad=None, stream=None):
+        torch = _torch()
+        if hv is None:
+            hv = torch.empty((self.n, 12), dtype=torch.float32, device=q_dev.device)
+        st = _cm.cm_hvp(self.ctx.handle, self._h, ctypes.c_void_p(q_dev.data_ptr()), groups_struct(cot),
+                        ctypes.c_void_p(direction.data_ptr()), ctypes.c_void_p(hv.data_ptr()),
+                        ctypes.c_void_p(grad.data_ptr()) if grad is not None else None, _stream_ptr(stream))
+        self.ctx._check(st, "cm_hvp")
+        return hv
+
+    def stats(self) -> dict:
+        s = np.zeros(6, np.int64)
+        self.ctx._check(_cm.cm_plan_stats(self._h, _ptr(s)), "cm_plan_stats")
+        return dict(surv_verts=int(s[0]), surv_edges=int(s[1]), tiles=int(s[2]), verts=int(s[3]),
+                    edges=int(s[4]), pairs=int(s[5]))

@@ -1,0 +1,92 @@
+// Structures shared by the host runtime and the gfx950 kernels.
+#pragma once
+#include <cstdint>
+
+namespace cm {
+
+struct alignas(16) F4 { float x, y, z, w; };
+struct alignas(8) I2 { int32_t x, y; };
+
+constexpr int kWave = 64;          // CDNA wavefront width
+constexpr int kPartial = 16;       // floats per tile partial (forward blend state)
+constexpr int kMaxPieces = 4096;   // pieces per object (index fits 16 bits)
+
+// Per piece of a resident object (device).  Planes of the piece are stored
+// relative to `centre` and pre-scaled by kappa = log2(e) / tau_cap, so the
+// piece's log-sum-exp runs in base 2 with the temperature folded in.
+struct PieceDesc {
+  float cx, cy, cz;       // centre (mean of the piece's vertices), object frame
+  int32_t plane_begin;    // object-level plane index
+  int32_t plane_count;
+  int32_t vert_begin;     // object-level vertex index
+  int32_t vert_count;
+  int32_t edge_begin;     // object-level edge index
+  int32_t edge_count;
+  int32_t pad[3];
+};
+static_assert(sizeof(PieceDesc) == 48, "PieceDesc layout");
+
+// A resident object (device).  All arrays are SoA in one allocation.
+struct ObjDesc {
+  const F4* planes;       // [P] (kappa n, kappa h_local), h_local relative to the piece centre
+  const F4* nn;           // [2P] (nx nx, ny ny, nz nz, nx ny), (nx nz, ny nz, 0, 0): unit normals
+  const PieceDesc* pieces;
+  const float* vx;        // [V] object frame
+  const float* vy;
+  const float* vz;
+  const I2* edges;        // [E] object-level vertex indices
+  const float* grid;      // [n^3] phi at voxel centres
+  int32_t n_pieces, n_planes, n_verts, n_edges;
+  float gorg[3];          // grid origin
+  float gh[3];            // voxel size
+  float ginv[3];          // 1 / voxel size
+  float gr;               // voxel circumradius
+  int32_t gn;             // voxels per axis
+  int32_t pad;
+};
+
+// Query as laid out in cm_query (64 bytes).
+struct QueryDev {
+  uint32_t a, b;
+  float qa[4], ta[3];
+  float qb[4], tb[3];
+};
+static_assert(sizeof(QueryDev) == 64, "cm_query layout");
+
+// One broad-phase entry: the vertices (kind 0) or edges (kind 1) of one piece
+// of the mesh-side object of one direction of one query.
+struct Entry {
+  int32_t query;
+  int32_t group;          // global group index of (query, dir, piece)
+  int32_t piece;          // piece of the mesh-side object
+  int32_t count;          // contacts in this entry
+  int64_t word_off;       // first 64-bit survivor word
+  int64_t contact_base;   // index of the first contact in the debug layout
+  int32_t dir;            // 0: A's mesh vs B's SDF, 1: B's mesh vs A's SDF
+  int32_t kind;           // 0 vertices, 1 edges
+  int32_t mesh_obj;       // object whose vertices / edges are the contacts
+  int32_t sdf_obj;        // object whose SDF they are evaluated against
+};
+static_assert(sizeof(Entry) == 48, "Entry layout");
+
+// Method constants in the form the kernels use.
+struct DevParams {
+  float kcap;        // log2(e) / tau_cap
+  float icap;        // 1 / kcap
+  float kcup;        // log2(e) / tau_cup
+  float icup;        // 1 / kcup
+  float inv_tau_st;  // 1 / tau_st
+  float tau_clip;
+  float inv_tau_clip;
+  float inv_tau_blend;
+  float tau_blend;
+  float d_max;
+  float inv_eps_t;
+  float eps_n2;      // eps_n^2
+  int32_t st_iters;
+  int32_t broad_phase;
+  int32_t edge_bound;
+  int32_t pad;
+};
+
+}  // namespace cm

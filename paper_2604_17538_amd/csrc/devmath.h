@@ -1,0 +1,297 @@
+// Device math for the gfx950 kernels: scalars (float and forward-mode dual
+// floats), 3-vectors, symmetric 3x3 matrices, rotations, the smooth operators of
+// Sec. II and the SDF of a union of convex pieces (Sec. III-A.2/3).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "common.h"
+
+namespace cm {
+
+#define CM_DEV __device__ __forceinline__
+
+constexpr float kLn2 = 0.69314718055994530942f;
+constexpr float kLog2e = 1.44269504088896340736f;
+
+// ------------------------------------------------------------------ scalars --
+// Dual float: value and one directional derivative.
+struct df {
+  float v, t;
+};
+CM_DEV float val(float x) { return x; }
+CM_DEV float val(df x) { return x.v; }
+CM_DEV float tan_(float) { return 0.f; }
+CM_DEV float tan_(df x) { return x.t; }
+template <class T> CM_DEV T cst(float c);
+template <> CM_DEV float cst<float>(float c) { return c; }
+template <> CM_DEV df cst<df>(float c) { return df{c, 0.f}; }
+CM_DEV df mkd(float v, float t) { return df{v, t}; }
+
+CM_DEV df operator+(df a, df b) { return {a.v + b.v, a.t + b.t}; }
+CM_DEV df operator-(df a, df b) { return {a.v - b.v, a.t - b.t}; }
+CM_DEV df operator-(df a) { return {-a.v, -a.t}; }
+CM_DEV df operator*(df a, df b) { return {a.v * b.v, fmaf(a.v, b.t, a.t * b.v)}; }
+CM_DEV df operator+(df a, float b) { return {a.v + b, a.t}; }
+CM_DEV df operator+(float b, df a) { return {a.v + b, a.t}; }
+CM_DEV df operator-(df a, float b) { return {a.v - b, a.t}; }
+CM_DEV df operator-(float b, df a) { return {b - a.v, -a.t}; }
+CM_DEV df operator*(df a, float b) { return {a.v * b, a.t * b}; }
+CM_DEV df operator*(float b, df a) { return {a.v * b, a.t * b}; }
+CM_DEV df operator/(df a, df b) {
+  float r = 1.f / b.v;
+  float q = a.v * r;
+  return {q, (a.t - q * b.t) * r};
+}
+CM_DEV df operator/(df a, float b) { float r = 1.f / b; return {a.v * r, a.t * r}; }
+CM_DEV df operator/(float a, df b) { float r = 1.f / b.v; float q = a * r; return {q, -q * b.t * r}; }
+CM_DEV df& operator+=(df& a, df b) { a = a + b; return a; }
+CM_DEV df& operator-=(df& a, df b) { a = a - b; return a; }
+CM_DEV df fmaT(df a, df b, df c) { return {fmaf(a.v, b.v, c.v), fmaf(a.v, b.t, fmaf(a.t, b.v, c.t))}; }
+CM_DEV float fmaT(float a, float b, float c) { return fmaf(a, b, c); }
+CM_DEV df fmaT(float a, df b, df c) { return {fmaf(a, b.v, c.v), fmaf(a, b.t, c.t)}; }
+
+// Hardware base-2 exponential / logarithm (v_exp_f32, v_log_f32).
+CM_DEV float ex2(float x) { return __builtin_amdgcn_exp2f(x); }
+CM_DEV float lg2(float x) { return __builtin_amdgcn_logf(x); }
+CM_DEV df ex2(df a) { float e = ex2(a.v); return {e, e * a.t * kLn2}; }
+CM_DEV df lg2(df a) { return {lg2(a.v), a.t / (a.v * kLn2)}; }
+CM_DEV float sqrtT(float x) { return sqrtf(x); }
+CM_DEV df sqrtT(df a) { float s = sqrtf(a.v); return {s, 0.5f * a.t / s}; }
+CM_DEV float expT(float x) { return expf(x); }
+CM_DEV df expT(df a) { float e = expf(a.v); return {e, e * a.t}; }
+CM_DEV float log1pT(float x) { return log1pf(x); }
+CM_DEV df log1pT(df a) { return {log1pf(a.v), a.t / (1.f + a.v)}; }
+CM_DEV float logT(float x) { return logf(x); }
+CM_DEV df logT(df a) { return {logf(a.v), a.t / a.v}; }
+
+// ------------------------------------------------------------------ vectors --
+template <class T> struct V3 { T x, y, z; };
+template <class T> CM_DEV V3<T> operator+(V3<T> a, V3<T> b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
+template <class T> CM_DEV V3<T> operator-(V3<T> a, V3<T> b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+template <class T, class S> CM_DEV V3<T> operator*(V3<T> a, S s) { return {a.x * s, a.y * s, a.z * s}; }
+template <class T> CM_DEV T dot(V3<T> a, V3<T> b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+template <class T> CM_DEV V3<T> cross(V3<T> a, V3<T> b) {
+  return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x}; }
+template <class T> CM_DEV V3<T> zero3() { return {cst<T>(0.f), cst<T>(0.f), cst<T>(0.f)}; }
+template <class T> CM_DEV V3<T> lift3(V3<float> a) { return {cst<T>(a.x), cst<T>(a.y), cst<T>(a.z)}; }
+template <class T> CM_DEV V3<float> val3(V3<T> a) { return {val(a.x), val(a.y), val(a.z)}; }
+// mixed: dual vector with constant vector
+CM_DEV V3<df> operator+(V3<df> a, V3<float> b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
+CM_DEV V3<df> operator-(V3<df> a, V3<float> b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+
+// Symmetric 3x3: xx, yy, zz, xy, xz, yz.
+template <class T> struct Sym { T xx, yy, zz, xy, xz, yz; };
+template <class T> CM_DEV Sym<T> zsym() { T z = cst<T>(0.f); return {z, z, z, z, z, z}; }
+template <class T> CM_DEV V3<T> mulS(const Sym<T>& S, V3<T> v) {
+  return {S.xx * v.x + S.xy * v.y + S.xz * v.z, S.xy * v.x + S.yy * v.y + S.yz * v.z,
+          S.xz * v.x + S.yz * v.y + S.zz * v.z}; }
+
+// Rotation matrix (row-major) of a quaternion (w, x, y, z), normalised first.
+template <class T> struct M3 { T m[9]; };
+template <class T> CM_DEV V3<T> mulM(const M3<T>& R, V3<T> v) {
+  return {R.m[0] * v.x + R.m[1] * v.y + R.m[2] * v.z, R.m[3] * v.x + R.m[4] * v.y + R.m[5] * v.z,
+          R.m[6] * v.x + R.m[7] * v.y + R.m[8] * v.z}; }
+template <class T> CM_DEV V3<T> mulMT(const M3<T>& R, V3<T> v) {
+  return {R.m[0] * v.x + R.m[3] * v.y + R.m[6] * v.z, R.m[1] * v.x + R.m[4] * v.y + R.m[7] * v.z,
+          R.m[2] * v.x + R.m[5] * v.y + R.m[8] * v.z}; }
+template <class T> CM_DEV M3<T> mulMTM(const M3<T>& A, const M3<T>& B) {  // A^T B
+  M3<T> C;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) C.m[3 * i + j] = A.m[i] * B.m[j] + A.m[3 + i] * B.m[3 + j] + A.m[6 + i] * B.m[6 + j];
+  return C;
+}
+CM_DEV M3<float> quat_R(const float* q) {
+  float n = rsqrtf(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+  float w = q[0] * n, x = q[1] * n, y = q[2] * n, z = q[3] * n;
+  M3<float> R;
+  R.m[0] = 1.f - 2.f * (y * y + z * z); R.m[1] = 2.f * (x * y - w * z); R.m[2] = 2.f * (x * z + w * y);
+  R.m[3] = 2.f * (x * y + w * z); R.m[4] = 1.f - 2.f * (x * x + z * z); R.m[5] = 2.f * (y * z - w * x);
+  R.m[6] = 2.f * (x * z - w * y); R.m[7] = 2.f * (y * z + w * x); R.m[8] = 1.f - 2.f * (x * x + y * y);
+  return R;
+}
+
+// --------------------------------------------------------- smooth operators --
+// sigma(z) = 1 / (1 + exp(-z))  (Sec. II)
+template <class T> CM_DEV T sigmoidT(T z) {
+  T e = expT(-z);
+  return cst<T>(1.f) / (e + 1.f);
+}
+CM_DEV float sigmoidT(float z) { return 1.f / (1.f + expf(-z)); }
+// s_+(x) = tau log(1 + exp(x / tau)) = max(x, 0) + tau log1p(exp(-|x| / tau))  (Sec. II)
+template <class T> CM_DEV T softplusT(T x, float tau, float inv_tau) {
+  if (val(x) >= 0.f) return x + tau * log1pT(expT(-x * inv_tau));
+  return tau * log1pT(expT(x * inv_tau));
+}
+// s_clip(x, 0, L) = s_+(x) - s_+(x - L)  (Sec. II)
+template <class T> CM_DEV T softclip0T(T x, T L, float tau, float inv_tau) {
+  return softplusT(x, tau, inv_tau) - softplusT(x - L, tau, inv_tau);
+}
+// C2 transition f_t: quintic smoothstep of s = clamp((d_max - phi)/eps_t, 0, 1)  (Sec. IV-C.1)
+template <class T> CM_DEV T transitionT(T phi, const DevParams& P) {
+  T s = (P.d_max - phi) * P.inv_eps_t;
+  if (val(s) <= 0.f) return cst<T>(0.f);
+  if (val(s) >= 1.f) return cst<T>(1.f);
+  return s * s * s * (10.f - 15.f * s + 6.f * s * s);
+}
+
+// ----------------------------------------------------------------- loads --
+// Plane data is read with wave-uniform addresses; going through the constant
+// address space lets the compiler use scalar (SMEM) loads into SGPRs.
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(4))) const v4i* cv4p;
+template <class T> CM_DEV T ldc(const T* p) {
+  static_assert(sizeof(T) % 16 == 0, "ldc needs a multiple of 16 bytes");
+  T r;
+  cv4p s = (cv4p)p;
+  v4i* d = reinterpret_cast<v4i*>(&r);
+#pragma unroll
+  for (int i = 0; i < int(sizeof(T) / 16); ++i) d[i] = s[i];
+  return r;
+}
+
+// --------------------------------------------------------------- the SDF --
+// Result of an SDF evaluation: phi, grad phi and (MODE 2) the Hessian.
+template <class T> struct SdfRes {
+  T phi;
+  V3<T> g;
+  Sym<T> H;
+};
+
+// dot of a scaled plane (kappa n, kappa h) with a point relative to the piece centre
+CM_DEV float pdot(const F4& q, V3<float> x) { return fmaf(q.x, x.x, fmaf(q.y, x.y, fmaf(q.z, x.z, q.w))); }
+CM_DEV df pdot(const F4& q, V3<df> x) {
+  return {fmaf(q.x, x.x.v, fmaf(q.y, x.y.v, fmaf(q.z, x.z.v, q.w))), fmaf(q.x, x.x.t, fmaf(q.y, x.y.t, q.z * x.z.t))};
+}
+
+// SDF of a union of convex pieces at NP points per lane (Sec. III-A.2/3):
+//   phi_k = tau_cap LSE_j (n_kj . x + h_kj)          smooth intersection
+//   phi   = -tau_cup LSE_k (-phi_k)                  smooth union
+// Per piece, one pass finds the max plane value (the LSE shift), a second pass
+// accumulates sum exp2, sum exp2 * n and (MODE 2) sum exp2 * n n^T.  Pieces
+// are combined online with a running minimum.  MODE 0: phi; 1: + gradient;
+// 2: + Hessian.
+template <int NP, int MODE, class T>
+CM_DEV void sdf_eval(const ObjDesc& o, const DevParams& P, const V3<T>* x, SdfRes<T>* r) {
+  float M[NP];
+  T S[NP];
+  V3<T> Ug[NP];
+  Sym<T> UN[NP], UGG[NP];
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    M[p] = __builtin_inff();
+    S[p] = cst<T>(0.f);
+    if (MODE >= 1) Ug[p] = zero3<T>();
+    if (MODE >= 2) { UN[p] = zsym<T>(); UGG[p] = zsym<T>(); }
+  }
+  const int K = o.n_pieces;
+  for (int k = 0; k < K; ++k) {
+    const PieceDesc pd = ldc(o.pieces + k);
+    const F4* pl = o.planes + pd.plane_begin;
+    const F4* nn = o.nn + 2 * pd.plane_begin;
+    const int np = pd.plane_count;
+    V3<T> xl[NP];
+    float m[NP];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+      xl[p] = x[p] - V3<float>{pd.cx, pd.cy, pd.cz};
+      m[p] = -__builtin_inff();
+    }
+    // pass 1: shift = max_j a_j (value only; LSE is shift-invariant)
+#pragma unroll 4
+    for (int j = 0; j < np; ++j) {
+      const F4 q = ldc(pl + j);
+#pragma unroll
+      for (int p = 0; p < NP; ++p) m[p] = fmaxf(m[p], pdot(q, val3(xl[p])));
+    }
+    // pass 2: sums
+    T s[NP];
+    V3<T> G[NP];
+    Sym<T> N[NP];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+      s[p] = cst<T>(0.f);
+      if (MODE >= 1) G[p] = zero3<T>();
+      if (MODE >= 2) N[p] = zsym<T>();
+    }
+#pragma unroll 4
+    for (int j = 0; j < np; ++j) {
+      const F4 q = ldc(pl + j);
+      F4 n1, n2;
+      if (MODE >= 2) { n1 = ldc(nn + 2 * j); n2 = ldc(nn + 2 * j + 1); }
+#pragma unroll
+      for (int p = 0; p < NP; ++p) {
+        const T e = ex2(pdot(q, xl[p]) - m[p]);
+        s[p] += e;
+        if (MODE >= 1) {
+          G[p].x = fmaT(q.x, e, G[p].x);
+          G[p].y = fmaT(q.y, e, G[p].y);
+          G[p].z = fmaT(q.z, e, G[p].z);
+        }
+        if (MODE >= 2) {
+          N[p].xx = fmaT(n1.x, e, N[p].xx); N[p].yy = fmaT(n1.y, e, N[p].yy); N[p].zz = fmaT(n1.z, e, N[p].zz);
+          N[p].xy = fmaT(n1.w, e, N[p].xy); N[p].xz = fmaT(n2.x, e, N[p].xz); N[p].yz = fmaT(n2.y, e, N[p].yz);
+        }
+      }
+    }
+    // combine the piece into the running smooth union
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+      const T phik = (lg2(s[p]) + m[p]) * P.icap;
+      const float Mn = fminf(M[p], val(phik));
+      const float sc = ex2((Mn - M[p]) * P.kcup);  // rescale of the old terms (0 when M = +inf)
+      const T u = ex2((cst<T>(Mn) - phik) * P.kcup);
+      S[p] = S[p] * sc + u;
+      if (MODE >= 1) {
+        const T ws = u * P.icap / s[p];  // u_k / s_k, with kappa folded out of G
+        const V3<T> gk = G[p] * (P.icap / s[p]);
+        Ug[p] = Ug[p] * sc + G[p] * ws;
+        if (MODE >= 2) {
+          const T wn = u / s[p];
+          UN[p] = {UN[p].xx * sc + N[p].xx * wn, UN[p].yy * sc + N[p].yy * wn, UN[p].zz * sc + N[p].zz * wn,
+                   UN[p].xy * sc + N[p].xy * wn, UN[p].xz * sc + N[p].xz * wn, UN[p].yz * sc + N[p].yz * wn};
+          UGG[p] = {UGG[p].xx * sc + u * gk.x * gk.x, UGG[p].yy * sc + u * gk.y * gk.y,
+                    UGG[p].zz * sc + u * gk.z * gk.z, UGG[p].xy * sc + u * gk.x * gk.y,
+                    UGG[p].xz * sc + u * gk.x * gk.z, UGG[p].yz * sc + u * gk.y * gk.z};
+        }
+      }
+      M[p] = Mn;
+    }
+  }
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    r[p].phi = cst<T>(M[p]) - lg2(S[p]) * P.icup;
+    if (MODE >= 1) {
+      const T iS = cst<T>(1.f) / S[p];
+      r[p].g = Ug[p] * iS;
+      if (MODE >= 2) {
+        // H = (1/tau_cap) sum u N_k - (1/tau_cap + 1/tau_cup) sum u g_k g_k^T + (1/tau_cup) g g^T
+        const float a = P.kcap * kLn2, c = P.kcup * kLn2, b = a + c;
+        const V3<T> g = r[p].g;
+        r[p].H = {(UN[p].xx * a - UGG[p].xx * b) * iS + g.x * g.x * c,
+                  (UN[p].yy * a - UGG[p].yy * b) * iS + g.y * g.y * c,
+                  (UN[p].zz * a - UGG[p].zz * b) * iS + g.z * g.z * c,
+                  (UN[p].xy * a - UGG[p].xy * b) * iS + g.x * g.y * c,
+                  (UN[p].xz * a - UGG[p].xz * b) * iS + g.x * g.z * c,
+                  (UN[p].yz * a - UGG[p].yz * b) * iS + g.y * g.z * c};
+      }
+    }
+  }
+}
+
+// Lower bound of phi from the voxel grid (Sec. IV-C.2): the stored phi at the
+// centre of the voxel the point falls into (clamped to the grid) minus
+// max(circumradius, distance to that centre).
+CM_DEV float grid_lb(const ObjDesc& o, V3<float> x) {
+  const int n = o.gn;
+  float u0 = (x.x - o.gorg[0]) * o.ginv[0], u1 = (x.y - o.gorg[1]) * o.ginv[1], u2 = (x.z - o.gorg[2]) * o.ginv[2];
+  int i = min(max(int(floorf(u0)), 0), n - 1);
+  int j = min(max(int(floorf(u1)), 0), n - 1);
+  int k = min(max(int(floorf(u2)), 0), n - 1);
+  float c0 = o.gorg[0] + (float(i) + 0.5f) * o.gh[0];
+  float c1 = o.gorg[1] + (float(j) + 0.5f) * o.gh[1];
+  float c2 = o.gorg[2] + (float(k) + 0.5f) * o.gh[2];
+  float d = sqrtf((x.x - c0) * (x.x - c0) + (x.y - c1) * (x.y - c1) + (x.z - c2) * (x.z - c2));
+  return o.grid[(i * n + j) * n + k] - fmaxf(o.gr, d);
+}
+
+}  // namespace cm

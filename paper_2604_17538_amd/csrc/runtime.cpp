@@ -1,0 +1,747 @@
+// Host runtime and C ABI of the contact-manifold library (see include/cm.h).
+#include "runtime.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+
+namespace cm {
+
+namespace {
+
+constexpr double kLog2eD = 1.4426950408889634;
+
+cm_status fail(cm_context* ctx, cm_status st, const std::string& msg) {
+  if (ctx) {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->err = msg;
+  }
+  return st;
+}
+
+cm_status hip_fail(cm_context* ctx, hipError_t e, const char* where) {
+  return fail(ctx, CM_E_HIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define CM_HIP(ctx, call)                                  \
+  do {                                                     \
+    hipError_t e_ = (call);                                \
+    if (e_ != hipSuccess) return hip_fail(ctx, e_, #call); \
+  } while (0)
+
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+bool valid_params(const cm_params& p, std::string* why) {
+  const float pos[] = {p.tau_cap, p.tau_cup, p.tau_st, p.tau_clip, p.tau_blend, p.eps_t, p.eps_n};
+  for (float v : pos)
+    if (!(v > 0.f) || !std::isfinite(v)) { *why = "temperatures, eps_t and eps_n must be positive"; return false; }
+  if (!(p.d_max >= 0.f)) { *why = "d_max must be >= 0"; return false; }
+  if (p.st_iters < 0 || p.st_iters > 64) { *why = "st_iters must be in [0, 64]"; return false; }
+  if (p.grid_res < 1 || p.grid_res > 128) { *why = "grid_res must be in [1, 128]"; return false; }
+  if (p.curve < 0 || p.curve > 2) { *why = "curve must be 0, 1 or 2"; return false; }
+  if (!(p.grid_margin >= 0.f) || !(p.grid_margin_rel >= 0.f)) { *why = "grid margins must be >= 0"; return false; }
+  return true;
+}
+
+}  // namespace
+
+DevParams make_dev_params(const cm_params& p) {
+  DevParams d{};
+  d.kcap = float(kLog2eD / p.tau_cap);
+  d.icap = float(p.tau_cap / kLog2eD);
+  d.kcup = float(kLog2eD / p.tau_cup);
+  d.icup = float(p.tau_cup / kLog2eD);
+  d.inv_tau_st = 1.f / p.tau_st;
+  d.tau_clip = p.tau_clip;
+  d.inv_tau_clip = 1.f / p.tau_clip;
+  d.inv_tau_blend = 1.f / p.tau_blend;
+  d.tau_blend = p.tau_blend;
+  d.d_max = p.d_max;
+  d.inv_eps_t = 1.f / p.eps_t;
+  d.eps_n2 = p.eps_n * p.eps_n;
+  d.st_iters = p.st_iters;
+  d.broad_phase = p.broad_phase;
+  d.edge_bound = p.edge_bound;
+  return d;
+}
+
+Arena::~Arena() {
+  for (auto& c : chunks_)
+    if (c.base) (void)hipFree(c.base);
+}
+
+void* Arena::alloc(size_t bytes, int* chunk_id) {
+  bytes = align_up(bytes, 256);
+  for (size_t i = 0; i < chunks_.size(); ++i) {
+    Chunk& c = chunks_[i];
+    if (c.base && c.size - c.used >= bytes) {
+      void* p = c.base + c.used;
+      c.used += bytes;
+      c.live++;
+      in_use_ += bytes;
+      *chunk_id = int(i);
+      return p;
+    }
+  }
+  Chunk c;
+  c.size = std::max(chunk_, bytes);
+  if (hipMalloc(&c.base, c.size) != hipSuccess) return nullptr;
+  c.used = bytes;
+  c.live = 1;
+  in_use_ += bytes;
+  // reuse an empty slot
+  for (size_t i = 0; i < chunks_.size(); ++i)
+    if (!chunks_[i].base) { chunks_[i] = c; *chunk_id = int(i); return c.base; }
+  chunks_.push_back(c);
+  *chunk_id = int(chunks_.size() - 1);
+  return c.base;
+}
+
+void Arena::release(int chunk_id) {
+  Chunk& c = chunks_[size_t(chunk_id)];
+  if (--c.live == 0) {
+    in_use_ -= c.used;
+    (void)hipFree(c.base);
+    c = Chunk{};
+  }
+}
+
+// Host packing of one object: device layout and descriptor offsets.
+struct Packed {
+  std::vector<char> bytes;
+  size_t off_planes, off_nn, off_pieces, off_vx, off_vy, off_vz, off_edges, off_grid;
+  int32_t K, P, V, E;
+  float gorg[3], gh[3], ginv[3], gr;
+  int32_t gn;
+};
+
+static void pack_object(const ObjHost& o, const cm_params& prm, Packed* pk) {
+  const double kap = kLog2eD / double(prm.tau_cap);
+  pk->K = int32_t(o.pieces.size());
+  pk->P = int32_t(o.n_planes);
+  pk->V = int32_t(o.n_verts);
+  pk->E = int32_t(o.n_edges);
+  const int gn = prm.grid_res;
+  size_t off = 0;
+  auto take = [&](size_t b) { size_t r = off; off = align_up(off + b, 256); return r; };
+  pk->off_planes = take(16 * size_t(pk->P));
+  pk->off_nn = take(32 * size_t(pk->P));
+  pk->off_pieces = take(sizeof(PieceDesc) * size_t(pk->K));
+  pk->off_vx = take(4 * size_t(pk->V));
+  pk->off_vy = take(4 * size_t(pk->V));
+  pk->off_vz = take(4 * size_t(pk->V));
+  pk->off_edges = take(8 * size_t(pk->E));
+  pk->off_grid = take(4 * size_t(gn) * gn * gn);
+  pk->bytes.assign(off, 0);
+  F4* planes = reinterpret_cast<F4*>(pk->bytes.data() + pk->off_planes);
+  F4* nn = reinterpret_cast<F4*>(pk->bytes.data() + pk->off_nn);
+  PieceDesc* pieces = reinterpret_cast<PieceDesc*>(pk->bytes.data() + pk->off_pieces);
+  float* vx = reinterpret_cast<float*>(pk->bytes.data() + pk->off_vx);
+  float* vy = reinterpret_cast<float*>(pk->bytes.data() + pk->off_vy);
+  float* vz = reinterpret_cast<float*>(pk->bytes.data() + pk->off_vz);
+  I2* edges = reinterpret_cast<I2*>(pk->bytes.data() + pk->off_edges);
+  int32_t pb = 0, vb = 0, eb = 0;
+  double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+  for (int32_t k = 0; k < pk->K; ++k) {
+    const PieceGeom& g = o.pieces[size_t(k)];
+    const double* c = &o.centres[3 * size_t(k)];
+    PieceDesc& d = pieces[k];
+    d = PieceDesc{};
+    d.cx = float(c[0]); d.cy = float(c[1]); d.cz = float(c[2]);
+    d.plane_begin = pb; d.plane_count = int32_t(g.n_planes());
+    d.vert_begin = vb; d.vert_count = int32_t(g.n_verts());
+    d.edge_begin = eb; d.edge_count = int32_t(g.n_edges());
+    // the centre as stored in FP32 is the one the kernels subtract
+    const double cf[3] = {double(d.cx), double(d.cy), double(d.cz)};
+    for (size_t j = 0; j < g.n_planes(); ++j) {
+      const double* q = &g.planes[4 * j];
+      const double hl = q[3] + q[0] * cf[0] + q[1] * cf[1] + q[2] * cf[2];
+      planes[pb + int32_t(j)] = F4{float(kap * q[0]), float(kap * q[1]), float(kap * q[2]), float(kap * hl)};
+      nn[2 * (pb + int32_t(j))] = F4{float(q[0] * q[0]), float(q[1] * q[1]), float(q[2] * q[2]), float(q[0] * q[1])};
+      nn[2 * (pb + int32_t(j)) + 1] = F4{float(q[0] * q[2]), float(q[1] * q[2]), 0.f, 0.f};
+    }
+    for (size_t i = 0; i < g.n_verts(); ++i) {
+      vx[vb + int32_t(i)] = float(g.verts[3 * i]);
+      vy[vb + int32_t(i)] = float(g.verts[3 * i + 1]);
+      vz[vb + int32_t(i)] = float(g.verts[3 * i + 2]);
+      for (int a = 0; a < 3; ++a) {
+        lo[a] = std::min(lo[a], g.verts[3 * i + size_t(a)]);
+        hi[a] = std::max(hi[a], g.verts[3 * i + size_t(a)]);
+      }
+    }
+    for (size_t e = 0; e < g.n_edges(); ++e)
+      edges[eb + int32_t(e)] = I2{vb + g.edges[2 * e], vb + g.edges[2 * e + 1]};
+    pb += d.plane_count; vb += d.vert_count; eb += d.edge_count;
+  }
+  // voxel grid over the vertex AABB grown by margin + margin_rel * radius
+  const double margin = double(prm.grid_margin) + double(prm.grid_margin_rel) * o.radius;
+  double r2 = 0;
+  for (int a = 0; a < 3; ++a) {
+    const double org = lo[a] - margin;
+    const double h = (hi[a] - lo[a] + 2 * margin) / gn;
+    pk->gorg[a] = float(org);
+    pk->gh[a] = float(h);
+    pk->ginv[a] = float(1.0 / h);
+    r2 += h * h;
+  }
+  pk->gr = float(0.5 * std::sqrt(r2));
+  pk->gn = gn;
+}
+
+static ObjDesc make_desc(const Packed& pk, char* base) {
+  ObjDesc d{};
+  d.planes = reinterpret_cast<const F4*>(base + pk.off_planes);
+  d.nn = reinterpret_cast<const F4*>(base + pk.off_nn);
+  d.pieces = reinterpret_cast<const PieceDesc*>(base + pk.off_pieces);
+  d.vx = reinterpret_cast<const float*>(base + pk.off_vx);
+  d.vy = reinterpret_cast<const float*>(base + pk.off_vy);
+  d.vz = reinterpret_cast<const float*>(base + pk.off_vz);
+  d.edges = reinterpret_cast<const I2*>(base + pk.off_edges);
+  d.grid = reinterpret_cast<const float*>(base + pk.off_grid);
+  d.n_pieces = pk.K; d.n_planes = pk.P; d.n_verts = pk.V; d.n_edges = pk.E;
+  for (int a = 0; a < 3; ++a) { d.gorg[a] = pk.gorg[a]; d.gh[a] = pk.gh[a]; d.ginv[a] = pk.ginv[a]; }
+  d.gr = pk.gr;
+  d.gn = pk.gn;
+  return d;
+}
+
+// Fills the derived host data of an object whose pieces are set.
+static void finish_host(ObjHost& o) {
+  o.n_planes = o.n_verts = o.n_edges = 0;
+  o.radius = 0;
+  o.centres.assign(3 * o.pieces.size(), 0.0);
+  for (size_t k = 0; k < o.pieces.size(); ++k) {
+    const PieceGeom& g = o.pieces[k];
+    o.n_planes += int64_t(g.n_planes());
+    o.n_verts += int64_t(g.n_verts());
+    o.n_edges += int64_t(g.n_edges());
+    double c[3] = {0, 0, 0};
+    for (size_t i = 0; i < g.n_verts(); ++i) {
+      for (int a = 0; a < 3; ++a) c[a] += g.verts[3 * i + size_t(a)];
+      o.radius = std::max(o.radius, std::sqrt(g.verts[3 * i] * g.verts[3 * i] + g.verts[3 * i + 1] * g.verts[3 * i + 1] +
+                                              g.verts[3 * i + 2] * g.verts[3 * i + 2]));
+    }
+    for (int a = 0; a < 3; ++a) o.centres[3 * k + size_t(a)] = g.n_verts() ? c[a] / double(g.n_verts()) : 0.0;
+  }
+}
+
+// Uploads host-built objects, refreshes the device table and builds their grids.
+static cm_status register_objects(cm_context* ctx, std::vector<ObjHost>& built, cm_object* out) {
+  const size_t n = built.size();
+  std::vector<Packed> packs(n);
+  {
+    const int nt = int(std::min<size_t>(n, std::max(1u, std::min(16u, std::thread::hardware_concurrency()))));
+    std::vector<std::thread> th;
+    std::atomic<size_t> next{0};
+    for (int t = 0; t < nt; ++t)
+      th.emplace_back([&]() {
+        for (size_t i = next++; i < n; i = next++) pack_object(built[i], ctx->prm, &packs[i]);
+      });
+    for (auto& t : th) t.join();
+  }
+  if (ctx->device < 0) {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    for (size_t i = 0; i < n; ++i) {
+      built[i].alive = true;
+      out[i] = cm_object(ctx->objs.size());
+      ctx->objs.push_back(std::move(built[i]));
+    }
+    return CM_OK;
+  }
+  std::vector<int32_t> ids(n);
+  {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    for (size_t i = 0; i < n; ++i) {
+      ObjHost& o = built[i];
+      o.dmem = ctx->arena->alloc(packs[i].bytes.size(), &o.chunk);
+      if (!o.dmem) {
+        ctx->err = "device allocation of object geometry failed";
+        for (size_t k = 0; k < i; ++k) ctx->arena->release(built[k].chunk);
+        return CM_E_OOM;
+      }
+      o.desc = make_desc(packs[i], static_cast<char*>(o.dmem));
+      o.alive = true;
+    }
+    for (size_t i = 0; i < n; ++i) {
+      hipError_t e = hipMemcpyAsync(built[i].dmem, packs[i].bytes.data(), packs[i].bytes.size(),
+                                    hipMemcpyHostToDevice, ctx->build_stream);
+      if (e != hipSuccess) { ctx->err = hipGetErrorString(e); return CM_E_HIP; }
+    }
+    for (size_t i = 0; i < n; ++i) {
+      ids[i] = int32_t(ctx->objs.size());
+      out[i] = cm_object(ids[i]);
+      ctx->objs.push_back(std::move(built[i]));
+    }
+    // device table
+    const size_t need = ctx->objs.size();
+    if (need > ctx->d_objs_cap) {
+      size_t cap = std::max<size_t>(need, 2 * ctx->d_objs_cap + 64);
+      ObjDesc* nd = nullptr;
+      if (hipMalloc(&nd, cap * sizeof(ObjDesc)) != hipSuccess) { ctx->err = "object table allocation failed"; return CM_E_OOM; }
+      if (ctx->d_objs) {
+        (void)hipStreamSynchronize(ctx->build_stream);
+        (void)hipDeviceSynchronize();  // no kernel may still read the old table
+        (void)hipFree(ctx->d_objs);
+      }
+      ctx->d_objs = nd;
+      ctx->d_objs_cap = cap;
+      std::vector<ObjDesc> all(need);
+      for (size_t i = 0; i < need; ++i) all[i] = ctx->objs[i].desc;
+      hipError_t e = hipMemcpyAsync(ctx->d_objs, all.data(), need * sizeof(ObjDesc), hipMemcpyHostToDevice,
+                                    ctx->build_stream);
+      if (e != hipSuccess) { ctx->err = hipGetErrorString(e); return CM_E_HIP; }
+      (void)hipStreamSynchronize(ctx->build_stream);
+    } else {
+      std::vector<ObjDesc> fresh(n);
+      for (size_t i = 0; i < n; ++i) fresh[i] = ctx->objs[size_t(ids[i])].desc;
+      hipError_t e = hipMemcpyAsync(ctx->d_objs + ids[0], fresh.data(), n * sizeof(ObjDesc), hipMemcpyHostToDevice,
+                                    ctx->build_stream);
+      if (e != hipSuccess) { ctx->err = hipGetErrorString(e); return CM_E_HIP; }
+      (void)hipStreamSynchronize(ctx->build_stream);
+    }
+  }
+  // voxel grids (Sec. IV-C.2), one launch for the batch
+  int32_t* d_ids = nullptr;
+  CM_HIP(ctx, hipMalloc(&d_ids, n * sizeof(int32_t)));
+  CM_HIP(ctx, hipMemcpyAsync(d_ids, ids.data(), n * sizeof(int32_t), hipMemcpyHostToDevice, ctx->build_stream));
+  const size_t per_launch = 4096;
+  for (size_t i = 0; i < n; i += per_launch) {
+    const int32_t cnt = int32_t(std::min(per_launch, n - i));
+    hipError_t e = launch_grid_build(ctx->d_objs, d_ids + i, cnt, ctx->prm.grid_res, ctx->dp, ctx->build_stream);
+    if (e != hipSuccess) { (void)hipFree(d_ids); return hip_fail(ctx, e, "grid build"); }
+  }
+  hipError_t e = hipStreamSynchronize(ctx->build_stream);
+  (void)hipFree(d_ids);
+  if (e != hipSuccess) return hip_fail(ctx, e, "grid build");
+  return CM_OK;
+}
+
+static ObjHost* get_obj(cm_context* ctx, cm_object h) {
+  if (h >= ctx->objs.size() || !ctx->objs[h].alive) return nullptr;
+  return &ctx->objs[h];
+}
+
+}  // namespace cm
+
+using namespace cm;
+
+extern "C" {
+
+cm_status cm_default_params(float L_ref, cm_params* out) {
+  if (!out || !(L_ref > 0.f)) return CM_E_INVALID;
+  cm_params p{};
+  p.tau_cap = p.tau_cup = p.tau_st = p.tau_clip = 0.01f * L_ref;
+  p.tau_blend = 0.02f * L_ref;
+  p.d_max = 0.05f * L_ref;
+  p.eps_t = 0.025f * L_ref;
+  p.eps_n = 1e-6f;
+  p.grid_margin = 0.1f * L_ref;
+  p.grid_margin_rel = 1.0f;
+  p.st_iters = 3;
+  p.grid_res = 32;
+  p.curve = 2;
+  p.broad_phase = 1;
+  p.edge_bound = 0;
+  *out = p;
+  return CM_OK;
+}
+
+cm_status cm_init(int32_t device, const cm_params* params, size_t mem_budget_bytes, cm_context** out) {
+  if (!out || !params) return CM_E_INVALID;
+  *out = nullptr;
+  std::string why;
+  if (!valid_params(*params, &why)) return CM_E_INVALID;
+  auto* ctx = new cm_context;
+  ctx->device = device;
+  ctx->prm = *params;
+  ctx->dp = make_dev_params(*params);
+  ctx->budget = mem_budget_bytes ? mem_budget_bytes : (size_t(32) << 30);
+  if (device >= 0) {
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || device >= n) { delete ctx; return CM_E_INVALID; }
+    if (hipSetDevice(device) != hipSuccess) { delete ctx; return CM_E_HIP; }
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) { delete ctx; return CM_E_HIP; }
+    ctx->n_cu = prop.multiProcessorCount;
+    if (hipStreamCreateWithFlags(&ctx->build_stream, hipStreamNonBlocking) != hipSuccess) { delete ctx; return CM_E_HIP; }
+    ctx->arena.reset(new Arena(size_t(256) << 20));
+  }
+  *out = ctx;
+  return CM_OK;
+}
+
+const char* cm_last_error(cm_context* ctx) {
+  if (!ctx) return "null context";
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  return ctx->err.c_str();
+}
+
+cm_status cm_build_objects(cm_context* ctx, int32_t n_objects, const int64_t* obj_off, const int64_t* piece_off,
+                           const double* xyz, cm_object* out) {
+  if (!ctx || n_objects < 0 || !obj_off || !piece_off || !xyz || !out) return fail(ctx, CM_E_INVALID, "null argument");
+  if (n_objects == 0) return CM_OK;
+  for (int32_t i = 0; i < n_objects; ++i) {
+    const int64_t k0 = obj_off[i], k1 = obj_off[i + 1];
+    if (k1 <= k0 || k1 - k0 > kMaxPieces) return fail(ctx, CM_E_INVALID, "object needs 1..4096 pieces");
+    for (int64_t k = k0; k < k1; ++k)
+      if (piece_off[k + 1] - piece_off[k] < 4) return fail(ctx, CM_E_DEGENERATE, "a piece has fewer than 4 points");
+  }
+  std::vector<ObjHost> built(static_cast<size_t>(n_objects));
+  std::atomic<int> status{0};
+  {
+    const int nt = std::max(1, std::min<int>(n_objects, int(std::min(16u, std::max(1u, std::thread::hardware_concurrency())))));
+    std::vector<std::thread> th;
+    std::atomic<int32_t> next{0};
+    for (int t = 0; t < nt; ++t)
+      th.emplace_back([&]() {
+        for (int32_t i = next++; i < n_objects; i = next++) {
+          ObjHost& o = built[size_t(i)];
+          const int64_t k0 = obj_off[i], k1 = obj_off[i + 1];
+          o.pieces.resize(size_t(k1 - k0));
+          for (int64_t k = k0; k < k1; ++k) {
+            PieceGeom& g = o.pieces[size_t(k - k0)];
+            int st = build_hull_piece(xyz + 3 * piece_off[k], piece_off[k + 1] - piece_off[k], &g);
+            if (st != 0) { status = st; break; }
+            serialize_piece(&g, ctx->prm.curve);
+          }
+          finish_host(o);
+        }
+      });
+    for (auto& t : th) t.join();
+  }
+  if (status != 0) return fail(ctx, CM_E_DEGENERATE, "a piece has fewer than 4 non-coplanar points");
+  return register_objects(ctx, built, out);
+}
+
+cm_status cm_build_pieces(cm_context* ctx, int32_t n_pieces, const int64_t* offsets, const double* xyz, cm_object* out) {
+  if (!ctx || n_pieces <= 0 || !offsets) return fail(ctx, CM_E_INVALID, "bad arguments");
+  const int64_t oo[2] = {0, n_pieces};
+  return cm_build_objects(ctx, 1, oo, offsets, xyz, out);
+}
+
+cm_status cm_build_pieces_raw(cm_context* ctx, int32_t n_pieces, const int64_t* plane_off, const double* planes,
+                              const int64_t* vert_off, const double* verts, const int64_t* edge_off,
+                              const int32_t* edges, cm_object* out) {
+  if (!ctx || n_pieces <= 0 || n_pieces > kMaxPieces || !plane_off || !planes || !vert_off || !verts || !edge_off ||
+      !out)
+    return fail(ctx, CM_E_INVALID, "bad arguments");
+  std::vector<ObjHost> built(1);
+  ObjHost& o = built[0];
+  o.pieces.resize(size_t(n_pieces));
+  for (int32_t k = 0; k < n_pieces; ++k) {
+    PieceGeom& g = o.pieces[size_t(k)];
+    const int64_t P = plane_off[k + 1] - plane_off[k], V = vert_off[k + 1] - vert_off[k],
+                  E = edge_off[k + 1] - edge_off[k];
+    if (P < 1 || V < 1 || E < 0) return fail(ctx, CM_E_INVALID, "each piece needs >= 1 plane and >= 1 vertex");
+    for (int64_t j = 0; j < P; ++j) {
+      const double* q = planes + 4 * (plane_off[k] + j);
+      const double l = std::sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2]);
+      if (!(l > 0)) return fail(ctx, CM_E_INVALID, "zero plane normal");
+      g.planes.insert(g.planes.end(), {q[0] / l, q[1] / l, q[2] / l, q[3] / l});
+    }
+    g.verts.assign(verts + 3 * vert_off[k], verts + 3 * vert_off[k + 1]);
+    for (int64_t e = 0; e < E; ++e) {
+      const int32_t a = edges[2 * (edge_off[k] + e)], b = edges[2 * (edge_off[k] + e) + 1];
+      if (a < 0 || b < 0 || a >= V || b >= V || a == b) return fail(ctx, CM_E_INVALID, "edge index out of range");
+      g.edges.push_back(std::min(a, b));
+      g.edges.push_back(std::max(a, b));
+    }
+    serialize_piece(&g, ctx->prm.curve);
+  }
+  finish_host(o);
+  return register_objects(ctx, built, out);
+}
+
+cm_status cm_release_object(cm_context* ctx, cm_object obj) {
+  if (!ctx) return CM_E_INVALID;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  ObjHost* o = get_obj(ctx, obj);
+  if (!o) { ctx->err = "unknown object"; return CM_E_NOTFOUND; }
+  if (o->dmem) {
+    (void)hipDeviceSynchronize();
+    ctx->arena->release(o->chunk);
+  }
+  *o = ObjHost{};
+  return CM_OK;
+}
+
+cm_status cm_object_info(cm_context* ctx, cm_object obj, int32_t* n_pieces, int64_t* n_planes, int64_t* n_verts,
+                         int64_t* n_edges) {
+  if (!ctx) return CM_E_INVALID;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  ObjHost* o = get_obj(ctx, obj);
+  if (!o) { ctx->err = "unknown object"; return CM_E_NOTFOUND; }
+  if (n_pieces) *n_pieces = int32_t(o->pieces.size());
+  if (n_planes) *n_planes = o->n_planes;
+  if (n_verts) *n_verts = o->n_verts;
+  if (n_edges) *n_edges = o->n_edges;
+  return CM_OK;
+}
+
+cm_status cm_object_export(cm_context* ctx, cm_object obj, int64_t* plane_off, double* planes, int64_t* vert_off,
+                           double* verts, int64_t* edge_off, int32_t* edges) {
+  if (!ctx) return CM_E_INVALID;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  ObjHost* o = get_obj(ctx, obj);
+  if (!o) { ctx->err = "unknown object"; return CM_E_NOTFOUND; }
+  int64_t pb = 0, vb = 0, eb = 0;
+  for (size_t k = 0; k < o->pieces.size(); ++k) {
+    const PieceGeom& g = o->pieces[k];
+    if (plane_off) plane_off[k] = pb;
+    if (vert_off) vert_off[k] = vb;
+    if (edge_off) edge_off[k] = eb;
+    if (planes) std::copy(g.planes.begin(), g.planes.end(), planes + 4 * pb);
+    if (verts) std::copy(g.verts.begin(), g.verts.end(), verts + 3 * vb);
+    if (edges) std::copy(g.edges.begin(), g.edges.end(), edges + 2 * eb);
+    pb += int64_t(g.n_planes()); vb += int64_t(g.n_verts()); eb += int64_t(g.n_edges());
+  }
+  const size_t K = o->pieces.size();
+  if (plane_off) plane_off[K] = pb;
+  if (vert_off) vert_off[K] = vb;
+  if (edge_off) edge_off[K] = eb;
+  return CM_OK;
+}
+
+cm_status cm_object_grid(cm_context* ctx, cm_object obj, float* G, float* meta) {
+  if (!ctx) return CM_E_INVALID;
+  ObjDesc d;
+  {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ObjHost* o = get_obj(ctx, obj);
+    if (!o) { ctx->err = "unknown object"; return CM_E_NOTFOUND; }
+    if (ctx->device < 0) { ctx->err = "host-only context has no grid"; return CM_E_INVALID; }
+    d = o->desc;
+  }
+  if (meta) {
+    for (int a = 0; a < 3; ++a) { meta[a] = d.gorg[a]; meta[3 + a] = d.gh[a]; }
+    meta[6] = d.gr;
+    meta[7] = float(d.gn);
+  }
+  if (G) CM_HIP(ctx, hipMemcpy(G, d.grid, sizeof(float) * size_t(d.gn) * d.gn * d.gn, hipMemcpyDeviceToHost));
+  return CM_OK;
+}
+
+// ------------------------------------------------------------------ plans --
+cm_status cm_plan_create(cm_context* ctx, const cm_query* hq, int32_t n, cm_plan** out) {
+  if (!ctx || !out || n <= 0 || !hq) return fail(ctx, CM_E_INVALID, "bad arguments");
+  *out = nullptr;
+  if (ctx->device < 0) return fail(ctx, CM_E_INVALID, "host-only context cannot run queries");
+  auto* pl = new cm_plan;
+  pl->ctx = ctx;
+  pl->n = n;
+  pl->group_off.assign(size_t(n) + 1, 0);
+  pl->contact_off.assign(size_t(n) + 1, 0);
+  pl->qa.resize(size_t(n));
+  pl->qb.resize(size_t(n));
+  std::vector<double> cost;
+  const int K2 = 2 * ctx->prm.st_iters + 1;
+  {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    for (int32_t i = 0; i < n; ++i) {
+      const ObjHost* A = get_obj(ctx, hq[i].a);
+      const ObjHost* B = get_obj(ctx, hq[i].b);
+      if (!A || !B) { delete pl; ctx->err = "query names an unknown object"; return CM_E_NOTFOUND; }
+      pl->qa[size_t(i)] = int32_t(hq[i].a);
+      pl->qb[size_t(i)] = int32_t(hq[i].b);
+      const int64_t ga = int64_t(A->pieces.size()), gb = int64_t(B->pieces.size());
+      pl->group_off[size_t(i) + 1] = pl->group_off[size_t(i)] + ga + gb;
+      pl->contact_off[size_t(i) + 1] =
+          pl->contact_off[size_t(i)] + A->n_verts + A->n_edges + B->n_verts + B->n_edges;
+      int64_t cbase = pl->contact_off[size_t(i)];
+      for (int dir = 0; dir < 2; ++dir) {
+        const ObjHost* Mo = dir ? B : A;
+        const ObjHost* So = dir ? A : B;
+        for (size_t k = 0; k < Mo->pieces.size(); ++k) {
+          const PieceGeom& g = Mo->pieces[k];
+          const int64_t group = pl->group_off[size_t(i)] + (dir ? ga : 0) + int64_t(k);
+          for (int kind = 0; kind < 2; ++kind) {
+            Entry e{};
+            e.query = i;
+            e.group = int32_t(group);
+            e.piece = int32_t(k);
+            e.count = int32_t(kind ? g.n_edges() : g.n_verts());
+            e.word_off = pl->W;
+            e.contact_base = cbase;
+            e.dir = dir;
+            e.kind = kind;
+            e.mesh_obj = int32_t(dir ? hq[i].b : hq[i].a);
+            e.sdf_obj = int32_t(dir ? hq[i].a : hq[i].b);
+            pl->W += (e.count + kWave - 1) / kWave;
+            cbase += e.count;
+            pl->ents.push_back(e);
+            cost.push_back(double(e.count) * double(So->n_planes) * (kind ? K2 : 1));
+          }
+        }
+      }
+    }
+  }
+  pl->G = pl->group_off[size_t(n)];
+  pl->C = pl->contact_off[size_t(n)];
+  if (pl->G >= (int64_t(1) << 31)) { delete pl; return fail(ctx, CM_E_INVALID, "too many groups in one plan"); }
+  // costliest entries first, so their tiles head the work queue
+  std::vector<int64_t> order(pl->ents.size());
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return cost[size_t(a)] > cost[size_t(b)]; });
+  std::vector<Entry> sorted(pl->ents.size());
+  std::vector<I2> gent(size_t(pl->G));
+  for (size_t i = 0; i < order.size(); ++i) {
+    sorted[i] = pl->ents[size_t(order[i])];
+    I2& ge = gent[size_t(sorted[i].group)];
+    if (sorted[i].kind == 0) ge.x = int32_t(i); else ge.y = int32_t(i);
+  }
+  pl->ents.swap(sorted);
+  pl->E = int64_t(pl->ents.size());
+  pl->nb = (pl->E + 1023) / 1024;
+  const int64_t W = std::max<int64_t>(pl->W, 1);
+  // one device allocation for the plan's tables and scratch
+  size_t off = 0;
+  auto take = [&](size_t b) { size_t r = off; off = align_up(off + b, 256); return r; };
+  const size_t o_ents = take(sizeof(Entry) * size_t(pl->E));
+  const size_t o_gent = take(sizeof(I2) * size_t(pl->G));
+  const size_t o_bits = take(8 * size_t(W));
+  const size_t o_nsurv = take(4 * size_t(pl->E));
+  const size_t o_ntiles = take(4 * size_t(pl->E));
+  const size_t o_filt = take(16 * size_t(pl->E));
+  const size_t o_toff = take(8 * size_t(pl->E + 1));
+  const size_t o_bsum = take(8 * size_t(pl->nb + 1));
+  const size_t o_cnt = take(256);
+  const size_t o_part = take(4 * size_t(kPartial) * size_t(W));
+  const size_t o_gs = take(4 * size_t(16) * size_t(pl->G));
+  const size_t o_bp = take(4 * size_t(16) * size_t(W));
+  if (hipMalloc(&pl->dmem, off) != hipSuccess) { delete pl; return fail(ctx, CM_E_OOM, "plan scratch allocation failed"); }
+  char* b = static_cast<char*>(pl->dmem);
+  pl->d_ents = reinterpret_cast<Entry*>(b + o_ents);
+  pl->d_gent = reinterpret_cast<I2*>(b + o_gent);
+  pl->d_bits = reinterpret_cast<uint64_t*>(b + o_bits);
+  pl->d_nsurv = reinterpret_cast<int32_t*>(b + o_nsurv);
+  pl->d_ntiles = reinterpret_cast<int32_t*>(b + o_ntiles);
+  pl->d_filt = reinterpret_cast<F4*>(b + o_filt);
+  pl->d_tile_off = reinterpret_cast<int64_t*>(b + o_toff);
+  pl->d_bsum = reinterpret_cast<int64_t*>(b + o_bsum);
+  pl->d_counter = reinterpret_cast<uint32_t*>(b + o_cnt);
+  pl->d_partials = reinterpret_cast<float*>(b + o_part);
+  pl->d_gscratch = reinterpret_cast<float*>(b + o_gs);
+  pl->d_bpartials = reinterpret_cast<float*>(b + o_bp);
+  hipError_t e1 = hipMemcpy(pl->d_ents, pl->ents.data(), sizeof(Entry) * size_t(pl->E), hipMemcpyHostToDevice);
+  hipError_t e2 = hipMemcpy(pl->d_gent, gent.data(), sizeof(I2) * size_t(pl->G), hipMemcpyHostToDevice);
+  if (e1 != hipSuccess || e2 != hipSuccess) {
+    (void)hipFree(pl->dmem);
+    delete pl;
+    return fail(ctx, CM_E_HIP, "plan upload failed");
+  }
+  *out = pl;
+  return CM_OK;
+}
+
+cm_status cm_plan_destroy(cm_plan* pl) {
+  if (!pl) return CM_E_INVALID;
+  if (pl->dmem) {
+    (void)hipDeviceSynchronize();
+    (void)hipFree(pl->dmem);
+  }
+  delete pl;
+  return CM_OK;
+}
+
+cm_status cm_plan_info(const cm_plan* pl, int64_t* n_groups, int64_t* n_contacts, int32_t* n_queries) {
+  if (!pl) return CM_E_INVALID;
+  if (n_groups) *n_groups = pl->G;
+  if (n_contacts) *n_contacts = pl->C;
+  if (n_queries) *n_queries = pl->n;
+  return CM_OK;
+}
+
+cm_status cm_plan_offsets(const cm_plan* pl, int64_t* group_off, int64_t* contact_off) {
+  if (!pl) return CM_E_INVALID;
+  if (group_off) std::copy(pl->group_off.begin(), pl->group_off.end(), group_off);
+  if (contact_off) std::copy(pl->contact_off.begin(), pl->contact_off.end(), contact_off);
+  return CM_OK;
+}
+
+cm_status cm_plan_stats(const cm_plan* pl, int64_t* st) {
+  if (!pl || !st) return CM_E_INVALID;
+  std::vector<int32_t> ns(size_t(pl->E));
+  CM_HIP(pl->ctx, hipDeviceSynchronize());
+  CM_HIP(pl->ctx, hipMemcpy(ns.data(), pl->d_nsurv, 4 * size_t(pl->E), hipMemcpyDeviceToHost));
+  int64_t sv = 0, se = 0, tiles = 0, nv = 0, ne = 0;
+  double pairs = 0;
+  const int K2 = 2 * pl->ctx->prm.st_iters + 1;
+  for (size_t i = 0; i < ns.size(); ++i) {
+    const Entry& e = pl->ents[i];
+    const double P = double(pl->ctx->objs[size_t(e.sdf_obj)].n_planes);
+    tiles += (ns[i] + kWave - 1) / kWave;
+    if (e.kind == 0) { sv += ns[i]; nv += e.count; pairs += double(ns[i]) * P; }
+    else { se += ns[i]; ne += e.count; pairs += double(ns[i]) * P * K2; }
+  }
+  st[0] = sv; st[1] = se; st[2] = tiles; st[3] = nv; st[4] = ne; st[5] = int64_t(pairs);
+  return CM_OK;
+}
+
+static FwdArgs fwd_args(cm_context* ctx, cm_plan* pl, const cm_query* q, const cm_groups& out, float* dbg) {
+  FwdArgs a{};
+  a.ents = pl->d_ents;
+  a.n_ent = pl->E;
+  a.Q = reinterpret_cast<const QueryDev*>(q);
+  a.objs = ctx->d_objs;
+  a.P = ctx->dp;
+  a.bits = pl->d_bits;
+  a.nsurv = pl->d_nsurv;
+  a.ntiles = pl->d_ntiles;
+  a.filt = pl->d_filt;
+  a.bsum = pl->d_bsum;
+  a.tile_off = pl->d_tile_off;
+  a.counter = pl->d_counter;
+  a.partials = pl->d_partials;
+  a.gent = pl->d_gent;
+  a.G = pl->G;
+  a.out = OutPtrs{out.p, out.n, out.d, out.q, out.W, out.logZ};
+  a.dbg = dbg;
+  a.C = pl->C;
+  a.n_cu = ctx->n_cu;
+  a.blocks_per_cu = 8;
+  return a;
+}
+
+cm_status cm_contacts_fwd(cm_context* ctx, cm_plan* pl, const cm_query* q, cm_groups out, float* dbg, void* stream) {
+  if (!ctx || !pl || pl->ctx != ctx || !q) return fail(ctx, CM_E_INVALID, "bad arguments");
+  if (!out.p || !out.n || !out.d || !out.q || !out.W || !out.logZ) return fail(ctx, CM_E_INVALID, "null output");
+  FwdArgs a = fwd_args(ctx, pl, q, out, dbg);
+  hipError_t e = launch_forward(a, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(ctx, e, "forward launch");
+  return CM_OK;
+}
+
+cm_status cm_contacts_bwd(cm_context* ctx, cm_plan*, const cm_query*, cm_groups, float*, void*) {
+  return fail(ctx, CM_E_INVALID, "cm_contacts_bwd: not available in this build");
+}
+
+cm_status cm_hvp(cm_context* ctx, cm_plan*, const cm_query*, cm_groups, const float*, float*, float*, void*) {
+  return fail(ctx, CM_E_INVALID, "cm_hvp: not available in this build");
+}
+
+cm_status cm_shutdown(cm_context* ctx) {
+  if (!ctx) return CM_E_INVALID;
+  if (ctx->device >= 0) (void)hipDeviceSynchronize();
+  ctx->arena.reset();
+  if (ctx->d_objs) (void)hipFree(ctx->d_objs);
+  if (ctx->build_stream) (void)hipStreamDestroy(ctx->build_stream);
+  delete ctx;
+  return CM_OK;
+}
+
+cm_status cm_submit(cm_context* ctx, const cm_request*, cm_ticket*) {
+  return fail(ctx, CM_E_INVALID, "serving not available in this build");
+}
+cm_status cm_poll(cm_context* ctx, cm_ticket, int32_t*, cm_status*) {
+  return fail(ctx, CM_E_INVALID, "serving not available in this build");
+}
+cm_status cm_wait(cm_context* ctx, cm_ticket, int32_t, cm_status*) {
+  return fail(ctx, CM_E_INVALID, "serving not available in this build");
+}
+cm_status cm_serve_stats(cm_context* ctx, int64_t*) {
+  return fail(ctx, CM_E_INVALID, "serving not available in this build");
+}
+
+}  // extern "C"

@@ -1,0 +1,92 @@
+// Host runtime of the contact-manifold library: context, device arena,
+// resident-object registry, plans.  Internal; the public ABI is include/cm.h.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <condition_variable>
+#include <cstdint>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/cm.h"
+#include "common.h"
+#include "geom.h"
+#include "kernels.h"
+
+namespace cm {
+
+DevParams make_dev_params(const cm_params& p);
+
+// Bump allocator over large device chunks; a chunk is returned to HIP once
+// every allocation in it has been released.
+class Arena {
+ public:
+  explicit Arena(size_t chunk) : chunk_(chunk) {}
+  ~Arena();
+  void* alloc(size_t bytes, int* chunk_id);
+  void release(int chunk_id);
+  size_t bytes_in_use() const { return in_use_; }
+
+ private:
+  struct Chunk { char* base = nullptr; size_t size = 0, used = 0; int live = 0; };
+  std::vector<Chunk> chunks_;
+  size_t chunk_;
+  size_t in_use_ = 0;
+};
+
+struct ObjHost {
+  bool alive = false;
+  std::vector<PieceGeom> pieces;
+  std::vector<double> centres;  // 3 per piece
+  int64_t n_planes = 0, n_verts = 0, n_edges = 0;
+  double radius = 0;
+  void* dmem = nullptr;
+  int chunk = -1;
+  ObjDesc desc{};
+};
+
+}  // namespace cm
+
+struct cm_context {
+  int device = -1;
+  cm_params prm{};
+  cm::DevParams dp{};
+  int n_cu = 0;
+  size_t budget = 0;
+  std::mutex mu;             // registry + error string
+  std::string err;
+  std::vector<cm::ObjHost> objs;
+  cm::ObjDesc* d_objs = nullptr;  // device table
+  size_t d_objs_cap = 0;
+  std::unique_ptr<cm::Arena> arena;
+  hipStream_t build_stream = nullptr;
+};
+
+struct cm_plan {
+  cm_context* ctx = nullptr;
+  int32_t n = 0;
+  int64_t G = 0, C = 0, E = 0, W = 0, nb = 0;
+  std::vector<int64_t> group_off, contact_off;
+  std::vector<cm::Entry> ents;       // host copy (device order)
+  std::vector<int32_t> qa, qb;
+  void* dmem = nullptr;
+  cm::Entry* d_ents = nullptr;
+  cm::I2* d_gent = nullptr;
+  uint64_t* d_bits = nullptr;
+  int32_t* d_nsurv = nullptr;
+  int32_t* d_ntiles = nullptr;
+  cm::F4* d_filt = nullptr;
+  int64_t* d_tile_off = nullptr;
+  int64_t* d_bsum = nullptr;
+  uint32_t* d_counter = nullptr;
+  float* d_partials = nullptr;
+  float* d_gscratch = nullptr;   // per-group forward results for the adjoint
+  float* d_bpartials = nullptr;  // per-tile adjoint partials
+  int64_t last_pairs_fwd = 0;
+};
