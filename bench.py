@@ -1,0 +1,258 @@
+#!/usr/bin/env python
+"""Benchmark of the contact-manifold hot path on one MI355X.
+
+A step is one pass of the whole path over the batch: broad phase, vertex-SDF
+and edge-SDF narrow phase, mollification and per-piece blending (forward),
+the adjoint w.r.t. both 6-DoF poses (gradient) and the Hessian-vector product
+along a unit direction, i.e. cm_contacts_fwd + cm_contacts_bwd + cm_hvp on the
+16384-pair workload with log-uniform piece counts [1, 32] and hull sizes
+[8, 512] (synthetic, seeded).  `value` is whole-batch pair-queries per second
+with the inputs resident in device memory.
+
+Beside it the JSON line carries:
+  roofline      the dominant narrow-phase kernel's algorithmic VALU lane-ops
+                per second (HIP events on the launch stream) against the chip's
+                FP32 VALU issue rate (256 CU x 4 SIMD x 16 lanes x 2.4 GHz);
+  cpu_baseline  the FP64 oracle (forward + hyper-dual gradient and HVP) on a
+                bounded sample of the same workload, on the host's cores;
+  plain_launch  the same kernels launched one pair-query at a time;
+  parity        sampled GPU-vs-oracle errors at the benchmark's launch shape.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, HERE)
+
+PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9  # FP32 VALU lane-ops/s (non-packed issue rate)
+K_TRACE = 3
+# Algorithmic VALU lane-ops per (surviving vertex, opposing plane) and per
+# (surviving edge, opposing plane) for each narrow-phase kernel; see DESIGN.
+OPS = {
+    "narrow_fwd": (10, 2 * K_TRACE * 7 + 10),
+    "narrow_tan": (18, 2 * K_TRACE * 12 + 18),
+    "narrow_adj": (16, 2 * K_TRACE * 10 + 16),
+    "narrow_dual_adj": (30, 2 * K_TRACE * 18 + 30),
+}
+
+
+def log(msg):
+    print("[bench %.1fs] %s" % (time.time() - T0, msg), file=sys.stderr, flush=True)
+
+
+T0 = time.time()
+
+
+def build_workload(cfg, pairs):
+    from paper_2604_17538_amd import workloads as W
+    if cfg == "c0":
+        return W.config0()
+    if cfg == "c1":
+        return W.config1(n_envs=pairs or 4096)
+    if cfg == "c2":
+        return W.config2(n_pairs=pairs or 16384)
+    if cfg == "c4":
+        return W.config4(n_envs=pairs or 65536, library=2048)
+    raise ValueError(cfg)
+
+
+def cpu_baseline(w, sample, threads, want_grad=True):
+    """Oracle (FP64, OpenMP over pair-queries) on the first `sample` queries."""
+    import oracle as O
+    prm = O.default_params(w.L_ref)
+    sel = np.arange(min(sample, w.n))
+    objs = [None] * len(w.objects)
+    for i in sel:
+        for j in (w.qa[i], w.qb[i]):
+            if objs[j] is None:
+                objs[j] = O.from_workload_object(w.objects[j])
+                objs[j].build_grid(prm)
+    t = time.time()
+    g, goff = O.contacts(prm, objs, w.qa[sel], w.qb[sel], w.poses[sel], threads=threads)
+    from paper_2604_17538_amd import workloads as W
+    cot = W.cotangents(w.cot_seed or 1, goff[-1])
+    d = W.directions(w.cot_seed or 1, len(sel))
+    grad, hv = O.grad_hvp(prm, objs, w.qa[sel], w.qb[sel], w.poses[sel], cot, d, threads=threads)
+    dt = time.time() - t
+    return dict(sel=sel, groups=g, goff=goff, grad=grad, hv=hv, cot=cot, dir=d, seconds=dt)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", default="c2", choices=["c0", "c1", "c2", "c4"])
+    ap.add_argument("--pairs", type=int, default=None, help="batch size override (default: the config's)")
+    ap.add_argument("--cpu-sample", type=int, default=16)
+    ap.add_argument("--plain-sample", type=int, default=64)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: pair-queries are independent and the path has no "
+              "cross-GPU step; run with --gpus 1 (sharding across GPUs is described in DESIGN.md)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2604_17538_amd import api, workloads as W
+
+    w = build_workload(args.config, args.pairs)
+    log("workload %s: %d pair-queries, %d objects" % (args.config, w.n, len(w.objects)))
+    ctx = api.Context(0, L_ref=w.L_ref)
+    hs = ctx.build_objects(w.objects)
+    torch.cuda.synchronize()
+    log("objects resident")
+    plan = ctx.plan(hs[w.qa], hs[w.qb])
+    qd = plan.device_queries(w.poses)
+    cot = W.cotangents(w.cot_seed or 1, plan.G)
+    direc = W.directions(w.cot_seed or 1, w.n)
+    cot_d = torch.tensor(cot.T.astype(np.float32)).contiguous().cuda()
+    dir_d = torch.tensor(direc.astype(np.float32)).cuda()
+    out = torch.empty((12, plan.G), dtype=torch.float32, device="cuda")
+    grad = torch.empty((w.n, 12), dtype=torch.float32, device="cuda")
+    grad2 = torch.empty_like(grad)
+    hv = torch.empty_like(grad)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        plan.forward(qd, out=out, stream=stream)
+        plan.backward(qd, cot_d, grad=grad, stream=stream)
+        plan.hvp(qd, cot_d, dir_d, hv=hv, grad=grad2, stream=stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    log("warmup done")
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_wall = time.time()
+    e0.record(stream)
+    for _ in range(args.steps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.time() - t_wall
+    ms = e0.elapsed_time(e1) / args.steps
+    log("timed %d steps: %.2f ms/step (wall %.2f s)" % (args.steps, ms, wall))
+
+    # per-pass and per-kernel timing (events on the launch stream), untimed region
+    plan.set_timing(True)
+    split = {}
+    for name, fn in (("fwd", lambda: plan.forward(qd, out=out, stream=stream)),
+                     ("bwd", lambda: plan.backward(qd, cot_d, grad=grad, stream=stream)),
+                     ("hvp", lambda: plan.hvp(qd, cot_d, dir_d, hv=hv, grad=grad2, stream=stream))):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        split[name + "_ms"] = a.elapsed_time(b)
+        split.update({"%s:%s" % (name, k): v for k, v in plan.timing().items() if v >= 0})
+    plan.set_timing(False)
+    st = plan.stats()
+    kern = {k: max(v for kk, v in split.items() if kk.endswith(":" + k)) for k in OPS}
+    dom = max(kern, key=kern.get)
+    ov, oe = OPS[dom]
+    alg_ops = st["vertex_pairs"] * ov + st["edge_pairs"] * oe
+    achieved = alg_ops / (kern[dom] * 1e-3) / 1e9
+    roofline = {"bound": "alu", "kernel": "k_narrow (%s)" % dom, "achieved": round(achieved, 1),
+                "peak": round(PEAK_LANE_OPS / 1e9, 1), "unit": "Gop/s",
+                "frac": round(achieved * 1e9 / PEAK_LANE_OPS, 4), "traffic": None,
+                "kernel_ms": round(kern[dom], 3), "alg_ops_per_launch": int(alg_ops)}
+    log("roofline %s" % roofline)
+
+    # plain per-pair launch: same kernels, one pair-query per launch
+    plain = None
+    if not args.no_plain:
+        ns = min(args.plain_sample, w.n)
+        plans = []
+        for i in range(ns):
+            p1 = ctx.plan(hs[w.qa[i:i + 1]], hs[w.qb[i:i + 1]])
+            q1 = p1.device_queries(w.poses[i:i + 1])
+            g0, g1 = plan.group_off[i], plan.group_off[i + 1]
+            c1 = cot_d[:, g0:g1].contiguous()
+            o1 = torch.empty((12, p1.G), dtype=torch.float32, device="cuda")
+            gr1 = torch.empty((1, 12), dtype=torch.float32, device="cuda")
+            plans.append((p1, q1, c1, dir_d[i:i + 1].contiguous(), o1, gr1, torch.empty_like(gr1),
+                          torch.empty_like(gr1)))
+
+        def plain_pass():
+            for p1, q1, c1, d1, o1, gr1, gr2, hv1 in plans:
+                p1.forward(q1, out=o1, stream=stream)
+                p1.backward(q1, c1, grad=gr1, stream=stream)
+                p1.hvp(q1, c1, d1, hv=hv1, grad=gr2, stream=stream)
+
+        plain_pass()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        plain_pass()
+        b.record(stream)
+        torch.cuda.synchronize()
+        pms = a.elapsed_time(b)
+        batched_sample_rate = None
+        plain = {"sample": ns, "ms": round(pms, 3), "value": round(ns / (pms * 1e-3), 1), "unit": "pair-queries/s",
+                 "note": "first %d pair-queries, fwd+bwd+hvp one query per launch, same kernels" % ns}
+        log("plain launch %s" % plain)
+
+    # parity on sampled outputs against the oracle, plus the CPU baseline timing
+    cpu = None
+    parity = None
+    if not args.no_cpu_baseline:
+        threads = min(os.cpu_count() or 1, 16)
+        res = cpu_baseline(w, args.cpu_sample, threads)
+        ns = len(res["sel"])
+        cpu = {"value": round(ns / res["seconds"], 4), "unit": "pair-queries/s", "cores": threads, "kind": "oracle",
+               "sample": "first %d pair-queries of the workload, FP64 forward + hyper-dual gradient and HVP, "
+                         "OpenMP over queries (%.1f s)" % (ns, res["seconds"])}
+        g_gpu = out.cpu().numpy().T.astype(np.float64)[: plan.group_off[ns]]
+        r = np.array([o.radius() for o in w.objects])
+        Ls = np.repeat(r[w.qa[:ns]] + r[w.qb[:ns]], np.diff(plan.group_off[: ns + 1]))
+        pos = np.abs(g_gpu[:, [0, 1, 2, 6, 7, 8, 9]] - res["groups"][:, [0, 1, 2, 6, 7, 8, 9]]).max(1) / Ls
+        gg = grad.cpu().numpy()[:ns].astype(np.float64)
+        hh = hv.cpu().numpy()[:ns].astype(np.float64)
+        # the oracle used the same cotangents and directions for these queries
+        gerr = np.linalg.norm(gg - res["grad"], axis=1) / np.maximum(np.linalg.norm(res["grad"], axis=1), 1e-30)
+        herr = np.linalg.norm(hh - res["hv"], axis=1) / np.maximum(np.linalg.norm(res["hv"], axis=1), 1e-30)
+        parity = {"queries": ns, "max_pos_err_over_Ls": float(pos.max()), "max_grad_rel_err": float(gerr.max()),
+                  "max_hvp_rel_err": float(herr.max())}
+        log("cpu baseline %s parity %s" % (cpu, parity))
+
+    value = w.n / (ms * 1e-3)
+    line = {
+        "metric": "pair-queries/s fwd+grad at 1e-5 err vs plain launch; p50/p99 request latency",
+        "value": round(value, 1),
+        "unit": "pair-queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "%s: %d pair-queries, forward + gradient (both poses) + HVP per step" % (args.config, w.n),
+                   "pair_queries": w.n, "groups": plan.G, "contacts": plan.C, "step": "cm_contacts_fwd+cm_contacts_bwd+cm_hvp"},
+        "split_ms": {k: round(v, 3) for k, v in split.items()},
+        "work": st,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "plain_launch": plain,
+        "parity": parity,
+    }
+    if plain:
+        line["vs_plain_launch"] = round(value / plain["value"], 2)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

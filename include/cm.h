@@ -156,8 +156,19 @@ cm_status cm_plan_info(const cm_plan* plan, int64_t* n_groups, int64_t* n_contac
 cm_status cm_plan_offsets(const cm_plan* plan, int64_t* group_off, int64_t* contact_off);
 /* Work statistics of the last launch on this plan (synchronous):
  * [0] surviving vertices, [1] surviving edges, [2] tiles, [3] vertices,
- * [4] edges, [5] point-plane pairs evaluated by the last forward pass. */
-cm_status cm_plan_stats(const cm_plan* plan, int64_t* stats6);
+ * [4] edges, [5] point-plane evaluations of a forward pass (vertices once,
+ * edges 2 K + 1 times), [6] surviving-vertex x opposing-plane pairs,
+ * [7] surviving-edge x opposing-plane pairs. */
+cm_status cm_plan_stats(const cm_plan* plan, int64_t* stats8);
+
+/* Kernel timing with HIP events recorded on the launch stream around the
+ * broad phase and each narrow-phase kernel of the plan's launches (off by
+ * default).  cm_plan_timing (synchronous) returns the last durations in ms:
+ * [0] broad phase, [1] forward narrow phase, [2] forward narrow phase with
+ * tangents (HVP), [3] adjoint narrow phase, [4] dual adjoint narrow phase
+ * (HVP); -1 for a kernel not yet launched with timing on. */
+cm_status cm_plan_set_timing(cm_plan* plan, int32_t enable);
+cm_status cm_plan_timing(const cm_plan* plan, float* ms5);
 
 /* Forward pass over the plan's batch.  q_dev: device cm_query[n] (objects
  * must match the plan).  out: device group records.  contact_dbg (nullable):
@@ -171,7 +182,8 @@ cm_status cm_contacts_fwd(cm_context* ctx, cm_plan* plan, const cm_query* q_dev,
 /* Gradient of L = sum_g <cot_g, y_g> w.r.t. xi = (w_A, v_A, w_B, v_B), the
  * world-frame perturbation T_X <- (exp([w_X]x) R_X, t_X + v_X) at xi = 0.
  * cot: device group records (same layout as out).  grad: device float [n][12].
- * Recomputes the forward pass (no stored intermediates). */
+ * Recomputes the forward pass (no stored intermediates).  Requires
+ * st_iters <= 4 (CM_E_INVALID otherwise). */
 cm_status cm_contacts_bwd(cm_context* ctx, cm_plan* plan, const cm_query* q_dev, cm_groups cot, float* grad,
                           void* stream);
 /* Hessian-vector product H dir of the same L (dir: device float [n][12]),

@@ -252,6 +252,9 @@ void build_grid(Object& o, const Params& prm) {
   }
   g.r = 0.5 * std::sqrt(r2);  // circumradius of a voxel
   g.G.assign(size_t(g.n) * g.n * g.n, 0.0);
+#ifdef _OPENMP
+#pragma omp parallel for collapse(2) schedule(dynamic, 4)
+#endif
   for (int i = 0; i < g.n; ++i)
     for (int j = 0; j < g.n; ++j)
       for (int k = 0; k < g.n; ++k) {

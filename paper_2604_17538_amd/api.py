@@ -238,8 +238,18 @@ class Plan:
         self.ctx._check(st, "cm_hvp")
         return hv
 
+    def set_timing(self, enable: bool = True):
+        self.ctx._check(_cm.cm_plan_set_timing(self._h, int(enable)), "cm_plan_set_timing")
+
+    def timing(self) -> dict:
+        """Last kernel durations (ms) measured with HIP events on the launch stream."""
+        ms = np.zeros(5, np.float32)
+        self.ctx._check(_cm.cm_plan_timing(self._h, _ptr(ms)), "cm_plan_timing")
+        return dict(broad=float(ms[0]), narrow_fwd=float(ms[1]), narrow_tan=float(ms[2]),
+                    narrow_adj=float(ms[3]), narrow_dual_adj=float(ms[4]))
+
     def stats(self) -> dict:
-        s = np.zeros(6, np.int64)
+        s = np.zeros(8, np.int64)
         self.ctx._check(_cm.cm_plan_stats(self._h, _ptr(s)), "cm_plan_stats")
         return dict(surv_verts=int(s[0]), surv_edges=int(s[1]), tiles=int(s[2]), verts=int(s[3]),
-                    edges=int(s[4]), pairs=int(s[5]))
+                    edges=int(s[4]), pairs=int(s[5]), vertex_pairs=int(s[6]), edge_pairs=int(s[7]))

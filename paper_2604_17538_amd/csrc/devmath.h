@@ -143,9 +143,11 @@ template <class T> CM_DEV T ldc(const T* p) {
   static_assert(sizeof(T) % 16 == 0, "ldc needs a multiple of 16 bytes");
   T r;
   cv4p s = (cv4p)p;
-  v4i* d = reinterpret_cast<v4i*>(&r);
 #pragma unroll
-  for (int i = 0; i < int(sizeof(T) / 16); ++i) d[i] = s[i];
+  for (int i = 0; i < int(sizeof(T) / 16); ++i) {
+    const v4i w = s[i];
+    __builtin_memcpy(reinterpret_cast<char*>(&r) + 16 * i, &w, 16);
+  }
   return r;
 }
 
@@ -183,12 +185,13 @@ CM_DEV void sdf_eval(const ObjDesc& o, const DevParams& P, const V3<T>* x, SdfRe
     if (MODE >= 1) Ug[p] = zero3<T>();
     if (MODE >= 2) { UN[p] = zsym<T>(); UGG[p] = zsym<T>(); }
   }
-  const int K = o.n_pieces;
+  const int K = min(o.n_pieces, kMaxPieces);
   for (int k = 0; k < K; ++k) {
     const PieceDesc pd = ldc(o.pieces + k);
-    const F4* pl = o.planes + pd.plane_begin;
-    const F4* nn = o.nn + 2 * pd.plane_begin;
-    const int np = pd.plane_count;
+    const int pb = min(max(pd.plane_begin, 0), o.n_planes);
+    const F4* pl = o.planes + pb;
+    const F4* nn = o.nn + 2 * pb;
+    const int np = min(max(pd.plane_count, 0), o.n_planes - pb);  // never past the object's planes
     V3<T> xl[NP];
     float m[NP];
 #pragma unroll

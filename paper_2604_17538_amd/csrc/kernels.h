@@ -14,6 +14,8 @@ struct OutPtrs {
   float *p, *n, *d, *q, *W, *logZ;
 };
 
+constexpr int kStride = 32;  // floats per tile partial / per-group adjoint record
+
 struct FwdArgs {
   const Entry* ents;
   int64_t n_ent;
@@ -35,10 +37,59 @@ struct FwdArgs {
   int64_t C;
   int32_t n_cu;
   int32_t blocks_per_cu;
+  // adjoint / HVP
+  OutPtrs cot;          // cotangent group records
+  float* gscratch;      // [G][kStride] per-piece adjoint seeds
+  float* bpartials;     // [tiles][kStride] per-tile pose gradients
+  const float* dir;     // [n][12] HVP direction (nullable)
+  const int64_t* group_off;  // [n + 1]
+  int32_t n;
+  float* grad;          // [n][12]
+  float* hv;            // [n][12] (nullable)
+  hipEvent_t* ev;       // nullable: start/stop events per timed kernel (kTimed pairs)
+};
+
+// Kernels timed with events when a plan has timing enabled.
+enum { kTBroad = 0, kTNarrowFwd = 1, kTNarrowTan = 2, kTNarrowAdj = 3, kTNarrowDualAdj = 4, kTimed = 5 };
+
+struct NarrowArgs {
+  const Entry* ents;
+  int64_t n_ent;
+  const int64_t* tile_off;
+  const uint64_t* bits;
+  const QueryDev* Q;
+  const ObjDesc* objs;
+  DevParams P;
+  uint32_t* counter;
+  float* partials;        // output partials
+  const float* gscratch;  // per-piece adjoint seeds (adjoint pass)
+  const float* dir;       // HVP direction (dual passes)
+  float* dbg;
+  int64_t C;
+};
+
+struct FinArgs {
+  int64_t G;
+  const I2* gent;
+  const int64_t* tile_off;
+  const F4* filt;
+  const float* partials;
+  const Entry* ents;
+  const QueryDev* Q;
+  DevParams P;
+  OutPtrs out;
+  OutPtrs cot;
+  float* gscratch;
+  const float* dir;
 };
 
 hipError_t launch_grid_build(const ObjDesc* objs, const int32_t* ids, int32_t n_ids, int32_t grid_res,
                              const DevParams& P, hipStream_t s);
+// broad phase + tile scan (shared by every pass)
+void launch_front(const FwdArgs& a, hipStream_t s);
+void launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
 hipError_t launch_forward(const FwdArgs& a, hipStream_t s);
+hipError_t launch_backward(const FwdArgs& a, hipStream_t s);
+hipError_t launch_hvp(const FwdArgs& a, hipStream_t s);
 
 }  // namespace cm

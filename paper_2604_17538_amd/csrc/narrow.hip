@@ -1,0 +1,620 @@
+// Narrow phase, blending and its adjoint on gfx950, written once over a scalar
+// type T (float, or the dual float `df` for forward-mode tangents):
+//   k_narrow<float, false>  forward contacts -> per-tile blend partials
+//   k_narrow<df,    false>  the same with tangents along a pose direction
+//   k_finalize<T, 0/1>      fixed-order per-piece merge -> outputs, or the
+//                           per-piece adjoint seeds of L = sum_g <c_g, y_g>
+//   k_narrow<T, true>       per-contact adjoint -> per-tile pose gradients
+//   k_reduce<T>             fixed-order per-query sum (+ filtered closed forms)
+// The Hessian-vector product is this hand-written adjoint evaluated in dual
+// numbers (forward over reverse).  Forward intermediates are recomputed per
+// tile, not stored.
+#include "devmath.h"
+#include "kernels.h"
+#include "wave.h"
+
+namespace cm {
+
+constexpr int kMaxTraceAdj = 4;  // sphere-trace steps supported by the adjoint
+
+CM_DEV void putT(float* o, float x) { o[0] = x; }
+CM_DEV void putT(float* o, df x) { o[0] = x.v; o[1] = x.t; }
+template <class T> CM_DEV T getT(const float* o);
+template <> CM_DEV float getT<float>(const float* o) { return o[0]; }
+template <> CM_DEV df getT<df>(const float* o) { return df{o[0], o[1]}; }
+template <class T> constexpr int nT() { return int(sizeof(T) / sizeof(float)); }
+
+// Stable dual sigmoid: sigma' = sigma (1 - sigma).
+CM_DEV df sigmoidT(df z) {
+  const float s = sigmoidT(z.v);
+  return {s, s * (1.f - s) * z.t};
+}
+
+template <class T> CM_DEV V3<T> mulMc(const M3<T>& R, V3<float> v) {
+  return {R.m[0] * v.x + R.m[1] * v.y + R.m[2] * v.z, R.m[3] * v.x + R.m[4] * v.y + R.m[5] * v.z,
+          R.m[6] * v.x + R.m[7] * v.y + R.m[8] * v.z};
+}
+template <class T> CM_DEV V3<T> neg3(V3<T> a) { return {-a.x, -a.y, -a.z}; }
+
+// ------------------------------------------------------------------ poses --
+template <class T> struct FrameT {
+  M3<T> RM, RS, Rrel;
+  V3<T> tM, tS, trel;
+};
+// Body pose; with duals, the tangent of the world-frame perturbation
+// (exp([w]x) R, t + v) along d6 = (w, v): R' = [w]x R, t' = v.
+CM_DEV void body_pose(const float* q, const float* t, const float*, M3<float>* R, V3<float>* tt) {
+  *R = quat_R(q);
+  *tt = {t[0], t[1], t[2]};
+}
+CM_DEV void body_pose(const float* q, const float* t, const float* d6, M3<df>* R, V3<df>* tt) {
+  const M3<float> R0 = quat_R(q);
+  for (int j = 0; j < 3; ++j) {
+    const float r0 = R0.m[j], r1 = R0.m[3 + j], r2 = R0.m[6 + j];
+    R->m[j] = {r0, d6[1] * r2 - d6[2] * r1};
+    R->m[3 + j] = {r1, d6[2] * r0 - d6[0] * r2};
+    R->m[6 + j] = {r2, d6[0] * r1 - d6[1] * r0};
+  }
+  *tt = {df{t[0], d6[3]}, df{t[1], d6[4]}, df{t[2], d6[5]}};
+}
+template <class T> CM_DEV FrameT<T> frame_t(const QueryDev& q, int dir, const float* d12) {
+  M3<T> RA, RB;
+  V3<T> tA, tB;
+  body_pose(q.qa, q.ta, d12, &RA, &tA);
+  body_pose(q.qb, q.tb, d12 ? d12 + 6 : nullptr, &RB, &tB);
+  FrameT<T> F;
+  F.RM = dir ? RB : RA;
+  F.RS = dir ? RA : RB;
+  F.tM = dir ? tB : tA;
+  F.tS = dir ? tA : tB;
+  F.Rrel = mulMTM(F.RS, F.RM);
+  F.trel = mulMT(F.RS, F.tM - F.tS);
+  return F;
+}
+
+// ------------------------------------------------------- contact forward --
+template <class T> struct CF {
+  T phi;
+  V3<T> g;      // grad phi at the contact point (SDF frame)
+  Sym<T> H;     // Hessian of phi there (adjoint only)
+  T sg;         // sqrt(|g|^2 + eps_n^2)
+  V3<T> nS;     // normal, SDF frame
+  V3<T> N;      // normal, world
+  V3<T> p;      // contact point, world
+  V3<T> prest;  // point a filtered contact would carry (vertex / edge midpoint)
+  T f, fd;      // transition f_t(phi) and its derivative
+  T d;          // mollified depth
+};
+
+template <class T> CM_DEV void finish_contact(CF<T>& c, const FrameT<T>& F, const DevParams& P) {
+  c.sg = sqrtT(dot(c.g, c.g) + P.eps_n2);
+  c.nS = c.g * (cst<T>(1.f) / c.sg);
+  c.N = mulM(F.RS, c.nS);
+  // C2 transition (Sec. IV-C.1): quintic smoothstep and its derivative
+  const T s = (P.d_max - c.phi) * P.inv_eps_t;
+  if (val(s) <= 0.f) {
+    c.f = cst<T>(0.f); c.fd = cst<T>(0.f);
+  } else if (val(s) >= 1.f) {
+    c.f = cst<T>(1.f); c.fd = cst<T>(0.f);
+  } else {
+    const T s2 = s * s, om = cst<T>(1.f) - s;
+    c.f = s2 * s * (10.f - 15.f * s + 6.f * s2);
+    c.fd = s2 * om * om * (-30.f * P.inv_eps_t);
+  }
+  c.d = c.f * c.phi + (cst<T>(1.f) - c.f) * P.d_max;
+}
+
+// Vertex-SDF contact (Sec. IV-B): the vertex itself is the contact point.
+template <class T, bool ADJ>
+CM_DEV void vertex_fwd(const ObjDesc& M, const ObjDesc& S, const FrameT<T>& F, int vi, const DevParams& P,
+                       CF<T>& c) {
+  const V3<float> v = vert(M, vi);
+  V3<T> x = mulMc(F.Rrel, v) + F.trel;
+  SdfRes<T> r;
+  sdf_eval<1, ADJ ? 2 : 1, T>(S, P, &x, &r);
+  c.phi = r.phi;
+  c.g = r.g;
+  if (ADJ) c.H = r.H;
+  c.p = mulMc(F.RM, v) + F.tM;
+  c.prest = c.p;
+  finish_contact(c, F, P);
+}
+
+// Sphere-trace history kept for the adjoint.
+template <class T> struct Trace {
+  V3<float> v0, v1;
+  V3<T> x0, x1, e, pe;
+  T L, aK, bK, ac, bc;
+  T al[kMaxTraceAdj], be[kMaxTraceAdj], pa[kMaxTraceAdj], pb[kMaxTraceAdj];
+  V3<T> ga[kMaxTraceAdj], gb[kMaxTraceAdj];
+};
+
+// Edge-SDF contact (Sec. IV-B.2, Fig. e_s): trace both corners towards each
+// other with the gated step sigma(phi / tau_s) phi, K steps (both ends share
+// each pass over the planes), softclip the arc lengths to [0, L] and take the
+// midpoint of the two points.
+template <class T, bool ADJ>
+CM_DEV void edge_fwd(const ObjDesc& M, const ObjDesc& S, const FrameT<T>& F, int ei, const DevParams& P, CF<T>& c,
+                     Trace<T>& tr) {
+  const I2 ed = M.edges[ei];
+  tr.v0 = vert(M, ed.x);
+  tr.v1 = vert(M, ed.y);
+  tr.x0 = mulMc(F.Rrel, tr.v0) + F.trel;
+  tr.x1 = mulMc(F.Rrel, tr.v1) + F.trel;
+  const V3<T> dv = tr.x1 - tr.x0;
+  tr.L = sqrtT(dot(dv, dv));
+  tr.e = dv * (cst<T>(1.f) / tr.L);
+  T al = cst<T>(0.f), be = cst<T>(0.f);
+  if (ADJ) {
+#pragma unroll
+    for (int k = 0; k < kMaxTraceAdj; ++k) {
+      if (k < P.st_iters) {
+        V3<T> xs[2] = {tr.x0 + tr.e * al, tr.x1 - tr.e * be};
+        SdfRes<T> r[2];
+        sdf_eval<2, 1, T>(S, P, xs, r);
+        tr.al[k] = al; tr.be[k] = be;
+        tr.pa[k] = r[0].phi; tr.pb[k] = r[1].phi;
+        tr.ga[k] = r[0].g; tr.gb[k] = r[1].g;
+        al = al + sigmoidT(r[0].phi * P.inv_tau_st) * r[0].phi;
+        be = be + sigmoidT(r[1].phi * P.inv_tau_st) * r[1].phi;
+      }
+    }
+  } else {
+    for (int k = 0; k < P.st_iters; ++k) {
+      V3<T> xs[2] = {tr.x0 + tr.e * al, tr.x1 - tr.e * be};
+      SdfRes<T> r[2];
+      sdf_eval<2, 0, T>(S, P, xs, r);
+      al = al + sigmoidT(r[0].phi * P.inv_tau_st) * r[0].phi;
+      be = be + sigmoidT(r[1].phi * P.inv_tau_st) * r[1].phi;
+    }
+  }
+  tr.aK = al;
+  tr.bK = be;
+  tr.ac = softclip0T(al, tr.L, P.tau_clip, P.inv_tau_clip);
+  tr.bc = softclip0T(be, tr.L, P.tau_clip, P.inv_tau_clip);
+  tr.pe = (tr.x0 + tr.e * tr.ac + tr.x1 - tr.e * tr.bc) * 0.5f;
+  SdfRes<T> r;
+  sdf_eval<1, ADJ ? 2 : 1, T>(S, P, &tr.pe, &r);
+  c.phi = r.phi;
+  c.g = r.g;
+  if (ADJ) c.H = r.H;
+  c.p = mulM(F.RS, tr.pe) + F.tS;
+  c.prest = mulMc(F.RM, (tr.v0 + tr.v1) * 0.5f) + F.tM;
+  finish_contact(c, F, P);
+}
+
+// ------------------------------------------------------- contact adjoint --
+// Adjoint seeds of one piece's blend for L = <c, y>: u_bar = (c_d, c_p, m_bar,
+// c_q, c_W) pairs with the contact values (d, p_c, n_c, f p, f); B = <u_bar, y>
+// over the un-normalised blend; c_logZ; logZ.
+template <class T> struct GAdj {
+  T cd;
+  V3<T> cp, mb, cq;
+  T cW, B, clz, logZ;
+};
+template <class T> CM_DEV GAdj<T> load_gadj(const float* o) {
+  constexpr int s = nT<T>();
+  GAdj<T> a;
+  a.cd = getT<T>(o);
+  a.cp = {getT<T>(o + 1 * s), getT<T>(o + 2 * s), getT<T>(o + 3 * s)};
+  a.mb = {getT<T>(o + 4 * s), getT<T>(o + 5 * s), getT<T>(o + 6 * s)};
+  a.cq = {getT<T>(o + 7 * s), getT<T>(o + 8 * s), getT<T>(o + 9 * s)};
+  a.cW = getT<T>(o + 10 * s);
+  a.B = getT<T>(o + 11 * s);
+  a.clz = getT<T>(o + 12 * s);
+  a.logZ = getT<T>(o + 13 * s);
+  return a;
+}
+
+template <class T> struct PoseGrad {
+  V3<T> wM, vM, wS, vS;
+};
+
+// Through the blend softmax (Sec. IV-D.2) and the mollification (Sec. IV-C.1):
+// adjoints of phi, of the world normal N, of the world point p and of p_rest.
+template <class T>
+CM_DEV void blend_moll_adj(const CF<T>& c, const GAdj<T>& a, const DevParams& P, T& phib, V3<T>& Nb, V3<T>& pb,
+                           V3<T>& prb) {
+  const T omf = cst<T>(1.f) - c.f;
+  const V3<T> nc = c.N * c.f, pc = c.p * c.f + c.prest * omf, fp = c.p * c.f;
+  const T w = expT(c.d * (-P.inv_tau_blend) - a.logZ);
+  const T uu = a.cd * c.d + dot(a.cp, pc) + dot(a.mb, nc) + dot(a.cq, fp) + a.cW * c.f;
+  const T lb = w * (uu - a.B + a.clz);            // d L / d l_i
+  const T db = w * a.cd - lb * P.inv_tau_blend;    // d L / d d_c
+  const V3<T> pcb = a.cp * w, ncb = a.mb * w, fpb = a.cq * w;
+  const T fb = w * a.cW + db * (c.phi - P.d_max) + dot(ncb, c.N) + dot(pcb, c.p - c.prest) + dot(fpb, c.p);
+  phib = db * c.f + fb * c.fd;
+  Nb = ncb * c.f;
+  pb = (pcb + fpb) * c.f;
+  prb = pcb * omf;
+}
+
+// Through n_S = g / sqrt(|g|^2 + eps^2), N = R_S n_S and phi: adjoint of the
+// contact point in the SDF frame, x_bar = phi_bar grad phi + H g_bar.
+template <class T>
+CM_DEV V3<T> point_adj(const CF<T>& c, const FrameT<T>& F, T phib, V3<T> Nb, PoseGrad<T>& G) {
+  G.wS = G.wS + cross(c.N, Nb);
+  const V3<T> nSb = mulMT(F.RS, Nb);
+  const V3<T> gb = (nSb - c.nS * dot(c.nS, nSb)) * (cst<T>(1.f) / c.sg);
+  return c.g * phib + mulS(c.H, gb);
+}
+
+template <class T>
+CM_DEV void vertex_adj(const CF<T>& c, const FrameT<T>& F, const GAdj<T>& a, const DevParams& P, PoseGrad<T>& G) {
+  T phib;
+  V3<T> Nb, pb, prb;
+  blend_moll_adj(c, a, P, phib, Nb, pb, prb);
+  const V3<T> xb = point_adj(c, F, phib, Nb, G);
+  const V3<T> xbw = mulM(F.RS, xb);
+  const V3<T> Pb = pb + prb + xbw;  // p = p_rest = R_M v + t_M; x = R_S^T (p - t_S)
+  G.wM = G.wM + cross(c.p - F.tM, Pb);
+  G.vM = G.vM + Pb;
+  G.wS = G.wS - cross(c.p - F.tS, xbw);
+  G.vS = G.vS - xbw;
+}
+
+// Adjoint of the sphere trace: given the adjoint of p^e (SDF frame), the
+// adjoints of the two corners in the SDF frame.
+template <class T>
+CM_DEV void trace_adj(const Trace<T>& tr, V3<T> peb, const DevParams& P, V3<T>& x0b, V3<T>& x1b) {
+  x0b = peb * 0.5f;
+  x1b = peb * 0.5f;
+  const T pee = dot(peb, tr.e);
+  const T acb = pee * 0.5f, bcb = pee * (-0.5f);
+  V3<T> eb = peb * ((tr.ac - tr.bc) * 0.5f);
+  // s_clip(x, 0, L) = s_+(x) - s_+(x - L): d/dx = sig(x/tau) - sig((x-L)/tau), d/dL = sig((x-L)/tau)
+  const T sa0 = sigmoidT(tr.aK * P.inv_tau_clip), sa1 = sigmoidT((tr.aK - tr.L) * P.inv_tau_clip);
+  const T sb0 = sigmoidT(tr.bK * P.inv_tau_clip), sb1 = sigmoidT((tr.bK - tr.L) * P.inv_tau_clip);
+  const T Lb = acb * sa1 + bcb * sb1;
+  T ab = acb * (sa0 - sa1), bb = bcb * (sb0 - sb1);
+#pragma unroll
+  for (int kk = kMaxTraceAdj - 1; kk >= 0; --kk) {
+    if (kk < P.st_iters) {
+      // alpha_{k+1} = alpha_k + G(phi(x0 + alpha_k e)), G(phi) = sigma(phi / tau_s) phi
+      const T sa = sigmoidT(tr.pa[kk] * P.inv_tau_st);
+      const T Ga = sa + tr.pa[kk] * P.inv_tau_st * sa * (cst<T>(1.f) - sa);
+      const T c1 = ab * Ga;
+      x0b = x0b + tr.ga[kk] * c1;
+      eb = eb + tr.ga[kk] * (c1 * tr.al[kk]);
+      ab = ab + c1 * dot(tr.ga[kk], tr.e);
+      // beta_{k+1} = beta_k + G(phi(x1 - beta_k e))
+      const T sb = sigmoidT(tr.pb[kk] * P.inv_tau_st);
+      const T Gb = sb + tr.pb[kk] * P.inv_tau_st * sb * (cst<T>(1.f) - sb);
+      const T c2 = bb * Gb;
+      x1b = x1b + tr.gb[kk] * c2;
+      eb = eb - tr.gb[kk] * (c2 * tr.be[kk]);
+      bb = bb - c2 * dot(tr.gb[kk], tr.e);
+    }
+  }
+  // e = d / |d|, L = |d|, d = x1 - x0
+  const V3<T> db = (eb - tr.e * dot(tr.e, eb)) * (cst<T>(1.f) / tr.L) + tr.e * Lb;
+  x1b = x1b + db;
+  x0b = x0b - db;
+}
+
+template <class T>
+CM_DEV void edge_adj(const CF<T>& c, const Trace<T>& tr, const FrameT<T>& F, const GAdj<T>& a, const DevParams& P,
+                     PoseGrad<T>& G) {
+  T phib;
+  V3<T> Nb, pb, prb;
+  blend_moll_adj(c, a, P, phib, Nb, pb, prb);
+  const V3<T> xb = point_adj(c, F, phib, Nb, G);
+  // p = R_S p^e + t_S
+  G.wS = G.wS + cross(c.p - F.tS, pb);
+  G.vS = G.vS + pb;
+  const V3<T> peb = mulMT(F.RS, pb) + xb;
+  V3<T> x0b, x1b;
+  trace_adj(tr, peb, P, x0b, x1b);
+  const V3<T> P0 = mulMc(F.RM, tr.v0) + F.tM, P1 = mulMc(F.RM, tr.v1) + F.tM;
+  const V3<T> x0w = mulM(F.RS, x0b), x1w = mulM(F.RS, x1b);
+  G.wS = G.wS - cross(P0 - F.tS, x0w) - cross(P1 - F.tS, x1w);
+  G.vS = G.vS - x0w - x1w;
+  const V3<T> P0b = x0w + prb * 0.5f, P1b = x1w + prb * 0.5f;
+  G.wM = G.wM + cross(P0 - F.tM, P0b) + cross(P1 - F.tM, P1b);
+  G.vM = G.vM + P0b + P1b;
+}
+
+// ------------------------------------------------------------ narrow kernel --
+template <class T, bool ADJ>
+__global__ __launch_bounds__(256) void k_narrow(NarrowArgs a) {
+  const int l = lane();
+  const int64_t total = a.tile_off[a.n_ent];
+  const DevParams& P = a.P;
+  // each pop returns a distinct tile, so a wave pops at most total + 1 times
+  for (int64_t it = 0; it <= total; ++it) {
+    uint32_t t0 = 0;
+    if (l == 0) t0 = atomicAdd(a.counter, 1u);
+    const int64_t t = int64_t(uint32_t(uni(int(t0))));
+    if (t >= total) break;
+    const int64_t e = find_entry(a.tile_off, a.n_ent, t);
+    const int j = int(t - a.tile_off[e]);
+    const Entry E = ldc(a.ents + e);
+    const QueryDev q = ldc(a.Q + E.query);
+    const ObjDesc M = ldc(a.objs + E.mesh_obj);
+    const ObjDesc S = ldc(a.objs + E.sdf_obj);
+    const PieceDesc pd = ldc(M.pieces + E.piece);
+    const float* d12 = (nT<T>() == 2) ? a.dir + 12 * int64_t(E.query) : nullptr;
+    const FrameT<T> F = frame_t<T>(q, E.dir, d12);
+    int c = tile_contact(a.bits, E, j);
+    const bool valid = c >= 0;
+    const int c0 = uni(c);  // lane 0 always holds a survivor
+    if (!valid) c = c0;
+    CF<T> ct;
+    Trace<T> tr;
+    if (E.kind == 0) vertex_fwd<T, ADJ>(M, S, F, pd.vert_begin + c, P, ct);
+    else edge_fwd<T, ADJ>(M, S, F, pd.edge_begin + c, P, ct, tr);
+    float* o = a.partials + t * kStride;
+    if (!ADJ) {
+      // online softmax over l_i = -d_c,i / tau_b of the tile's contacts
+      const T li = ct.d * (-P.inv_tau_blend);
+      const float Lam = wmax(valid ? val(li) : -__builtin_inff());
+      const T w = valid ? expT(li - Lam) : cst<T>(0.f);
+      const T omf = cst<T>(1.f) - ct.f;
+      const V3<T> nc = ct.N * ct.f, pc = ct.p * ct.f + ct.prest * omf, fp = ct.p * ct.f;
+      T acc[13] = {w, w * ct.d, w * nc.x, w * nc.y, w * nc.z, w * pc.x, w * pc.y, w * pc.z,
+                   w * fp.x, w * fp.y, w * fp.z, w * ct.f, cst<T>(valid ? 1.f : 0.f)};
+#pragma unroll
+      for (int i = 0; i < 13; ++i) acc[i] = wsum(acc[i]);
+      if (l == 0) {
+        o[0] = Lam;
+#pragma unroll
+        for (int i = 0; i < 13; ++i) putT(o + 1 + i * nT<T>(), acc[i]);
+      }
+      if (nT<T>() == 1 && a.dbg != nullptr && valid) {
+        const int64_t ci = E.contact_base + c;
+        const float rec[13] = {1.f, val(ct.d), val(ct.f), 0.f, val(pc.x), val(pc.y), val(pc.z), val(nc.x),
+                               val(nc.y), val(nc.z), val(ct.phi), float(E.kind), __int_as_float(E.group)};
+#pragma unroll
+        for (int r = 0; r < 13; ++r) a.dbg[r * a.C + ci] = rec[r];
+      }
+    } else {
+      const GAdj<T> ga = load_gadj<T>(a.gscratch + int64_t(E.group) * kStride);
+      PoseGrad<T> G{zero3<T>(), zero3<T>(), zero3<T>(), zero3<T>()};
+      if (E.kind == 0) vertex_adj(ct, F, ga, P, G);
+      else edge_adj(ct, tr, F, ga, P, G);
+      // (w_A, v_A, w_B, v_B)
+      const V3<T> g4[4] = {E.dir ? G.wS : G.wM, E.dir ? G.vS : G.vM, E.dir ? G.wM : G.wS, E.dir ? G.vM : G.vS};
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const T gx = wsum(valid ? g4[i].x : cst<T>(0.f));
+        const T gy = wsum(valid ? g4[i].y : cst<T>(0.f));
+        const T gz = wsum(valid ? g4[i].z : cst<T>(0.f));
+        if (l == 0) {
+          putT(o + (3 * i) * nT<T>(), gx);
+          putT(o + (3 * i + 1) * nT<T>(), gy);
+          putT(o + (3 * i + 2) * nT<T>(), gz);
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------- finalize --
+template <class T> struct BlendT {
+  float L;
+  T Z, d, f;
+  V3<T> n, p, q;
+};
+template <class T> CM_DEV void blend_merge(BlendT<T>& a, float L, const T& Z, const T& d, const V3<T>& n,
+                                           const V3<T>& p, const V3<T>& q, const T& f) {
+  if (!(val(Z) > 0.f)) return;
+  const float Ln = fmaxf(a.L, L);
+  const float sa = val(a.Z) > 0.f ? expf(a.L - Ln) : 0.f;
+  const float sb = expf(L - Ln);
+  a.L = Ln;
+  a.Z = a.Z * sa + Z * sb;
+  a.d = a.d * sa + d * sb;
+  a.n = a.n * sa + n * sb;
+  a.p = a.p * sa + p * sb;
+  a.q = a.q * sa + q * sb;
+  a.f = a.f * sa + f * sb;
+}
+
+// World-frame sum of the points of an entry's filtered contacts; with duals
+// its tangent follows from the mesh body's perturbation: S' = w x (S - n t) + n v.
+template <class T> CM_DEV V3<T> filt_sum(const F4& fl, const QueryDev& q, int dir, const float* d12);
+template <> CM_DEV V3<float> filt_sum<float>(const F4& fl, const QueryDev&, int, const float*) {
+  return {fl.y, fl.z, fl.w};
+}
+template <> CM_DEV V3<df> filt_sum<df>(const F4& fl, const QueryDev& q, int dir, const float* d12) {
+  const float* d6 = d12 + (dir ? 6 : 0);
+  const float* t = dir ? q.tb : q.ta;
+  const V3<float> r{fl.y - fl.x * t[0], fl.z - fl.x * t[1], fl.w - fl.x * t[2]};
+  const V3<float> w{d6[0], d6[1], d6[2]};
+  const V3<float> tt = cross(w, r);
+  return {df{fl.y, tt.x + fl.x * d6[3]}, df{fl.z, tt.y + fl.x * d6[4]}, df{fl.w, tt.z + fl.x * d6[5]}};
+}
+
+// Fixed-order merge of a piece's contacts: vertices (filtered closed form,
+// then tiles) then edges (filtered, then tiles) (Sec. IV-D.2-3).
+template <class T> CM_DEV BlendT<T> group_blend(const FinArgs& a, int64_t g) {
+  BlendT<T> b;
+  b.L = -__builtin_inff();
+  b.Z = b.d = b.f = cst<T>(0.f);
+  b.n = b.p = b.q = zero3<T>();
+  const I2 ge = a.gent[g];
+  const DevParams& P = a.P;
+  for (int k = 0; k < 2; ++k) {
+    const int e = k == 0 ? ge.x : ge.y;
+    const F4 fl = a.filt[e];
+    if (fl.x > 0.f) {
+      const Entry E = ldc(a.ents + e);
+      const QueryDev q = ldc(a.Q + E.query);
+      const float* d12 = (nT<T>() == 2) ? a.dir + 12 * int64_t(E.query) : nullptr;
+      const V3<T> S = filt_sum<T>(fl, q, E.dir, d12);
+      blend_merge(b, -P.d_max * P.inv_tau_blend, cst<T>(fl.x), cst<T>(fl.x * P.d_max), zero3<T>(), S, zero3<T>(),
+                  cst<T>(0.f));
+    }
+    for (int64_t t = a.tile_off[e]; t < a.tile_off[e + 1]; ++t) {
+      const float* o = a.partials + t * kStride;
+      constexpr int s = nT<T>();
+      const T* dummy = nullptr;
+      (void)dummy;
+      blend_merge(b, o[0], getT<T>(o + 1), getT<T>(o + 1 + s),
+                  V3<T>{getT<T>(o + 1 + 2 * s), getT<T>(o + 1 + 3 * s), getT<T>(o + 1 + 4 * s)},
+                  V3<T>{getT<T>(o + 1 + 5 * s), getT<T>(o + 1 + 6 * s), getT<T>(o + 1 + 7 * s)},
+                  V3<T>{getT<T>(o + 1 + 8 * s), getT<T>(o + 1 + 9 * s), getT<T>(o + 1 + 10 * s)},
+                  getT<T>(o + 1 + 11 * s));
+    }
+  }
+  return b;
+}
+
+// WHAT 0: write the group records.  WHAT 1: write the per-piece adjoint seeds
+// for the cotangent `cot` (n_bar = cot_n, m_bar through the normalisation).
+template <class T, int WHAT>
+__global__ __launch_bounds__(256) void k_finalize(FinArgs a) {
+  const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (g >= a.G) return;
+  const BlendT<T> b = group_blend<T>(a, g);
+  const T iz = cst<T>(1.f) / b.Z;
+  const V3<T> m = b.n * iz;
+  const T sg = sqrtT(dot(m, m) + a.P.eps_n2);
+  const V3<T> n = m * (cst<T>(1.f) / sg);
+  const V3<T> p = b.p * iz, q = b.q * iz;
+  const T d = b.d * iz, W = b.f * iz;
+  const T logZ = logT(b.Z) + b.L;
+  const int64_t G = a.G;
+  if (WHAT == 0) {
+    a.out.p[g] = val(p.x); a.out.p[G + g] = val(p.y); a.out.p[2 * G + g] = val(p.z);
+    a.out.n[g] = val(n.x); a.out.n[G + g] = val(n.y); a.out.n[2 * G + g] = val(n.z);
+    a.out.q[g] = val(q.x); a.out.q[G + g] = val(q.y); a.out.q[2 * G + g] = val(q.z);
+    a.out.d[g] = val(d);
+    a.out.W[g] = val(W);
+    a.out.logZ[g] = val(logZ);
+  } else {
+    const V3<float> cp{a.cot.p[g], a.cot.p[G + g], a.cot.p[2 * G + g]};
+    const V3<float> cn{a.cot.n[g], a.cot.n[G + g], a.cot.n[2 * G + g]};
+    const V3<float> cq{a.cot.q[g], a.cot.q[G + g], a.cot.q[2 * G + g]};
+    const float cd = a.cot.d[g], cW = a.cot.W[g], clz = a.cot.logZ[g];
+    const V3<T> cnT = lift3<T>(cn);
+    const V3<T> mb = (cnT - n * dot(n, cnT)) * (cst<T>(1.f) / sg);
+    const T B = d * cd + dot(lift3<T>(cp), p) + dot(mb, m) + dot(lift3<T>(cq), q) + W * cW;
+    float* o = a.gscratch + g * kStride;
+    constexpr int s = nT<T>();
+    putT(o, cst<T>(cd));
+    putT(o + 1 * s, cst<T>(cp.x)); putT(o + 2 * s, cst<T>(cp.y)); putT(o + 3 * s, cst<T>(cp.z));
+    putT(o + 4 * s, mb.x); putT(o + 5 * s, mb.y); putT(o + 6 * s, mb.z);
+    putT(o + 7 * s, cst<T>(cq.x)); putT(o + 8 * s, cst<T>(cq.y)); putT(o + 9 * s, cst<T>(cq.z));
+    putT(o + 10 * s, cst<T>(cW));
+    putT(o + 11 * s, B);
+    putT(o + 12 * s, cst<T>(clz));
+    putT(o + 13 * s, logZ);
+  }
+}
+
+// Per-contact blending weight w_i = exp(l_i - logZ_g) for the debug output.
+__global__ void k_dbg_weights(float* __restrict__ dbg, int64_t C, const float* __restrict__ logZ, DevParams P) {
+  const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (c >= C) return;
+  const int g = __float_as_int(dbg[12 * C + c]);
+  dbg[3 * C + c] = expf(-dbg[C + c] * P.inv_tau_blend - logZ[g]);
+}
+
+// ----------------------------------------------------------------- reduce --
+// Per query, in a fixed order: for each piece (group) its vertex then edge
+// entry, the filtered contacts' closed form (their points move with the mesh
+// body, with weight exp(-d_max / tau_b - logZ)) and then the tiles' partials.
+// With duals, hv = d/de grad - (1/2) w_dir x grad_w per body: the second term
+// converts the derivative of the world-frame gradient into the Hessian of
+// L(exp([w]x) R, t + v) at zero.
+template <class T>
+__global__ __launch_bounds__(256) void k_reduce(FinArgs a, const float* __restrict__ bpartials,
+                                                const int64_t* __restrict__ group_off, int32_t n,
+                                                float* __restrict__ grad, float* __restrict__ hv) {
+  const int64_t qi = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (qi >= n) return;
+  T acc[12];
+  for (int i = 0; i < 12; ++i) acc[i] = cst<T>(0.f);
+  const DevParams& P = a.P;
+  const float* d12 = (nT<T>() == 2) ? a.dir + 12 * qi : nullptr;
+  for (int64_t g = group_off[qi]; g < group_off[qi + 1]; ++g) {
+    const GAdj<T> ga = load_gadj<T>(a.gscratch + g * kStride);
+    const I2 ge = a.gent[g];
+    for (int k = 0; k < 2; ++k) {
+      const int e = k == 0 ? ge.x : ge.y;
+      const F4 fl = a.filt[e];
+      if (fl.x > 0.f) {
+        const Entry E = ldc(a.ents + e);
+        const QueryDev q = ldc(a.Q + E.query);
+        const FrameT<T> F = frame_t<T>(q, E.dir, d12);
+        const V3<T> S = filt_sum<T>(fl, q, E.dir, d12);
+        const T wf = expT(ga.logZ * -1.f - P.d_max * P.inv_tau_blend);
+        const V3<T> wM = cross(S - F.tM * fl.x, ga.cp) * wf;
+        const V3<T> vM = ga.cp * (wf * fl.x);
+        const int o = E.dir ? 6 : 0;
+        acc[o + 0] += wM.x; acc[o + 1] += wM.y; acc[o + 2] += wM.z;
+        acc[o + 3] += vM.x; acc[o + 4] += vM.y; acc[o + 5] += vM.z;
+      }
+      for (int64_t t = a.tile_off[e]; t < a.tile_off[e + 1]; ++t) {
+        const float* o = bpartials + t * kStride;
+        for (int i = 0; i < 12; ++i) acc[i] += getT<T>(o + i * nT<T>());
+      }
+    }
+  }
+  for (int i = 0; i < 12; ++i) grad[12 * qi + i] = val(acc[i]);
+  if (nT<T>() == 2 && hv != nullptr) {
+    for (int body = 0; body < 2; ++body) {
+      const float* w = d12 + 6 * body;
+      const float gw[3] = {val(acc[6 * body]), val(acc[6 * body + 1]), val(acc[6 * body + 2])};
+      const float corr[3] = {w[1] * gw[2] - w[2] * gw[1], w[2] * gw[0] - w[0] * gw[2], w[0] * gw[1] - w[1] * gw[0]};
+      for (int i = 0; i < 3; ++i) hv[12 * qi + 6 * body + i] = tan_(acc[6 * body + i]) - 0.5f * corr[i];
+      for (int i = 3; i < 6; ++i) hv[12 * qi + 6 * body + i] = tan_(acc[6 * body + i]);
+    }
+  }
+}
+
+// ------------------------------------------------------------- launchers --
+static inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+template <class T, bool ADJ>
+static void narrow_launch(const NarrowArgs& na, int grid, hipStream_t s, hipEvent_t* ev) {
+  launch_fill_u32(na.counter, 0u, 1, s);
+  const int slot = nT<T>() == 1 ? (ADJ ? kTNarrowAdj : kTNarrowFwd) : (ADJ ? kTNarrowDualAdj : kTNarrowTan);
+  if (ev) (void)hipEventRecord(ev[2 * slot], s);
+  hipLaunchKernelGGL((k_narrow<T, ADJ>), dim3(unsigned(grid)), dim3(256), 0, s, na);
+  if (ev) (void)hipEventRecord(ev[2 * slot + 1], s);
+}
+
+static NarrowArgs narrow_args(const FwdArgs& a, float* partials, const float* dir, float* dbg) {
+  NarrowArgs na{};
+  na.ents = a.ents; na.n_ent = a.n_ent; na.tile_off = a.tile_off; na.bits = a.bits; na.Q = a.Q; na.objs = a.objs;
+  na.P = a.P; na.counter = a.counter; na.partials = partials; na.gscratch = a.gscratch; na.dir = dir;
+  na.dbg = dbg; na.C = a.C;
+  return na;
+}
+static FinArgs fin_args(const FwdArgs& a, const float* partials, const float* dir) {
+  FinArgs fa{};
+  fa.G = a.G; fa.gent = a.gent; fa.tile_off = a.tile_off; fa.filt = a.filt; fa.partials = partials;
+  fa.ents = a.ents; fa.Q = a.Q; fa.P = a.P; fa.out = a.out; fa.cot = a.cot; fa.gscratch = a.gscratch; fa.dir = dir;
+  return fa;
+}
+
+hipError_t launch_forward(const FwdArgs& a, hipStream_t s) {
+  launch_front(a, s);
+  const int grid = a.n_cu * a.blocks_per_cu;
+  narrow_launch<float, false>(narrow_args(a, a.partials, nullptr, a.dbg), grid, s, a.ev);
+  hipLaunchKernelGGL((k_finalize<float, 0>), dim3(unsigned(cdiv(a.G, 256))), dim3(256), 0, s,
+                     fin_args(a, a.partials, nullptr));
+  if (a.dbg != nullptr)
+    hipLaunchKernelGGL(k_dbg_weights, dim3(unsigned(cdiv(a.C, 256))), dim3(256), 0, s, a.dbg, a.C, a.out.logZ, a.P);
+  return hipGetLastError();
+}
+
+template <class T> static hipError_t adjoint_impl(const FwdArgs& a, hipStream_t s) {
+  launch_front(a, s);
+  const int grid = a.n_cu * a.blocks_per_cu;
+  const float* dir = a.dir;
+  narrow_launch<T, false>(narrow_args(a, a.partials, dir, nullptr), grid, s, a.ev);
+  hipLaunchKernelGGL((k_finalize<T, 1>), dim3(unsigned(cdiv(a.G, 256))), dim3(256), 0, s,
+                     fin_args(a, a.partials, dir));
+  narrow_launch<T, true>(narrow_args(a, a.bpartials, dir, nullptr), grid, s, a.ev);
+  hipLaunchKernelGGL((k_reduce<T>), dim3(unsigned(cdiv(a.n, 256))), dim3(256), 0, s, fin_args(a, a.partials, dir),
+                     a.bpartials, a.group_off, a.n, a.grad, a.hv);
+  return hipGetLastError();
+}
+
+hipError_t launch_backward(const FwdArgs& a, hipStream_t s) { return adjoint_impl<float>(a, s); }
+hipError_t launch_hvp(const FwdArgs& a, hipStream_t s) { return adjoint_impl<df>(a, s); }
+
+}  // namespace cm

@@ -607,9 +607,11 @@ cm_status cm_plan_create(cm_context* ctx, const cm_query* hq, int32_t n, cm_plan
   const size_t o_toff = take(8 * size_t(pl->E + 1));
   const size_t o_bsum = take(8 * size_t(pl->nb + 1));
   const size_t o_cnt = take(256);
-  const size_t o_part = take(4 * size_t(kPartial) * size_t(W));
-  const size_t o_gs = take(4 * size_t(16) * size_t(pl->G));
-  const size_t o_bp = take(4 * size_t(16) * size_t(W));
+  const size_t o_part = take(4 * size_t(kStride) * size_t(W));
+  const size_t o_gs = take(4 * size_t(kStride) * size_t(pl->G));
+  const size_t o_bp = take(4 * size_t(kStride) * size_t(W));
+  const size_t o_goff = take(8 * size_t(n + 1));
+  const size_t o_gt = take(4 * 12 * size_t(n));
   if (hipMalloc(&pl->dmem, off) != hipSuccess) { delete pl; return fail(ctx, CM_E_OOM, "plan scratch allocation failed"); }
   char* b = static_cast<char*>(pl->dmem);
   pl->d_ents = reinterpret_cast<Entry*>(b + o_ents);
@@ -624,9 +626,12 @@ cm_status cm_plan_create(cm_context* ctx, const cm_query* hq, int32_t n, cm_plan
   pl->d_partials = reinterpret_cast<float*>(b + o_part);
   pl->d_gscratch = reinterpret_cast<float*>(b + o_gs);
   pl->d_bpartials = reinterpret_cast<float*>(b + o_bp);
+  pl->d_group_off = reinterpret_cast<int64_t*>(b + o_goff);
+  pl->d_gradtmp = reinterpret_cast<float*>(b + o_gt);
+  hipError_t e3 = hipMemcpy(pl->d_group_off, pl->group_off.data(), 8 * size_t(n + 1), hipMemcpyHostToDevice);
   hipError_t e1 = hipMemcpy(pl->d_ents, pl->ents.data(), sizeof(Entry) * size_t(pl->E), hipMemcpyHostToDevice);
   hipError_t e2 = hipMemcpy(pl->d_gent, gent.data(), sizeof(I2) * size_t(pl->G), hipMemcpyHostToDevice);
-  if (e1 != hipSuccess || e2 != hipSuccess) {
+  if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
     (void)hipFree(pl->dmem);
     delete pl;
     return fail(ctx, CM_E_HIP, "plan upload failed");
@@ -641,7 +646,30 @@ cm_status cm_plan_destroy(cm_plan* pl) {
     (void)hipDeviceSynchronize();
     (void)hipFree(pl->dmem);
   }
+  for (auto& e : pl->ev)
+    if (e) (void)hipEventDestroy(e);
   delete pl;
+  return CM_OK;
+}
+
+cm_status cm_plan_set_timing(cm_plan* pl, int32_t enable) {
+  if (!pl) return CM_E_INVALID;
+  if (enable && !pl->ev[0])
+    for (auto& e : pl->ev)
+      if (hipEventCreate(&e) != hipSuccess) return fail(pl->ctx, CM_E_HIP, "hipEventCreate failed");
+  pl->timing = enable != 0;
+  return CM_OK;
+}
+
+cm_status cm_plan_timing(const cm_plan* pl, float* ms) {
+  if (!pl || !ms) return CM_E_INVALID;
+  for (int k = 0; k < kTimed; ++k) {
+    ms[k] = -1.f;
+    if (!pl->ev[0]) continue;
+    if (hipEventSynchronize(pl->ev[2 * k + 1]) != hipSuccess) continue;
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, pl->ev[2 * k], pl->ev[2 * k + 1]) == hipSuccess) ms[k] = t;
+  }
   return CM_OK;
 }
 
@@ -660,22 +688,23 @@ cm_status cm_plan_offsets(const cm_plan* pl, int64_t* group_off, int64_t* contac
   return CM_OK;
 }
 
-cm_status cm_plan_stats(const cm_plan* pl, int64_t* st) {
+cm_status cm_plan_stats(const cm_plan* pl, int64_t* st) {  // 8 entries
   if (!pl || !st) return CM_E_INVALID;
   std::vector<int32_t> ns(size_t(pl->E));
   CM_HIP(pl->ctx, hipDeviceSynchronize());
   CM_HIP(pl->ctx, hipMemcpy(ns.data(), pl->d_nsurv, 4 * size_t(pl->E), hipMemcpyDeviceToHost));
   int64_t sv = 0, se = 0, tiles = 0, nv = 0, ne = 0;
-  double pairs = 0;
+  double pairs = 0, vpairs = 0, epairs = 0;
   const int K2 = 2 * pl->ctx->prm.st_iters + 1;
   for (size_t i = 0; i < ns.size(); ++i) {
     const Entry& e = pl->ents[i];
     const double P = double(pl->ctx->objs[size_t(e.sdf_obj)].n_planes);
     tiles += (ns[i] + kWave - 1) / kWave;
-    if (e.kind == 0) { sv += ns[i]; nv += e.count; pairs += double(ns[i]) * P; }
-    else { se += ns[i]; ne += e.count; pairs += double(ns[i]) * P * K2; }
+    if (e.kind == 0) { sv += ns[i]; nv += e.count; pairs += double(ns[i]) * P; vpairs += double(ns[i]) * P; }
+    else { se += ns[i]; ne += e.count; pairs += double(ns[i]) * P * K2; epairs += double(ns[i]) * P; }
   }
   st[0] = sv; st[1] = se; st[2] = tiles; st[3] = nv; st[4] = ne; st[5] = int64_t(pairs);
+  st[6] = int64_t(vpairs); st[7] = int64_t(epairs);
   return CM_OK;
 }
 
@@ -701,6 +730,11 @@ static FwdArgs fwd_args(cm_context* ctx, cm_plan* pl, const cm_query* q, const c
   a.C = pl->C;
   a.n_cu = ctx->n_cu;
   a.blocks_per_cu = 8;
+  a.gscratch = pl->d_gscratch;
+  a.bpartials = pl->d_bpartials;
+  a.group_off = pl->d_group_off;
+  a.n = pl->n;
+  a.ev = pl->timing ? pl->ev : nullptr;
   return a;
 }
 
@@ -713,12 +747,35 @@ cm_status cm_contacts_fwd(cm_context* ctx, cm_plan* pl, const cm_query* q, cm_gr
   return CM_OK;
 }
 
-cm_status cm_contacts_bwd(cm_context* ctx, cm_plan*, const cm_query*, cm_groups, float*, void*) {
-  return fail(ctx, CM_E_INVALID, "cm_contacts_bwd: not available in this build");
+static bool valid_groups(const cm_groups& g) { return g.p && g.n && g.d && g.q && g.W && g.logZ; }
+
+cm_status cm_contacts_bwd(cm_context* ctx, cm_plan* pl, const cm_query* q, cm_groups cot, float* grad, void* stream) {
+  if (!ctx || !pl || pl->ctx != ctx || !q || !grad || !valid_groups(cot))
+    return fail(ctx, CM_E_INVALID, "bad arguments");
+  if (ctx->prm.st_iters > 4) return fail(ctx, CM_E_INVALID, "the adjoint supports st_iters <= 4");
+  FwdArgs a = fwd_args(ctx, pl, q, cm_groups{}, nullptr);
+  a.cot = OutPtrs{cot.p, cot.n, cot.d, cot.q, cot.W, cot.logZ};
+  a.grad = grad;
+  a.hv = nullptr;
+  a.dir = nullptr;
+  hipError_t e = launch_backward(a, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(ctx, e, "backward launch");
+  return CM_OK;
 }
 
-cm_status cm_hvp(cm_context* ctx, cm_plan*, const cm_query*, cm_groups, const float*, float*, float*, void*) {
-  return fail(ctx, CM_E_INVALID, "cm_hvp: not available in this build");
+cm_status cm_hvp(cm_context* ctx, cm_plan* pl, const cm_query* q, cm_groups cot, const float* dir, float* hv,
+                 float* grad, void* stream) {
+  if (!ctx || !pl || pl->ctx != ctx || !q || !dir || !hv || !valid_groups(cot))
+    return fail(ctx, CM_E_INVALID, "bad arguments");
+  if (ctx->prm.st_iters > 4) return fail(ctx, CM_E_INVALID, "the adjoint supports st_iters <= 4");
+  FwdArgs a = fwd_args(ctx, pl, q, cm_groups{}, nullptr);
+  a.cot = OutPtrs{cot.p, cot.n, cot.d, cot.q, cot.W, cot.logZ};
+  a.grad = grad ? grad : pl->d_gradtmp;
+  a.hv = hv;
+  a.dir = dir;
+  hipError_t e = launch_hvp(a, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(ctx, e, "hvp launch");
+  return CM_OK;
 }
 
 cm_status cm_shutdown(cm_context* ctx) {

@@ -88,5 +88,8 @@ struct cm_plan {
   float* d_partials = nullptr;
   float* d_gscratch = nullptr;   // per-group forward results for the adjoint
   float* d_bpartials = nullptr;  // per-tile adjoint partials
-  int64_t last_pairs_fwd = 0;
+  int64_t* d_group_off = nullptr;
+  float* d_gradtmp = nullptr;    // [n][12] gradient when the caller passes none
+  bool timing = false;
+  hipEvent_t ev[2 * cm::kTimed] = {};
 };
