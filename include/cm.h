@@ -216,6 +216,10 @@ cm_status cm_submit(cm_context* ctx, const cm_request* req, cm_ticket* ticket);
 cm_status cm_poll(cm_context* ctx, cm_ticket ticket, int32_t* done, cm_status* result);
 /* Blocks until the ticket finishes (or timeout_ms elapses: CM_E_BUSY). */
 cm_status cm_wait(cm_context* ctx, cm_ticket ticket, int32_t timeout_ms, cm_status* result);
+/* Latencies (seconds, from cm_submit to results written) of completed
+ * requests in completion order since the last call; copies at most cap and
+ * removes them from the record; *n = number copied. */
+cm_status cm_serve_latencies(cm_context* ctx, double* out, int64_t cap, int64_t* n);
 /* Serving statistics: [0] submitted, [1] completed, [2] batches, [3] queued,
  * [4] in flight, [5] peak in-flight bytes, [6] queries completed. */
 cm_status cm_serve_stats(cm_context* ctx, int64_t* stats7);

@@ -17,6 +17,14 @@ if not os.path.exists(LIB_PATH):
     raise ImportError("libcm.so is not built; run `python -m paper_2604_17538_amd.build` "
                       "(hipcc for gfx950) first")
 
+try:
+    # torch's HIP code links the HIP runtime by its unversioned name from its own
+    # lib directory; loading torch first makes this library bind to that same
+    # runtime instead of bringing a second copy into the process
+    import torch  # noqa: F401
+except ImportError:
+    pass
+
 lib = ctypes.CDLL(LIB_PATH)
 
 CM_OK, CM_E_INVALID, CM_E_OOM, CM_E_DEGENERATE, CM_E_HIP, CM_E_BUSY, CM_E_NOTFOUND = 0, -1, -2, -3, -4, -5, -6
@@ -83,9 +91,11 @@ cm_submit = _sig("cm_submit", I32, [P, ctypes.POINTER(cm_request), ctypes.POINTE
 cm_poll = _sig("cm_poll", I32, [P, U64, ctypes.POINTER(I32), ctypes.POINTER(I32)])
 cm_wait = _sig("cm_wait", I32, [P, U64, I32, ctypes.POINTER(I32)])
 cm_serve_stats = _sig("cm_serve_stats", I32, [P, P])
+cm_serve_latencies = _sig("cm_serve_latencies", I32, [P, P, I64, ctypes.POINTER(I64)])
 
 EXPORTED = ["cm_default_params", "cm_init", "cm_shutdown", "cm_last_error", "cm_build_pieces", "cm_build_objects",
             "cm_build_pieces_raw", "cm_release_object", "cm_object_info", "cm_object_export", "cm_object_grid",
             "cm_plan_create", "cm_plan_destroy", "cm_plan_info", "cm_plan_offsets", "cm_plan_stats",
             "cm_plan_set_timing", "cm_plan_timing",
-            "cm_contacts_fwd", "cm_contacts_bwd", "cm_hvp", "cm_submit", "cm_poll", "cm_wait", "cm_serve_stats"]
+            "cm_contacts_fwd", "cm_contacts_bwd", "cm_hvp", "cm_submit", "cm_poll", "cm_wait", "cm_serve_stats",
+            "cm_serve_latencies"]

@@ -52,6 +52,10 @@ class Context:
     def __init__(self, device: int = 0, params: Optional[cm_params] = None, L_ref: float = 0.1,
                  budget_bytes: int = 0, **overrides):
         self.params = params if params is not None else default_params(L_ref, **overrides)
+        if device >= 0:
+            # let torch bring up the device first: it shares the HIP runtime with
+            # the library and must own the device's initialisation
+            _torch().cuda.init()
         self._h = ctypes.c_void_p()
         st = _cm.cm_init(int(device), ctypes.byref(self.params), int(budget_bytes), ctypes.byref(self._h))
         if st != 0:
@@ -253,3 +257,73 @@ class Plan:
         self.ctx._check(_cm.cm_plan_stats(self._h, _ptr(s)), "cm_plan_stats")
         return dict(surv_verts=int(s[0]), surv_edges=int(s[1]), tiles=int(s[2]), verts=int(s[3]),
                     edges=int(s[4]), pairs=int(s[5]), vertex_pairs=int(s[6]), edge_pairs=int(s[7]))
+
+
+class Server:
+    """Client side of the serving loop (cm_submit / cm_poll / cm_wait).
+
+    Requests are host arrays; their results are written into host buffers
+    owned by the returned Ticket and are valid once it is done.
+    """
+
+    def __init__(self, ctx: Context):
+        self.ctx = ctx
+
+    def submit(self, qa, qb, poses, cotangent=None) -> "Ticket":
+        q = make_queries(qa, qb, poses)
+        G = int(sum(self.ctx.object_info(int(a))[0] + self.ctx.object_info(int(b))[0] for a, b in zip(qa, qb)))
+        out = np.zeros((G, 12), np.float32)
+        grad = np.zeros((len(q), 12), np.float32) if cotangent is not None else None
+        cot = np.ascontiguousarray(cotangent, np.float32).reshape(G, 12) if cotangent is not None else None
+        req = _cm.cm_request(q=_ptr(q), n=len(q), want_grad=int(cotangent is not None),
+                             cotangent=_ptr(cot) if cot is not None else None, out_groups=_ptr(out),
+                             out_grad=_ptr(grad) if grad is not None else None)
+        t = ctypes.c_uint64()
+        self.ctx._check(_cm.cm_submit(self.ctx.handle, ctypes.byref(req), ctypes.byref(t)), "cm_submit")
+        return Ticket(self, t.value, q, cot, out, grad)
+
+    def latencies(self) -> np.ndarray:
+        """Seconds from submit to results written, of requests completed since the last call."""
+        out = []
+        while True:
+            buf = np.zeros(65536)
+            n = ctypes.c_int64()
+            self.ctx._check(_cm.cm_serve_latencies(self.ctx.handle, _ptr(buf), len(buf), ctypes.byref(n)),
+                            "cm_serve_latencies")
+            out.append(buf[:n.value])
+            if n.value < len(buf):
+                return np.concatenate(out)
+
+    def stats(self) -> dict:
+        s = np.zeros(7, np.int64)
+        self.ctx._check(_cm.cm_serve_stats(self.ctx.handle, _ptr(s)), "cm_serve_stats")
+        return dict(submitted=int(s[0]), completed=int(s[1]), batches=int(s[2]), queued=int(s[3]),
+                    in_flight=int(s[4]), peak_inflight_bytes=int(s[5]), queries=int(s[6]))
+
+
+class Ticket:
+    def __init__(self, server, tid, q, cot, out, grad):
+        self.server, self.id = server, tid
+        self._keep = (q, cot)  # inputs are copied at submit; kept for symmetry
+        self.out, self.grad = out, grad
+        self.status = None
+
+    def poll(self) -> bool:
+        if self.status is not None:
+            return True
+        done, res = ctypes.c_int32(), ctypes.c_int32()
+        self.server.ctx._check(_cm.cm_poll(self.server.ctx.handle, self.id, ctypes.byref(done), ctypes.byref(res)),
+                               "cm_poll")
+        if done.value:
+            self.status = res.value
+        return bool(done.value)
+
+    def wait(self, timeout_ms: int = 60000):
+        if self.status is None:
+            res = ctypes.c_int32()
+            self.server.ctx._check(_cm.cm_wait(self.server.ctx.handle, self.id, int(timeout_ms), ctypes.byref(res)),
+                                   "cm_wait")
+            self.status = res.value
+        if self.status != 0:
+            raise CMError(self.status, "request failed")
+        return self.out, self.grad

@@ -9,8 +9,6 @@
 
 namespace cm {
 
-namespace {
-
 constexpr double kLog2eD = 1.4426950408889634;
 
 cm_status fail(cm_context* ctx, cm_status st, const std::string& msg) {
@@ -25,13 +23,14 @@ cm_status hip_fail(cm_context* ctx, hipError_t e, const char* where) {
   return fail(ctx, CM_E_HIP, std::string(where) + ": " + hipGetErrorString(e));
 }
 
+namespace {
+
+
 #define CM_HIP(ctx, call)                                  \
   do {                                                     \
     hipError_t e_ = (call);                                \
     if (e_ != hipSuccess) return hip_fail(ctx, e_, #call); \
   } while (0)
-
-inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 bool valid_params(const cm_params& p, std::string* why) {
   const float pos[] = {p.tau_cap, p.tau_cup, p.tau_st, p.tau_clip, p.tau_blend, p.eps_t, p.eps_n};
@@ -318,7 +317,7 @@ static cm_status register_objects(cm_context* ctx, std::vector<ObjHost>& built, 
   return CM_OK;
 }
 
-static ObjHost* get_obj(cm_context* ctx, cm_object h) {
+ObjHost* get_obj(cm_context* ctx, cm_object h) {
   if (h >= ctx->objs.size() || !ctx->objs[h].alive) return nullptr;
   return &ctx->objs[h];
 }
@@ -524,11 +523,13 @@ cm_status cm_object_grid(cm_context* ctx, cm_object obj, float* G, float* meta) 
 }
 
 // ------------------------------------------------------------------ plans --
-cm_status cm_plan_create(cm_context* ctx, const cm_query* hq, int32_t n, cm_plan** out) {
-  if (!ctx || !out || n <= 0 || !hq) return fail(ctx, CM_E_INVALID, "bad arguments");
-  *out = nullptr;
-  if (ctx->device < 0) return fail(ctx, CM_E_INVALID, "host-only context cannot run queries");
-  auto* pl = new cm_plan;
+}  // extern "C"
+
+namespace cm {
+
+// Host tables of a plan (entries sorted by estimated cost, group -> entries)
+// and the size of its device scratch.  Takes ctx->mu.
+cm_status plan_host(cm_context* ctx, const cm_query* hq, int32_t n, cm_plan* pl, size_t* dev_bytes) {
   pl->ctx = ctx;
   pl->n = n;
   pl->group_off.assign(size_t(n) + 1, 0);
@@ -542,7 +543,7 @@ cm_status cm_plan_create(cm_context* ctx, const cm_query* hq, int32_t n, cm_plan
     for (int32_t i = 0; i < n; ++i) {
       const ObjHost* A = get_obj(ctx, hq[i].a);
       const ObjHost* B = get_obj(ctx, hq[i].b);
-      if (!A || !B) { delete pl; ctx->err = "query names an unknown object"; return CM_E_NOTFOUND; }
+      if (!A || !B) { ctx->err = "query names an unknown object"; return CM_E_NOTFOUND; }
       pl->qa[size_t(i)] = int32_t(hq[i].a);
       pl->qb[size_t(i)] = int32_t(hq[i].b);
       const int64_t ga = int64_t(A->pieces.size()), gb = int64_t(B->pieces.size());
@@ -579,25 +580,30 @@ cm_status cm_plan_create(cm_context* ctx, const cm_query* hq, int32_t n, cm_plan
   }
   pl->G = pl->group_off[size_t(n)];
   pl->C = pl->contact_off[size_t(n)];
-  if (pl->G >= (int64_t(1) << 31)) { delete pl; return fail(ctx, CM_E_INVALID, "too many groups in one plan"); }
+  if (pl->G >= (int64_t(1) << 31)) { std::lock_guard<std::mutex> lk(ctx->mu); ctx->err = "too many groups"; return CM_E_INVALID; }
   // costliest entries first, so their tiles head the work queue
   std::vector<int64_t> order(pl->ents.size());
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return cost[size_t(a)] > cost[size_t(b)]; });
   std::vector<Entry> sorted(pl->ents.size());
-  std::vector<I2> gent(size_t(pl->G));
+  pl->gent.assign(size_t(pl->G), I2{0, 0});
   for (size_t i = 0; i < order.size(); ++i) {
     sorted[i] = pl->ents[size_t(order[i])];
-    I2& ge = gent[size_t(sorted[i].group)];
+    I2& ge = pl->gent[size_t(sorted[i].group)];
     if (sorted[i].kind == 0) ge.x = int32_t(i); else ge.y = int32_t(i);
   }
   pl->ents.swap(sorted);
   pl->E = int64_t(pl->ents.size());
   pl->nb = (pl->E + 1023) / 1024;
+  *dev_bytes = plan_layout(pl, nullptr);
+  return CM_OK;
+}
+
+// Carves the plan's device scratch out of `base` (nullptr: only sizes it).
+size_t plan_layout(cm_plan* pl, char* b) {
   const int64_t W = std::max<int64_t>(pl->W, 1);
-  // one device allocation for the plan's tables and scratch
   size_t off = 0;
-  auto take = [&](size_t b) { size_t r = off; off = align_up(off + b, 256); return r; };
+  auto take = [&](size_t bytes) { size_t r = off; off = align_up(off + bytes, 256); return r; };
   const size_t o_ents = take(sizeof(Entry) * size_t(pl->E));
   const size_t o_gent = take(sizeof(I2) * size_t(pl->G));
   const size_t o_bits = take(8 * size_t(W));
@@ -610,31 +616,58 @@ cm_status cm_plan_create(cm_context* ctx, const cm_query* hq, int32_t n, cm_plan
   const size_t o_part = take(4 * size_t(kStride) * size_t(W));
   const size_t o_gs = take(4 * size_t(kStride) * size_t(pl->G));
   const size_t o_bp = take(4 * size_t(kStride) * size_t(W));
-  const size_t o_goff = take(8 * size_t(n + 1));
-  const size_t o_gt = take(4 * 12 * size_t(n));
-  if (hipMalloc(&pl->dmem, off) != hipSuccess) { delete pl; return fail(ctx, CM_E_OOM, "plan scratch allocation failed"); }
-  char* b = static_cast<char*>(pl->dmem);
-  pl->d_ents = reinterpret_cast<Entry*>(b + o_ents);
-  pl->d_gent = reinterpret_cast<I2*>(b + o_gent);
-  pl->d_bits = reinterpret_cast<uint64_t*>(b + o_bits);
-  pl->d_nsurv = reinterpret_cast<int32_t*>(b + o_nsurv);
-  pl->d_ntiles = reinterpret_cast<int32_t*>(b + o_ntiles);
-  pl->d_filt = reinterpret_cast<F4*>(b + o_filt);
-  pl->d_tile_off = reinterpret_cast<int64_t*>(b + o_toff);
-  pl->d_bsum = reinterpret_cast<int64_t*>(b + o_bsum);
-  pl->d_counter = reinterpret_cast<uint32_t*>(b + o_cnt);
-  pl->d_partials = reinterpret_cast<float*>(b + o_part);
-  pl->d_gscratch = reinterpret_cast<float*>(b + o_gs);
-  pl->d_bpartials = reinterpret_cast<float*>(b + o_bp);
-  pl->d_group_off = reinterpret_cast<int64_t*>(b + o_goff);
-  pl->d_gradtmp = reinterpret_cast<float*>(b + o_gt);
-  hipError_t e3 = hipMemcpy(pl->d_group_off, pl->group_off.data(), 8 * size_t(n + 1), hipMemcpyHostToDevice);
-  hipError_t e1 = hipMemcpy(pl->d_ents, pl->ents.data(), sizeof(Entry) * size_t(pl->E), hipMemcpyHostToDevice);
-  hipError_t e2 = hipMemcpy(pl->d_gent, gent.data(), sizeof(I2) * size_t(pl->G), hipMemcpyHostToDevice);
-  if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
+  const size_t o_goff = take(8 * size_t(pl->n + 1));
+  const size_t o_gt = take(4 * 12 * size_t(pl->n));
+  if (b) {
+    pl->d_ents = reinterpret_cast<Entry*>(b + o_ents);
+    pl->d_gent = reinterpret_cast<I2*>(b + o_gent);
+    pl->d_bits = reinterpret_cast<uint64_t*>(b + o_bits);
+    pl->d_nsurv = reinterpret_cast<int32_t*>(b + o_nsurv);
+    pl->d_ntiles = reinterpret_cast<int32_t*>(b + o_ntiles);
+    pl->d_filt = reinterpret_cast<F4*>(b + o_filt);
+    pl->d_tile_off = reinterpret_cast<int64_t*>(b + o_toff);
+    pl->d_bsum = reinterpret_cast<int64_t*>(b + o_bsum);
+    pl->d_counter = reinterpret_cast<uint32_t*>(b + o_cnt);
+    pl->d_partials = reinterpret_cast<float*>(b + o_part);
+    pl->d_gscratch = reinterpret_cast<float*>(b + o_gs);
+    pl->d_bpartials = reinterpret_cast<float*>(b + o_bp);
+    pl->d_group_off = reinterpret_cast<int64_t*>(b + o_goff);
+    pl->d_gradtmp = reinterpret_cast<float*>(b + o_gt);
+  }
+  return off;
+}
+
+// Binds device scratch and uploads the plan's tables (asynchronously on `s`
+// when given; the host tables live in the plan until it is destroyed).
+cm_status plan_bind(cm_plan* pl, void* dmem, hipStream_t s) {
+  plan_layout(pl, static_cast<char*>(dmem));
+  hipError_t e1 = hipMemcpyAsync(pl->d_ents, pl->ents.data(), sizeof(Entry) * size_t(pl->E), hipMemcpyHostToDevice, s);
+  hipError_t e2 = hipMemcpyAsync(pl->d_gent, pl->gent.data(), sizeof(I2) * size_t(pl->G), hipMemcpyHostToDevice, s);
+  hipError_t e3 = hipMemcpyAsync(pl->d_group_off, pl->group_off.data(), 8 * size_t(pl->n + 1), hipMemcpyHostToDevice, s);
+  if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) return fail(pl->ctx, CM_E_HIP, "plan upload failed");
+  return CM_OK;
+}
+
+}  // namespace cm
+
+extern "C" {
+
+cm_status cm_plan_create(cm_context* ctx, const cm_query* hq, int32_t n, cm_plan** out) {
+  if (!ctx || !out || n <= 0 || !hq) return fail(ctx, CM_E_INVALID, "bad arguments");
+  *out = nullptr;
+  if (ctx->device < 0) return fail(ctx, CM_E_INVALID, "host-only context cannot run queries");
+  auto* pl = new cm_plan;
+  size_t bytes = 0;
+  cm_status st = plan_host(ctx, hq, n, pl, &bytes);
+  if (st != CM_OK) { delete pl; return st; }
+  if (hipMalloc(&pl->dmem, bytes) != hipSuccess) { delete pl; return fail(ctx, CM_E_OOM, "plan scratch allocation failed"); }
+  pl->owns_mem = true;
+  st = plan_bind(pl, pl->dmem, nullptr);
+  if (st == CM_OK && hipDeviceSynchronize() != hipSuccess) st = fail(ctx, CM_E_HIP, "plan upload failed");
+  if (st != CM_OK) {
     (void)hipFree(pl->dmem);
     delete pl;
-    return fail(ctx, CM_E_HIP, "plan upload failed");
+    return st;
   }
   *out = pl;
   return CM_OK;
@@ -642,7 +675,7 @@ cm_status cm_plan_create(cm_context* ctx, const cm_query* hq, int32_t n, cm_plan
 
 cm_status cm_plan_destroy(cm_plan* pl) {
   if (!pl) return CM_E_INVALID;
-  if (pl->dmem) {
+  if (pl->dmem && pl->owns_mem) {
     (void)hipDeviceSynchronize();
     (void)hipFree(pl->dmem);
   }
@@ -708,7 +741,10 @@ cm_status cm_plan_stats(const cm_plan* pl, int64_t* st) {  // 8 entries
   return CM_OK;
 }
 
-static FwdArgs fwd_args(cm_context* ctx, cm_plan* pl, const cm_query* q, const cm_groups& out, float* dbg) {
+}  // extern "C"
+
+namespace cm {
+FwdArgs fwd_args(cm_context* ctx, cm_plan* pl, const cm_query* q, const cm_groups& out, float* dbg) {
   FwdArgs a{};
   a.ents = pl->d_ents;
   a.n_ent = pl->E;
@@ -737,6 +773,9 @@ static FwdArgs fwd_args(cm_context* ctx, cm_plan* pl, const cm_query* q, const c
   a.ev = pl->timing ? pl->ev : nullptr;
   return a;
 }
+}  // namespace cm
+
+extern "C" {
 
 cm_status cm_contacts_fwd(cm_context* ctx, cm_plan* pl, const cm_query* q, cm_groups out, float* dbg, void* stream) {
   if (!ctx || !pl || pl->ctx != ctx || !q) return fail(ctx, CM_E_INVALID, "bad arguments");
@@ -780,25 +819,13 @@ cm_status cm_hvp(cm_context* ctx, cm_plan* pl, const cm_query* q, cm_groups cot,
 
 cm_status cm_shutdown(cm_context* ctx) {
   if (!ctx) return CM_E_INVALID;
+  serving_stop(ctx);
   if (ctx->device >= 0) (void)hipDeviceSynchronize();
   ctx->arena.reset();
   if (ctx->d_objs) (void)hipFree(ctx->d_objs);
   if (ctx->build_stream) (void)hipStreamDestroy(ctx->build_stream);
   delete ctx;
   return CM_OK;
-}
-
-cm_status cm_submit(cm_context* ctx, const cm_request*, cm_ticket*) {
-  return fail(ctx, CM_E_INVALID, "serving not available in this build");
-}
-cm_status cm_poll(cm_context* ctx, cm_ticket, int32_t*, cm_status*) {
-  return fail(ctx, CM_E_INVALID, "serving not available in this build");
-}
-cm_status cm_wait(cm_context* ctx, cm_ticket, int32_t, cm_status*) {
-  return fail(ctx, CM_E_INVALID, "serving not available in this build");
-}
-cm_status cm_serve_stats(cm_context* ctx, int64_t*) {
-  return fail(ctx, CM_E_INVALID, "serving not available in this build");
 }
 
 }  // extern "C"

@@ -23,6 +23,8 @@ namespace cm {
 
 DevParams make_dev_params(const cm_params& p);
 
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
 // Bump allocator over large device chunks; a chunk is returned to HIP once
 // every allocation in it has been released.
 class Arena {
@@ -51,6 +53,9 @@ struct ObjHost {
   ObjDesc desc{};
 };
 
+struct Serving;
+void serving_stop(cm_context* ctx);
+
 }  // namespace cm
 
 struct cm_context {
@@ -66,6 +71,7 @@ struct cm_context {
   size_t d_objs_cap = 0;
   std::unique_ptr<cm::Arena> arena;
   hipStream_t build_stream = nullptr;
+  cm::Serving* serving = nullptr;
 };
 
 struct cm_plan {
@@ -74,6 +80,8 @@ struct cm_plan {
   int64_t G = 0, C = 0, E = 0, W = 0, nb = 0;
   std::vector<int64_t> group_off, contact_off;
   std::vector<cm::Entry> ents;       // host copy (device order)
+  std::vector<cm::I2> gent;          // per group: (vertex entry, edge entry)
+  bool owns_mem = false;
   std::vector<int32_t> qa, qb;
   void* dmem = nullptr;
   cm::Entry* d_ents = nullptr;
@@ -93,3 +101,13 @@ struct cm_plan {
   bool timing = false;
   hipEvent_t ev[2 * cm::kTimed] = {};
 };
+
+namespace cm {
+cm_status fail(cm_context* ctx, cm_status st, const std::string& msg);
+cm_status hip_fail(cm_context* ctx, hipError_t e, const char* where);
+ObjHost* get_obj(cm_context* ctx, cm_object h);
+cm_status plan_host(cm_context* ctx, const cm_query* hq, int32_t n, cm_plan* pl, size_t* dev_bytes);
+size_t plan_layout(cm_plan* pl, char* base);
+cm_status plan_bind(cm_plan* pl, void* dmem, hipStream_t s);
+FwdArgs fwd_args(cm_context* ctx, cm_plan* pl, const cm_query* q, const cm_groups& out, float* dbg);
+}  // namespace cm

@@ -1,0 +1,455 @@
+// Serving: continuous batching of contact queries from many clients.
+//
+// cm_submit copies a request (host queries, optional cotangents) into the
+// pending queue.  A scheduler thread, started on the first submit, keeps up to
+// kSlots batches in flight on their own streams: whenever a slot is free it
+// admits pending requests in arrival order while the device memory they need
+// (plan scratch + buffers, estimated exactly as the plan lays it out) stays
+// within the context's budget, packs their queries into one batch, runs the
+// forward pass over all of them and the adjoint over those that asked for a
+// gradient, and copies the results back into pinned staging.  Batches on
+// different streams overlap; the next batch is formed while others run.
+// Completion is detected with events; results are scattered to the callers'
+// buffers and the tickets are marked done.  A query's results depend only on
+// that query (fixed-order reductions), so they are the same alone and mixed.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <unordered_map>
+
+#include "runtime.h"
+
+namespace cm {
+
+namespace {
+
+constexpr int kSlots = 3;
+constexpr int64_t kMaxBatchQueries = 16384;
+constexpr size_t kQueueLimit = 1 << 20;
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+struct Req {
+  cm_ticket id = 0;
+  std::vector<cm_query> q;
+  bool grad = false;
+  std::vector<float> cot;  // AoS [G][12]
+  float* out_groups = nullptr;
+  float* out_grad = nullptr;
+  int64_t G = 0;
+  size_t bytes = 0;
+  double t_submit = 0;
+};
+
+// Device and pinned buffers of one in-flight batch, grown on demand.
+struct Slot {
+  hipStream_t stream = nullptr;
+  hipEvent_t done = nullptr;
+  void* dmem = nullptr;
+  size_t dcap = 0;
+  char* pinned = nullptr;
+  size_t pcap = 0;
+  bool busy = false;
+  std::vector<Req*> reqs;
+  std::unique_ptr<cm_plan> pf, pg;  // forward plan (all queries), adjoint plan (gradient requests)
+  size_t bytes = 0;
+  // offsets into dmem / pinned
+  size_t d_q = 0, d_qg = 0, d_out = 0, d_cot = 0, d_grad = 0, d_pf = 0, d_pg = 0;
+  size_t h_q = 0, h_qg = 0, h_out = 0, h_cot = 0, h_grad = 0;
+  int64_t n = 0, ng = 0, G = 0, Gg = 0;
+};
+
+}  // namespace
+
+struct Serving {
+  cm_context* ctx = nullptr;
+  std::thread th;
+  std::mutex mu;
+  std::condition_variable cv, done_cv;
+  std::deque<Req*> pending;
+  std::unordered_map<cm_ticket, cm_status> finished;
+  std::unordered_map<cm_ticket, int> live;  // submitted, not yet finished
+  size_t inflight = 0, peak_inflight = 0;
+  bool stop = false;
+  cm_ticket next = 1;
+  int64_t n_submitted = 0, n_completed = 0, n_batches = 0, n_queries = 0;
+  std::vector<double> latencies;  // seconds from submit to results written, in completion order
+  Slot slots[kSlots];
+};
+
+namespace {
+
+// Device bytes a request needs inside a batch: its share of the plan scratch
+// (entries, bitmask, partials, ...) plus its input and output buffers.
+size_t request_bytes(const cm_plan& pl, bool grad) {
+  size_t b = plan_layout(const_cast<cm_plan*>(&pl), nullptr);
+  b += 64 * size_t(pl.n) + 48 * size_t(pl.G);              // queries, outputs
+  if (grad) b += b + 48 * size_t(pl.G) + 48 * size_t(pl.n);  // adjoint plan, cotangents, gradients
+  return b;
+}
+
+bool ensure_device(Slot& s, size_t bytes) {
+  if (s.dcap >= bytes) return true;
+  if (s.dmem) {
+    (void)hipStreamSynchronize(s.stream);
+    (void)hipFree(s.dmem);
+  }
+  s.dcap = std::max(bytes, 2 * s.dcap);
+  if (hipMalloc(&s.dmem, s.dcap) != hipSuccess) { s.dmem = nullptr; s.dcap = 0; return false; }
+  return true;
+}
+
+bool ensure_pinned(Slot& s, size_t bytes) {
+  if (s.pcap >= bytes) return true;
+  if (s.pinned) (void)hipHostFree(s.pinned);
+  s.pcap = std::max(bytes, 2 * s.pcap);
+  if (hipHostMalloc(reinterpret_cast<void**>(&s.pinned), s.pcap, 0) != hipSuccess) {
+    s.pinned = nullptr; s.pcap = 0; return false;
+  }
+  return true;
+}
+
+// Builds the batch's plans and buffers and enqueues its work on the slot's stream.
+cm_status launch_batch(cm_context* ctx, Slot& s) {
+  std::vector<cm_query> qa, qg;
+  std::vector<const Req*> gr;
+  for (const Req* r : s.reqs) {
+    qa.insert(qa.end(), r->q.begin(), r->q.end());
+    if (r->grad) { qg.insert(qg.end(), r->q.begin(), r->q.end()); gr.push_back(r); }
+  }
+  s.n = int64_t(qa.size());
+  s.ng = int64_t(qg.size());
+  s.pf.reset(new cm_plan);
+  size_t bf = 0, bg = 0;
+  cm_status st = plan_host(ctx, qa.data(), int32_t(s.n), s.pf.get(), &bf);
+  if (st != CM_OK) return st;
+  if (s.ng) {
+    s.pg.reset(new cm_plan);
+    st = plan_host(ctx, qg.data(), int32_t(s.ng), s.pg.get(), &bg);
+    if (st != CM_OK) return st;
+  } else {
+    s.pg.reset();
+  }
+  s.G = s.pf->G;
+  s.Gg = s.ng ? s.pg->G : 0;
+  size_t off = 0;
+  auto take = [&](size_t b) { size_t r = off; off = align_up(off + b, 256); return r; };
+  s.d_pf = take(bf);
+  s.d_pg = take(bg);
+  s.d_q = take(64 * size_t(s.n));
+  s.d_qg = take(64 * size_t(s.ng));
+  s.d_out = take(48 * size_t(s.G));
+  s.d_cot = take(48 * size_t(s.Gg));
+  s.d_grad = take(48 * size_t(s.ng));
+  if (!ensure_device(s, off)) return fail(ctx, CM_E_OOM, "serving: device allocation failed");
+  size_t hoff = 0;
+  auto htake = [&](size_t b) { size_t r = hoff; hoff = align_up(hoff + b, 256); return r; };
+  s.h_q = htake(64 * size_t(s.n));
+  s.h_qg = htake(64 * size_t(s.ng));
+  s.h_out = htake(48 * size_t(s.G));
+  s.h_cot = htake(48 * size_t(s.Gg));
+  s.h_grad = htake(48 * size_t(s.ng));
+  if (!ensure_pinned(s, hoff)) return fail(ctx, CM_E_OOM, "serving: pinned allocation failed");
+  char* d = static_cast<char*>(s.dmem);
+  std::memcpy(s.pinned + s.h_q, qa.data(), 64 * size_t(s.n));
+  if (s.ng) {
+    std::memcpy(s.pinned + s.h_qg, qg.data(), 64 * size_t(s.ng));
+    // cotangents AoS [G][12] per request -> SoA [12][Gg] for the adjoint plan
+    float* c = reinterpret_cast<float*>(s.pinned + s.h_cot);
+    int64_t g0 = 0;
+    for (const Req* r : gr) {
+      for (int64_t g = 0; g < r->G; ++g)
+        for (int k = 0; k < 12; ++k) c[k * s.Gg + g0 + g] = r->cot[size_t(12 * g + k)];
+      g0 += r->G;
+    }
+  }
+  hipStream_t st_ = s.stream;
+  if (hipMemcpyAsync(d + s.d_q, s.pinned + s.h_q, 64 * size_t(s.n), hipMemcpyHostToDevice, st_) != hipSuccess)
+    return fail(ctx, CM_E_HIP, "serving: upload failed");
+  if ((st = plan_bind(s.pf.get(), d + s.d_pf, st_)) != CM_OK) return st;
+  float* out = reinterpret_cast<float*>(d + s.d_out);
+  const int64_t G = s.G;
+  cm_groups og{out, out + 3 * G, out + 6 * G, out + 7 * G, out + 10 * G, out + 11 * G};
+  FwdArgs a = fwd_args(ctx, s.pf.get(), reinterpret_cast<const cm_query*>(d + s.d_q), og, nullptr);
+  if (launch_forward(a, st_) != hipSuccess) return fail(ctx, CM_E_HIP, "serving: forward launch failed");
+  if (s.ng) {
+    if (hipMemcpyAsync(d + s.d_qg, s.pinned + s.h_qg, 64 * size_t(s.ng), hipMemcpyHostToDevice, st_) != hipSuccess ||
+        hipMemcpyAsync(d + s.d_cot, s.pinned + s.h_cot, 48 * size_t(s.Gg), hipMemcpyHostToDevice, st_) != hipSuccess)
+      return fail(ctx, CM_E_HIP, "serving: upload failed");
+    if ((st = plan_bind(s.pg.get(), d + s.d_pg, st_)) != CM_OK) return st;
+    float* c = reinterpret_cast<float*>(d + s.d_cot);
+    const int64_t Gg = s.Gg;
+    FwdArgs b = fwd_args(ctx, s.pg.get(), reinterpret_cast<const cm_query*>(d + s.d_qg), cm_groups{}, nullptr);
+    b.cot = OutPtrs{c, c + 3 * Gg, c + 6 * Gg, c + 7 * Gg, c + 10 * Gg, c + 11 * Gg};
+    b.grad = reinterpret_cast<float*>(d + s.d_grad);
+    if (launch_backward(b, st_) != hipSuccess) return fail(ctx, CM_E_HIP, "serving: adjoint launch failed");
+    if (hipMemcpyAsync(s.pinned + s.h_grad, d + s.d_grad, 48 * size_t(s.ng), hipMemcpyDeviceToHost, st_) != hipSuccess)
+      return fail(ctx, CM_E_HIP, "serving: download failed");
+  }
+  if (hipMemcpyAsync(s.pinned + s.h_out, d + s.d_out, 48 * size_t(s.G), hipMemcpyDeviceToHost, st_) != hipSuccess)
+    return fail(ctx, CM_E_HIP, "serving: download failed");
+  if (hipEventRecord(s.done, st_) != hipSuccess) return fail(ctx, CM_E_HIP, "serving: event record failed");
+  return CM_OK;
+}
+
+// Scatters a finished batch's results to the callers' buffers.
+void scatter(Slot& s) {
+  const float* out = reinterpret_cast<const float*>(s.pinned + s.h_out);
+  const float* grad = reinterpret_cast<const float*>(s.pinned + s.h_grad);
+  int64_t g0 = 0, qg0 = 0;
+  for (Req* r : s.reqs) {
+    for (int64_t g = 0; g < r->G; ++g)
+      for (int k = 0; k < 12; ++k) r->out_groups[12 * g + k] = out[k * s.G + g0 + g];
+    g0 += r->G;
+    if (r->grad) {
+      std::memcpy(r->out_grad, grad + 12 * qg0, 48 * r->q.size());
+      qg0 += int64_t(r->q.size());
+    }
+  }
+}
+
+void scheduler(Serving* S) {
+  cm_context* ctx = S->ctx;
+  (void)hipSetDevice(ctx->device);
+  std::unique_lock<std::mutex> lk(S->mu);
+  for (;;) {
+    bool progressed = false;
+    // completions
+    for (Slot& s : S->slots) {
+      if (!s.busy) continue;
+      hipError_t q = hipEventQuery(s.done);
+      if (q == hipErrorNotReady) continue;
+      const cm_status st = q == hipSuccess ? CM_OK : CM_E_HIP;
+      lk.unlock();
+      if (st == CM_OK) scatter(s);
+      const double t_done = now_s();
+      lk.lock();
+      for (Req* r : s.reqs) {
+        S->finished[r->id] = st;
+        S->live.erase(r->id);
+        S->n_completed++;
+        S->n_queries += int64_t(r->q.size());
+        if (S->latencies.size() < (size_t(1) << 24)) S->latencies.push_back(t_done - r->t_submit);
+        delete r;
+      }
+      s.reqs.clear();
+      S->inflight -= s.bytes;
+      s.bytes = 0;
+      s.busy = false;
+      progressed = true;
+      S->done_cv.notify_all();
+    }
+    // admission into free slots
+    for (Slot& s : S->slots) {
+      if (s.busy || S->pending.empty()) continue;
+      size_t bytes = 0;
+      int64_t nq = 0;
+      while (!S->pending.empty()) {
+        Req* r = S->pending.front();
+        const bool fits = S->inflight + bytes + r->bytes <= ctx->budget;
+        if (!s.reqs.empty() && (!fits || nq + int64_t(r->q.size()) > kMaxBatchQueries)) break;
+        if (s.reqs.empty() && !fits && S->inflight > 0) break;  // wait for memory to free up
+        S->pending.pop_front();
+        s.reqs.push_back(r);
+        bytes += r->bytes;
+        nq += int64_t(r->q.size());
+      }
+      if (s.reqs.empty()) continue;
+      s.busy = true;
+      s.bytes = bytes;
+      S->inflight += bytes;
+      S->peak_inflight = std::max(S->peak_inflight, S->inflight);
+      S->n_batches++;
+      lk.unlock();
+      const cm_status st = launch_batch(ctx, s);
+      lk.lock();
+      if (st != CM_OK) {
+        for (Req* r : s.reqs) {
+          S->finished[r->id] = st;
+          S->live.erase(r->id);
+          S->n_completed++;
+          delete r;
+        }
+        s.reqs.clear();
+        S->inflight -= s.bytes;
+        s.bytes = 0;
+        s.busy = false;
+        S->done_cv.notify_all();
+      }
+      progressed = true;
+    }
+    bool any_busy = false;
+    for (Slot& s : S->slots) any_busy = any_busy || s.busy;
+    if (S->stop && !any_busy) break;
+    if (!progressed) {
+      if (any_busy) S->cv.wait_for(lk, std::chrono::microseconds(50));
+      else if (S->pending.empty()) S->cv.wait_for(lk, std::chrono::milliseconds(50));
+    }
+  }
+}
+
+Serving* start(cm_context* ctx) {
+  auto* S = new Serving;
+  S->ctx = ctx;
+  for (Slot& s : S->slots) {
+    if (hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess) {
+      delete S;
+      return nullptr;
+    }
+  }
+  S->th = std::thread(scheduler, S);
+  return S;
+}
+
+}  // namespace
+
+void serving_stop(cm_context* ctx) {
+  Serving* S = ctx->serving;
+  if (!S) return;
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->stop = true;
+    // requests not yet admitted fail
+    for (Req* r : S->pending) {
+      S->finished[r->id] = CM_E_BUSY;
+      S->live.erase(r->id);
+      delete r;
+    }
+    S->pending.clear();
+  }
+  S->cv.notify_all();
+  S->th.join();
+  for (Slot& s : S->slots) {
+    if (s.dmem) (void)hipFree(s.dmem);
+    if (s.pinned) (void)hipHostFree(s.pinned);
+    if (s.done) (void)hipEventDestroy(s.done);
+    if (s.stream) (void)hipStreamDestroy(s.stream);
+  }
+  delete S;
+  ctx->serving = nullptr;
+}
+
+}  // namespace cm
+
+using namespace cm;
+
+extern "C" {
+
+cm_status cm_submit(cm_context* ctx, const cm_request* req, cm_ticket* ticket) {
+  if (!ctx || !req || !ticket || !req->q || req->n <= 0 || !req->out_groups)
+    return fail(ctx, CM_E_INVALID, "bad request");
+  if (ctx->device < 0) return fail(ctx, CM_E_INVALID, "host-only context cannot serve");
+  if (req->want_grad && (!req->cotangent || !req->out_grad)) return fail(ctx, CM_E_INVALID, "gradient request needs cotangent and out_grad");
+  if (req->want_grad && ctx->prm.st_iters > 4) return fail(ctx, CM_E_INVALID, "the adjoint supports st_iters <= 4");
+  for (int32_t i = 0; i < req->n; ++i) {
+    const cm_query& q = req->q[i];
+    const float na = q.qa[0] * q.qa[0] + q.qa[1] * q.qa[1] + q.qa[2] * q.qa[2] + q.qa[3] * q.qa[3];
+    const float nb = q.qb[0] * q.qb[0] + q.qb[1] * q.qb[1] + q.qb[2] * q.qb[2] + q.qb[3] * q.qb[3];
+    if (!(std::sqrt(na) >= 1e-12f) || !(std::sqrt(nb) >= 1e-12f)) return fail(ctx, CM_E_INVALID, "degenerate quaternion");
+  }
+  auto* r = new Req;
+  r->q.assign(req->q, req->q + req->n);
+  r->grad = req->want_grad != 0;
+  r->out_groups = req->out_groups;
+  r->out_grad = req->out_grad;
+  r->t_submit = now_s();
+  {
+    cm_plan probe;
+    size_t b = 0;
+    cm_status st = plan_host(ctx, r->q.data(), req->n, &probe, &b);
+    if (st != CM_OK) { delete r; return st; }
+    r->G = probe.G;
+    r->bytes = request_bytes(probe, r->grad);
+  }
+  if (r->bytes > ctx->budget) { delete r; return fail(ctx, CM_E_OOM, "request exceeds the memory budget on its own"); }
+  if (r->grad) r->cot.assign(req->cotangent, req->cotangent + 12 * r->G);
+  {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    if (!ctx->serving) {
+      ctx->serving = start(ctx);
+      if (!ctx->serving) { delete r; ctx->err = "serving: stream creation failed"; return CM_E_HIP; }
+    }
+  }
+  Serving* S = ctx->serving;
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (S->pending.size() >= kQueueLimit) { delete r; return CM_E_BUSY; }
+    r->id = S->next++;
+    *ticket = r->id;
+    S->live[r->id] = 1;
+    S->pending.push_back(r);
+    S->n_submitted++;
+  }
+  S->cv.notify_one();
+  return CM_OK;
+}
+
+cm_status cm_poll(cm_context* ctx, cm_ticket t, int32_t* done, cm_status* result) {
+  if (!ctx || !done) return CM_E_INVALID;
+  Serving* S = ctx->serving;
+  if (!S) return fail(ctx, CM_E_NOTFOUND, "unknown ticket");
+  std::lock_guard<std::mutex> lk(S->mu);
+  auto it = S->finished.find(t);
+  if (it != S->finished.end()) {
+    *done = 1;
+    if (result) *result = it->second;
+    S->finished.erase(it);
+    return CM_OK;
+  }
+  if (S->live.count(t)) { *done = 0; return CM_OK; }
+  return CM_E_NOTFOUND;
+}
+
+cm_status cm_wait(cm_context* ctx, cm_ticket t, int32_t timeout_ms, cm_status* result) {
+  if (!ctx) return CM_E_INVALID;
+  Serving* S = ctx->serving;
+  if (!S) return fail(ctx, CM_E_NOTFOUND, "unknown ticket");
+  std::unique_lock<std::mutex> lk(S->mu);
+  const auto deadline = std::chrono::steady_clock::now() + std::chrono::milliseconds(timeout_ms);
+  for (;;) {
+    auto it = S->finished.find(t);
+    if (it != S->finished.end()) {
+      if (result) *result = it->second;
+      S->finished.erase(it);
+      return CM_OK;
+    }
+    if (!S->live.count(t)) return CM_E_NOTFOUND;
+    if (S->done_cv.wait_until(lk, deadline) == std::cv_status::timeout) return CM_E_BUSY;
+  }
+}
+
+cm_status cm_serve_latencies(cm_context* ctx, double* out, int64_t cap, int64_t* n) {
+  if (!ctx || !n) return CM_E_INVALID;
+  *n = 0;
+  Serving* S = ctx->serving;
+  if (!S) return CM_OK;
+  std::lock_guard<std::mutex> lk(S->mu);
+  const int64_t m = std::min<int64_t>(cap, int64_t(S->latencies.size()));
+  if (out) std::copy(S->latencies.begin(), S->latencies.begin() + m, out);
+  S->latencies.erase(S->latencies.begin(), S->latencies.begin() + m);
+  *n = m;
+  return CM_OK;
+}
+
+cm_status cm_serve_stats(cm_context* ctx, int64_t* st) {
+  if (!ctx || !st) return CM_E_INVALID;
+  Serving* S = ctx->serving;
+  for (int i = 0; i < 7; ++i) st[i] = 0;
+  if (!S) return CM_OK;
+  std::lock_guard<std::mutex> lk(S->mu);
+  int64_t busy = 0;
+  for (Slot& s : S->slots) busy += s.busy ? int64_t(s.reqs.size()) : 0;
+  st[0] = S->n_submitted;
+  st[1] = S->n_completed;
+  st[2] = S->n_batches;
+  st[3] = int64_t(S->pending.size());
+  st[4] = busy;
+  st[5] = int64_t(S->peak_inflight);
+  st[6] = S->n_queries;
+  return CM_OK;
+}
+
+}  // extern "C"
