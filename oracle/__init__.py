@@ -42,7 +42,8 @@ class Params(ctypes.Structure):
     _fields_ = [(n, ctypes.c_double) for n in
                 ("tau_cap", "tau_cup", "tau_st", "tau_clip", "tau_blend", "d_max", "eps_t", "eps_n",
                  "grid_margin", "grid_margin_rel")] + \
-               [(n, ctypes.c_int32) for n in ("st_iters", "grid_res", "broad_phase", "edge_bound")]
+               [(n, ctypes.c_int32) for n in ("st_iters", "grid_res", "broad_phase", "edge_bound")] + \
+               [("jitter", ctypes.c_double), ("jitter_seed", ctypes.c_int32), ("pad_", ctypes.c_int32)]
 
 
 def default_params(L_ref: float = 0.1, broad_phase: bool = True, **kw) -> Params:
@@ -236,3 +237,32 @@ def grad_hvp(prm: Params, objs, qa, qb, poses, cot, direction: Optional[np.ndarr
     lib().orc_grad_hvp(ctypes.byref(prm), n, _p(qa_h), _p(qb_h), _p(poses), _p(goff), _p(cot), _p(d),
                        _p(grad), _p(hv), int(threads))
     return (grad, hv) if direction is not None else grad
+
+
+FP32_UNIT_ROUNDOFF = 2.0 ** -24
+
+
+def fp32_spread(prm: Params, objs, qa, qb, poses, cot, direction: Optional[np.ndarray] = None,
+                seeds=(1, 2, 3), threads: int = 0):
+    """Conditioning of each query at FP32 precision (the oracle's probe).
+
+    Re-evaluates the gradient (and H v) with every intermediate that an FP32
+    evaluation rounds perturbed by an independent uniform amount of relative
+    size 2^-24 (lengths relative to the scene scale r_A + r_B), once per seed,
+    and returns the largest per-query change: (dg [n], dh [n] or None), norms
+    over the 12-vector.  A result that moves by dg under this perturbation
+    cannot be held to less than about dg by any FP32 implementation.
+    """
+    base = grad_hvp(prm, objs, qa, qb, poses, cot, direction, threads)
+    g0, h0 = base if direction is not None else (base, None)
+    dg = np.zeros(len(g0))
+    dh = np.zeros(len(g0)) if direction is not None else None
+    for s in seeds:
+        p = Params.from_buffer_copy(prm)
+        p.jitter, p.jitter_seed = FP32_UNIT_ROUNDOFF, int(s)
+        r = grad_hvp(p, objs, qa, qb, poses, cot, direction, threads)
+        g, h = r if direction is not None else (r, None)
+        dg = np.maximum(dg, np.linalg.norm(g - g0, axis=1))
+        if dh is not None:
+            dh = np.maximum(dh, np.linalg.norm(h - h0, axis=1))
+    return dg, dh

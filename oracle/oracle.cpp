@@ -131,7 +131,47 @@ struct Params {
   double tau_cap, tau_cup, tau_st, tau_clip, tau_blend, d_max, eps_t, eps_n;
   double grid_margin, grid_margin_rel;  // grid = vertex AABB grown by margin + margin_rel * radius
   int32_t st_iters, grid_res, broad_phase, edge_bound;  // edge_bound: 0 paper's min form, 1 tight form
+  double jitter;        // FP32 conditioning probe: relative size of the injected perturbations (0: off)
+  int32_t jitter_seed;  // its seed
+  int32_t pad_;
 };
+
+// ------------------------------------------------ FP32 conditioning probe --
+// Not part of the method.  With Params::jitter = 2^-24 it perturbs every
+// intermediate an FP32 evaluation has to round (positions in the SDF frame,
+// plane values, piece and object phi and gradient, trace iterates, the edge
+// point) by an independent uniform amount of that relative size: the value
+// relative to the query's scene scale L_s (lengths) or to 1 (unit vectors),
+// each derivative component relative to its own magnitude.  Comparing the perturbed result with the unperturbed one measures how
+// far rounding alone moves the exact result of this query: its conditioning.
+// Draws are a counter-based hash of (seed, query index, call index).
+struct Probe {
+  double rel = 0, len = 0;
+  uint64_t key = 0, ctr = 0;
+};
+thread_local Probe g_probe;
+inline uint64_t mix64(uint64_t z) {  // SplitMix64 finaliser
+  z += 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+inline double probe_u() {  // uniform in [-1, 1)
+  const uint64_t h = mix64(g_probe.key ^ mix64(g_probe.ctr++));
+  return double(h >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+}
+// Real part: absolute perturbation of size rel * scale; every derivative
+// component: relative to its own magnitude (an FP32 kernel rounds those too).
+inline void perturb(double& x, double scale) { x += probe_u() * g_probe.rel * (scale > 0 ? scale : std::abs(x)); }
+template <class T, int N> inline void perturb(Dual<T, N>& x, double scale) {
+  perturb(x.v, scale);
+  for (int i = 0; i < N; ++i) perturb(x.d[i], 0.0);
+}
+template <class T> inline void probe(T& x, bool length) {
+  if (g_probe.rel == 0) return;
+  perturb(x, length ? g_probe.len : 1.0);
+}
+template <class T> inline void probe3(V3<T>& v, bool length) { probe(v.x, length); probe(v.y, length); probe(v.z, length); }
 
 // --------------------------------------------------------------- geometry --
 struct Piece {
@@ -157,6 +197,26 @@ std::vector<Object*> g_objects;
 
 inline const Object& obj(int h) { return *g_objects.at(size_t(h)); }
 
+// Bounding radius: largest vertex norm in the object frame.
+inline double radius_of(const Object& o) {
+  double r2 = 0;
+  for (const Piece& pc : o.pieces)
+    for (size_t i = 0; i < pc.n_verts(); ++i) {
+      const double* v = &pc.verts[3 * i];
+      r2 = std::max(r2, v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+    }
+  return std::sqrt(r2);
+}
+
+// Arms the conditioning probe for query i (no-op when prm.jitter == 0).
+inline void probe_begin(const Params& prm, int64_t i, const Object& A, const Object& B) {
+  g_probe.rel = prm.jitter;
+  g_probe.len = radius_of(A) + radius_of(B);
+  g_probe.key = mix64(uint64_t(int64_t(prm.jitter_seed)) * 0x100000001B3ull ^ uint64_t(i));
+  g_probe.ctr = 0;
+}
+inline void probe_end() { g_probe.rel = 0; }
+
 // ---------------------------------------------------------------- O2 / O3 --
 // Smooth intersection of the piece's half-spaces, phi_k = LSE_j(n_j.x + h_j) with
 // temperature tau (Sec. II LSE; Sec. III-A.2 smooth intersection; Sec. III-A.3
@@ -174,12 +234,15 @@ void piece_sdf(const Piece& pc, const V3<T>& x, double tau, T& phi, V3<T>& grad)
   for (size_t j = 0; j < P; ++j) {
     const double* p = &pc.planes[4 * j];
     T a = x.x * p[0] + x.y * p[1] + x.z * p[2] + p[3];
+    probe(a, true);
     T w = exp((a - m) / tau);
     s += w;
     G.x += w * p[0]; G.y += w * p[1]; G.z += w * p[2];
   }
   phi = m + tau * log(s);
   grad = G * (1.0 / s);
+  probe(phi, true);
+  probe3(grad, false);
 }
 
 // Smooth union of the object's pieces, phi = -LSE_k(-phi_k) (eq. soft_union).
@@ -202,6 +265,8 @@ void object_sdf(const Object& o, const V3<T>& x, const Params& prm, T& phi, V3<T
   }
   phi = M - prm.tau_cup * log(S);
   grad = G * (1.0 / S);
+  probe(phi, true);
+  probe3(grad, false);
 }
 
 template <class T>
@@ -304,6 +369,8 @@ V3<T> edge_point(const Sdf& sdf, const V3<T>& xI, const V3<T>& xII, const Params
     T pb = sdf(xII - e * beta);
     alpha = alpha + sigmoid(pa * (1.0 / prm.tau_st)) * pa;
     beta = beta + sigmoid(pb * (1.0 / prm.tau_st)) * pb;
+    probe(alpha, true);
+    probe(beta, true);
   }
   T zero(0.0);
   T ac = softclip(alpha, zero, L, prm.tau_clip);
@@ -416,6 +483,7 @@ void direction(const Object& mesh, const Object& sdf, const Pose<T>& PM, const P
     for (size_t i = 0; i < V; ++i) {
       Pw[i] = mul(PM.R, cvt<T>(&pc.verts[3 * i])) + PM.t;  // world position of the vertex
       xs[i] = mulT(PS.R, Pw[i] - PS.t);                       // in the SDF object's frame
+      probe3(xs[i], true);
     }
     // O5: vertex-SDF contacts (Sec. IV-B).
     for (size_t i = 0; i < V; ++i) {
@@ -457,6 +525,7 @@ void direction(const Object& mesh, const Object& sdf, const Pose<T>& PM, const P
         }
       }
       V3<T> pe = edge_point(fn, xs[i0], xs[i1], prm);
+      probe3(pe, true);
       T phi; V3<T> g;
       object_sdf(sdf, pe, prm, phi, g);
       V3<T> Nw = mul(PS.R, normal_of(g, prm));
@@ -651,7 +720,9 @@ void orc_contacts(const Params* prm, int64_t n, const int32_t* qa, const int32_t
     Pose<double> PB{quat_to_R(ps + 7), V3<double>{ps[11], ps[12], ps[13]}};
     std::vector<GroupOut<double>> out;
     std::vector<double> dbg;
+    probe_begin(*prm, i, obj(qa[i]), obj(qb[i]));
     query(obj(qa[i]), obj(qb[i]), PA, PB, *prm, out, contacts ? &dbg : nullptr);
+    probe_end();
     for (size_t g = 0; g < out.size(); ++g) put(out[g], groups + 12 * (group_off[i] + int64_t(g)));
     if (contacts) std::copy(dbg.begin(), dbg.end(), contacts + 14 * contact_off[i]);
   }
@@ -693,7 +764,9 @@ void orc_grad_hvp(const Params* prm, int64_t n, const int32_t* qa, const int32_t
       Pose<HD> PA = perturbed<HD>(RA, ps + 4, xi, xi + 3, true);
       Pose<HD> PB = perturbed<HD>(RB, ps + 11, xi + 6, xi + 9, true);
       std::vector<GroupOut<HD>> out;
+      probe_begin(*prm, i, obj(qa[i]), obj(qb[i]));
       query(obj(qa[i]), obj(qb[i]), PA, PB, *prm, out, nullptr);
+      probe_end();
       HD L(0.0);
       for (size_t g = 0; g < out.size(); ++g)
         for (int k = 0; k < 12; ++k) L += comp(out[g], k) * c[12 * g + k];
@@ -708,7 +781,9 @@ void orc_grad_hvp(const Params* prm, int64_t n, const int32_t* qa, const int32_t
       Pose<D> PA = perturbed<D>(RA, ps + 4, xi, xi + 3, true);
       Pose<D> PB = perturbed<D>(RB, ps + 11, xi + 6, xi + 9, true);
       std::vector<GroupOut<D>> out;
+      probe_begin(*prm, i, obj(qa[i]), obj(qb[i]));
       query(obj(qa[i]), obj(qb[i]), PA, PB, *prm, out, nullptr);
+      probe_end();
       D L(0.0);
       for (size_t g = 0; g < out.size(); ++g)
         for (int k = 0; k < 12; ++k) L += comp(out[g], k) * c[12 * g + k];

@@ -29,7 +29,6 @@ static_assert(sizeof(PieceDesc) == 48, "PieceDesc layout");
 // A resident object (device).  All arrays are SoA in one allocation.
 struct ObjDesc {
   const F4* planes;       // [P] (kappa n, kappa h_local), h_local relative to the piece centre
-  const F4* nn;           // [2P] (nx nx, ny ny, nz nz, nx ny), (nx nz, ny nz, 0, 0): unit normals
   const PieceDesc* pieces;
   const float* vx;        // [V] object frame
   const float* vy;
@@ -42,8 +41,9 @@ struct ObjDesc {
   float ginv[3];          // 1 / voxel size
   float gr;               // voxel circumradius
   int32_t gn;             // voxels per axis
-  int32_t pad;
+  int32_t pad[3];
 };
+static_assert(sizeof(ObjDesc) == 128, "ObjDesc layout");
 
 // Query as laid out in cm_query (64 bytes).
 struct QueryDev {

@@ -169,44 +169,75 @@ CM_DEV df pdot(const F4& q, V3<df> x) {
 //   phi_k = tau_cap LSE_j (n_kj . x + h_kj)          smooth intersection
 //   phi   = -tau_cup LSE_k (-phi_k)                  smooth union
 // Per piece, one pass finds the max plane value (the LSE shift), a second pass
-// accumulates sum exp2, sum exp2 * n and (MODE 2) sum exp2 * n n^T.  Pieces
-// are combined online with a running minimum.  MODE 0: phi; 1: + gradient;
-// 2: + Hessian.
+// accumulates sum exp2 and the weighted normal sums.  Pieces are combined
+// online with a running minimum.  MODE 0: phi; 1: + gradient; 2: + Hessian.
+//
+// The Hessian is (1/tau_cap) sum_k u_k Cov_k(n) - (1/tau_cup) Cov_u(g_k), two
+// weighted covariances.  Expanded as E[n n^T] - g g^T they cancel terms of size
+// 1/tau down to results that can be many times smaller (a point in the face
+// region of a piece), which costs FP32 most of its digits; the same happens to
+// the tangent of the gradient with dual scalars.  Whenever second-order
+// quantities are formed (MODE 2, or dual scalars), the covariances are therefore
+// accumulated without that cancellation: the normals of a piece relative to
+// the normal of its max plane, and the piece gradients with a weighted Welford
+// update of their running mean.
+template <class T> struct IsDual { static constexpr bool value = false; };
+template <> struct IsDual<df> { static constexpr bool value = true; };
+template <class T, class S> CM_DEV Sym<T> operator*(const Sym<T>& a, S s) {
+  return {a.xx * s, a.yy * s, a.zz * s, a.xy * s, a.xz * s, a.yz * s}; }
+template <class T> CM_DEV Sym<T> operator+(const Sym<T>& a, const Sym<T>& b) {
+  return {a.xx + b.xx, a.yy + b.yy, a.zz + b.zz, a.xy + b.xy, a.xz + b.xz, a.yz + b.yz}; }
+template <class T> CM_DEV Sym<T> operator-(const Sym<T>& a, const Sym<T>& b) {
+  return {a.xx - b.xx, a.yy - b.yy, a.zz - b.zz, a.xy - b.xy, a.xz - b.xz, a.yz - b.yz}; }
+template <class T> CM_DEV Sym<T> outer(V3<T> a) {
+  return {a.x * a.x, a.y * a.y, a.z * a.z, a.x * a.y, a.x * a.z, a.y * a.z}; }
+
 template <int NP, int MODE, class T>
 CM_DEV void sdf_eval(const ObjDesc& o, const DevParams& P, const V3<T>* x, SdfRes<T>* r) {
+  constexpr bool PREC = MODE == 2 || (MODE == 1 && IsDual<T>::value);
   float M[NP];
   T S[NP];
-  V3<T> Ug[NP];
-  Sym<T> UN[NP], UGG[NP];
+  V3<T> Ug[NP];           // sum u_k g_k (kappa folded out); PREC: running weighted mean of g_k
+  Sym<T> C[NP], M2[NP];   // MODE 2: sum u_k kappa^2 Cov_k(n), sum u_k (g_k - mean)(g_k - mean)^T
 #pragma unroll
   for (int p = 0; p < NP; ++p) {
     M[p] = __builtin_inff();
     S[p] = cst<T>(0.f);
     if (MODE >= 1) Ug[p] = zero3<T>();
-    if (MODE >= 2) { UN[p] = zsym<T>(); UGG[p] = zsym<T>(); }
+    if (MODE >= 2) { C[p] = zsym<T>(); M2[p] = zsym<T>(); }
   }
   const int K = min(o.n_pieces, kMaxPieces);
   for (int k = 0; k < K; ++k) {
     const PieceDesc pd = ldc(o.pieces + k);
     const int pb = min(max(pd.plane_begin, 0), o.n_planes);
     const F4* pl = o.planes + pb;
-    const F4* nn = o.nn + 2 * pb;
     const int np = min(max(pd.plane_count, 0), o.n_planes - pb);  // never past the object's planes
     V3<T> xl[NP];
     float m[NP];
+    V3<float> ref[NP];  // PREC: kappa n of the max plane
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
       xl[p] = x[p] - V3<float>{pd.cx, pd.cy, pd.cz};
       m[p] = -__builtin_inff();
+      ref[p] = {0.f, 0.f, 0.f};
     }
     // pass 1: shift = max_j a_j (value only; LSE is shift-invariant)
 #pragma unroll 4
     for (int j = 0; j < np; ++j) {
       const F4 q = ldc(pl + j);
 #pragma unroll
-      for (int p = 0; p < NP; ++p) m[p] = fmaxf(m[p], pdot(q, val3(xl[p])));
+      for (int p = 0; p < NP; ++p) {
+        const float a = pdot(q, val3(xl[p]));
+        if (PREC) {
+          const bool up = a > m[p];
+          m[p] = up ? a : m[p];
+          ref[p] = up ? V3<float>{q.x, q.y, q.z} : ref[p];
+        } else {
+          m[p] = fmaxf(m[p], a);
+        }
+      }
     }
-    // pass 2: sums
+    // pass 2: sums (PREC: of kappa (n - n_ref) and its outer products)
     T s[NP];
     V3<T> G[NP];
     Sym<T> N[NP];
@@ -219,20 +250,22 @@ CM_DEV void sdf_eval(const ObjDesc& o, const DevParams& P, const V3<T>* x, SdfRe
 #pragma unroll 4
     for (int j = 0; j < np; ++j) {
       const F4 q = ldc(pl + j);
-      F4 n1, n2;
-      if (MODE >= 2) { n1 = ldc(nn + 2 * j); n2 = ldc(nn + 2 * j + 1); }
 #pragma unroll
       for (int p = 0; p < NP; ++p) {
         const T e = ex2(pdot(q, xl[p]) - m[p]);
         s[p] += e;
         if (MODE >= 1) {
-          G[p].x = fmaT(q.x, e, G[p].x);
-          G[p].y = fmaT(q.y, e, G[p].y);
-          G[p].z = fmaT(q.z, e, G[p].z);
-        }
-        if (MODE >= 2) {
-          N[p].xx = fmaT(n1.x, e, N[p].xx); N[p].yy = fmaT(n1.y, e, N[p].yy); N[p].zz = fmaT(n1.z, e, N[p].zz);
-          N[p].xy = fmaT(n1.w, e, N[p].xy); N[p].xz = fmaT(n2.x, e, N[p].xz); N[p].yz = fmaT(n2.y, e, N[p].yz);
+          const float dx = PREC ? q.x - ref[p].x : q.x;
+          const float dy = PREC ? q.y - ref[p].y : q.y;
+          const float dz = PREC ? q.z - ref[p].z : q.z;
+          G[p].x = fmaT(dx, e, G[p].x);
+          G[p].y = fmaT(dy, e, G[p].y);
+          G[p].z = fmaT(dz, e, G[p].z);
+          if (MODE >= 2) {
+            N[p].xx = fmaT(dx * dx, e, N[p].xx); N[p].yy = fmaT(dy * dy, e, N[p].yy);
+            N[p].zz = fmaT(dz * dz, e, N[p].zz); N[p].xy = fmaT(dx * dy, e, N[p].xy);
+            N[p].xz = fmaT(dx * dz, e, N[p].xz); N[p].yz = fmaT(dy * dz, e, N[p].yz);
+          }
         }
       }
     }
@@ -243,18 +276,22 @@ CM_DEV void sdf_eval(const ObjDesc& o, const DevParams& P, const V3<T>* x, SdfRe
       const float Mn = fminf(M[p], val(phik));
       const float sc = ex2((Mn - M[p]) * P.kcup);  // rescale of the old terms (0 when M = +inf)
       const T u = ex2((cst<T>(Mn) - phik) * P.kcup);
-      S[p] = S[p] * sc + u;
-      if (MODE >= 1) {
-        const T ws = u * P.icap / s[p];  // u_k / s_k, with kappa folded out of G
-        const V3<T> gk = G[p] * (P.icap / s[p]);
-        Ug[p] = Ug[p] * sc + G[p] * ws;
+      if (!PREC) {
+        S[p] = S[p] * sc + u;
+        if (MODE >= 1) Ug[p] = Ug[p] * sc + G[p] * (u * P.icap / s[p]);
+      } else {
+        const T is = cst<T>(1.f) / s[p];
+        const V3<T> dg = G[p] * is;                          // kappa (g_k - n_ref)
+        const V3<T> gk = (dg + ref[p]) * P.icap;             // g_k
+        const bool first = M[p] == __builtin_inff();
+        const T w_old = S[p] * sc;
+        S[p] = w_old + u;
+        const T t = first ? cst<T>(1.f) : u / S[p];
+        const V3<T> dl = gk - Ug[p];
+        Ug[p] = first ? gk : Ug[p] + dl * t;
         if (MODE >= 2) {
-          const T wn = u / s[p];
-          UN[p] = {UN[p].xx * sc + N[p].xx * wn, UN[p].yy * sc + N[p].yy * wn, UN[p].zz * sc + N[p].zz * wn,
-                   UN[p].xy * sc + N[p].xy * wn, UN[p].xz * sc + N[p].xz * wn, UN[p].yz * sc + N[p].yz * wn};
-          UGG[p] = {UGG[p].xx * sc + u * gk.x * gk.x, UGG[p].yy * sc + u * gk.y * gk.y,
-                    UGG[p].zz * sc + u * gk.z * gk.z, UGG[p].xy * sc + u * gk.x * gk.y,
-                    UGG[p].xz * sc + u * gk.x * gk.z, UGG[p].yz * sc + u * gk.y * gk.z};
+          M2[p] = first ? zsym<T>() : M2[p] * sc + outer(dl) * (w_old * t);
+          C[p] = C[p] * sc + (N[p] * is - outer(dg)) * u;
         }
       }
       M[p] = Mn;
@@ -265,17 +302,10 @@ CM_DEV void sdf_eval(const ObjDesc& o, const DevParams& P, const V3<T>* x, SdfRe
     r[p].phi = cst<T>(M[p]) - lg2(S[p]) * P.icup;
     if (MODE >= 1) {
       const T iS = cst<T>(1.f) / S[p];
-      r[p].g = Ug[p] * iS;
+      r[p].g = PREC ? Ug[p] : Ug[p] * iS;
       if (MODE >= 2) {
-        // H = (1/tau_cap) sum u N_k - (1/tau_cap + 1/tau_cup) sum u g_k g_k^T + (1/tau_cup) g g^T
-        const float a = P.kcap * kLn2, c = P.kcup * kLn2, b = a + c;
-        const V3<T> g = r[p].g;
-        r[p].H = {(UN[p].xx * a - UGG[p].xx * b) * iS + g.x * g.x * c,
-                  (UN[p].yy * a - UGG[p].yy * b) * iS + g.y * g.y * c,
-                  (UN[p].zz * a - UGG[p].zz * b) * iS + g.z * g.z * c,
-                  (UN[p].xy * a - UGG[p].xy * b) * iS + g.x * g.y * c,
-                  (UN[p].xz * a - UGG[p].xz * b) * iS + g.x * g.z * c,
-                  (UN[p].yz * a - UGG[p].yz * b) * iS + g.y * g.z * c};
+        // (1/tau_cap) / kappa^2 = ln2 / kappa;  1/tau_cup = ln2 kappa_cup
+        r[p].H = C[p] * (iS * (kLn2 * P.icap)) - M2[p] * (iS * (kLn2 * P.kcup));
       }
     }
   }

@@ -14,7 +14,8 @@ struct OutPtrs {
   float *p, *n, *d, *q, *W, *logZ;
 };
 
-constexpr int kStride = 32;  // floats per tile partial / per-group adjoint record
+constexpr int kStride = 32;   // floats per tile partial
+constexpr int kGStride = 64;  // floats per per-group adjoint record (24 values, dual: 48)
 
 struct FwdArgs {
   const Entry* ents;
@@ -39,7 +40,7 @@ struct FwdArgs {
   int32_t blocks_per_cu;
   // adjoint / HVP
   OutPtrs cot;          // cotangent group records
-  float* gscratch;      // [G][kStride] per-piece adjoint seeds
+  float* gscratch;      // [G][kGStride] per-piece adjoint seeds
   float* bpartials;     // [tiles][kStride] per-tile pose gradients
   const float* dir;     // [n][12] HVP direction (nullable)
   const int64_t* group_off;  // [n + 1]

@@ -185,24 +185,39 @@ CM_DEV void edge_fwd(const ObjDesc& M, const ObjDesc& S, const FrameT<T>& F, int
 
 // ------------------------------------------------------- contact adjoint --
 // Adjoint seeds of one piece's blend for L = <c, y>: u_bar = (c_d, c_p, m_bar,
-// c_q, c_W) pairs with the contact values (d, p_c, n_c, f p, f); B = <u_bar, y>
-// over the un-normalised blend; c_logZ; logZ.
+// c_q, c_W) pairs with the contact values u_i = (d, p_c, n_c, f p, f); the
+// blended values (d, p, m, q, W) of the piece, i.e. sum_i w_i u_i; c_logZ; logZ.
 template <class T> struct GAdj {
   T cd;
   V3<T> cp, mb, cq;
-  T cW, B, clz, logZ;
+  T cW, clz, logZ;
+  T yd;
+  V3<T> yp, ym, yq;
+  T yW;
 };
+template <class T> CM_DEV V3<T> getV3(const float* o, int i) {
+  constexpr int s = nT<T>();
+  return {getT<T>(o + i * s), getT<T>(o + (i + 1) * s), getT<T>(o + (i + 2) * s)};
+}
+template <class T> CM_DEV void putV3(float* o, int i, const V3<T>& v) {
+  constexpr int s = nT<T>();
+  putT(o + i * s, v.x); putT(o + (i + 1) * s, v.y); putT(o + (i + 2) * s, v.z);
+}
 template <class T> CM_DEV GAdj<T> load_gadj(const float* o) {
   constexpr int s = nT<T>();
   GAdj<T> a;
   a.cd = getT<T>(o);
-  a.cp = {getT<T>(o + 1 * s), getT<T>(o + 2 * s), getT<T>(o + 3 * s)};
-  a.mb = {getT<T>(o + 4 * s), getT<T>(o + 5 * s), getT<T>(o + 6 * s)};
-  a.cq = {getT<T>(o + 7 * s), getT<T>(o + 8 * s), getT<T>(o + 9 * s)};
+  a.cp = getV3<T>(o, 1);
+  a.mb = getV3<T>(o, 4);
+  a.cq = getV3<T>(o, 7);
   a.cW = getT<T>(o + 10 * s);
-  a.B = getT<T>(o + 11 * s);
-  a.clz = getT<T>(o + 12 * s);
-  a.logZ = getT<T>(o + 13 * s);
+  a.clz = getT<T>(o + 11 * s);
+  a.logZ = getT<T>(o + 12 * s);
+  a.yd = getT<T>(o + 13 * s);
+  a.yp = getV3<T>(o, 14);
+  a.ym = getV3<T>(o, 17);
+  a.yq = getV3<T>(o, 20);
+  a.yW = getT<T>(o + 23 * s);
   return a;
 }
 
@@ -218,8 +233,12 @@ CM_DEV void blend_moll_adj(const CF<T>& c, const GAdj<T>& a, const DevParams& P,
   const T omf = cst<T>(1.f) - c.f;
   const V3<T> nc = c.N * c.f, pc = c.p * c.f + c.prest * omf, fp = c.p * c.f;
   const T w = expT(c.d * (-P.inv_tau_blend) - a.logZ);
-  const T uu = a.cd * c.d + dot(a.cp, pc) + dot(a.mb, nc) + dot(a.cq, fp) + a.cW * c.f;
-  const T lb = w * (uu - a.B + a.clz);            // d L / d l_i
+  // d L / d l_i = w_i (<u_bar, u_i - y> + c_logZ), with the differences formed
+  // before the products: contacts close to the blend would otherwise cancel
+  // terms of the size of the outputs down to their much smaller difference
+  const T du = a.cd * (c.d - a.yd) + dot(a.cp, pc - a.yp) + dot(a.mb, nc - a.ym) + dot(a.cq, fp - a.yq) +
+               a.cW * (c.f - a.yW);
+  const T lb = w * (du + a.clz);
   const T db = w * a.cd - lb * P.inv_tau_blend;    // d L / d d_c
   const V3<T> pcb = a.cp * w, ncb = a.mb * w, fpb = a.cq * w;
   const T fb = w * a.cW + db * (c.phi - P.d_max) + dot(ncb, c.N) + dot(pcb, c.p - c.prest) + dot(fpb, c.p);
@@ -368,7 +387,7 @@ __global__ __launch_bounds__(256) void k_narrow(NarrowArgs a) {
         for (int r = 0; r < 13; ++r) a.dbg[r * a.C + ci] = rec[r];
       }
     } else {
-      const GAdj<T> ga = load_gadj<T>(a.gscratch + int64_t(E.group) * kStride);
+      const GAdj<T> ga = load_gadj<T>(a.gscratch + int64_t(E.group) * kGStride);
       PoseGrad<T> G{zero3<T>(), zero3<T>(), zero3<T>(), zero3<T>()};
       if (E.kind == 0) vertex_adj(ct, F, ga, P, G);
       else edge_adj(ct, tr, F, ga, P, G);
@@ -489,17 +508,20 @@ __global__ __launch_bounds__(256) void k_finalize(FinArgs a) {
     const float cd = a.cot.d[g], cW = a.cot.W[g], clz = a.cot.logZ[g];
     const V3<T> cnT = lift3<T>(cn);
     const V3<T> mb = (cnT - n * dot(n, cnT)) * (cst<T>(1.f) / sg);
-    const T B = d * cd + dot(lift3<T>(cp), p) + dot(mb, m) + dot(lift3<T>(cq), q) + W * cW;
-    float* o = a.gscratch + g * kStride;
+    float* o = a.gscratch + g * kGStride;
     constexpr int s = nT<T>();
     putT(o, cst<T>(cd));
-    putT(o + 1 * s, cst<T>(cp.x)); putT(o + 2 * s, cst<T>(cp.y)); putT(o + 3 * s, cst<T>(cp.z));
-    putT(o + 4 * s, mb.x); putT(o + 5 * s, mb.y); putT(o + 6 * s, mb.z);
-    putT(o + 7 * s, cst<T>(cq.x)); putT(o + 8 * s, cst<T>(cq.y)); putT(o + 9 * s, cst<T>(cq.z));
+    putV3(o, 1, lift3<T>(cp));
+    putV3(o, 4, mb);
+    putV3(o, 7, lift3<T>(cq));
     putT(o + 10 * s, cst<T>(cW));
-    putT(o + 11 * s, B);
-    putT(o + 12 * s, cst<T>(clz));
-    putT(o + 13 * s, logZ);
+    putT(o + 11 * s, cst<T>(clz));
+    putT(o + 12 * s, logZ);
+    putT(o + 13 * s, d);
+    putV3(o, 14, p);
+    putV3(o, 17, m);
+    putV3(o, 20, q);
+    putT(o + 23 * s, W);
   }
 }
 
@@ -529,7 +551,7 @@ __global__ __launch_bounds__(256) void k_reduce(FinArgs a, const float* __restri
   const DevParams& P = a.P;
   const float* d12 = (nT<T>() == 2) ? a.dir + 12 * qi : nullptr;
   for (int64_t g = group_off[qi]; g < group_off[qi + 1]; ++g) {
-    const GAdj<T> ga = load_gadj<T>(a.gscratch + g * kStride);
+    const GAdj<T> ga = load_gadj<T>(a.gscratch + g * kGStride);
     const I2 ge = a.gent[g];
     for (int k = 0; k < 2; ++k) {
       const int e = k == 0 ? ge.x : ge.y;
@@ -590,7 +612,10 @@ static FinArgs fin_args(const FwdArgs& a, const float* partials, const float* di
   return fa;
 }
 
+// Each launcher reports the launch errors of its own kernels: a stale error
+// left by an unrelated runtime call is cleared first.
 hipError_t launch_forward(const FwdArgs& a, hipStream_t s) {
+  (void)hipGetLastError();
   launch_front(a, s);
   const int grid = a.n_cu * a.blocks_per_cu;
   narrow_launch<float, false>(narrow_args(a, a.partials, nullptr, a.dbg), grid, s, a.ev);
@@ -602,6 +627,7 @@ hipError_t launch_forward(const FwdArgs& a, hipStream_t s) {
 }
 
 template <class T> static hipError_t adjoint_impl(const FwdArgs& a, hipStream_t s) {
+  (void)hipGetLastError();
   launch_front(a, s);
   const int grid = a.n_cu * a.blocks_per_cu;
   const float* dir = a.dir;

@@ -110,7 +110,7 @@ void Arena::release(int chunk_id) {
 // Host packing of one object: device layout and descriptor offsets.
 struct Packed {
   std::vector<char> bytes;
-  size_t off_planes, off_nn, off_pieces, off_vx, off_vy, off_vz, off_edges, off_grid;
+  size_t off_planes, off_pieces, off_vx, off_vy, off_vz, off_edges, off_grid;
   int32_t K, P, V, E;
   float gorg[3], gh[3], ginv[3], gr;
   int32_t gn;
@@ -126,7 +126,6 @@ static void pack_object(const ObjHost& o, const cm_params& prm, Packed* pk) {
   size_t off = 0;
   auto take = [&](size_t b) { size_t r = off; off = align_up(off + b, 256); return r; };
   pk->off_planes = take(16 * size_t(pk->P));
-  pk->off_nn = take(32 * size_t(pk->P));
   pk->off_pieces = take(sizeof(PieceDesc) * size_t(pk->K));
   pk->off_vx = take(4 * size_t(pk->V));
   pk->off_vy = take(4 * size_t(pk->V));
@@ -135,7 +134,6 @@ static void pack_object(const ObjHost& o, const cm_params& prm, Packed* pk) {
   pk->off_grid = take(4 * size_t(gn) * gn * gn);
   pk->bytes.assign(off, 0);
   F4* planes = reinterpret_cast<F4*>(pk->bytes.data() + pk->off_planes);
-  F4* nn = reinterpret_cast<F4*>(pk->bytes.data() + pk->off_nn);
   PieceDesc* pieces = reinterpret_cast<PieceDesc*>(pk->bytes.data() + pk->off_pieces);
   float* vx = reinterpret_cast<float*>(pk->bytes.data() + pk->off_vx);
   float* vy = reinterpret_cast<float*>(pk->bytes.data() + pk->off_vy);
@@ -158,8 +156,6 @@ static void pack_object(const ObjHost& o, const cm_params& prm, Packed* pk) {
       const double* q = &g.planes[4 * j];
       const double hl = q[3] + q[0] * cf[0] + q[1] * cf[1] + q[2] * cf[2];
       planes[pb + int32_t(j)] = F4{float(kap * q[0]), float(kap * q[1]), float(kap * q[2]), float(kap * hl)};
-      nn[2 * (pb + int32_t(j))] = F4{float(q[0] * q[0]), float(q[1] * q[1]), float(q[2] * q[2]), float(q[0] * q[1])};
-      nn[2 * (pb + int32_t(j)) + 1] = F4{float(q[0] * q[2]), float(q[1] * q[2]), 0.f, 0.f};
     }
     for (size_t i = 0; i < g.n_verts(); ++i) {
       vx[vb + int32_t(i)] = float(g.verts[3 * i]);
@@ -192,7 +188,6 @@ static void pack_object(const ObjHost& o, const cm_params& prm, Packed* pk) {
 static ObjDesc make_desc(const Packed& pk, char* base) {
   ObjDesc d{};
   d.planes = reinterpret_cast<const F4*>(base + pk.off_planes);
-  d.nn = reinterpret_cast<const F4*>(base + pk.off_nn);
   d.pieces = reinterpret_cast<const PieceDesc*>(base + pk.off_pieces);
   d.vx = reinterpret_cast<const float*>(base + pk.off_vx);
   d.vy = reinterpret_cast<const float*>(base + pk.off_vy);
@@ -614,7 +609,7 @@ size_t plan_layout(cm_plan* pl, char* b) {
   const size_t o_bsum = take(8 * size_t(pl->nb + 1));
   const size_t o_cnt = take(256);
   const size_t o_part = take(4 * size_t(kStride) * size_t(W));
-  const size_t o_gs = take(4 * size_t(kStride) * size_t(pl->G));
+  const size_t o_gs = take(4 * size_t(kGStride) * size_t(pl->G));
   const size_t o_bp = take(4 * size_t(kStride) * size_t(W));
   const size_t o_goff = take(8 * size_t(pl->n + 1));
   const size_t o_gt = take(4 * 12 * size_t(pl->n));
@@ -699,10 +694,14 @@ cm_status cm_plan_timing(const cm_plan* pl, float* ms) {
   for (int k = 0; k < kTimed; ++k) {
     ms[k] = -1.f;
     if (!pl->ev[0]) continue;
-    if (hipEventSynchronize(pl->ev[2 * k + 1]) != hipSuccess) continue;
     float t = 0.f;
-    if (hipEventElapsedTime(&t, pl->ev[2 * k], pl->ev[2 * k + 1]) == hipSuccess) ms[k] = t;
+    if (hipEventSynchronize(pl->ev[2 * k + 1]) == hipSuccess &&
+        hipEventElapsedTime(&t, pl->ev[2 * k], pl->ev[2 * k + 1]) == hipSuccess)
+      ms[k] = t;
   }
+  // slots the last pass did not record fail their query; that must not be
+  // reported by the next launch
+  (void)hipGetLastError();
   return CM_OK;
 }
 

@@ -19,6 +19,10 @@ written below):
   ``dir = normalize(N(0, I3))``, ``t_B = dist * dir`` with
   ``dist = (r_A + r_B) * U[0.6, 1.05]`` where ``r_X`` is the largest point norm of
   object X in its own frame.
+
+Every coordinate, pose and direction is rounded to the nearest FP32 value after
+it is drawn (rounding draws nothing, so the sequences are unchanged): the FP32
+kernels and the FP64 oracle then see exactly the same inputs.
 """
 from __future__ import annotations
 
@@ -98,6 +102,11 @@ def unit_box(side: float = 1.0) -> RawObject:
                      np.array([0, len(edges)], np.int64), edges)
 
 
+def _f32(x):
+    """Nearest FP32-representable value, kept as float64."""
+    return np.asarray(x, np.float64).astype(np.float32).astype(np.float64)
+
+
 def _unit_gauss(rng, n, d):
     x = rng.standard_normal((n, d))
     return x / np.linalg.norm(x, axis=1, keepdims=True)
@@ -107,7 +116,7 @@ def ellipsoid_points(rng, n, axes, noise=0.0):
     p = np.asarray(axes)[None, :] * _unit_gauss(rng, n, 3)
     if noise > 0:
         p = p * (1.0 + rng.uniform(-noise, noise, size=(n, 1)))
-    return p
+    return _f32(p)
 
 
 def log_uniform_int(rng, lo, hi, size=None):
@@ -124,7 +133,7 @@ def random_poses(rng, radii_a, radii_b, lo=0.6, hi=1.05):
     dist = (np.asarray(radii_a) + np.asarray(radii_b)) * rng.uniform(lo, hi, size=n)
     poses[:, 7:11] = qb
     poses[:, 11:14] = d * dist[:, None]
-    return poses
+    return _f32(poses)
 
 
 def multi_piece_object(rng, n_pieces, counts, axes_lo=0.02, axes_hi=0.2, centre=0.1,
@@ -133,7 +142,7 @@ def multi_piece_object(rng, n_pieces, counts, axes_lo=0.02, axes_hi=0.2, centre=
     for k in range(n_pieces):
         axes = rng.uniform(axes_lo, axes_hi, size=3)
         c = rng.uniform(-centre, centre, size=3)
-        p = ellipsoid_points(rng, int(counts[k]), axes, noise) + c[None, :]
+        p = _f32(ellipsoid_points(rng, int(counts[k]), axes, noise) + c[None, :])
         pts.append(p)
         off.append(off[-1] + len(p))
     return PointObject(np.array(off, np.int64), np.concatenate(pts, 0))
@@ -209,13 +218,13 @@ def config4(seed: int = SEED_BASE + 4, n_envs: int = 65536, library: Optional[in
 def cotangents(seed: int, n_groups: int) -> np.ndarray:
     """Cotangent c ~ N(0, 1) for every group output (12 per group)."""
     rng = np.random.Generator(np.random.PCG64(seed))
-    return rng.standard_normal((n_groups, 12))
+    return _f32(rng.standard_normal((n_groups, 12)))
 
 
 def directions(seed: int, n: int) -> np.ndarray:
     """Unit Gaussian direction in R^12 per pair-query."""
     rng = np.random.Generator(np.random.PCG64(seed + 1))
-    return _unit_gauss(rng, n, 12)
+    return _f32(_unit_gauss(rng, n, 12))
 
 
 @dataclasses.dataclass
