@@ -166,7 +166,7 @@ cm_status cm_plan_stats(const cm_plan* plan, int64_t* stats8);
  * default).  cm_plan_timing (synchronous) returns the last durations in ms:
  * [0] broad phase, [1] forward narrow phase, [2] forward narrow phase with
  * tangents (HVP), [3] adjoint narrow phase, [4] dual adjoint narrow phase
- * (HVP); -1 for a kernel not yet launched with timing on. */
+ * (HVP); -1 for a kernel the plan's last pass did not launch. */
 cm_status cm_plan_set_timing(cm_plan* plan, int32_t enable);
 cm_status cm_plan_timing(const cm_plan* plan, float* ms5);
 

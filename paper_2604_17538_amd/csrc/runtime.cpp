@@ -693,7 +693,7 @@ cm_status cm_plan_timing(const cm_plan* pl, float* ms) {
   if (!pl || !ms) return CM_E_INVALID;
   for (int k = 0; k < kTimed; ++k) {
     ms[k] = -1.f;
-    if (!pl->ev[0]) continue;
+    if (!pl->ev[0] || !(pl->timed_mask & (1u << k))) continue;
     float t = 0.f;
     if (hipEventSynchronize(pl->ev[2 * k + 1]) == hipSuccess &&
         hipEventElapsedTime(&t, pl->ev[2 * k], pl->ev[2 * k + 1]) == hipSuccess)
@@ -780,6 +780,7 @@ cm_status cm_contacts_fwd(cm_context* ctx, cm_plan* pl, const cm_query* q, cm_gr
   if (!ctx || !pl || pl->ctx != ctx || !q) return fail(ctx, CM_E_INVALID, "bad arguments");
   if (!out.p || !out.n || !out.d || !out.q || !out.W || !out.logZ) return fail(ctx, CM_E_INVALID, "null output");
   FwdArgs a = fwd_args(ctx, pl, q, out, dbg);
+  pl->timed_mask = (1u << kTBroad) | (1u << kTNarrowFwd);
   hipError_t e = launch_forward(a, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(ctx, e, "forward launch");
   return CM_OK;
@@ -796,6 +797,7 @@ cm_status cm_contacts_bwd(cm_context* ctx, cm_plan* pl, const cm_query* q, cm_gr
   a.grad = grad;
   a.hv = nullptr;
   a.dir = nullptr;
+  pl->timed_mask = (1u << kTBroad) | (1u << kTNarrowFwd) | (1u << kTNarrowAdj);
   hipError_t e = launch_backward(a, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(ctx, e, "backward launch");
   return CM_OK;
@@ -811,6 +813,7 @@ cm_status cm_hvp(cm_context* ctx, cm_plan* pl, const cm_query* q, cm_groups cot,
   a.grad = grad ? grad : pl->d_gradtmp;
   a.hv = hv;
   a.dir = dir;
+  pl->timed_mask = (1u << kTBroad) | (1u << kTNarrowTan) | (1u << kTNarrowDualAdj);
   hipError_t e = launch_hvp(a, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(ctx, e, "hvp launch");
   return CM_OK;

@@ -99,6 +99,7 @@ struct cm_plan {
   int64_t* d_group_off = nullptr;
   float* d_gradtmp = nullptr;    // [n][12] gradient when the caller passes none
   bool timing = false;
+  uint32_t timed_mask = 0;  // timing slots launched by the last pass
   hipEvent_t ev[2 * cm::kTimed] = {};
 };
 
