@@ -16,6 +16,16 @@ struct OutPtrs {
 
 constexpr int kStride = 32;   // floats per tile partial
 constexpr int kGStride = 64;  // floats per per-group adjoint record (24 values, dual: 48)
+constexpr int kMaxTraceAdj = 4;  // sphere-trace steps supported by the adjoint
+
+// Tape: what the sweep before an adjoint keeps of each contact so that the
+// adjoint needs no pass over the planes.  SoA [value][slot], slot = tile * 64
+// + lane; with duals the tangent plane of value v follows its value plane
+// (rows 2v, 2v + 1).  Values: phi, grad phi (3) and the Hessian (6) at the
+// contact point, then per sphere-trace step phi and grad phi at both iterates.
+constexpr int kTapeFixed = 10;
+constexpr int kTapeStep = 8;
+inline int tape_values(int st_iters) { return kTapeFixed + kTapeStep * st_iters; }
 
 struct FwdArgs {
   const Entry* ents;
@@ -48,6 +58,9 @@ struct FwdArgs {
   float* grad;          // [n][12]
   float* hv;            // [n][12] (nullable)
   hipEvent_t* ev;       // nullable: start/stop events per timed kernel (kTimed pairs)
+  float* tape;          // [2 * tape_nv][tape_tiles * 64] (nullable)
+  int64_t tape_tiles;   // tiles [0, tape_tiles) are taped; the rest is recomputed
+  int32_t tape_nv;
 };
 
 // Kernels timed with events when a plan has timing enabled.
@@ -67,6 +80,10 @@ struct NarrowArgs {
   const float* dir;       // HVP direction (dual passes)
   float* dbg;
   int64_t C;
+  float* tape;            // see FwdArgs
+  int64_t tape_tiles;
+  int32_t tape_nv;
+  int64_t t_begin;        // first tile of this launch (recomputing adjoint)
 };
 
 struct FinArgs {

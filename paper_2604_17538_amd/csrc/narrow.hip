@@ -7,15 +7,16 @@
 //   k_narrow<T, true>       per-contact adjoint -> per-tile pose gradients
 //   k_reduce<T>             fixed-order per-query sum (+ filtered closed forms)
 // The Hessian-vector product is this hand-written adjoint evaluated in dual
-// numbers (forward over reverse).  Forward intermediates are recomputed per
-// tile, not stored.
+// numbers (forward over reverse).  Before an adjoint, the forward sweep keeps
+// what needed passes over the planes (phi, gradient and Hessian at the contact
+// point and at the sphere-trace iterates) on a tape for the tiles the plan's
+// memory holds; the adjoint rebuilds the rest of each contact with a few
+// arithmetic operations.  Tiles past the tape recompute their forward pass.
 #include "devmath.h"
 #include "kernels.h"
 #include "wave.h"
 
 namespace cm {
-
-constexpr int kMaxTraceAdj = 4;  // sphere-trace steps supported by the adjoint
 
 CM_DEV void putT(float* o, float x) { o[0] = x; }
 CM_DEV void putT(float* o, df x) { o[0] = x.v; o[1] = x.t; }
@@ -23,6 +24,27 @@ template <class T> CM_DEV T getT(const float* o);
 template <> CM_DEV float getT<float>(const float* o) { return o[0]; }
 template <> CM_DEV df getT<df>(const float* o) { return df{o[0], o[1]}; }
 template <class T> constexpr int nT() { return int(sizeof(T) / sizeof(float)); }
+
+// Tape access (layout in kernels.h): float values in rows v, duals in rows 2v
+// (value) and 2v + 1 (tangent); `rs` is the row stride (taped slots).
+CM_DEV void tput(float* tp, int64_t rs, int v, int64_t slot, float x) { tp[int64_t(v) * rs + slot] = x; }
+CM_DEV void tput(float* tp, int64_t rs, int v, int64_t slot, df x) {
+  tp[int64_t(2 * v) * rs + slot] = x.v;
+  tp[int64_t(2 * v + 1) * rs + slot] = x.t;
+}
+template <class T> CM_DEV T tget(const float* tp, int64_t rs, int v, int64_t slot);
+template <> CM_DEV float tget<float>(const float* tp, int64_t rs, int v, int64_t slot) {
+  return tp[int64_t(v) * rs + slot];
+}
+template <> CM_DEV df tget<df>(const float* tp, int64_t rs, int v, int64_t slot) {
+  return df{tp[int64_t(2 * v) * rs + slot], tp[int64_t(2 * v + 1) * rs + slot]};
+}
+template <class T> CM_DEV void tput3(float* tp, int64_t rs, int v, int64_t slot, const V3<T>& x) {
+  tput(tp, rs, v, slot, x.x); tput(tp, rs, v + 1, slot, x.y); tput(tp, rs, v + 2, slot, x.z);
+}
+template <class T> CM_DEV V3<T> tget3(const float* tp, int64_t rs, int v, int64_t slot) {
+  return {tget<T>(tp, rs, v, slot), tget<T>(tp, rs, v + 1, slot), tget<T>(tp, rs, v + 2, slot)};
+}
 
 // Stable dual sigmoid: sigma' = sigma (1 - sigma).
 CM_DEV df sigmoidT(df z) {
@@ -105,16 +127,31 @@ template <class T> CM_DEV void finish_contact(CF<T>& c, const FrameT<T>& F, cons
 }
 
 // Vertex-SDF contact (Sec. IV-B): the vertex itself is the contact point.
-template <class T, bool ADJ>
+// HIST: also the Hessian (for the adjoint).
+template <class T, bool HIST>
 CM_DEV void vertex_fwd(const ObjDesc& M, const ObjDesc& S, const FrameT<T>& F, int vi, const DevParams& P,
                        CF<T>& c) {
   const V3<float> v = vert(M, vi);
   V3<T> x = mulMc(F.Rrel, v) + F.trel;
   SdfRes<T> r;
-  sdf_eval<1, ADJ ? 2 : 1, T>(S, P, &x, &r);
+  sdf_eval<1, HIST ? 2 : 1, T>(S, P, &x, &r);
   c.phi = r.phi;
   c.g = r.g;
-  if (ADJ) c.H = r.H;
+  if (HIST) c.H = r.H;
+  c.p = mulMc(F.RM, v) + F.tM;
+  c.prest = c.p;
+  finish_contact(c, F, P);
+}
+
+// The same contact rebuilt from its tape record (phi, gradient, Hessian).
+template <class T>
+CM_DEV void vertex_load(const ObjDesc& M, const FrameT<T>& F, int vi, const DevParams& P, const float* tp,
+                        int64_t rs, int64_t slot, CF<T>& c) {
+  const V3<float> v = vert(M, vi);
+  c.phi = tget<T>(tp, rs, 0, slot);
+  c.g = tget3<T>(tp, rs, 1, slot);
+  c.H = {tget<T>(tp, rs, 4, slot), tget<T>(tp, rs, 5, slot), tget<T>(tp, rs, 6, slot),
+         tget<T>(tp, rs, 7, slot), tget<T>(tp, rs, 8, slot), tget<T>(tp, rs, 9, slot)};
   c.p = mulMc(F.RM, v) + F.tM;
   c.prest = c.p;
   finish_contact(c, F, P);
@@ -129,13 +166,9 @@ template <class T> struct Trace {
   V3<T> ga[kMaxTraceAdj], gb[kMaxTraceAdj];
 };
 
-// Edge-SDF contact (Sec. IV-B.2, Fig. e_s): trace both corners towards each
-// other with the gated step sigma(phi / tau_s) phi, K steps (both ends share
-// each pass over the planes), softclip the arc lengths to [0, L] and take the
-// midpoint of the two points.
-template <class T, bool ADJ>
-CM_DEV void edge_fwd(const ObjDesc& M, const ObjDesc& S, const FrameT<T>& F, int ei, const DevParams& P, CF<T>& c,
-                     Trace<T>& tr) {
+// Edge geometry in the SDF frame: corners, length, direction.
+template <class T>
+CM_DEV void edge_setup(const ObjDesc& M, const FrameT<T>& F, int ei, Trace<T>& tr) {
   const I2 ed = M.edges[ei];
   tr.v0 = vert(M, ed.x);
   tr.v1 = vert(M, ed.y);
@@ -144,17 +177,54 @@ CM_DEV void edge_fwd(const ObjDesc& M, const ObjDesc& S, const FrameT<T>& F, int
   const V3<T> dv = tr.x1 - tr.x0;
   tr.L = sqrtT(dot(dv, dv));
   tr.e = dv * (cst<T>(1.f) / tr.L);
+}
+
+// Softclipped arc lengths and the edge point from the traced ones.
+template <class T>
+CM_DEV void edge_point(Trace<T>& tr, T al, T be, const DevParams& P) {
+  tr.aK = al;
+  tr.bK = be;
+  tr.ac = softclip0T(al, tr.L, P.tau_clip, P.inv_tau_clip);
+  tr.bc = softclip0T(be, tr.L, P.tau_clip, P.inv_tau_clip);
+  tr.pe = (tr.x0 + tr.e * tr.ac + tr.x1 - tr.e * tr.bc) * 0.5f;
+}
+
+template <class T>
+CM_DEV void edge_contact(const ObjDesc& M, const FrameT<T>& F, const DevParams& P, const Trace<T>& tr, CF<T>& c) {
+  c.p = mulM(F.RS, tr.pe) + F.tS;
+  c.prest = mulMc(F.RM, (tr.v0 + tr.v1) * 0.5f) + F.tM;
+  finish_contact(c, F, P);
+}
+
+// Edge-SDF contact (Sec. IV-B.2, Fig. e_s): trace both corners towards each
+// other with the gated step sigma(phi / tau_s) phi, K steps (both ends share
+// each pass over the planes), softclip the arc lengths to [0, L] and take the
+// midpoint of the two points.  HIST: keep the trace and the Hessian; with a
+// tape (tp != nullptr) the trace steps go to the tape as they are computed
+// instead of being kept.
+template <class T, bool HIST>
+CM_DEV void edge_fwd(const ObjDesc& M, const ObjDesc& S, const FrameT<T>& F, int ei, const DevParams& P, CF<T>& c,
+                     Trace<T>& tr, float* tp = nullptr, int64_t rs = 0, int64_t slot = 0) {
+  edge_setup(M, F, ei, tr);
   T al = cst<T>(0.f), be = cst<T>(0.f);
-  if (ADJ) {
+  if (HIST) {
 #pragma unroll
     for (int k = 0; k < kMaxTraceAdj; ++k) {
       if (k < P.st_iters) {
         V3<T> xs[2] = {tr.x0 + tr.e * al, tr.x1 - tr.e * be};
         SdfRes<T> r[2];
         sdf_eval<2, 1, T>(S, P, xs, r);
-        tr.al[k] = al; tr.be[k] = be;
-        tr.pa[k] = r[0].phi; tr.pb[k] = r[1].phi;
-        tr.ga[k] = r[0].g; tr.gb[k] = r[1].g;
+        if (tp != nullptr) {
+          const int v = kTapeFixed + kTapeStep * k;
+          tput(tp, rs, v, slot, r[0].phi);
+          tput(tp, rs, v + 1, slot, r[1].phi);
+          tput3(tp, rs, v + 2, slot, r[0].g);
+          tput3(tp, rs, v + 5, slot, r[1].g);
+        } else {
+          tr.al[k] = al; tr.be[k] = be;
+          tr.pa[k] = r[0].phi; tr.pb[k] = r[1].phi;
+          tr.ga[k] = r[0].g; tr.gb[k] = r[1].g;
+        }
         al = al + sigmoidT(r[0].phi * P.inv_tau_st) * r[0].phi;
         be = be + sigmoidT(r[1].phi * P.inv_tau_st) * r[1].phi;
       }
@@ -168,19 +238,51 @@ CM_DEV void edge_fwd(const ObjDesc& M, const ObjDesc& S, const FrameT<T>& F, int
       be = be + sigmoidT(r[1].phi * P.inv_tau_st) * r[1].phi;
     }
   }
-  tr.aK = al;
-  tr.bK = be;
-  tr.ac = softclip0T(al, tr.L, P.tau_clip, P.inv_tau_clip);
-  tr.bc = softclip0T(be, tr.L, P.tau_clip, P.inv_tau_clip);
-  tr.pe = (tr.x0 + tr.e * tr.ac + tr.x1 - tr.e * tr.bc) * 0.5f;
+  edge_point(tr, al, be, P);
   SdfRes<T> r;
-  sdf_eval<1, ADJ ? 2 : 1, T>(S, P, &tr.pe, &r);
+  sdf_eval<1, HIST ? 2 : 1, T>(S, P, &tr.pe, &r);
   c.phi = r.phi;
   c.g = r.g;
-  if (ADJ) c.H = r.H;
-  c.p = mulM(F.RS, tr.pe) + F.tS;
-  c.prest = mulMc(F.RM, (tr.v0 + tr.v1) * 0.5f) + F.tM;
-  finish_contact(c, F, P);
+  if (HIST) c.H = r.H;
+  edge_contact(M, F, P, tr, c);
+}
+
+// The same contact rebuilt from its tape record: the trace steps replayed from
+// the stored phi values, the rest from the stored phi, gradient and Hessian.
+template <class T>
+CM_DEV void edge_load(const ObjDesc& M, const FrameT<T>& F, int ei, const DevParams& P, const float* tp, int64_t rs,
+                      int64_t slot, CF<T>& c, Trace<T>& tr) {
+  edge_setup(M, F, ei, tr);
+  T al = cst<T>(0.f), be = cst<T>(0.f);
+#pragma unroll
+  for (int k = 0; k < kMaxTraceAdj; ++k) {
+    if (k < P.st_iters) {
+      const int v = kTapeFixed + kTapeStep * k;
+      tr.al[k] = al; tr.be[k] = be;
+      tr.pa[k] = tget<T>(tp, rs, v, slot);
+      tr.pb[k] = tget<T>(tp, rs, v + 1, slot);
+      tr.ga[k] = tget3<T>(tp, rs, v + 2, slot);
+      tr.gb[k] = tget3<T>(tp, rs, v + 5, slot);
+      al = al + sigmoidT(tr.pa[k] * P.inv_tau_st) * tr.pa[k];
+      be = be + sigmoidT(tr.pb[k] * P.inv_tau_st) * tr.pb[k];
+    }
+  }
+  edge_point(tr, al, be, P);
+  c.phi = tget<T>(tp, rs, 0, slot);
+  c.g = tget3<T>(tp, rs, 1, slot);
+  c.H = {tget<T>(tp, rs, 4, slot), tget<T>(tp, rs, 5, slot), tget<T>(tp, rs, 6, slot),
+         tget<T>(tp, rs, 7, slot), tget<T>(tp, rs, 8, slot), tget<T>(tp, rs, 9, slot)};
+  edge_contact(M, F, P, tr, c);
+}
+
+// Writes the contact-point part of a tape record (the trace steps of an edge
+// were written by edge_fwd).
+template <class T>
+CM_DEV void tape_store(const CF<T>& c, float* tp, int64_t rs, int64_t slot) {
+  tput(tp, rs, 0, slot, c.phi);
+  tput3(tp, rs, 1, slot, c.g);
+  tput(tp, rs, 4, slot, c.H.xx); tput(tp, rs, 5, slot, c.H.yy); tput(tp, rs, 6, slot, c.H.zz);
+  tput(tp, rs, 7, slot, c.H.xy); tput(tp, rs, 8, slot, c.H.xz); tput(tp, rs, 9, slot, c.H.yz);
 }
 
 // ------------------------------------------------------- contact adjoint --
@@ -334,17 +436,28 @@ CM_DEV void edge_adj(const CF<T>& c, const Trace<T>& tr, const FrameT<T>& F, con
 }
 
 // ------------------------------------------------------------ narrow kernel --
-template <class T, bool ADJ>
+// One persistent launch; waves pop tiles (one entry's <= 64 surviving
+// contacts) from a counter.
+//   ADJ = false, TAPE = false  forward: tile blend partials
+//   ADJ = false, TAPE = true   forward before an adjoint: partials, and the
+//                              tape records of tiles [0, tape_tiles)
+//   ADJ = true,  TAPE = true   adjoint of tiles [0, tape_tiles) from the tape
+//   ADJ = true,  TAPE = false  adjoint of tiles [t_begin, total), recomputing
+template <class T, bool ADJ, bool TAPE>
 __global__ __launch_bounds__(256) void k_narrow(NarrowArgs a) {
   const int l = lane();
   const int64_t total = a.tile_off[a.n_ent];
+  const int64_t t_end = (ADJ && TAPE) ? min(total, a.tape_tiles) : total;
+  const int64_t t_begin = (ADJ && !TAPE) ? a.t_begin : 0;
+  const int64_t rs = a.tape_tiles * kWave;
   const DevParams& P = a.P;
+  constexpr bool HIST = ADJ || TAPE;  // Hessian and trace history
   // each pop returns a distinct tile, so a wave pops at most total + 1 times
   for (int64_t it = 0; it <= total; ++it) {
     uint32_t t0 = 0;
     if (l == 0) t0 = atomicAdd(a.counter, 1u);
-    const int64_t t = int64_t(uint32_t(uni(int(t0))));
-    if (t >= total) break;
+    const int64_t t = t_begin + int64_t(uint32_t(uni(int(t0))));
+    if (t >= t_end) break;
     const int64_t e = find_entry(a.tile_off, a.n_ent, t);
     const int j = int(t - a.tile_off[e]);
     const Entry E = ldc(a.ents + e);
@@ -360,8 +473,17 @@ __global__ __launch_bounds__(256) void k_narrow(NarrowArgs a) {
     if (!valid) c = c0;
     CF<T> ct;
     Trace<T> tr;
-    if (E.kind == 0) vertex_fwd<T, ADJ>(M, S, F, pd.vert_begin + c, P, ct);
-    else edge_fwd<T, ADJ>(M, S, F, pd.edge_begin + c, P, ct, tr);
+    const int64_t slot = t * kWave + l;
+    if (ADJ && TAPE) {
+      if (E.kind == 0) vertex_load<T>(M, F, pd.vert_begin + c, P, a.tape, rs, slot, ct);
+      else edge_load<T>(M, F, pd.edge_begin + c, P, a.tape, rs, slot, ct, tr);
+    } else {
+      // the store sweep writes the records of taped tiles
+      float* tp = (!ADJ && TAPE && t < a.tape_tiles) ? a.tape : nullptr;
+      if (E.kind == 0) vertex_fwd<T, HIST>(M, S, F, pd.vert_begin + c, P, ct);
+      else edge_fwd<T, HIST>(M, S, F, pd.edge_begin + c, P, ct, tr, tp, rs, slot);
+      if (tp != nullptr) tape_store(ct, tp, rs, slot);
+    }
     float* o = a.partials + t * kStride;
     if (!ADJ) {
       // online softmax over l_i = -d_c,i / tau_b of the tile's contacts
@@ -589,13 +711,16 @@ __global__ __launch_bounds__(256) void k_reduce(FinArgs a, const float* __restri
 // ------------------------------------------------------------- launchers --
 static inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
-template <class T, bool ADJ>
-static void narrow_launch(const NarrowArgs& na, int grid, hipStream_t s, hipEvent_t* ev) {
+// Timing events bracket a group of launches: `first` records the start,
+// `last` the stop.
+template <class T, bool ADJ, bool TAPE>
+static void narrow_launch(const NarrowArgs& na, int grid, hipStream_t s, hipEvent_t* ev, bool first = true,
+                          bool last = true) {
   launch_fill_u32(na.counter, 0u, 1, s);
   const int slot = nT<T>() == 1 ? (ADJ ? kTNarrowAdj : kTNarrowFwd) : (ADJ ? kTNarrowDualAdj : kTNarrowTan);
-  if (ev) (void)hipEventRecord(ev[2 * slot], s);
-  hipLaunchKernelGGL((k_narrow<T, ADJ>), dim3(unsigned(grid)), dim3(256), 0, s, na);
-  if (ev) (void)hipEventRecord(ev[2 * slot + 1], s);
+  if (ev && first) (void)hipEventRecord(ev[2 * slot], s);
+  hipLaunchKernelGGL((k_narrow<T, ADJ, TAPE>), dim3(unsigned(grid)), dim3(256), 0, s, na);
+  if (ev && last) (void)hipEventRecord(ev[2 * slot + 1], s);
 }
 
 static NarrowArgs narrow_args(const FwdArgs& a, float* partials, const float* dir, float* dbg) {
@@ -603,6 +728,7 @@ static NarrowArgs narrow_args(const FwdArgs& a, float* partials, const float* di
   na.ents = a.ents; na.n_ent = a.n_ent; na.tile_off = a.tile_off; na.bits = a.bits; na.Q = a.Q; na.objs = a.objs;
   na.P = a.P; na.counter = a.counter; na.partials = partials; na.gscratch = a.gscratch; na.dir = dir;
   na.dbg = dbg; na.C = a.C;
+  na.tape = a.tape; na.tape_tiles = a.tape_tiles; na.tape_nv = a.tape_nv; na.t_begin = 0;
   return na;
 }
 static FinArgs fin_args(const FwdArgs& a, const float* partials, const float* dir) {
@@ -618,7 +744,7 @@ hipError_t launch_forward(const FwdArgs& a, hipStream_t s) {
   (void)hipGetLastError();
   launch_front(a, s);
   const int grid = a.n_cu * a.blocks_per_cu;
-  narrow_launch<float, false>(narrow_args(a, a.partials, nullptr, a.dbg), grid, s, a.ev);
+  narrow_launch<float, false, false>(narrow_args(a, a.partials, nullptr, a.dbg), grid, s, a.ev);
   hipLaunchKernelGGL((k_finalize<float, 0>), dim3(unsigned(cdiv(a.G, 256))), dim3(256), 0, s,
                      fin_args(a, a.partials, nullptr));
   if (a.dbg != nullptr)
@@ -631,10 +757,15 @@ template <class T> static hipError_t adjoint_impl(const FwdArgs& a, hipStream_t 
   launch_front(a, s);
   const int grid = a.n_cu * a.blocks_per_cu;
   const float* dir = a.dir;
-  narrow_launch<T, false>(narrow_args(a, a.partials, dir, nullptr), grid, s, a.ev);
+  const bool tape = a.tape != nullptr && a.tape_tiles > 0;
+  if (tape) narrow_launch<T, false, true>(narrow_args(a, a.partials, dir, nullptr), grid, s, a.ev);
+  else narrow_launch<T, false, false>(narrow_args(a, a.partials, dir, nullptr), grid, s, a.ev);
   hipLaunchKernelGGL((k_finalize<T, 1>), dim3(unsigned(cdiv(a.G, 256))), dim3(256), 0, s,
                      fin_args(a, a.partials, dir));
-  narrow_launch<T, true>(narrow_args(a, a.bpartials, dir, nullptr), grid, s, a.ev);
+  NarrowArgs nb = narrow_args(a, a.bpartials, dir, nullptr);
+  if (tape) narrow_launch<T, true, true>(nb, grid, s, a.ev, true, false);
+  nb.t_begin = tape ? a.tape_tiles : 0;  // tiles past the tape, if any
+  narrow_launch<T, true, false>(nb, grid, s, a.ev, !tape, true);
   hipLaunchKernelGGL((k_reduce<T>), dim3(unsigned(cdiv(a.n, 256))), dim3(256), 0, s, fin_args(a, a.partials, dir),
                      a.bpartials, a.group_off, a.n, a.grad, a.hv);
   return hipGetLastError();

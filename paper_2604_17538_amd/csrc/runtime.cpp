@@ -613,6 +613,13 @@ size_t plan_layout(cm_plan* pl, char* b) {
   const size_t o_bp = take(4 * size_t(kStride) * size_t(W));
   const size_t o_goff = take(8 * size_t(pl->n + 1));
   const size_t o_gt = take(4 * 12 * size_t(pl->n));
+  // the adjoint tape, for as many tiles as a quarter of the memory budget holds
+  // (dual values); tiles past it are recomputed by the adjoint
+  const int st = pl->ctx->prm.st_iters;
+  const int64_t tape_slot_bytes = int64_t(2 * 4 * tape_values(st));
+  const int64_t budget_tiles = int64_t(pl->ctx->budget / 4) / (tape_slot_bytes * kWave);
+  pl->tape_tiles = (st <= kMaxTraceAdj) ? std::min<int64_t>(W, budget_tiles) : 0;
+  const size_t o_tape = take(size_t(tape_slot_bytes) * kWave * size_t(pl->tape_tiles));
   if (b) {
     pl->d_ents = reinterpret_cast<Entry*>(b + o_ents);
     pl->d_gent = reinterpret_cast<I2*>(b + o_gent);
@@ -628,6 +635,7 @@ size_t plan_layout(cm_plan* pl, char* b) {
     pl->d_bpartials = reinterpret_cast<float*>(b + o_bp);
     pl->d_group_off = reinterpret_cast<int64_t*>(b + o_goff);
     pl->d_gradtmp = reinterpret_cast<float*>(b + o_gt);
+    pl->d_tape = pl->tape_tiles ? reinterpret_cast<float*>(b + o_tape) : nullptr;
   }
   return off;
 }
@@ -770,6 +778,9 @@ FwdArgs fwd_args(cm_context* ctx, cm_plan* pl, const cm_query* q, const cm_group
   a.group_off = pl->d_group_off;
   a.n = pl->n;
   a.ev = pl->timing ? pl->ev : nullptr;
+  a.tape = pl->d_tape;
+  a.tape_tiles = pl->d_tape ? pl->tape_tiles : 0;
+  a.tape_nv = tape_values(ctx->prm.st_iters);
   return a;
 }
 }  // namespace cm

@@ -98,6 +98,8 @@ struct cm_plan {
   float* d_bpartials = nullptr;  // per-tile adjoint partials
   int64_t* d_group_off = nullptr;
   float* d_gradtmp = nullptr;    // [n][12] gradient when the caller passes none
+  float* d_tape = nullptr;       // adjoint tape (see kernels.h)
+  int64_t tape_tiles = 0;
   bool timing = false;
   uint32_t timed_mask = 0;  // timing slots launched by the last pass
   hipEvent_t ev[2 * cm::kTimed] = {};
