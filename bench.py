@@ -2,12 +2,15 @@
 """Benchmark of the contact-manifold hot path on one MI355X.
 
 A step is one pass of the whole path over the batch: broad phase, vertex-SDF
-and edge-SDF narrow phase, mollification and per-piece blending (forward),
-the adjoint w.r.t. both 6-DoF poses (gradient) and the Hessian-vector product
-along a unit direction, i.e. cm_contacts_fwd + cm_contacts_bwd + cm_hvp on the
-16384-pair workload with log-uniform piece counts [1, 32] and hull sizes
-[8, 512] (synthetic, seeded).  `value` is whole-batch pair-queries per second
-with the inputs resident in device memory.
+and edge-SDF narrow phase, mollification and per-piece blending (the group
+records), the adjoint w.r.t. both 6-DoF poses (gradient) and the
+Hessian-vector product along a unit direction, as one cm_contacts_step call
+(one forward sweep in dual numbers that keeps the adjoint tape, one adjoint)
+on the 16384-pair workload with log-uniform piece counts [1, 32] and hull
+sizes [8, 512] (synthetic, seeded).  `value` is whole-batch pair-queries per
+second with the inputs resident in device memory.  The same outputs from the
+three separate calls (cm_contacts_fwd + cm_contacts_bwd + cm_hvp) and the
+forward + gradient step without H v are timed beside it.
 
 Beside it the JSON line carries:
   roofline      the dominant narrow-phase kernel's algorithmic VALU lane-ops
@@ -31,13 +34,15 @@ sys.path.insert(0, HERE)
 
 PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9  # FP32 VALU lane-ops/s (non-packed issue rate)
 K_TRACE = 3
-# Algorithmic VALU lane-ops per (surviving vertex, opposing plane) and per
-# (surviving edge, opposing plane) for each narrow-phase kernel; see DESIGN.
+# Algorithmic VALU lane-ops per (point, opposing plane) for an SDF evaluation
+# returning the value (7: 3 FMA dot, max, shift, exp, add), + gradient (10:
+# + 3 FMA), + Hessian (16: + 6 FMA); in dual numbers 12, 18 and 30.  A
+# surviving vertex is one evaluation, a surviving edge 2K trace evaluations
+# plus one at the edge point.  Per (vertex, plane) and (edge, plane):
 OPS = {
-    "narrow_fwd": (10, 2 * K_TRACE * 7 + 10),
-    "narrow_tan": (18, 2 * K_TRACE * 12 + 18),
-    "narrow_adj": (16, 2 * K_TRACE * 10 + 16),
-    "narrow_dual_adj": (30, 2 * K_TRACE * 18 + 30),
+    "forward": (10, 2 * K_TRACE * 7 + 10),             # value + gradient at the contact
+    "forward_tape": (16, 2 * K_TRACE * 10 + 16),       # + trace gradients and Hessian (before an adjoint)
+    "forward_tape_dual": (30, 2 * K_TRACE * 18 + 30),  # the same in dual numbers (before H v)
 }
 
 
@@ -123,9 +128,26 @@ def main():
     stream = torch.cuda.current_stream()
 
     def step():
+        plan.step(qd, cot_d, dir_d, out=out, grad=grad, hv=hv, stream=stream)
+
+    def separate():
         plan.forward(qd, out=out, stream=stream)
-        plan.backward(qd, cot_d, grad=grad, stream=stream)
+        plan.backward(qd, cot_d, grad=grad2, stream=stream)
         plan.hvp(qd, cot_d, dir_d, hv=hv, grad=grad2, stream=stream)
+
+    def fwd_grad():
+        plan.step(qd, cot_d, out=out, grad=grad2, stream=stream)
+
+    def timed(fn, reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        fn()
+        torch.cuda.synchronize()
+        a.record(stream)
+        for _ in range(reps):
+            fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
 
     for _ in range(args.warmup):
         step()
@@ -143,30 +165,27 @@ def main():
     ms = e0.elapsed_time(e1) / args.steps
     log("timed %d steps: %.2f ms/step (wall %.2f s)" % (args.steps, ms, wall))
 
-    # per-pass and per-kernel timing (events on the launch stream), untimed region
+    # the same outputs by the separate calls, and the forward + gradient step
+    sep_ms = timed(separate, 2)
+    fg_ms = timed(fwd_grad, 2)
+    log("separate calls %.2f ms, forward + gradient step %.2f ms" % (sep_ms, fg_ms))
+
+    # per-kernel timing of the step (events on the launch stream), untimed region
     plan.set_timing(True)
-    split = {}
-    for name, fn in (("fwd", lambda: plan.forward(qd, out=out, stream=stream)),
-                     ("bwd", lambda: plan.backward(qd, cot_d, grad=grad, stream=stream)),
-                     ("hvp", lambda: plan.hvp(qd, cot_d, dir_d, hv=hv, grad=grad2, stream=stream))):
-        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        a.record(stream)
-        fn()
-        b.record(stream)
-        torch.cuda.synchronize()
-        split[name + "_ms"] = a.elapsed_time(b)
-        split.update({"%s:%s" % (name, k): v for k, v in plan.timing().items() if v >= 0})
+    step()
+    torch.cuda.synchronize()
+    tk = plan.timing()
     plan.set_timing(False)
+    split = {k: round(v, 3) for k, v in tk.items() if v >= 0}
     st = plan.stats()
-    kern = {k: max(v for kk, v in split.items() if kk.endswith(":" + k)) for k in OPS}
-    dom = max(kern, key=kern.get)
-    ov, oe = OPS[dom]
+    dom_ms = tk["narrow_tan"]  # the dual forward sweep keeping the tape
+    ov, oe = OPS["forward_tape_dual"]
     alg_ops = st["vertex_pairs"] * ov + st["edge_pairs"] * oe
-    achieved = alg_ops / (kern[dom] * 1e-3) / 1e9
-    roofline = {"bound": "alu", "kernel": "k_narrow (%s)" % dom, "achieved": round(achieved, 1),
-                "peak": round(PEAK_LANE_OPS / 1e9, 1), "unit": "Gop/s",
-                "frac": round(achieved * 1e9 / PEAK_LANE_OPS, 4), "traffic": None,
-                "kernel_ms": round(kern[dom], 3), "alg_ops_per_launch": int(alg_ops)}
+    achieved = alg_ops / (dom_ms * 1e-3)
+    roofline = {"bound": "alu", "kernel": "k_narrow<df, forward, tape>", "achieved": round(achieved / 1e12, 3),
+                "peak": round(PEAK_LANE_OPS / 1e12, 3), "unit": "T lane-op/s (FP32 VALU)",
+                "frac": round(achieved / PEAK_LANE_OPS, 4), "traffic": None,
+                "kernel_ms": round(dom_ms, 3), "alg_ops_per_launch": int(alg_ops)}
     log("roofline %s" % roofline)
 
     # plain per-pair launch: same kernels, one pair-query per launch
@@ -186,9 +205,7 @@ def main():
 
         def plain_pass():
             for p1, q1, c1, d1, o1, gr1, gr2, hv1 in plans:
-                p1.forward(q1, out=o1, stream=stream)
-                p1.backward(q1, c1, grad=gr1, stream=stream)
-                p1.hvp(q1, c1, d1, hv=hv1, grad=gr2, stream=stream)
+                p1.step(q1, c1, d1, out=o1, grad=gr1, hv=hv1, stream=stream)
 
         plain_pass()
         torch.cuda.synchronize()
@@ -200,13 +217,15 @@ def main():
         pms = a.elapsed_time(b)
         batched_sample_rate = None
         plain = {"sample": ns, "ms": round(pms, 3), "value": round(ns / (pms * 1e-3), 1), "unit": "pair-queries/s",
-                 "note": "first %d pair-queries, fwd+bwd+hvp one query per launch, same kernels" % ns}
+                 "note": "first %d pair-queries, one cm_contacts_step (records + gradient + H v) per query, same kernels" % ns}
         log("plain launch %s" % plain)
 
-    # parity on sampled outputs against the oracle, plus the CPU baseline timing
+    # parity on sampled outputs of the step against the oracle, plus the CPU baseline timing
     cpu = None
     parity = None
     if not args.no_cpu_baseline:
+        step()
+        torch.cuda.synchronize()
         threads = min(os.cpu_count() or 1, 16)
         res = cpu_baseline(w, args.cpu_sample, threads)
         ns = len(res["sel"])
@@ -241,8 +260,11 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "%s: %d pair-queries, forward + gradient (both poses) + HVP per step" % (args.config, w.n),
-                   "pair_queries": w.n, "groups": plan.G, "contacts": plan.C, "step": "cm_contacts_fwd+cm_contacts_bwd+cm_hvp"},
-        "split_ms": {k: round(v, 3) for k, v in split.items()},
+                   "pair_queries": w.n, "groups": plan.G, "contacts": plan.C, "step": "cm_contacts_step"},
+        "split_ms": split,
+        "separate_calls_ms_per_step": round(sep_ms, 3),
+        "forward_gradient_step_ms": round(fg_ms, 3),
+        "forward_gradient_value": round(w.n / (fg_ms * 1e-3), 1),
         "work": st,
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -220,6 +220,18 @@ cm_status cm_wait(cm_context* ctx, cm_ticket ticket, int32_t timeout_ms, cm_stat
  * requests in completion order since the last call; copies at most cap and
  * removes them from the record; *n = number copied. */
 cm_status cm_serve_latencies(cm_context* ctx, double* out, int64_t cap, int64_t* n);
+/* One pass of the whole path for the plan's batch: the group records (out;
+ * all members null to skip them), the gradient of L = <cot, y> w.r.t. both
+ * poses (grad, [n][12]) and, when dir is given, H dir (hv, [n][12]; dir and
+ * hv both null or both set).  One broad phase, one forward sweep that keeps
+ * the adjoint tape (in dual numbers when dir is given), one adjoint: the work
+ * of cm_contacts_fwd + cm_contacts_bwd (+ cm_hvp) without repeating the
+ * forward.  The records and the gradient equal theirs up to rounding (with
+ * dir they are the value parts of the dual evaluation).  Device pointers,
+ * enqueued on `stream`; CM_E_INVALID as for cm_hvp. */
+cm_status cm_contacts_step(cm_context* ctx, cm_plan* plan, const cm_query* q_dev, cm_groups out, cm_groups cot,
+                           float* grad, const float* dir, float* hv, void* stream);
+
 /* Serving statistics: [0] submitted, [1] completed, [2] batches, [3] queued,
  * [4] in flight, [5] peak in-flight bytes, [6] queries completed. */
 cm_status cm_serve_stats(cm_context* ctx, int64_t* stats7);

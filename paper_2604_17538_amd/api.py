@@ -232,6 +232,25 @@ class Plan:
         self.ctx._check(st, "cm_contacts_bwd")
         return grad
 
+    def step(self, q_dev, cot, direction=None, out=None, grad=None, hv=None, records=True, stream=None):
+        """Records [12, G] (if records), gradient [n, 12] and, with a direction, H v [n, 12]
+        from one forward sweep and one adjoint (cm_contacts_step)."""
+        torch = _torch()
+        if records and out is None:
+            out = torch.empty((12, self.G), dtype=torch.float32, device=q_dev.device)
+        if grad is None:
+            grad = torch.empty((self.n, 12), dtype=torch.float32, device=q_dev.device)
+        if direction is not None and hv is None:
+            hv = torch.empty((self.n, 12), dtype=torch.float32, device=q_dev.device)
+        st = _cm.cm_contacts_step(self.ctx.handle, self._h, ctypes.c_void_p(q_dev.data_ptr()),
+                                  groups_struct(out) if records else _cm.cm_groups(), groups_struct(cot),
+                                  ctypes.c_void_p(grad.data_ptr()),
+                                  ctypes.c_void_p(direction.data_ptr()) if direction is not None else None,
+                                  ctypes.c_void_p(hv.data_ptr()) if direction is not None else None,
+                                  _stream_ptr(stream))
+        self.ctx._check(st, "cm_contacts_step")
+        return (out if records else None), grad, (hv if direction is not None else None)
+
     def hvp(self, q_dev, cot, direction, hv=None, grad=None, stream=None):
         torch = _torch()
         if hv is None:

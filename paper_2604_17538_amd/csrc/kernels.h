@@ -107,7 +107,8 @@ hipError_t launch_grid_build(const ObjDesc* objs, const int32_t* ids, int32_t n_
 void launch_front(const FwdArgs& a, hipStream_t s);
 void launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
 hipError_t launch_forward(const FwdArgs& a, hipStream_t s);
-hipError_t launch_backward(const FwdArgs& a, hipStream_t s);
-hipError_t launch_hvp(const FwdArgs& a, hipStream_t s);
+// records: also write the group records a.out (from the same sweep)
+hipError_t launch_backward(const FwdArgs& a, hipStream_t s, bool records = false);
+hipError_t launch_hvp(const FwdArgs& a, hipStream_t s, bool records = false);
 
 }  // namespace cm

@@ -603,6 +603,7 @@ template <class T> CM_DEV BlendT<T> group_blend(const FinArgs& a, int64_t g) {
 
 // WHAT 0: write the group records.  WHAT 1: write the per-piece adjoint seeds
 // for the cotangent `cot` (n_bar = cot_n, m_bar through the normalisation).
+// WHAT 2: both (the records are the value parts).
 template <class T, int WHAT>
 __global__ __launch_bounds__(256) void k_finalize(FinArgs a) {
   const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -616,14 +617,15 @@ __global__ __launch_bounds__(256) void k_finalize(FinArgs a) {
   const T d = b.d * iz, W = b.f * iz;
   const T logZ = logT(b.Z) + b.L;
   const int64_t G = a.G;
-  if (WHAT == 0) {
+  if (WHAT == 0 || WHAT == 2) {
     a.out.p[g] = val(p.x); a.out.p[G + g] = val(p.y); a.out.p[2 * G + g] = val(p.z);
     a.out.n[g] = val(n.x); a.out.n[G + g] = val(n.y); a.out.n[2 * G + g] = val(n.z);
     a.out.q[g] = val(q.x); a.out.q[G + g] = val(q.y); a.out.q[2 * G + g] = val(q.z);
     a.out.d[g] = val(d);
     a.out.W[g] = val(W);
     a.out.logZ[g] = val(logZ);
-  } else {
+  }
+  if (WHAT >= 1) {
     const V3<float> cp{a.cot.p[g], a.cot.p[G + g], a.cot.p[2 * G + g]};
     const V3<float> cn{a.cot.n[g], a.cot.n[G + g], a.cot.n[2 * G + g]};
     const V3<float> cq{a.cot.q[g], a.cot.q[G + g], a.cot.q[2 * G + g]};
@@ -752,7 +754,10 @@ hipError_t launch_forward(const FwdArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <class T> static hipError_t adjoint_impl(const FwdArgs& a, hipStream_t s) {
+// Forward sweep (taping), per-piece seeds (and, with records, the group
+// records), adjoint from the tape and for tiles past it by recomputation,
+// per-query reduction.  T = df adds the tangents along `dir` (H v).
+template <class T> static hipError_t adjoint_impl(const FwdArgs& a, hipStream_t s, bool records) {
   (void)hipGetLastError();
   launch_front(a, s);
   const int grid = a.n_cu * a.blocks_per_cu;
@@ -760,8 +765,12 @@ template <class T> static hipError_t adjoint_impl(const FwdArgs& a, hipStream_t 
   const bool tape = a.tape != nullptr && a.tape_tiles > 0;
   if (tape) narrow_launch<T, false, true>(narrow_args(a, a.partials, dir, nullptr), grid, s, a.ev);
   else narrow_launch<T, false, false>(narrow_args(a, a.partials, dir, nullptr), grid, s, a.ev);
-  hipLaunchKernelGGL((k_finalize<T, 1>), dim3(unsigned(cdiv(a.G, 256))), dim3(256), 0, s,
-                     fin_args(a, a.partials, dir));
+  if (records)
+    hipLaunchKernelGGL((k_finalize<T, 2>), dim3(unsigned(cdiv(a.G, 256))), dim3(256), 0, s,
+                       fin_args(a, a.partials, dir));
+  else
+    hipLaunchKernelGGL((k_finalize<T, 1>), dim3(unsigned(cdiv(a.G, 256))), dim3(256), 0, s,
+                       fin_args(a, a.partials, dir));
   NarrowArgs nb = narrow_args(a, a.bpartials, dir, nullptr);
   if (tape) narrow_launch<T, true, true>(nb, grid, s, a.ev, true, false);
   nb.t_begin = tape ? a.tape_tiles : 0;  // tiles past the tape, if any
@@ -771,7 +780,7 @@ template <class T> static hipError_t adjoint_impl(const FwdArgs& a, hipStream_t 
   return hipGetLastError();
 }
 
-hipError_t launch_backward(const FwdArgs& a, hipStream_t s) { return adjoint_impl<float>(a, s); }
-hipError_t launch_hvp(const FwdArgs& a, hipStream_t s) { return adjoint_impl<df>(a, s); }
+hipError_t launch_backward(const FwdArgs& a, hipStream_t s, bool records) { return adjoint_impl<float>(a, s, records); }
+hipError_t launch_hvp(const FwdArgs& a, hipStream_t s, bool records) { return adjoint_impl<df>(a, s, records); }
 
 }  // namespace cm

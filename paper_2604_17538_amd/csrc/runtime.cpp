@@ -830,6 +830,30 @@ cm_status cm_hvp(cm_context* ctx, cm_plan* pl, const cm_query* q, cm_groups cot,
   return CM_OK;
 }
 
+cm_status cm_contacts_step(cm_context* ctx, cm_plan* pl, const cm_query* q, cm_groups out, cm_groups cot,
+                           float* grad, const float* dir, float* hv, void* stream) {
+  if (!ctx || !pl || pl->ctx != ctx || !q || !grad || !valid_groups(cot) || (dir != nullptr) != (hv != nullptr))
+    return fail(ctx, CM_E_INVALID, "bad arguments");
+  const bool records = out.p || out.n || out.d || out.q || out.W || out.logZ;
+  if (records && !valid_groups(out)) return fail(ctx, CM_E_INVALID, "partial output records");
+  if (ctx->prm.st_iters > 4) return fail(ctx, CM_E_INVALID, "the adjoint supports st_iters <= 4");
+  FwdArgs a = fwd_args(ctx, pl, q, out, nullptr);
+  a.cot = OutPtrs{cot.p, cot.n, cot.d, cot.q, cot.W, cot.logZ};
+  a.grad = grad;
+  a.hv = hv;
+  a.dir = dir;
+  hipError_t e;
+  if (dir) {
+    pl->timed_mask = (1u << kTBroad) | (1u << kTNarrowTan) | (1u << kTNarrowDualAdj);
+    e = launch_hvp(a, static_cast<hipStream_t>(stream), records);
+  } else {
+    pl->timed_mask = (1u << kTBroad) | (1u << kTNarrowFwd) | (1u << kTNarrowAdj);
+    e = launch_backward(a, static_cast<hipStream_t>(stream), records);
+  }
+  if (e != hipSuccess) return hip_fail(ctx, e, "step launch");
+  return CM_OK;
+}
+
 cm_status cm_shutdown(cm_context* ctx) {
   if (!ctx) return CM_E_INVALID;
   serving_stop(ctx);

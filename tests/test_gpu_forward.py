@@ -69,9 +69,6 @@ def test_broad_phase_masks_bit_exact(c0):
 
 def test_group_records_within_tolerance(c0):
     LsG, _ = _Ls(c0)
-    # m = sum w n_c from the oracle's per-contact records, to find near-zero normals
-    co = c0["c_o"]
-    gid = np.repeat(np.arange(len(c0["g_o"])), 0)  # placeholder to keep shapes explicit
     err = PT.check_groups(c0["g"], c0["g_o"], LsG, c0["prm"].tau_blend)
     for k in ("pos", "logZ", "W", "n"):
         assert err[k] <= 1.0, (k, err)

@@ -32,6 +32,8 @@ import pytest
 import oracle as O
 from paper_2604_17538_amd import workloads as W
 
+from . import parity as PT
+
 pytestmark = pytest.mark.gpu
 
 REL = 1e-4
@@ -73,6 +75,8 @@ def c0g():
     cq = np.sqrt(np.add.reduceat((cot ** 2).sum(1), goff[:-1]))
     floor = 1e-3 * cq * np.maximum(1.0, Ls)
     dg, dh = O.fp32_spread(prm, objs, w.qa, w.qb, w.poses, cot, direc, threads=8)
+    g_rec, _ = O.contacts(prm, objs, w.qa, w.qb, w.poses, threads=8)
+    LsG = np.repeat(Ls, np.diff(goff))
     _step("oracle done; context")
     ctx = api.Context(0, L_ref=w.L_ref)
     hs = ctx.build_objects(w.objects)
@@ -92,7 +96,8 @@ def c0g():
     _step("hvp done")
     return dict(g_o=g_o, hv_o=hv_o, grad=grad.cpu().numpy().astype(np.float64),
                 grad2=grad2.cpu().numpy().astype(np.float64), hv=hv.cpu().numpy().astype(np.float64),
-                plan=plan, qd=qd, cot_d=cot_d, dir_d=dir_d, floor=floor, dg=dg, dh=dh)
+                plan=plan, qd=qd, cot_d=cot_d, dir_d=dir_d, floor=floor, dg=dg, dh=dh,
+                g_rec=g_rec, LsG=LsG, tau_b=prm.tau_blend)
 
 
 def test_gradient_matches_oracle(c0g):
@@ -115,3 +120,31 @@ def test_adjoint_is_deterministic(c0g):
     g = c0g["plan"].backward(c0g["qd"], c0g["cot_d"])
     torch.cuda.synchronize()
     assert np.array_equal(g.cpu().numpy(), c0g["grad"].astype(np.float32))
+
+
+def _check_step(c0g, out, grad, hv):
+    err = PT.check_groups(out.cpu().numpy().T.astype(np.float64), c0g["g_rec"], c0g["LsG"], c0g["tau_b"])
+    for k in ("pos", "logZ", "W", "n"):
+        assert err[k] <= 1.0, (k, err)
+    r = _ratio(grad.cpu().numpy().astype(np.float64), c0g["g_o"], c0g["floor"], c0g["dg"])
+    assert r.max() <= 1.0, ("grad", r.max(), int(np.argmax(r)))
+    if hv is not None:
+        r = _ratio(hv.cpu().numpy().astype(np.float64), c0g["hv_o"], c0g["floor"], c0g["dh"], REL_HVP)
+        assert r.max() <= 1.0, ("hvp", r.max(), int(np.argmax(r)))
+
+
+def test_step_records_gradient_hvp(c0g):
+    """cm_contacts_step with a direction: records, gradient and H v from one dual sweep."""
+    import torch
+    out, grad, hv = c0g["plan"].step(c0g["qd"], c0g["cot_d"], c0g["dir_d"])
+    torch.cuda.synchronize()
+    _check_step(c0g, out, grad, hv)
+
+
+def test_step_records_gradient(c0g):
+    """cm_contacts_step without a direction: records and gradient from one float sweep."""
+    import torch
+    out, grad, hv = c0g["plan"].step(c0g["qd"], c0g["cot_d"])
+    torch.cuda.synchronize()
+    assert hv is None
+    _check_step(c0g, out, grad, None)
