@@ -80,6 +80,9 @@ typedef struct {
   int32_t curve;     /* vertex/edge serialization: 0 none, 1 Morton, 2 Hilbert */
   int32_t broad_phase;  /* 0 off, 1 on */
   int32_t edge_bound;   /* 0: min(lb1, lb2) - l (the paper's); 1: tight form */
+  int32_t prune_pieces; /* 1: skip, per wave, pieces whose union weight is provably
+                           below 2^-28 at all its points (results equal within
+                           FP32 rounding); 0: every piece at every point */
 } cm_params;
 
 /* A pair-query: objects and poses (body -> world). 64 bytes. */

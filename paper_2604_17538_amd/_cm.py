@@ -36,7 +36,7 @@ class cm_params(ctypes.Structure):
     _fields_ = [(n, ctypes.c_float) for n in
                 ("tau_cap", "tau_cup", "tau_st", "tau_clip", "tau_blend", "d_max", "eps_t", "eps_n",
                  "grid_margin", "grid_margin_rel")] + \
-               [(n, ctypes.c_int32) for n in ("st_iters", "grid_res", "curve", "broad_phase", "edge_bound")]
+               [(n, ctypes.c_int32) for n in ("st_iters", "grid_res", "curve", "broad_phase", "edge_bound", "prune_pieces")]
 
 
 class cm_groups(ctypes.Structure):

@@ -10,6 +10,8 @@ struct alignas(8) I2 { int32_t x, y; };
 constexpr int kWave = 64;          // CDNA wavefront width
 constexpr int kPartial = 16;       // floats per tile partial (forward blend state)
 constexpr int kMaxPieces = 4096;   // pieces per object (index fits 16 bits)
+constexpr int kSub = 16;           // support planes per piece (lower bound of its SDF)
+constexpr float kPruneTau = 20.f;  // a piece this many tau_cup above the union's minimum has weight < 2^-28
 
 // Per piece of a resident object (device).  Planes of the piece are stored
 // relative to `centre` and pre-scaled by kappa = log2(e) / tau_cap, so the
@@ -22,7 +24,8 @@ struct PieceDesc {
   int32_t vert_count;
   int32_t edge_begin;     // object-level edge index
   int32_t edge_count;
-  int32_t pad[3];
+  float ub_off;           // tau_cap ln(plane_count) - (distance from the centre to the nearest plane)
+  int32_t pad[2];
 };
 static_assert(sizeof(PieceDesc) == 48, "PieceDesc layout");
 
@@ -41,7 +44,8 @@ struct ObjDesc {
   float ginv[3];          // 1 / voxel size
   float gr;               // voxel circumradius
   int32_t gn;             // voxels per axis
-  int32_t pad[3];
+  int32_t pad;
+  const F4* sub;          // [n_pieces][kSub] support planes (scaled like planes), min(kSub, plane_count) used
 };
 static_assert(sizeof(ObjDesc) == 128, "ObjDesc layout");
 
@@ -86,7 +90,9 @@ struct DevParams {
   int32_t st_iters;
   int32_t broad_phase;
   int32_t edge_bound;
-  int32_t pad;
+  int32_t prune;       // skip pieces that cannot matter (see sdf_eval)
+  float prune_margin;  // kPruneTau * tau_cup
+  int32_t pad[3];
 };
 
 }  // namespace cm

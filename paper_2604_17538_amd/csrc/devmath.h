@@ -172,6 +172,12 @@ CM_DEV df pdot(const F4& q, V3<df> x) {
 // accumulates sum exp2 and the weighted normal sums.  Pieces are combined
 // online with a running minimum.  MODE 0: phi; 1: + gradient; 2: + Hessian.
 //
+// Pieces that cannot matter at any of the wave's points are skipped (when
+// P.prune): a piece's SDF is at least the max over its support subset of
+// planes, and the union's minimum is at most min_k (|x - c_k| + ub_off_k).  A
+// piece whose lower bound exceeds that by prune_margin = 20 tau_cup has union
+// weight below e^-20 < 2^-28 relative to the sum, under FP32 resolution.
+//
 // The Hessian is (1/tau_cap) sum_k u_k Cov_k(n) - (1/tau_cup) Cov_u(g_k), two
 // weighted covariances.  Expanded as E[n n^T] - g g^T they cancel terms of size
 // 1/tau down to results that can be many times smaller (a point in the face
@@ -207,11 +213,26 @@ CM_DEV void sdf_eval(const ObjDesc& o, const DevParams& P, const V3<T>* x, SdfRe
     if (MODE >= 2) { C[p] = zsym<T>(); M2[p] = zsym<T>(); }
   }
   const int K = min(o.n_pieces, kMaxPieces);
+  float mub[NP];  // upper bound of the union's minimum
+#pragma unroll
+  for (int p = 0; p < NP; ++p) mub[p] = __builtin_inff();
+  if (P.prune) {
+    for (int k = 0; k < K; ++k) {
+      const PieceDesc pd = ldc(o.pieces + k);
+#pragma unroll
+      for (int p = 0; p < NP; ++p) {
+        const V3<float> d = val3(x[p]) - V3<float>{pd.cx, pd.cy, pd.cz};
+        mub[p] = fminf(mub[p], sqrtf(dot(d, d)) + pd.ub_off);
+      }
+    }
+  }
   for (int k = 0; k < K; ++k) {
     const PieceDesc pd = ldc(o.pieces + k);
     const int pb = min(max(pd.plane_begin, 0), o.n_planes);
     const F4* pl = o.planes + pb;
     const int np = min(max(pd.plane_count, 0), o.n_planes - pb);  // never past the object's planes
+    const int ns = min(np, kSub);
+    const F4* sp = o.sub + int64_t(kSub) * k;
     V3<T> xl[NP];
     float m[NP];
     V3<float> ref[NP];  // PREC: kappa n of the max plane
@@ -221,19 +242,45 @@ CM_DEV void sdf_eval(const ObjDesc& o, const DevParams& P, const V3<T>* x, SdfRe
       m[p] = -__builtin_inff();
       ref[p] = {0.f, 0.f, 0.f};
     }
-    // pass 1: shift = max_j a_j (value only; LSE is shift-invariant)
-#pragma unroll 4
-    for (int j = 0; j < np; ++j) {
-      const F4 q = ldc(pl + j);
+    // the support subset: a lower bound of the piece SDF, and for a piece of
+    // at most kSub planes (the subset is all of them) already the LSE shift
+    if (P.prune || np <= kSub) {
+      for (int j = 0; j < ns; ++j) {
+        const F4 q = ldc(sp + j);
 #pragma unroll
-      for (int p = 0; p < NP; ++p) {
-        const float a = pdot(q, val3(xl[p]));
-        if (PREC) {
-          const bool up = a > m[p];
-          m[p] = up ? a : m[p];
-          ref[p] = up ? V3<float>{q.x, q.y, q.z} : ref[p];
-        } else {
-          m[p] = fmaxf(m[p], a);
+        for (int p = 0; p < NP; ++p) {
+          const float a = pdot(q, val3(xl[p]));
+          if (PREC) {
+            const bool up = a > m[p];
+            m[p] = up ? a : m[p];
+            ref[p] = up ? V3<float>{q.x, q.y, q.z} : ref[p];
+          } else {
+            m[p] = fmaxf(m[p], a);
+          }
+        }
+      }
+      if (P.prune) {
+        bool need = false;
+#pragma unroll
+        for (int p = 0; p < NP; ++p) need = need || m[p] * P.icap < mub[p] + P.prune_margin;
+        if (!__any(need)) continue;  // no lane of the wave needs this piece
+      }
+    }
+    // pass 1: shift = max_j a_j (value only; LSE is shift-invariant)
+    if (np > kSub) {
+#pragma unroll 4
+      for (int j = 0; j < np; ++j) {
+        const F4 q = ldc(pl + j);
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+          const float a = pdot(q, val3(xl[p]));
+          if (PREC) {
+            const bool up = a > m[p];
+            m[p] = up ? a : m[p];
+            ref[p] = up ? V3<float>{q.x, q.y, q.z} : ref[p];
+          } else {
+            m[p] = fmaxf(m[p], a);
+          }
         }
       }
     }

@@ -41,6 +41,7 @@ bool valid_params(const cm_params& p, std::string* why) {
   if (p.grid_res < 1 || p.grid_res > 128) { *why = "grid_res must be in [1, 128]"; return false; }
   if (p.curve < 0 || p.curve > 2) { *why = "curve must be 0, 1 or 2"; return false; }
   if (!(p.grid_margin >= 0.f) || !(p.grid_margin_rel >= 0.f)) { *why = "grid margins must be >= 0"; return false; }
+  if (p.prune_pieces < 0 || p.prune_pieces > 1) { *why = "prune_pieces must be 0 or 1"; return false; }
   return true;
 }
 
@@ -63,6 +64,8 @@ DevParams make_dev_params(const cm_params& p) {
   d.st_iters = p.st_iters;
   d.broad_phase = p.broad_phase;
   d.edge_bound = p.edge_bound;
+  d.prune = p.prune_pieces;
+  d.prune_margin = kPruneTau * p.tau_cup;
   return d;
 }
 
@@ -110,7 +113,7 @@ void Arena::release(int chunk_id) {
 // Host packing of one object: device layout and descriptor offsets.
 struct Packed {
   std::vector<char> bytes;
-  size_t off_planes, off_pieces, off_vx, off_vy, off_vz, off_edges, off_grid;
+  size_t off_planes, off_sub, off_pieces, off_vx, off_vy, off_vz, off_edges, off_grid;
   int32_t K, P, V, E;
   float gorg[3], gh[3], ginv[3], gr;
   int32_t gn;
@@ -126,6 +129,7 @@ static void pack_object(const ObjHost& o, const cm_params& prm, Packed* pk) {
   size_t off = 0;
   auto take = [&](size_t b) { size_t r = off; off = align_up(off + b, 256); return r; };
   pk->off_planes = take(16 * size_t(pk->P));
+  pk->off_sub = take(16 * size_t(kSub) * size_t(pk->K));
   pk->off_pieces = take(sizeof(PieceDesc) * size_t(pk->K));
   pk->off_vx = take(4 * size_t(pk->V));
   pk->off_vy = take(4 * size_t(pk->V));
@@ -134,6 +138,7 @@ static void pack_object(const ObjHost& o, const cm_params& prm, Packed* pk) {
   pk->off_grid = take(4 * size_t(gn) * gn * gn);
   pk->bytes.assign(off, 0);
   F4* planes = reinterpret_cast<F4*>(pk->bytes.data() + pk->off_planes);
+  F4* sub = reinterpret_cast<F4*>(pk->bytes.data() + pk->off_sub);
   PieceDesc* pieces = reinterpret_cast<PieceDesc*>(pk->bytes.data() + pk->off_pieces);
   float* vx = reinterpret_cast<float*>(pk->bytes.data() + pk->off_vx);
   float* vy = reinterpret_cast<float*>(pk->bytes.data() + pk->off_vy);
@@ -152,10 +157,33 @@ static void pack_object(const ObjHost& o, const cm_params& prm, Packed* pk) {
     d.edge_begin = eb; d.edge_count = int32_t(g.n_edges());
     // the centre as stored in FP32 is the one the kernels subtract
     const double cf[3] = {double(d.cx), double(d.cy), double(d.cz)};
+    double rin = 1e300;
     for (size_t j = 0; j < g.n_planes(); ++j) {
       const double* q = &g.planes[4 * j];
       const double hl = q[3] + q[0] * cf[0] + q[1] * cf[1] + q[2] * cf[2];
       planes[pb + int32_t(j)] = F4{float(kap * q[0]), float(kap * q[1]), float(kap * q[2]), float(kap * hl)};
+      rin = std::min(rin, -hl);
+    }
+    // upper bound of the piece SDF: phi_k(x) <= |x - c| - rin + tau_cap ln P
+    d.ub_off = float(double(prm.tau_cap) * std::log(double(g.n_planes())) - rin);
+    // support subset: farthest-point sampling of the normals; the max plane
+    // value over any subset is a lower bound of the piece's SDF
+    {
+      const size_t P = g.n_planes();
+      std::vector<double> best(P, -2.0);
+      size_t j = 0;
+      for (int m = 0; m < kSub && m < int(P); ++m) {
+        sub[size_t(kSub) * size_t(k) + size_t(m)] = planes[pb + int32_t(j)];
+        const double* a = &g.planes[4 * j];
+        size_t nxt = 0;
+        double lo = 3.0;
+        for (size_t i = 0; i < P; ++i) {
+          const double* b = &g.planes[4 * i];
+          best[i] = std::max(best[i], a[0] * b[0] + a[1] * b[1] + a[2] * b[2]);
+          if (best[i] < lo) { lo = best[i]; nxt = i; }
+        }
+        j = nxt;
+      }
     }
     for (size_t i = 0; i < g.n_verts(); ++i) {
       vx[vb + int32_t(i)] = float(g.verts[3 * i]);
@@ -188,6 +216,7 @@ static void pack_object(const ObjHost& o, const cm_params& prm, Packed* pk) {
 static ObjDesc make_desc(const Packed& pk, char* base) {
   ObjDesc d{};
   d.planes = reinterpret_cast<const F4*>(base + pk.off_planes);
+  d.sub = reinterpret_cast<const F4*>(base + pk.off_sub);
   d.pieces = reinterpret_cast<const PieceDesc*>(base + pk.off_pieces);
   d.vx = reinterpret_cast<const float*>(base + pk.off_vx);
   d.vy = reinterpret_cast<const float*>(base + pk.off_vy);
@@ -338,6 +367,7 @@ cm_status cm_default_params(float L_ref, cm_params* out) {
   p.curve = 2;
   p.broad_phase = 1;
   p.edge_bound = 0;
+  p.prune_pieces = 1;
   *out = p;
   return CM_OK;
 }

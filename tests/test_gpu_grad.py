@@ -32,7 +32,7 @@ import pytest
 import oracle as O
 from paper_2604_17538_amd import workloads as W
 
-from . import parity as PT
+from tests import parity as PT
 
 pytestmark = pytest.mark.gpu
 
