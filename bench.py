@@ -46,6 +46,42 @@ OPS = {
 }
 
 
+TRAFFIC_PROFILE = os.path.join(HERE, "profiles", "k_narrow_dual_tape_c2_16384pairs_hbm_traffic.txt")
+DOMINANT = "k_narrow<df, false, true>"
+
+
+def kernel_source_hash():
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    src = os.path.join(HERE, "paper_2604_17538_amd", "csrc")
+    for p in sorted(glob.glob(os.path.join(src, "*.hip")) + glob.glob(os.path.join(src, "*.h"))):
+        h.update(os.path.basename(p).encode())
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary (FETCH_SIZE and WRITE_SIZE scaled by a 1 GiB copy), or None when the
+    kernel sources changed since the counters were taken."""
+    try:
+        with open(TRAFFIC_PROFILE) as f:
+            lines = f.read().splitlines()
+    except OSError:
+        return None
+    tag = "kernel sources sha256[:16] (csrc/*.hip, *.h): "
+    h = [l[len(tag):].strip() for l in lines if l.startswith(tag)]
+    if not h or h[0] != kernel_source_hash():
+        return None
+    for l in lines:
+        if l.startswith(DOMINANT):
+            v = l[len(DOMINANT):].split()
+            return (float(v[2]) + float(v[3])) * 1e9
+    return None
+
+
 def log(msg):
     print("[bench %.1fs] %s" % (time.time() - T0, msg), file=sys.stderr, flush=True)
 
@@ -87,6 +123,55 @@ def cpu_baseline(w, sample, threads, want_grad=True):
     return dict(sel=sel, groups=g, goff=goff, grad=grad, hv=hv, cot=cot, dir=d, seconds=dt)
 
 
+def serving_leg(api, W, rates, seconds):
+    """Poisson request streams over a library of 2048 resident objects (pieces
+    as in the differentiation workload): each request U{1..64} pairs, 70 %
+    forward, 30 % forward + gradient, admitted under a 32 GB budget.  Requests
+    are submitted at their arrival times; latency is the library's own record
+    from cm_submit to results written."""
+    lib = W.library_objects(2048)
+    ctx = api.Context(0, L_ref=0.1, budget_bytes=32 << 30)
+    hs = ctx.build_objects(lib)
+    srv = api.Server(ctx)
+    out = []
+    for k, rate in enumerate(rates):
+        tr = W.serving_trace(lib, rate_hz=rate, duration_s=seconds, seed=W.SEED_BASE + 3 + k)
+        rng = np.random.default_rng(11 + k)
+        reqs = []
+        for r in range(len(tr.arrival_s)):
+            a, b = hs[tr.pair_a[r]], hs[tr.pair_b[r]]
+            cot = None
+            if tr.want_grad[r]:
+                G = sum(srv._pieces(int(x)) + srv._pieces(int(y)) for x, y in zip(a, b))
+                cot = rng.standard_normal((G, 12))
+            reqs.append((a, b, tr.poses[r], cot))
+        srv.latencies()  # drop earlier records
+        b0 = srv.stats()["batches"]
+        tickets = []
+        t0 = time.perf_counter()
+        late = 0.0
+        for r, (a, b, ps, cot) in enumerate(reqs):
+            while True:
+                now = time.perf_counter() - t0
+                if now >= tr.arrival_s[r]:
+                    break
+                if tr.arrival_s[r] - now > 2e-4:
+                    time.sleep(1e-4)
+            late = max(late, now - tr.arrival_s[r])
+            tickets.append(srv.submit(a, b, ps, cot))
+        for t in tickets:
+            t.wait(120000)
+        wall = time.perf_counter() - t0
+        lat = srv.latencies() * 1e3
+        pairs = int(sum(len(x[0]) for x in reqs))
+        b1 = srv.stats()["batches"]
+        out.append({"rate_req_s": rate, "requests": len(reqs), "pairs": pairs,
+                    "throughput_req_s": round(len(reqs) / wall, 1), "pair_queries_s": round(pairs / wall, 1),
+                    "p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
+                    "max_submit_lag_ms": round(late * 1e3, 3), "batches": b1 - b0})
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -98,6 +183,11 @@ def main():
     ap.add_argument("--plain-sample", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a device copy of 1 GiB three times (scale of the HBM traffic counters)")
+    ap.add_argument("--serve-rates", default="2000,5000", help="Poisson request rates (req/s) for the serving leg")
+    ap.add_argument("--serve-seconds", type=float, default=2.0)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -107,6 +197,15 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.copy_calibration:
+        x = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": x.numel() * 4, "copy_bytes_written": y.numel() * 4, "dispatches": 3}))
+        return
     from paper_2604_17538_amd import api, workloads as W
 
     w = build_workload(args.config, args.pairs)
@@ -176,6 +275,7 @@ def main():
     torch.cuda.synchronize()
     tk = plan.timing()
     plan.set_timing(False)
+    performed = plan.work()
     split = {k: round(v, 3) for k, v in tk.items() if v >= 0}
     st = plan.stats()
     dom_ms = tk["narrow_tan"]  # the dual forward sweep keeping the tape
@@ -184,8 +284,9 @@ def main():
     achieved = alg_ops / (dom_ms * 1e-3)
     roofline = {"bound": "alu", "kernel": "k_narrow<df, forward, tape>", "achieved": round(achieved / 1e12, 3),
                 "peak": round(PEAK_LANE_OPS / 1e12, 3), "unit": "T lane-op/s (FP32 VALU)",
-                "frac": round(achieved / PEAK_LANE_OPS, 4), "traffic": None,
-                "kernel_ms": round(dom_ms, 3), "alg_ops_per_launch": int(alg_ops)}
+                "frac": round(achieved / PEAK_LANE_OPS, 4), "traffic": measured_traffic(),
+                "kernel_ms": round(dom_ms, 3), "alg_ops_per_launch": int(alg_ops),
+                "algorithmic_point_plane": int(st["pairs"]), "performed_point_plane": int(performed)}
     log("roofline %s" % roofline)
 
     # plain per-pair launch: same kernels, one pair-query per launch
@@ -245,6 +346,11 @@ def main():
                   "max_hvp_rel_err": float(herr.max())}
         log("cpu baseline %s parity %s" % (cpu, parity))
 
+    serving = None
+    if not args.no_serving:
+        serving = serving_leg(api, W, [float(r) for r in args.serve_rates.split(",")], args.serve_seconds)
+        log("serving %s" % serving)
+
     value = w.n / (ms * 1e-3)
     line = {
         "metric": "pair-queries/s fwd+grad at 1e-5 err vs plain launch; p50/p99 request latency",
@@ -270,6 +376,7 @@ def main():
         "cpu_baseline": cpu,
         "plain_launch": plain,
         "parity": parity,
+        "serving": serving,
     }
     if plain:
         line["vs_plain_launch"] = round(value / plain["value"], 2)

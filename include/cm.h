@@ -164,6 +164,12 @@ cm_status cm_plan_offsets(const cm_plan* plan, int64_t* group_off, int64_t* cont
  * [7] surviving-edge x opposing-plane pairs. */
 cm_status cm_plan_stats(const cm_plan* plan, int64_t* stats8);
 
+/* Point-plane evaluations the narrow-phase kernels of the plan's last pass
+ * performed (synchronous), counted per wave lane including lanes of partly
+ * filled tiles and the support-plane bounds, after piece pruning; compare
+ * with the dense count of cm_plan_stats [5] (times the evaluation passes). */
+cm_status cm_plan_work(const cm_plan* plan, int64_t* performed);
+
 /* Kernel timing with HIP events recorded on the launch stream around the
  * broad phase and each narrow-phase kernel of the plan's launches (off by
  * default).  cm_plan_timing (synchronous) returns the last durations in ms:

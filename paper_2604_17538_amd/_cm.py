@@ -82,6 +82,7 @@ cm_plan_destroy = _sig("cm_plan_destroy", I32, [P])
 cm_plan_info = _sig("cm_plan_info", I32, [P, ctypes.POINTER(I64), ctypes.POINTER(I64), ctypes.POINTER(I32)])
 cm_plan_offsets = _sig("cm_plan_offsets", I32, [P, P, P])
 cm_plan_stats = _sig("cm_plan_stats", I32, [P, P])
+cm_plan_work = _sig("cm_plan_work", I32, [P, ctypes.POINTER(I64)])
 cm_plan_set_timing = _sig("cm_plan_set_timing", I32, [P, I32])
 cm_plan_timing = _sig("cm_plan_timing", I32, [P, P])
 cm_contacts_fwd = _sig("cm_contacts_fwd", I32, [P, P, P, cm_groups, P, P])
@@ -96,7 +97,7 @@ cm_serve_latencies = _sig("cm_serve_latencies", I32, [P, P, I64, ctypes.POINTER(
 
 EXPORTED = ["cm_default_params", "cm_init", "cm_shutdown", "cm_last_error", "cm_build_pieces", "cm_build_objects",
             "cm_build_pieces_raw", "cm_release_object", "cm_object_info", "cm_object_export", "cm_object_grid",
-            "cm_plan_create", "cm_plan_destroy", "cm_plan_info", "cm_plan_offsets", "cm_plan_stats",
+            "cm_plan_create", "cm_plan_destroy", "cm_plan_info", "cm_plan_offsets", "cm_plan_stats", "cm_plan_work",
             "cm_plan_set_timing", "cm_plan_timing",
             "cm_contacts_fwd", "cm_contacts_bwd", "cm_hvp", "cm_contacts_step", "cm_submit", "cm_poll", "cm_wait", "cm_serve_stats",
             "cm_serve_latencies"]

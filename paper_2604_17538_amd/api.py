@@ -271,6 +271,12 @@ class Plan:
         return dict(broad=float(ms[0]), narrow_fwd=float(ms[1]), narrow_tan=float(ms[2]),
                     narrow_adj=float(ms[3]), narrow_dual_adj=float(ms[4]))
 
+    def work(self) -> int:
+        """Point-plane evaluations performed by the last pass (cm_plan_work)."""
+        v = ctypes.c_int64()
+        self.ctx._check(_cm.cm_plan_work(self._h, ctypes.byref(v)), "cm_plan_work")
+        return int(v.value)
+
     def stats(self) -> dict:
         s = np.zeros(8, np.int64)
         self.ctx._check(_cm.cm_plan_stats(self._h, _ptr(s)), "cm_plan_stats")
@@ -287,10 +293,17 @@ class Server:
 
     def __init__(self, ctx: Context):
         self.ctx = ctx
+        self._npieces = {}
+
+    def _pieces(self, h: int) -> int:
+        k = self._npieces.get(h)
+        if k is None:
+            k = self._npieces[h] = self.ctx.object_info(h)[0]
+        return k
 
     def submit(self, qa, qb, poses, cotangent=None) -> "Ticket":
         q = make_queries(qa, qb, poses)
-        G = int(sum(self.ctx.object_info(int(a))[0] + self.ctx.object_info(int(b))[0] for a, b in zip(qa, qb)))
+        G = int(sum(self._pieces(int(a)) + self._pieces(int(b)) for a, b in zip(qa, qb)))
         out = np.zeros((G, 12), np.float32)
         grad = np.zeros((len(q), 12), np.float32) if cotangent is not None else None
         cot = np.ascontiguousarray(cotangent, np.float32).reshape(G, 12) if cotangent is not None else None

@@ -199,7 +199,7 @@ template <class T> CM_DEV Sym<T> outer(V3<T> a) {
   return {a.x * a.x, a.y * a.y, a.z * a.z, a.x * a.y, a.x * a.z, a.y * a.z}; }
 
 template <int NP, int MODE, class T>
-CM_DEV void sdf_eval(const ObjDesc& o, const DevParams& P, const V3<T>* x, SdfRes<T>* r) {
+CM_DEV void sdf_eval(const ObjDesc& o, const DevParams& P, const V3<T>* x, SdfRes<T>* r, uint64_t* work = nullptr) {
   constexpr bool PREC = MODE == 2 || (MODE == 1 && IsDual<T>::value);
   float M[NP];
   T S[NP];
@@ -245,6 +245,7 @@ CM_DEV void sdf_eval(const ObjDesc& o, const DevParams& P, const V3<T>* x, SdfRe
     // the support subset: a lower bound of the piece SDF, and for a piece of
     // at most kSub planes (the subset is all of them) already the LSE shift
     if (P.prune || np <= kSub) {
+      if (work && P.prune) *work += uint64_t(ns * NP);  // the bound
       for (int j = 0; j < ns; ++j) {
         const F4 q = ldc(sp + j);
 #pragma unroll
@@ -266,6 +267,8 @@ CM_DEV void sdf_eval(const ObjDesc& o, const DevParams& P, const V3<T>* x, SdfRe
         if (!__any(need)) continue;  // no lane of the wave needs this piece
       }
     }
+    // point-plane evaluations performed by the wave (per lane)
+    if (work) *work += uint64_t(np * NP);
     // pass 1: shift = max_j a_j (value only; LSE is shift-invariant)
     if (np > kSub) {
 #pragma unroll 4

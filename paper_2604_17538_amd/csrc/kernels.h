@@ -58,6 +58,7 @@ struct FwdArgs {
   float* grad;          // [n][12]
   float* hv;            // [n][12] (nullable)
   hipEvent_t* ev;       // nullable: start/stop events per timed kernel (kTimed pairs)
+  unsigned long long* work;  // nullable: see NarrowArgs
   float* tape;          // [2 * tape_nv][tape_tiles * 64] (nullable)
   int64_t tape_tiles;   // tiles [0, tape_tiles) are taped; the rest is recomputed
   int32_t tape_nv;
@@ -84,6 +85,7 @@ struct NarrowArgs {
   int64_t tape_tiles;
   int32_t tape_nv;
   int64_t t_begin;        // first tile of this launch (recomputing adjoint)
+  unsigned long long* work;  // nullable: += point-plane evaluations performed (64 lanes per wave)
 };
 
 struct FinArgs {

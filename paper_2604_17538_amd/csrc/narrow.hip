@@ -130,11 +130,11 @@ template <class T> CM_DEV void finish_contact(CF<T>& c, const FrameT<T>& F, cons
 // HIST: also the Hessian (for the adjoint).
 template <class T, bool HIST>
 CM_DEV void vertex_fwd(const ObjDesc& M, const ObjDesc& S, const FrameT<T>& F, int vi, const DevParams& P,
-                       CF<T>& c) {
+                       CF<T>& c, uint64_t* work) {
   const V3<float> v = vert(M, vi);
   V3<T> x = mulMc(F.Rrel, v) + F.trel;
   SdfRes<T> r;
-  sdf_eval<1, HIST ? 2 : 1, T>(S, P, &x, &r);
+  sdf_eval<1, HIST ? 2 : 1, T>(S, P, &x, &r, work);
   c.phi = r.phi;
   c.g = r.g;
   if (HIST) c.H = r.H;
@@ -204,7 +204,7 @@ CM_DEV void edge_contact(const ObjDesc& M, const FrameT<T>& F, const DevParams& 
 // instead of being kept.
 template <class T, bool HIST>
 CM_DEV void edge_fwd(const ObjDesc& M, const ObjDesc& S, const FrameT<T>& F, int ei, const DevParams& P, CF<T>& c,
-                     Trace<T>& tr, float* tp = nullptr, int64_t rs = 0, int64_t slot = 0) {
+                     Trace<T>& tr, uint64_t* work, float* tp = nullptr, int64_t rs = 0, int64_t slot = 0) {
   edge_setup(M, F, ei, tr);
   T al = cst<T>(0.f), be = cst<T>(0.f);
   if (HIST) {
@@ -213,7 +213,7 @@ CM_DEV void edge_fwd(const ObjDesc& M, const ObjDesc& S, const FrameT<T>& F, int
       if (k < P.st_iters) {
         V3<T> xs[2] = {tr.x0 + tr.e * al, tr.x1 - tr.e * be};
         SdfRes<T> r[2];
-        sdf_eval<2, 1, T>(S, P, xs, r);
+        sdf_eval<2, 1, T>(S, P, xs, r, work);
         if (tp != nullptr) {
           const int v = kTapeFixed + kTapeStep * k;
           tput(tp, rs, v, slot, r[0].phi);
@@ -233,14 +233,14 @@ CM_DEV void edge_fwd(const ObjDesc& M, const ObjDesc& S, const FrameT<T>& F, int
     for (int k = 0; k < P.st_iters; ++k) {
       V3<T> xs[2] = {tr.x0 + tr.e * al, tr.x1 - tr.e * be};
       SdfRes<T> r[2];
-      sdf_eval<2, 0, T>(S, P, xs, r);
+      sdf_eval<2, 0, T>(S, P, xs, r, work);
       al = al + sigmoidT(r[0].phi * P.inv_tau_st) * r[0].phi;
       be = be + sigmoidT(r[1].phi * P.inv_tau_st) * r[1].phi;
     }
   }
   edge_point(tr, al, be, P);
   SdfRes<T> r;
-  sdf_eval<1, HIST ? 2 : 1, T>(S, P, &tr.pe, &r);
+  sdf_eval<1, HIST ? 2 : 1, T>(S, P, &tr.pe, &r, work);
   c.phi = r.phi;
   c.g = r.g;
   if (HIST) c.H = r.H;
@@ -452,6 +452,7 @@ __global__ __launch_bounds__(256) void k_narrow(NarrowArgs a) {
   const int64_t rs = a.tape_tiles * kWave;
   const DevParams& P = a.P;
   constexpr bool HIST = ADJ || TAPE;  // Hessian and trace history
+  uint64_t work = 0;                  // point-plane evaluations per lane (wave-uniform)
   // each pop returns a distinct tile, so a wave pops at most total + 1 times
   for (int64_t it = 0; it <= total; ++it) {
     uint32_t t0 = 0;
@@ -480,8 +481,8 @@ __global__ __launch_bounds__(256) void k_narrow(NarrowArgs a) {
     } else {
       // the store sweep writes the records of taped tiles
       float* tp = (!ADJ && TAPE && t < a.tape_tiles) ? a.tape : nullptr;
-      if (E.kind == 0) vertex_fwd<T, HIST>(M, S, F, pd.vert_begin + c, P, ct);
-      else edge_fwd<T, HIST>(M, S, F, pd.edge_begin + c, P, ct, tr, tp, rs, slot);
+      if (E.kind == 0) vertex_fwd<T, HIST>(M, S, F, pd.vert_begin + c, P, ct, &work);
+      else edge_fwd<T, HIST>(M, S, F, pd.edge_begin + c, P, ct, tr, &work, tp, rs, slot);
       if (tp != nullptr) tape_store(ct, tp, rs, slot);
     }
     float* o = a.partials + t * kStride;
@@ -528,6 +529,7 @@ __global__ __launch_bounds__(256) void k_narrow(NarrowArgs a) {
       }
     }
   }
+  if (a.work != nullptr && l == 0 && work != 0) atomicAdd(a.work, (unsigned long long)(work * kWave));
 }
 
 // ---------------------------------------------------------------- finalize --
@@ -731,6 +733,7 @@ static NarrowArgs narrow_args(const FwdArgs& a, float* partials, const float* di
   na.P = a.P; na.counter = a.counter; na.partials = partials; na.gscratch = a.gscratch; na.dir = dir;
   na.dbg = dbg; na.C = a.C;
   na.tape = a.tape; na.tape_tiles = a.tape_tiles; na.tape_nv = a.tape_nv; na.t_begin = 0;
+  na.work = a.work;
   return na;
 }
 static FinArgs fin_args(const FwdArgs& a, const float* partials, const float* dir) {
@@ -744,6 +747,7 @@ static FinArgs fin_args(const FwdArgs& a, const float* partials, const float* di
 // left by an unrelated runtime call is cleared first.
 hipError_t launch_forward(const FwdArgs& a, hipStream_t s) {
   (void)hipGetLastError();
+  if (a.work) launch_fill_u32(reinterpret_cast<uint32_t*>(a.work), 0u, 2, s);
   launch_front(a, s);
   const int grid = a.n_cu * a.blocks_per_cu;
   narrow_launch<float, false, false>(narrow_args(a, a.partials, nullptr, a.dbg), grid, s, a.ev);
@@ -759,6 +763,7 @@ hipError_t launch_forward(const FwdArgs& a, hipStream_t s) {
 // per-query reduction.  T = df adds the tangents along `dir` (H v).
 template <class T> static hipError_t adjoint_impl(const FwdArgs& a, hipStream_t s, bool records) {
   (void)hipGetLastError();
+  if (a.work) launch_fill_u32(reinterpret_cast<uint32_t*>(a.work), 0u, 2, s);
   launch_front(a, s);
   const int grid = a.n_cu * a.blocks_per_cu;
   const float* dir = a.dir;

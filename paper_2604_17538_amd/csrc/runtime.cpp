@@ -660,6 +660,7 @@ size_t plan_layout(cm_plan* pl, char* b) {
     pl->d_tile_off = reinterpret_cast<int64_t*>(b + o_toff);
     pl->d_bsum = reinterpret_cast<int64_t*>(b + o_bsum);
     pl->d_counter = reinterpret_cast<uint32_t*>(b + o_cnt);
+    pl->d_work = reinterpret_cast<unsigned long long*>(b + o_cnt + 8);
     pl->d_partials = reinterpret_cast<float*>(b + o_part);
     pl->d_gscratch = reinterpret_cast<float*>(b + o_gs);
     pl->d_bpartials = reinterpret_cast<float*>(b + o_bp);
@@ -758,6 +759,15 @@ cm_status cm_plan_offsets(const cm_plan* pl, int64_t* group_off, int64_t* contac
   return CM_OK;
 }
 
+cm_status cm_plan_work(const cm_plan* pl, int64_t* performed) {
+  if (!pl || !performed) return CM_E_INVALID;
+  unsigned long long w = 0;
+  CM_HIP(pl->ctx, hipDeviceSynchronize());
+  CM_HIP(pl->ctx, hipMemcpy(&w, pl->d_work, 8, hipMemcpyDeviceToHost));
+  *performed = int64_t(w);
+  return CM_OK;
+}
+
 cm_status cm_plan_stats(const cm_plan* pl, int64_t* st) {  // 8 entries
   if (!pl || !st) return CM_E_INVALID;
   std::vector<int32_t> ns(size_t(pl->E));
@@ -808,6 +818,7 @@ FwdArgs fwd_args(cm_context* ctx, cm_plan* pl, const cm_query* q, const cm_group
   a.group_off = pl->d_group_off;
   a.n = pl->n;
   a.ev = pl->timing ? pl->ev : nullptr;
+  a.work = pl->d_work;
   a.tape = pl->d_tape;
   a.tape_tiles = pl->d_tape ? pl->tape_tiles : 0;
   a.tape_nv = tape_values(ctx->prm.st_iters);

@@ -99,6 +99,7 @@ struct cm_plan {
   int64_t* d_group_off = nullptr;
   float* d_gradtmp = nullptr;    // [n][12] gradient when the caller passes none
   float* d_tape = nullptr;       // adjoint tape (see kernels.h)
+  unsigned long long* d_work = nullptr;  // point-plane evaluations of the last pass
   int64_t tape_tiles = 0;
   bool timing = false;
   uint32_t timed_mask = 0;  // timing slots launched by the last pass
