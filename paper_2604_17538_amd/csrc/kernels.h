@@ -35,10 +35,18 @@ struct FwdArgs {
   DevParams P;
   uint64_t* bits;
   int32_t* nsurv;
-  int32_t* ntiles;
+  int32_t* wpre;        // [W] survivors of an entry before each of its bitmask words
+  int64_t* surv_off;    // [E + 1]
+  const int64_t* run_off;   // [R + 1] entry ranges of the runs
+  const int32_t* ent_run;   // [E]
+  const int32_t* q_runs;    // [4n] run of (query, 2 dir + kind)
+  int32_t* ntr;         // [R] tiles per run
+  int32_t* npart;       // [E] blend partials per entry
+  int64_t* part_off;    // [E + 1]
+  int64_t n_run;
   F4* filt;
   int64_t* bsum;
-  int64_t* tile_off;
+  int64_t* tile_off;    // [R + 1] tile offsets of the runs
   uint32_t* counter;
   float* partials;
   const I2* gent;       // per group: (vertex entry, edge entry)
@@ -70,7 +78,12 @@ enum { kTBroad = 0, kTNarrowFwd = 1, kTNarrowTan = 2, kTNarrowAdj = 3, kTNarrowD
 struct NarrowArgs {
   const Entry* ents;
   int64_t n_ent;
-  const int64_t* tile_off;
+  const int64_t* tile_off;   // [R + 1]
+  const int64_t* run_off;    // [R + 1]
+  const int64_t* surv_off;   // [E + 1]
+  const int64_t* part_off;   // [E + 1]
+  const int32_t* wpre;       // [W]
+  int64_t n_run;
   const uint64_t* bits;
   const QueryDev* Q;
   const ObjDesc* objs;
@@ -91,7 +104,9 @@ struct NarrowArgs {
 struct FinArgs {
   int64_t G;
   const I2* gent;
-  const int64_t* tile_off;
+  const int64_t* tile_off;   // [R + 1] tiles of the runs
+  const int64_t* part_off;   // [E + 1] blend partials of the entries
+  const int32_t* q_runs;     // [4n]
   const F4* filt;
   const float* partials;
   const Entry* ents;

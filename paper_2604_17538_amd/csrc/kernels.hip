@@ -62,7 +62,7 @@ __global__ __launch_bounds__(256) void k_grid_build(const ObjDesc* __restrict__ 
 __global__ __launch_bounds__(256) void k_broad(const Entry* __restrict__ ents, int64_t n_ent,
                                                const QueryDev* __restrict__ Q, const ObjDesc* __restrict__ objs,
                                                DevParams P, uint64_t* __restrict__ bits, int32_t* __restrict__ nsurv,
-                                               int32_t* __restrict__ ntiles, F4* __restrict__ filt,
+                                               int32_t* __restrict__ wpre, F4* __restrict__ filt,
                                                float* __restrict__ dbg, int64_t C) {
   const int l = lane();
   const int64_t wave = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
@@ -104,7 +104,10 @@ __global__ __launch_bounds__(256) void k_broad(const Entry* __restrict__ ents, i
         prest = mulM(F.RM, (v0 + v1) * 0.5f) + F.tM;
       }
       const uint64_t word = __ballot(valid && surv);
-      if (l == 0) bits[E.word_off + base / kWave] = word;
+      if (l == 0) {
+        bits[E.word_off + base / kWave] = word;
+        wpre[E.word_off + base / kWave] = ns;
+      }
       ns += __popcll(word);
       if (valid && !surv) { fc += 1.f; fp = fp + prest; }
       if (dbg != nullptr && valid && !surv) {
@@ -119,14 +122,13 @@ __global__ __launch_bounds__(256) void k_broad(const Entry* __restrict__ ents, i
     fc = wsum(fc); fp.x = wsum(fp.x); fp.y = wsum(fp.y); fp.z = wsum(fp.z);
     if (l == 0) {
       nsurv[e] = ns;
-      ntiles[e] = (ns + kWave - 1) / kWave;
       filt[e] = F4{fc, fp.x, fp.y, fp.z};
     }
   }
 }
 
 // ------------------------------------------------------------------ scan --
-// Exclusive scan of per-entry tile counts into tile offsets (three passes:
+// Exclusive scans of per-entry and per-run counts into offsets (three passes:
 // per-block sums, a single-block scan of the sums, per-block application).
 constexpr int kScanItems = 4;
 constexpr int kScanBlock = 256 * kScanItems;
@@ -196,6 +198,27 @@ __global__ __launch_bounds__(256) void k_scan_apply(const int32_t* __restrict__ 
   }
 }
 
+// ------------------------------------------------------------- run tiles --
+// A run is the entries of one (query, direction, kind): every piece of the
+// mesh side.  Its survivors, in entry order, fill consecutive tiles of 64.
+__global__ void k_run_tiles(const int64_t* __restrict__ run_off, const int64_t* __restrict__ surv_off, int64_t R,
+                            int32_t* __restrict__ ntr) {
+  const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (r >= R) return;
+  const int64_t n = surv_off[run_off[r + 1]] - surv_off[run_off[r]];
+  ntr[r] = int32_t((n + kWave - 1) / kWave);
+}
+
+// Blend partials of an entry: one per tile its survivors reach.
+__global__ void k_entry_parts(const int64_t* __restrict__ run_off, const int32_t* __restrict__ ent_run,
+                              const int64_t* __restrict__ surv_off, int64_t E, int32_t* __restrict__ npart) {
+  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= E) return;
+  const int64_t rs = surv_off[run_off[ent_run[e]]];
+  const int64_t a = surv_off[e] - rs, b = surv_off[e + 1] - rs;
+  npart[e] = b > a ? int32_t((b - 1) / kWave - a / kWave + 1) : 0;
+}
+
 __global__ void k_fill_u32(uint32_t* p, uint32_t v, int64_t n) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
@@ -216,16 +239,27 @@ void launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL(k_fill_u32, dim3(unsigned(std::max<int64_t>(cdiv(n, 256), 1))), dim3(256), 0, s, p, v, n);
 }
 
+// out[0..n) = exclusive scan of in, out[n] = total.
+static void launch_scan(const int32_t* in, int64_t n, int64_t* out, int64_t* bsum, hipStream_t s) {
+  const int64_t nb = std::max<int64_t>(cdiv(n, kScanBlock), 1);
+  hipLaunchKernelGGL(k_scan_blocks, dim3(unsigned(nb)), dim3(256), 0, s, in, n, bsum);
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(256), 0, s, bsum, nb, out, n);
+  hipLaunchKernelGGL(k_scan_apply, dim3(unsigned(nb)), dim3(256), 0, s, in, n, bsum, out);
+}
+
 void launch_front(const FwdArgs& a, hipStream_t s) {
   const int64_t nb_broad = std::min<int64_t>(cdiv(a.n_ent, 4), int64_t(a.n_cu) * 16);
   if (a.ev) (void)hipEventRecord(a.ev[2 * kTBroad], s);
   hipLaunchKernelGGL(k_broad, dim3(unsigned(std::max<int64_t>(nb_broad, 1))), dim3(256), 0, s, a.ents, a.n_ent, a.Q,
-                     a.objs, a.P, a.bits, a.nsurv, a.ntiles, a.filt, a.dbg, a.C);
+                     a.objs, a.P, a.bits, a.nsurv, a.wpre, a.filt, a.dbg, a.C);
   if (a.ev) (void)hipEventRecord(a.ev[2 * kTBroad + 1], s);
-  const int64_t nb = cdiv(a.n_ent, kScanBlock);
-  hipLaunchKernelGGL(k_scan_blocks, dim3(unsigned(nb)), dim3(256), 0, s, a.ntiles, a.n_ent, a.bsum);
-  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(256), 0, s, a.bsum, nb, a.tile_off, a.n_ent);
-  hipLaunchKernelGGL(k_scan_apply, dim3(unsigned(nb)), dim3(256), 0, s, a.ntiles, a.n_ent, a.bsum, a.tile_off);
+  launch_scan(a.nsurv, a.n_ent, a.surv_off, a.bsum, s);
+  hipLaunchKernelGGL(k_run_tiles, dim3(unsigned(std::max<int64_t>(cdiv(a.n_run, 256), 1))), dim3(256), 0, s, a.run_off,
+                     a.surv_off, a.n_run, a.ntr);
+  launch_scan(a.ntr, a.n_run, a.tile_off, a.bsum, s);
+  hipLaunchKernelGGL(k_entry_parts, dim3(unsigned(std::max<int64_t>(cdiv(a.n_ent, 256), 1))), dim3(256), 0, s,
+                     a.run_off, a.ent_run, a.surv_off, a.n_ent, a.npart);
+  launch_scan(a.npart, a.n_ent, a.part_off, a.bsum, s);
 }
 
 }  // namespace cm

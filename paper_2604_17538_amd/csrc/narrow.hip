@@ -446,7 +446,7 @@ CM_DEV void edge_adj(const CF<T>& c, const Trace<T>& tr, const FrameT<T>& F, con
 template <class T, bool ADJ, bool TAPE>
 __global__ __launch_bounds__(256) void k_narrow(NarrowArgs a) {
   const int l = lane();
-  const int64_t total = a.tile_off[a.n_ent];
+  const int64_t total = a.tile_off[a.n_run];
   const int64_t t_end = (ADJ && TAPE) ? min(total, a.tape_tiles) : total;
   const int64_t t_begin = (ADJ && !TAPE) ? a.t_begin : 0;
   const int64_t rs = a.tape_tiles * kWave;
@@ -459,63 +459,80 @@ __global__ __launch_bounds__(256) void k_narrow(NarrowArgs a) {
     if (l == 0) t0 = atomicAdd(a.counter, 1u);
     const int64_t t = t_begin + int64_t(uint32_t(uni(int(t0))));
     if (t >= t_end) break;
-    const int64_t e = find_entry(a.tile_off, a.n_ent, t);
-    const int j = int(t - a.tile_off[e]);
-    const Entry E = ldc(a.ents + e);
-    const QueryDev q = ldc(a.Q + E.query);
-    const ObjDesc M = ldc(a.objs + E.mesh_obj);
-    const ObjDesc S = ldc(a.objs + E.sdf_obj);
-    const PieceDesc pd = ldc(M.pieces + E.piece);
-    const float* d12 = (nT<T>() == 2) ? a.dir + 12 * int64_t(E.query) : nullptr;
-    const FrameT<T> F = frame_t<T>(q, E.dir, d12);
-    int c = tile_contact(a.bits, E, j);
-    const bool valid = c >= 0;
-    const int c0 = uni(c);  // lane 0 always holds a survivor
-    if (!valid) c = c0;
+    // the tile: 64 consecutive survivors of a run (one query, direction, kind)
+    const int64_t r = last_le(a.tile_off, 0, a.n_run, t);
+    const int64_t j = t - a.tile_off[r];
+    const int64_t eb = a.run_off[r], ee = a.run_off[r + 1];
+    const int64_t sb = a.surv_off[eb];
+    const int64_t rank = j * kWave + l;
+    const bool valid = rank < a.surv_off[ee] - sb;
+    const int64_t rk = valid ? rank : j * kWave;  // lane 0 always holds a survivor
+    // this lane's entry (piece of the mesh side) and survivor within it
+    const int64_t e = last_le(a.surv_off, eb, ee, sb + rk);
+    const Entry E = a.ents[e];
+    const int c = entry_survivor(a.bits, a.wpre, E, int(sb + rk - a.surv_off[e]));
+    const Entry E0 = ldc(a.ents + eb);  // query, direction, kind, objects: uniform over the run
+    const QueryDev q = ldc(a.Q + E0.query);
+    const ObjDesc M = ldc(a.objs + E0.mesh_obj);
+    const ObjDesc S = ldc(a.objs + E0.sdf_obj);
+    const PieceDesc& pd = M.pieces[E.piece];
+    const int ci = E0.kind == 0 ? pd.vert_begin + c : pd.edge_begin + c;
+    const float* d12 = (nT<T>() == 2) ? a.dir + 12 * int64_t(E0.query) : nullptr;
+    const FrameT<T> F = frame_t<T>(q, E0.dir, d12);
     CF<T> ct;
     Trace<T> tr;
     const int64_t slot = t * kWave + l;
     if (ADJ && TAPE) {
-      if (E.kind == 0) vertex_load<T>(M, F, pd.vert_begin + c, P, a.tape, rs, slot, ct);
-      else edge_load<T>(M, F, pd.edge_begin + c, P, a.tape, rs, slot, ct, tr);
+      if (E0.kind == 0) vertex_load<T>(M, F, ci, P, a.tape, rs, slot, ct);
+      else edge_load<T>(M, F, ci, P, a.tape, rs, slot, ct, tr);
     } else {
       // the store sweep writes the records of taped tiles
       float* tp = (!ADJ && TAPE && t < a.tape_tiles) ? a.tape : nullptr;
-      if (E.kind == 0) vertex_fwd<T, HIST>(M, S, F, pd.vert_begin + c, P, ct, &work);
-      else edge_fwd<T, HIST>(M, S, F, pd.edge_begin + c, P, ct, tr, &work, tp, rs, slot);
+      if (E0.kind == 0) vertex_fwd<T, HIST>(M, S, F, ci, P, ct, &work);
+      else edge_fwd<T, HIST>(M, S, F, ci, P, ct, tr, &work, tp, rs, slot);
       if (tp != nullptr) tape_store(ct, tp, rs, slot);
     }
-    float* o = a.partials + t * kStride;
     if (!ADJ) {
-      // online softmax over l_i = -d_c,i / tau_b of the tile's contacts
+      // online softmax over l_i = -d_c,i / tau_b, one partial per piece present
+      // in the tile (its survivors are consecutive lanes)
       const T li = ct.d * (-P.inv_tau_blend);
-      const float Lam = wmax(valid ? val(li) : -__builtin_inff());
-      const T w = valid ? expT(li - Lam) : cst<T>(0.f);
       const T omf = cst<T>(1.f) - ct.f;
       const V3<T> nc = ct.N * ct.f, pc = ct.p * ct.f + ct.prest * omf, fp = ct.p * ct.f;
-      T acc[13] = {w, w * ct.d, w * nc.x, w * nc.y, w * nc.z, w * pc.x, w * pc.y, w * pc.z,
-                   w * fp.x, w * fp.y, w * fp.z, w * ct.f, cst<T>(valid ? 1.f : 0.f)};
+      const int e_first = uni(int(e));
+      const int e_last = wmax_i(valid ? int(e) : e_first);
+      for (int ex = e_first; ex <= e_last; ++ex) {
+        const bool in = valid && int(e) == ex;
+        if (!__any(in)) continue;
+        const float Lam = wmax(in ? val(li) : -__builtin_inff());
+        const T w = in ? expT(li - Lam) : cst<T>(0.f);
+        T acc[13] = {w, w * ct.d, w * nc.x, w * nc.y, w * nc.z, w * pc.x, w * pc.y, w * pc.z,
+                     w * fp.x, w * fp.y, w * fp.z, w * ct.f, cst<T>(in ? 1.f : 0.f)};
 #pragma unroll
-      for (int i = 0; i < 13; ++i) acc[i] = wsum(acc[i]);
-      if (l == 0) {
-        o[0] = Lam;
+        for (int i = 0; i < 13; ++i) acc[i] = wsum(acc[i]);
+        const int64_t k = j - (a.surv_off[ex] - sb) / kWave;  // the entry's k-th partial
+        float* o = a.partials + (a.part_off[ex] + k) * kStride;
+        if (l == 0) {
+          o[0] = Lam;
 #pragma unroll
-        for (int i = 0; i < 13; ++i) putT(o + 1 + i * nT<T>(), acc[i]);
+          for (int i = 0; i < 13; ++i) putT(o + 1 + i * nT<T>(), acc[i]);
+        }
       }
       if (nT<T>() == 1 && a.dbg != nullptr && valid) {
-        const int64_t ci = E.contact_base + c;
+        const int64_t cidx = E.contact_base + c;
         const float rec[13] = {1.f, val(ct.d), val(ct.f), 0.f, val(pc.x), val(pc.y), val(pc.z), val(nc.x),
-                               val(nc.y), val(nc.z), val(ct.phi), float(E.kind), __int_as_float(E.group)};
+                               val(nc.y), val(nc.z), val(ct.phi), float(E0.kind), __int_as_float(E.group)};
 #pragma unroll
-        for (int r = 0; r < 13; ++r) a.dbg[r * a.C + ci] = rec[r];
+        for (int rr = 0; rr < 13; ++rr) a.dbg[rr * a.C + cidx] = rec[rr];
       }
     } else {
       const GAdj<T> ga = load_gadj<T>(a.gscratch + int64_t(E.group) * kGStride);
       PoseGrad<T> G{zero3<T>(), zero3<T>(), zero3<T>(), zero3<T>()};
-      if (E.kind == 0) vertex_adj(ct, F, ga, P, G);
+      if (E0.kind == 0) vertex_adj(ct, F, ga, P, G);
       else edge_adj(ct, tr, F, ga, P, G);
-      // (w_A, v_A, w_B, v_B)
-      const V3<T> g4[4] = {E.dir ? G.wS : G.wM, E.dir ? G.vS : G.vM, E.dir ? G.wM : G.wS, E.dir ? G.vM : G.vS};
+      // (w_A, v_A, w_B, v_B): all lanes of a tile belong to one query
+      const V3<T> g4[4] = {E0.dir ? G.wS : G.wM, E0.dir ? G.vS : G.vM, E0.dir ? G.wM : G.wS,
+                           E0.dir ? G.vM : G.vS};
+      float* o = a.partials + t * kStride;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const T gx = wsum(valid ? g4[i].x : cst<T>(0.f));
@@ -588,7 +605,7 @@ template <class T> CM_DEV BlendT<T> group_blend(const FinArgs& a, int64_t g) {
       blend_merge(b, -P.d_max * P.inv_tau_blend, cst<T>(fl.x), cst<T>(fl.x * P.d_max), zero3<T>(), S, zero3<T>(),
                   cst<T>(0.f));
     }
-    for (int64_t t = a.tile_off[e]; t < a.tile_off[e + 1]; ++t) {
+    for (int64_t t = a.part_off[e]; t < a.part_off[e + 1]; ++t) {
       const float* o = a.partials + t * kStride;
       constexpr int s = nT<T>();
       const T* dummy = nullptr;
@@ -662,7 +679,8 @@ __global__ void k_dbg_weights(float* __restrict__ dbg, int64_t C, const float* _
 // ----------------------------------------------------------------- reduce --
 // Per query, in a fixed order: for each piece (group) its vertex then edge
 // entry, the filtered contacts' closed form (their points move with the mesh
-// body, with weight exp(-d_max / tau_b - logZ)) and then the tiles' partials.
+// body, with weight exp(-d_max / tau_b - logZ)); then the partials of the
+// tiles of its runs.
 // With duals, hv = d/de grad - (1/2) w_dir x grad_w per body: the second term
 // converts the derivative of the world-frame gradient into the Hessian of
 // L(exp([w]x) R, t + v) at zero.
@@ -694,10 +712,14 @@ __global__ __launch_bounds__(256) void k_reduce(FinArgs a, const float* __restri
         acc[o + 0] += wM.x; acc[o + 1] += wM.y; acc[o + 2] += wM.z;
         acc[o + 3] += vM.x; acc[o + 4] += vM.y; acc[o + 5] += vM.z;
       }
-      for (int64_t t = a.tile_off[e]; t < a.tile_off[e + 1]; ++t) {
-        const float* o = bpartials + t * kStride;
-        for (int i = 0; i < 12; ++i) acc[i] += getT<T>(o + i * nT<T>());
-      }
+    }
+  }
+  // the query's tiles: its four runs (direction, kind) in a fixed order
+  for (int k = 0; k < 4; ++k) {
+    const int64_t r = a.q_runs[4 * qi + k];
+    for (int64_t t = a.tile_off[r]; t < a.tile_off[r + 1]; ++t) {
+      const float* o = bpartials + t * kStride;
+      for (int i = 0; i < 12; ++i) acc[i] += getT<T>(o + i * nT<T>());
     }
   }
   for (int i = 0; i < 12; ++i) grad[12 * qi + i] = val(acc[i]);
@@ -730,6 +752,7 @@ static void narrow_launch(const NarrowArgs& na, int grid, hipStream_t s, hipEven
 static NarrowArgs narrow_args(const FwdArgs& a, float* partials, const float* dir, float* dbg) {
   NarrowArgs na{};
   na.ents = a.ents; na.n_ent = a.n_ent; na.tile_off = a.tile_off; na.bits = a.bits; na.Q = a.Q; na.objs = a.objs;
+  na.run_off = a.run_off; na.surv_off = a.surv_off; na.part_off = a.part_off; na.wpre = a.wpre; na.n_run = a.n_run;
   na.P = a.P; na.counter = a.counter; na.partials = partials; na.gscratch = a.gscratch; na.dir = dir;
   na.dbg = dbg; na.C = a.C;
   na.tape = a.tape; na.tape_tiles = a.tape_tiles; na.tape_nv = a.tape_nv; na.t_begin = 0;
@@ -739,6 +762,7 @@ static NarrowArgs narrow_args(const FwdArgs& a, float* partials, const float* di
 static FinArgs fin_args(const FwdArgs& a, const float* partials, const float* dir) {
   FinArgs fa{};
   fa.G = a.G; fa.gent = a.gent; fa.tile_off = a.tile_off; fa.filt = a.filt; fa.partials = partials;
+  fa.part_off = a.part_off; fa.q_runs = a.q_runs;
   fa.ents = a.ents; fa.Q = a.Q; fa.P = a.P; fa.out = a.out; fa.cot = a.cot; fa.gscratch = a.gscratch; fa.dir = dir;
   return fa;
 }

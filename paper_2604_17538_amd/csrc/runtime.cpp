@@ -606,20 +606,43 @@ cm_status plan_host(cm_context* ctx, const cm_query* hq, int32_t n, cm_plan* pl,
   pl->G = pl->group_off[size_t(n)];
   pl->C = pl->contact_off[size_t(n)];
   if (pl->G >= (int64_t(1) << 31)) { std::lock_guard<std::mutex> lk(ctx->mu); ctx->err = "too many groups"; return CM_E_INVALID; }
-  // costliest entries first, so their tiles head the work queue
-  std::vector<int64_t> order(pl->ents.size());
-  std::iota(order.begin(), order.end(), 0);
-  std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return cost[size_t(a)] > cost[size_t(b)]; });
-  std::vector<Entry> sorted(pl->ents.size());
+  // runs: the entries of one (query, direction, kind), i.e. every piece of the
+  // mesh side, whose survivors share tiles; costliest runs first, so their tiles
+  // head the work queue, pieces in order within a run
+  const int64_t R = 4 * int64_t(n);
+  std::vector<double> rcost(static_cast<size_t>(R), 0.0);
+  std::vector<std::vector<int64_t>> members(static_cast<size_t>(R));
+  for (size_t i = 0; i < pl->ents.size(); ++i) {
+    const Entry& e = pl->ents[i];
+    const int64_t r = 4 * int64_t(e.query) + 2 * e.dir + e.kind;
+    rcost[size_t(r)] += cost[i];
+    members[size_t(r)].push_back(int64_t(i));
+  }
+  std::vector<int64_t> rorder(static_cast<size_t>(R));
+  std::iota(rorder.begin(), rorder.end(), 0);
+  std::stable_sort(rorder.begin(), rorder.end(), [&](int64_t a, int64_t b) { return rcost[size_t(a)] > rcost[size_t(b)]; });
+  std::vector<Entry> sorted;
+  sorted.reserve(pl->ents.size());
+  pl->run_off.assign(size_t(R) + 1, 0);
+  pl->q_runs.assign(size_t(R), 0);
+  pl->ent_run.clear();
   pl->gent.assign(size_t(pl->G), I2{0, 0});
-  for (size_t i = 0; i < order.size(); ++i) {
-    sorted[i] = pl->ents[size_t(order[i])];
-    I2& ge = pl->gent[size_t(sorted[i].group)];
-    if (sorted[i].kind == 0) ge.x = int32_t(i); else ge.y = int32_t(i);
+  for (int64_t k = 0; k < R; ++k) {
+    const int64_t r = rorder[size_t(k)];
+    pl->q_runs[size_t(r)] = int32_t(k);
+    for (int64_t i : members[size_t(r)]) {
+      const Entry& e = pl->ents[size_t(i)];
+      I2& ge = pl->gent[size_t(e.group)];
+      if (e.kind == 0) ge.x = int32_t(sorted.size()); else ge.y = int32_t(sorted.size());
+      sorted.push_back(e);
+      pl->ent_run.push_back(int32_t(k));
+    }
+    pl->run_off[size_t(k) + 1] = int64_t(sorted.size());
   }
   pl->ents.swap(sorted);
   pl->E = int64_t(pl->ents.size());
-  pl->nb = (pl->E + 1023) / 1024;
+  pl->R = R;
+  pl->nb = (std::max(pl->E, pl->R) + 1023) / 1024;
   *dev_bytes = plan_layout(pl, nullptr);
   return CM_OK;
 }
@@ -633,12 +656,20 @@ size_t plan_layout(cm_plan* pl, char* b) {
   const size_t o_gent = take(sizeof(I2) * size_t(pl->G));
   const size_t o_bits = take(8 * size_t(W));
   const size_t o_nsurv = take(4 * size_t(pl->E));
-  const size_t o_ntiles = take(4 * size_t(pl->E));
+  const size_t o_wpre = take(4 * size_t(W));
+  const size_t o_soff = take(8 * size_t(pl->E + 1));
+  const size_t o_roff = take(8 * size_t(pl->R + 1));
+  const size_t o_erun = take(4 * size_t(pl->E));
+  const size_t o_qrun = take(4 * size_t(pl->R));
+  const size_t o_ntr = take(4 * size_t(pl->R));
+  const size_t o_npart = take(4 * size_t(pl->E));
+  const size_t o_poff = take(8 * size_t(pl->E + 1));
   const size_t o_filt = take(16 * size_t(pl->E));
-  const size_t o_toff = take(8 * size_t(pl->E + 1));
+  const size_t o_toff = take(8 * size_t(pl->R + 1));
   const size_t o_bsum = take(8 * size_t(pl->nb + 1));
   const size_t o_cnt = take(256);
-  const size_t o_part = take(4 * size_t(kStride) * size_t(W));
+  // blend partials: one per (entry, tile its survivors reach): at most W + E
+  const size_t o_part = take(4 * size_t(kStride) * size_t(W + pl->E));
   const size_t o_gs = take(4 * size_t(kGStride) * size_t(pl->G));
   const size_t o_bp = take(4 * size_t(kStride) * size_t(W));
   const size_t o_goff = take(8 * size_t(pl->n + 1));
@@ -655,7 +686,14 @@ size_t plan_layout(cm_plan* pl, char* b) {
     pl->d_gent = reinterpret_cast<I2*>(b + o_gent);
     pl->d_bits = reinterpret_cast<uint64_t*>(b + o_bits);
     pl->d_nsurv = reinterpret_cast<int32_t*>(b + o_nsurv);
-    pl->d_ntiles = reinterpret_cast<int32_t*>(b + o_ntiles);
+    pl->d_wpre = reinterpret_cast<int32_t*>(b + o_wpre);
+    pl->d_surv_off = reinterpret_cast<int64_t*>(b + o_soff);
+    pl->d_run_off = reinterpret_cast<int64_t*>(b + o_roff);
+    pl->d_ent_run = reinterpret_cast<int32_t*>(b + o_erun);
+    pl->d_q_runs = reinterpret_cast<int32_t*>(b + o_qrun);
+    pl->d_ntr = reinterpret_cast<int32_t*>(b + o_ntr);
+    pl->d_npart = reinterpret_cast<int32_t*>(b + o_npart);
+    pl->d_part_off = reinterpret_cast<int64_t*>(b + o_poff);
     pl->d_filt = reinterpret_cast<F4*>(b + o_filt);
     pl->d_tile_off = reinterpret_cast<int64_t*>(b + o_toff);
     pl->d_bsum = reinterpret_cast<int64_t*>(b + o_bsum);
@@ -678,7 +716,12 @@ cm_status plan_bind(cm_plan* pl, void* dmem, hipStream_t s) {
   hipError_t e1 = hipMemcpyAsync(pl->d_ents, pl->ents.data(), sizeof(Entry) * size_t(pl->E), hipMemcpyHostToDevice, s);
   hipError_t e2 = hipMemcpyAsync(pl->d_gent, pl->gent.data(), sizeof(I2) * size_t(pl->G), hipMemcpyHostToDevice, s);
   hipError_t e3 = hipMemcpyAsync(pl->d_group_off, pl->group_off.data(), 8 * size_t(pl->n + 1), hipMemcpyHostToDevice, s);
-  if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) return fail(pl->ctx, CM_E_HIP, "plan upload failed");
+  hipError_t e4 = hipMemcpyAsync(pl->d_run_off, pl->run_off.data(), 8 * size_t(pl->R + 1), hipMemcpyHostToDevice, s);
+  hipError_t e5 = hipMemcpyAsync(pl->d_ent_run, pl->ent_run.data(), 4 * size_t(pl->E), hipMemcpyHostToDevice, s);
+  hipError_t e6 = hipMemcpyAsync(pl->d_q_runs, pl->q_runs.data(), 4 * size_t(pl->R), hipMemcpyHostToDevice, s);
+  if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess || e4 != hipSuccess || e5 != hipSuccess ||
+      e6 != hipSuccess)
+    return fail(pl->ctx, CM_E_HIP, "plan upload failed");
   return CM_OK;
 }
 
@@ -776,10 +819,14 @@ cm_status cm_plan_stats(const cm_plan* pl, int64_t* st) {  // 8 entries
   int64_t sv = 0, se = 0, tiles = 0, nv = 0, ne = 0;
   double pairs = 0, vpairs = 0, epairs = 0;
   const int K2 = 2 * pl->ctx->prm.st_iters + 1;
+  for (int64_t r = 0; r < pl->R; ++r) {
+    int64_t s = 0;
+    for (int64_t e = pl->run_off[size_t(r)]; e < pl->run_off[size_t(r) + 1]; ++e) s += ns[size_t(e)];
+    tiles += (s + kWave - 1) / kWave;
+  }
   for (size_t i = 0; i < ns.size(); ++i) {
     const Entry& e = pl->ents[i];
     const double P = double(pl->ctx->objs[size_t(e.sdf_obj)].n_planes);
-    tiles += (ns[i] + kWave - 1) / kWave;
     if (e.kind == 0) { sv += ns[i]; nv += e.count; pairs += double(ns[i]) * P; vpairs += double(ns[i]) * P; }
     else { se += ns[i]; ne += e.count; pairs += double(ns[i]) * P * K2; epairs += double(ns[i]) * P; }
   }
@@ -800,7 +847,15 @@ FwdArgs fwd_args(cm_context* ctx, cm_plan* pl, const cm_query* q, const cm_group
   a.P = ctx->dp;
   a.bits = pl->d_bits;
   a.nsurv = pl->d_nsurv;
-  a.ntiles = pl->d_ntiles;
+  a.wpre = pl->d_wpre;
+  a.surv_off = pl->d_surv_off;
+  a.run_off = pl->d_run_off;
+  a.ent_run = pl->d_ent_run;
+  a.q_runs = pl->d_q_runs;
+  a.ntr = pl->d_ntr;
+  a.npart = pl->d_npart;
+  a.part_off = pl->d_part_off;
+  a.n_run = pl->R;
   a.filt = pl->d_filt;
   a.bsum = pl->d_bsum;
   a.tile_off = pl->d_tile_off;

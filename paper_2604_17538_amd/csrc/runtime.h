@@ -77,9 +77,12 @@ struct cm_context {
 struct cm_plan {
   cm_context* ctx = nullptr;
   int32_t n = 0;
-  int64_t G = 0, C = 0, E = 0, W = 0, nb = 0;
+  int64_t G = 0, C = 0, E = 0, W = 0, nb = 0, R = 0;
   std::vector<int64_t> group_off, contact_off;
-  std::vector<cm::Entry> ents;       // host copy (device order)
+  std::vector<cm::Entry> ents;       // host copy (device order: runs in cost order)
+  std::vector<int64_t> run_off;      // [R + 1] entry ranges of the runs (query, direction, kind)
+  std::vector<int32_t> ent_run;      // [E] run of each entry
+  std::vector<int32_t> q_runs;       // [4n] run of (query, 2 dir + kind)
   std::vector<cm::I2> gent;          // per group: (vertex entry, edge entry)
   bool owns_mem = false;
   std::vector<int32_t> qa, qb;
@@ -88,9 +91,16 @@ struct cm_plan {
   cm::I2* d_gent = nullptr;
   uint64_t* d_bits = nullptr;
   int32_t* d_nsurv = nullptr;
-  int32_t* d_ntiles = nullptr;
+  int32_t* d_wpre = nullptr;     // [W] survivors of an entry before each of its bitmask words
+  int64_t* d_surv_off = nullptr; // [E + 1] survivor offsets (entries in run order)
+  int64_t* d_run_off = nullptr;  // [R + 1]
+  int32_t* d_ent_run = nullptr;  // [E]
+  int32_t* d_q_runs = nullptr;   // [4n]
+  int32_t* d_ntr = nullptr;      // [R] tiles per run
+  int32_t* d_npart = nullptr;    // [E] partials per entry
+  int64_t* d_part_off = nullptr; // [E + 1]
   cm::F4* d_filt = nullptr;
-  int64_t* d_tile_off = nullptr;
+  int64_t* d_tile_off = nullptr; // [R + 1] tile offsets of the runs
   int64_t* d_bsum = nullptr;
   uint32_t* d_counter = nullptr;
   float* d_partials = nullptr;

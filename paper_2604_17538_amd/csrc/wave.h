@@ -16,6 +16,11 @@ CM_DEV float wmax(float v) {
   for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, kWave));
   return v;
 }
+CM_DEV int wmax_i(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, kWave));
+  return v;
+}
 CM_DEV int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
 // Index of the k-th set bit (k counted from 0) of a 64-bit word.
@@ -30,30 +35,25 @@ CM_DEV int kth_bit(uint64_t w, int k) {
   return pos;
 }
 
-// Piece-local contact index of this lane's survivor in tile j of entry E, or
-// -1 past the entry's last survivor.
-CM_DEV int tile_contact(const uint64_t* __restrict__ bits, const Entry& E, int j) {
-  const int r0 = j * kWave, r = r0 + lane();
-  const int nw = (max(E.count, 0) + kWave - 1) / kWave;
-  const uint64_t* wp = bits + E.word_off;
-  int pre = 0, c = -1;
-  for (int w = 0; w < nw && pre < r0 + kWave; ++w) {
-    const uint64_t word = wp[w];
-    const int pc = __popcll(word);
-    if (pre + pc > r0 && r >= pre && r < pre + pc) c = w * kWave + kth_bit(word, r - pre);
-    pre += pc;
-  }
-  return c;
-}
-
-// Entry of tile t: the largest e with tile_off[e] <= t.
-CM_DEV int64_t find_entry(const int64_t* __restrict__ tile_off, int64_t n_ent, int64_t t) {
-  int64_t lo = 0, hi = n_ent;
+// Largest index i in [lo, hi) with off[i] <= v (off non-decreasing, off[lo] <= v).
+CM_DEV int64_t last_le(const int64_t* __restrict__ off, int64_t lo, int64_t hi, int64_t v) {
   while (hi - lo > 1) {
     const int64_t mid = (lo + hi) >> 1;
-    if (tile_off[mid] <= t) lo = mid; else hi = mid;
+    if (off[mid] <= v) lo = mid; else hi = mid;
   }
   return lo;
+}
+
+// Entry-local index of the k-th survivor (k counted from 0) of entry E: the
+// word holding it from the per-word survivor prefix, then the bit in the word.
+CM_DEV int entry_survivor(const uint64_t* __restrict__ bits, const int32_t* __restrict__ wpre, const Entry& E, int k) {
+  const int nw = (max(E.count, 0) + kWave - 1) / kWave;
+  int lo = 0, hi = nw;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (wpre[E.word_off + mid] <= k) lo = mid; else hi = mid;
+  }
+  return lo * kWave + kth_bit(bits[E.word_off + lo], k - wpre[E.word_off + lo]);
 }
 
 CM_DEV V3<float> vert(const ObjDesc& o, int i) { return {o.vx[i], o.vy[i], o.vz[i]}; }
