@@ -248,6 +248,11 @@ def main():
         torch.cuda.synchronize()
         return a.elapsed_time(b) / reps
 
+    # launch shapes picked by the autotuner (persistent workgroups per CU), one
+    # for the sweeps in dual numbers (this step) and one for the float sweeps
+    shape = plan.autotune(qd, cot_d, grad, dir_d, hv, stream)
+    shape_f = plan.autotune(qd, cot_d, grad, stream=stream)
+    log("autotuned launch shape: %d workgroups per CU (dual sweeps), %d (float sweeps)" % (shape, shape_f))
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -268,6 +273,11 @@ def main():
     sep_ms = timed(separate, 2)
     fg_ms = timed(fwd_grad, 2)
     log("separate calls %.2f ms, forward + gradient step %.2f ms" % (sep_ms, fg_ms))
+    # the step replayed from a HIP graph of its launches
+    graph = plan.graph(qd, cot_d, grad, dir_d, hv, out)
+    graph_ms = timed(lambda: graph.launch(stream), max(args.steps, 2))
+    del graph
+    log("graph replay %.2f ms" % graph_ms)
 
     # per-kernel timing of the step (events on the launch stream), untimed region
     plan.set_timing(True)
@@ -369,6 +379,9 @@ def main():
                    "pair_queries": w.n, "groups": plan.G, "contacts": plan.C, "step": "cm_contacts_step"},
         "split_ms": split,
         "separate_calls_ms_per_step": round(sep_ms, 3),
+        "graph_replay_ms_per_step": round(graph_ms, 3),
+        "launch_shape": {"workgroups_per_cu": shape, "workgroups_per_cu_float": shape_f,
+                         "tile": "one wave of 64 contacts"},
         "forward_gradient_step_ms": round(fg_ms, 3),
         "forward_gradient_value": round(w.n / (fg_ms * 1e-3), 1),
         "work": st,

@@ -241,6 +241,29 @@ cm_status cm_serve_latencies(cm_context* ctx, double* out, int64_t cap, int64_t*
 cm_status cm_contacts_step(cm_context* ctx, cm_plan* plan, const cm_query* q_dev, cm_groups out, cm_groups cot,
                            float* grad, const float* dir, float* hv, void* stream);
 
+/* HIP graph of a plan's step: cm_graph_create records the launches of
+ * cm_contacts_step with these device buffers (same arguments and rules) into
+ * a graph; cm_graph_launch replays it on `stream`.  The kernels read every
+ * count on the device, so a replay computes the step for whatever poses the
+ * query buffer holds at that time; buffers and plan must outlive the graph,
+ * and replays of one plan must not overlap.  Timing events are not recorded
+ * into the graph.  For callers whose step launch overhead matters (small
+ * batches, serving loops). */
+typedef struct cm_graph cm_graph;
+cm_status cm_graph_create(cm_context* ctx, cm_plan* plan, const cm_query* q_dev, cm_groups out, cm_groups cot,
+                          float* grad, const float* dir, float* hv, cm_graph** graph);
+cm_status cm_graph_launch(cm_graph* graph, void* stream);
+cm_status cm_graph_destroy(cm_graph* graph);
+
+/* Launch-shape autotuner: times cm_contacts_step (records not written) with
+ * 2, 4, 6, 8, 12 and 16 persistent workgroups per CU on `stream`
+ * (synchronous) and keeps the fastest for the plan's later launches of the
+ * same kind: with dir the sweeps in dual numbers (H v), without dir the float
+ * sweeps (forward, gradient); *best (nullable) receives it.  The tile shape
+ * itself is one wave of 64 contacts. */
+cm_status cm_plan_autotune(cm_context* ctx, cm_plan* plan, const cm_query* q_dev, cm_groups cot, float* grad,
+                           const float* dir, float* hv, void* stream, int32_t* best);
+
 /* Serving statistics: [0] submitted, [1] completed, [2] batches, [3] queued,
  * [4] in flight, [5] peak in-flight bytes, [6] queries completed. */
 cm_status cm_serve_stats(cm_context* ctx, int64_t* stats7);

@@ -251,6 +251,28 @@ class Plan:
         self.ctx._check(st, "cm_contacts_step")
         return (out if records else None), grad, (hv if direction is not None else None)
 
+    def graph(self, q_dev, cot, grad, direction=None, hv=None, out=None) -> "Graph":
+        """HIP graph of step() with these device buffers (cm_graph_create)."""
+        h = ctypes.c_void_p()
+        st = _cm.cm_graph_create(self.ctx.handle, self._h, ctypes.c_void_p(q_dev.data_ptr()),
+                                 groups_struct(out) if out is not None else _cm.cm_groups(), groups_struct(cot),
+                                 ctypes.c_void_p(grad.data_ptr()),
+                                 ctypes.c_void_p(direction.data_ptr()) if direction is not None else None,
+                                 ctypes.c_void_p(hv.data_ptr()) if hv is not None else None, ctypes.byref(h))
+        self.ctx._check(st, "cm_graph_create")
+        return Graph(self, h, (q_dev, cot, grad, direction, hv, out))
+
+    def autotune(self, q_dev, cot, grad, direction=None, hv=None, stream=None) -> int:
+        """Picks the persistent launch shape for this plan (cm_plan_autotune); returns workgroups per CU."""
+        best = ctypes.c_int32()
+        st = _cm.cm_plan_autotune(self.ctx.handle, self._h, ctypes.c_void_p(q_dev.data_ptr()), groups_struct(cot),
+                                  ctypes.c_void_p(grad.data_ptr()),
+                                  ctypes.c_void_p(direction.data_ptr()) if direction is not None else None,
+                                  ctypes.c_void_p(hv.data_ptr()) if hv is not None else None,
+                                  _stream_ptr(stream), ctypes.byref(best))
+        self.ctx._check(st, "cm_plan_autotune")
+        return int(best.value)
+
     def hvp(self, q_dev, cot, direction, hv=None, grad=None, stream=None):
         torch = _torch()
         if hv is None:
@@ -282,6 +304,21 @@ class Plan:
         self.ctx._check(_cm.cm_plan_stats(self._h, _ptr(s)), "cm_plan_stats")
         return dict(surv_verts=int(s[0]), surv_edges=int(s[1]), tiles=int(s[2]), verts=int(s[3]),
                     edges=int(s[4]), pairs=int(s[5]), vertex_pairs=int(s[6]), edge_pairs=int(s[7]))
+
+
+class Graph:
+    """A captured step (cm_graph_*); keeps its plan and buffers alive."""
+
+    def __init__(self, plan, h, keep):
+        self.plan, self._h, self._keep = plan, h, keep
+
+    def launch(self, stream=None):
+        self.plan.ctx._check(_cm.cm_graph_launch(self._h, _stream_ptr(stream)), "cm_graph_launch")
+
+    def __del__(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _cm.cm_graph_destroy(self._h)
+            self._h = None
 
 
 class Server:

@@ -1,0 +1,108 @@
+// HIP graphs of a plan's step, and the launch-shape autotuner.
+//
+// Every count the kernels need (survivors, tiles, partial ranges) is computed
+// and read on the device and the work-queue counters are cleared by a kernel,
+// so the launches of a step do not depend on the poses: one graph replays the
+// step for any poses written into the same query buffer.
+#include <algorithm>
+
+#include "runtime.h"
+
+struct cm_graph {
+  cm_context* ctx = nullptr;
+  cm_plan* plan = nullptr;
+  hipStream_t stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+using namespace cm;
+
+extern "C" {
+
+cm_status cm_graph_create(cm_context* ctx, cm_plan* pl, const cm_query* q, cm_groups out, cm_groups cot,
+                          float* grad, const float* dir, float* hv, cm_graph** result) {
+  if (!ctx || !pl || pl->ctx != ctx || !result) return fail(ctx, CM_E_INVALID, "bad arguments");
+  *result = nullptr;
+  auto* g = new cm_graph;
+  g->ctx = ctx;
+  g->plan = pl;
+  if (hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking) != hipSuccess) {
+    delete g;
+    return fail(ctx, CM_E_HIP, "graph stream creation failed");
+  }
+  const bool timing = pl->timing;
+  pl->timing = false;  // events are not recorded into the graph
+  cm_status st = CM_OK;
+  hipError_t e = hipStreamBeginCapture(g->stream, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    st = cm_contacts_step(ctx, pl, q, out, cot, grad, dir, hv, g->stream);
+    e = hipStreamEndCapture(g->stream, &g->graph);
+  }
+  pl->timing = timing;
+  if (st == CM_OK && e == hipSuccess) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+  if (st != CM_OK || e != hipSuccess) {
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    (void)hipStreamDestroy(g->stream);
+    delete g;
+    (void)hipGetLastError();
+    return st != CM_OK ? st : hip_fail(ctx, e, "graph capture");
+  }
+  *result = g;
+  return CM_OK;
+}
+
+cm_status cm_graph_launch(cm_graph* g, void* stream) {
+  if (!g) return CM_E_INVALID;
+  const hipError_t e = hipGraphLaunch(g->exec, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(g->ctx, e, "graph launch");
+  return CM_OK;
+}
+
+cm_status cm_graph_destroy(cm_graph* g) {
+  if (!g) return CM_E_INVALID;
+  (void)hipStreamSynchronize(g->stream);
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  (void)hipStreamDestroy(g->stream);
+  delete g;
+  return CM_OK;
+}
+
+cm_status cm_plan_autotune(cm_context* ctx, cm_plan* pl, const cm_query* q, cm_groups cot, float* grad,
+                           const float* dir, float* hv, void* stream, int32_t* best) {
+  if (!ctx || !pl || pl->ctx != ctx) return fail(ctx, CM_E_INVALID, "bad arguments");
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  hipEvent_t a = nullptr, b = nullptr;
+  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+    if (a) (void)hipEventDestroy(a);
+    return fail(ctx, CM_E_HIP, "event creation failed");
+  }
+  const int32_t cand[] = {2, 4, 6, 8, 12, 16};
+  int32_t& shape = dir ? pl->blocks_per_cu_dual : pl->blocks_per_cu;  // the sweeps this step runs
+  const int32_t keep = shape;
+  float best_ms = 3.4e38f;
+  int32_t pick = keep;
+  cm_status st = CM_OK;
+  for (int32_t c : cand) {
+    shape = c;
+    st = cm_contacts_step(ctx, pl, q, cm_groups{}, cot, grad, dir, hv, stream);  // warm
+    if (st != CM_OK) break;
+    float ms = 0.f;
+    if (hipEventRecord(a, s) != hipSuccess) { st = CM_E_HIP; break; }
+    for (int r = 0; r < 2 && st == CM_OK; ++r) st = cm_contacts_step(ctx, pl, q, cm_groups{}, cot, grad, dir, hv, stream);
+    if (st != CM_OK || hipEventRecord(b, s) != hipSuccess || hipEventSynchronize(b) != hipSuccess ||
+        hipEventElapsedTime(&ms, a, b) != hipSuccess) {
+      if (st == CM_OK) st = CM_E_HIP;
+      break;
+    }
+    if (ms < best_ms) { best_ms = ms; pick = c; }
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  shape = st == CM_OK ? pick : keep;
+  if (best) *best = shape;
+  return st == CM_OK ? CM_OK : fail(ctx, st, "autotune failed");
+}
+
+}  // extern "C"

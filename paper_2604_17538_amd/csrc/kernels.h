@@ -55,7 +55,8 @@ struct FwdArgs {
   float* dbg;           // nullable
   int64_t C;
   int32_t n_cu;
-  int32_t blocks_per_cu;
+  int32_t blocks_per_cu;       // persistent workgroups per CU, float sweeps
+  int32_t blocks_per_cu_dual;  // the same in dual numbers
   // adjoint / HVP
   OutPtrs cot;          // cotangent group records
   float* gscratch;      // [G][kGStride] per-piece adjoint seeds

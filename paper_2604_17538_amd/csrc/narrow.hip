@@ -789,7 +789,7 @@ template <class T> static hipError_t adjoint_impl(const FwdArgs& a, hipStream_t 
   (void)hipGetLastError();
   if (a.work) launch_fill_u32(reinterpret_cast<uint32_t*>(a.work), 0u, 2, s);
   launch_front(a, s);
-  const int grid = a.n_cu * a.blocks_per_cu;
+  const int grid = a.n_cu * (nT<T>() == 2 ? a.blocks_per_cu_dual : a.blocks_per_cu);
   const float* dir = a.dir;
   const bool tape = a.tape != nullptr && a.tape_tiles > 0;
   if (tape) narrow_launch<T, false, true>(narrow_args(a, a.partials, dir, nullptr), grid, s, a.ev);

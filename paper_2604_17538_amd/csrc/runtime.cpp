@@ -867,7 +867,8 @@ FwdArgs fwd_args(cm_context* ctx, cm_plan* pl, const cm_query* q, const cm_group
   a.dbg = dbg;
   a.C = pl->C;
   a.n_cu = ctx->n_cu;
-  a.blocks_per_cu = 8;
+  a.blocks_per_cu = pl->blocks_per_cu;
+  a.blocks_per_cu_dual = pl->blocks_per_cu_dual;
   a.gscratch = pl->d_gscratch;
   a.bpartials = pl->d_bpartials;
   a.group_off = pl->d_group_off;

@@ -111,6 +111,8 @@ struct cm_plan {
   float* d_tape = nullptr;       // adjoint tape (see kernels.h)
   unsigned long long* d_work = nullptr;  // point-plane evaluations of the last pass
   int64_t tape_tiles = 0;
+  int32_t blocks_per_cu = 8;       // persistent workgroups per CU, float sweeps (cm_plan_autotune)
+  int32_t blocks_per_cu_dual = 8;  // the same for the sweeps in dual numbers
   bool timing = false;
   uint32_t timed_mask = 0;  // timing slots launched by the last pass
   hipEvent_t ev[2 * cm::kTimed] = {};
