@@ -102,6 +102,11 @@ def build_workload(cfg, pairs):
     raise ValueError(cfg)
 
 
+# device-memory budget of the context per workload (a quarter of it holds the
+# adjoint tape; tiles past it are recomputed by the adjoint)
+BUDGET_GB = {"c0": 32, "c1": 32, "c2": 32, "c4": 128}
+
+
 def cpu_baseline(w, sample, threads, want_grad=True):
     """Oracle (FP64, OpenMP over pair-queries) on the first `sample` queries."""
     import oracle as O
@@ -179,11 +184,15 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", default="c2", choices=["c0", "c1", "c2", "c4"])
     ap.add_argument("--pairs", type=int, default=None, help="batch size override (default: the config's)")
+    ap.add_argument("--budget-gb", type=float, default=None, help="device-memory budget (default per workload)")
     ap.add_argument("--cpu-sample", type=int, default=16)
     ap.add_argument("--plain-sample", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-separate", action="store_true", help="skip timing the three separate calls")
+    ap.add_argument("--tune-sample", type=int, default=16384,
+                    help="autotune on a plan of the first N pair-queries when the batch is larger")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a device copy of 1 GiB three times (scale of the HBM traffic counters)")
     ap.add_argument("--serve-rates", default="2000,5000", help="Poisson request rates (req/s) for the serving leg")
@@ -210,7 +219,8 @@ def main():
 
     w = build_workload(args.config, args.pairs)
     log("workload %s: %d pair-queries, %d objects" % (args.config, w.n, len(w.objects)))
-    ctx = api.Context(0, L_ref=w.L_ref)
+    budget_gb = args.budget_gb or BUDGET_GB[args.config]
+    ctx = api.Context(0, L_ref=w.L_ref, budget_bytes=int(budget_gb * (1 << 30)))
     hs = ctx.build_objects(w.objects)
     torch.cuda.synchronize()
     log("objects resident")
@@ -250,9 +260,24 @@ def main():
 
     # launch shapes picked by the autotuner (persistent workgroups per CU), one
     # for the sweeps in dual numbers (this step) and one for the float sweeps
-    shape = plan.autotune(qd, cot_d, grad, dir_d, hv, stream)
-    shape_f = plan.autotune(qd, cot_d, grad, stream=stream)
-    log("autotuned launch shape: %d workgroups per CU (dual sweeps), %d (float sweeps)" % (shape, shape_f))
+    if w.n <= args.tune_sample:
+        shape = plan.autotune(qd, cot_d, grad, dir_d, hv, stream)
+        shape_f = plan.autotune(qd, cot_d, grad, stream=stream)
+        tuned_on = w.n
+    else:
+        # a large batch: tune on a plan of its first pair-queries, apply to the whole
+        ns = args.tune_sample
+        tp = ctx.plan(hs[w.qa[:ns]], hs[w.qb[:ns]])
+        tq = tp.device_queries(w.poses[:ns])
+        tc = cot_d[:, : tp.G].contiguous()
+        tg = torch.empty((ns, 12), dtype=torch.float32, device="cuda")
+        shape = tp.autotune(tq, tc, tg, dir_d[:ns].contiguous(), torch.empty_like(tg), stream)
+        shape_f = tp.autotune(tq, tc, tg, stream=stream)
+        plan.launch_shape = (shape_f, shape)
+        del tp, tq, tc, tg
+        tuned_on = ns
+    log("autotuned launch shape (on %d pair-queries): %d workgroups per CU (dual sweeps), %d (float sweeps)"
+        % (tuned_on, shape, shape_f))
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -270,12 +295,12 @@ def main():
     log("timed %d steps: %.2f ms/step (wall %.2f s)" % (args.steps, ms, wall))
 
     # the same outputs by the separate calls, and the forward + gradient step
-    sep_ms = timed(separate, 2)
-    fg_ms = timed(fwd_grad, 2)
-    log("separate calls %.2f ms, forward + gradient step %.2f ms" % (sep_ms, fg_ms))
+    sep_ms = None if args.no_separate else timed(separate, 2)
+    fg_ms = timed(fwd_grad, 1 if w.n > args.tune_sample else 2)
+    log("separate calls %s ms, forward + gradient step %.2f ms" % (sep_ms, fg_ms))
     # the step replayed from a HIP graph of its launches
     graph = plan.graph(qd, cot_d, grad, dir_d, hv, out)
-    graph_ms = timed(lambda: graph.launch(stream), max(args.steps, 2))
+    graph_ms = timed(lambda: graph.launch(stream), max(args.steps, 1 if w.n > args.tune_sample else 2))
     del graph
     log("graph replay %.2f ms" % graph_ms)
 
@@ -376,12 +401,13 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "%s: %d pair-queries, forward + gradient (both poses) + HVP per step" % (args.config, w.n),
-                   "pair_queries": w.n, "groups": plan.G, "contacts": plan.C, "step": "cm_contacts_step"},
+                   "pair_queries": w.n, "groups": plan.G, "contacts": plan.C, "step": "cm_contacts_step",
+                   "budget_gb": budget_gb},
         "split_ms": split,
-        "separate_calls_ms_per_step": round(sep_ms, 3),
+        "separate_calls_ms_per_step": round(sep_ms, 3) if sep_ms is not None else None,
         "graph_replay_ms_per_step": round(graph_ms, 3),
         "launch_shape": {"workgroups_per_cu": shape, "workgroups_per_cu_float": shape_f,
-                         "tile": "one wave of 64 contacts"},
+                         "tile": "one wave of 64 contacts", "tuned_on_pair_queries": tuned_on},
         "forward_gradient_step_ms": round(fg_ms, 3),
         "forward_gradient_value": round(w.n / (fg_ms * 1e-3), 1),
         "work": st,

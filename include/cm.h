@@ -264,6 +264,15 @@ cm_status cm_graph_destroy(cm_graph* graph);
 cm_status cm_plan_autotune(cm_context* ctx, cm_plan* plan, const cm_query* q_dev, cm_groups cot, float* grad,
                            const float* dir, float* hv, void* stream, int32_t* best);
 
+/* Launch shape of a plan: persistent workgroups per CU for the float sweeps
+ * (forward, gradient) and for the sweeps in dual numbers (H v).  The setter
+ * takes values in [1, 32] (else CM_E_INVALID, shape unchanged) and lets a shape
+ * tuned on a representative sub-batch (cm_plan_autotune on a smaller plan of
+ * the same workload) be applied to a large plan; results do not depend on it.
+ * The getter's outputs are nullable. */
+cm_status cm_plan_set_launch_shape(cm_plan* plan, int32_t float_per_cu, int32_t dual_per_cu);
+cm_status cm_plan_launch_shape(const cm_plan* plan, int32_t* float_per_cu, int32_t* dual_per_cu);
+
 /* Serving statistics: [0] submitted, [1] completed, [2] batches, [3] queued,
  * [4] in flight, [5] peak in-flight bytes, [6] queries completed. */
 cm_status cm_serve_stats(cm_context* ctx, int64_t* stats7);

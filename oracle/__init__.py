@@ -243,7 +243,7 @@ FP32_UNIT_ROUNDOFF = 2.0 ** -24
 
 
 def fp32_spread(prm: Params, objs, qa, qb, poses, cot, direction: Optional[np.ndarray] = None,
-                seeds=(1, 2, 3), threads: int = 0):
+                seeds=(1, 2, 3), threads: int = 0, concurrent: bool = False, return_base: bool = False):
     """Conditioning of each query at FP32 precision (the oracle's probe).
 
     Re-evaluates the gradient (and H v) with every intermediate that an FP32
@@ -252,17 +252,33 @@ def fp32_spread(prm: Params, objs, qa, qb, poses, cot, direction: Optional[np.nd
     and returns the largest per-query change: (dg [n], dh [n] or None), norms
     over the 12-vector.  A result that moves by dg under this perturbation
     cannot be held to less than about dg by any FP32 implementation.
+    With ``concurrent`` the unperturbed and perturbed evaluations run at the
+    same time (each with ``threads`` threads), for batches of fewer queries
+    than cores; the results are the same.  With ``return_base`` the
+    unperturbed gradient (and H v) follow: (dg, dh, grad, hv).
     """
-    base = grad_hvp(prm, objs, qa, qb, poses, cot, direction, threads)
-    g0, h0 = base if direction is not None else (base, None)
-    dg = np.zeros(len(g0))
-    dh = np.zeros(len(g0)) if direction is not None else None
+    variants = [prm]
     for s in seeds:
         p = Params.from_buffer_copy(prm)
         p.jitter, p.jitter_seed = FP32_UNIT_ROUNDOFF, int(s)
-        r = grad_hvp(p, objs, qa, qb, poses, cot, direction, threads)
+        variants.append(p)
+
+    def run(p):
+        return grad_hvp(p, objs, qa, qb, poses, cot, direction, threads)
+
+    if concurrent:
+        from concurrent.futures import ThreadPoolExecutor
+        with ThreadPoolExecutor(len(variants)) as ex:
+            results = list(ex.map(run, variants))
+    else:
+        results = [run(p) for p in variants]
+    base = results[0]
+    g0, h0 = base if direction is not None else (base, None)
+    dg = np.zeros(len(g0))
+    dh = np.zeros(len(g0)) if direction is not None else None
+    for r in results[1:]:
         g, h = r if direction is not None else (r, None)
         dg = np.maximum(dg, np.linalg.norm(g - g0, axis=1))
         if dh is not None:
             dh = np.maximum(dh, np.linalg.norm(h - h0, axis=1))
-    return dg, dh
+    return (dg, dh, g0, h0) if return_base else (dg, dh)

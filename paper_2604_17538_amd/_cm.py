@@ -93,6 +93,8 @@ cm_graph_create = _sig("cm_graph_create", I32, [P, P, P, cm_groups, cm_groups, P
 cm_graph_launch = _sig("cm_graph_launch", I32, [P, P])
 cm_graph_destroy = _sig("cm_graph_destroy", I32, [P])
 cm_plan_autotune = _sig("cm_plan_autotune", I32, [P, P, P, cm_groups, P, P, P, P, ctypes.POINTER(I32)])
+cm_plan_set_launch_shape = _sig("cm_plan_set_launch_shape", I32, [P, I32, I32])
+cm_plan_launch_shape = _sig("cm_plan_launch_shape", I32, [P, ctypes.POINTER(I32), ctypes.POINTER(I32)])
 cm_submit = _sig("cm_submit", I32, [P, ctypes.POINTER(cm_request), ctypes.POINTER(U64)])
 cm_poll = _sig("cm_poll", I32, [P, U64, ctypes.POINTER(I32), ctypes.POINTER(I32)])
 cm_wait = _sig("cm_wait", I32, [P, U64, I32, ctypes.POINTER(I32)])
@@ -104,5 +106,6 @@ EXPORTED = ["cm_default_params", "cm_init", "cm_shutdown", "cm_last_error", "cm_
             "cm_plan_create", "cm_plan_destroy", "cm_plan_info", "cm_plan_offsets", "cm_plan_stats", "cm_plan_work",
             "cm_plan_set_timing", "cm_plan_timing",
             "cm_contacts_fwd", "cm_contacts_bwd", "cm_hvp", "cm_contacts_step", "cm_graph_create", "cm_graph_launch",
-            "cm_graph_destroy", "cm_plan_autotune", "cm_submit", "cm_poll", "cm_wait", "cm_serve_stats",
+            "cm_graph_destroy", "cm_plan_autotune", "cm_plan_set_launch_shape", "cm_plan_launch_shape",
+            "cm_submit", "cm_poll", "cm_wait", "cm_serve_stats",
             "cm_serve_latencies"]

@@ -273,6 +273,18 @@ class Plan:
         self.ctx._check(st, "cm_plan_autotune")
         return int(best.value)
 
+    @property
+    def launch_shape(self) -> tuple:
+        """(float sweeps, dual sweeps) persistent workgroups per CU."""
+        f, d = ctypes.c_int32(), ctypes.c_int32()
+        self.ctx._check(_cm.cm_plan_launch_shape(self._h, ctypes.byref(f), ctypes.byref(d)), "cm_plan_launch_shape")
+        return int(f.value), int(d.value)
+
+    @launch_shape.setter
+    def launch_shape(self, shape):
+        self.ctx._check(_cm.cm_plan_set_launch_shape(self._h, int(shape[0]), int(shape[1])),
+                        "cm_plan_set_launch_shape")
+
     def hvp(self, q_dev, cot, direction, hv=None, grad=None, stream=None):
         torch = _torch()
         if hv is None:

@@ -105,4 +105,20 @@ cm_status cm_plan_autotune(cm_context* ctx, cm_plan* pl, const cm_query* q, cm_g
   return st == CM_OK ? CM_OK : fail(ctx, st, "autotune failed");
 }
 
+cm_status cm_plan_set_launch_shape(cm_plan* pl, int32_t float_per_cu, int32_t dual_per_cu) {
+  if (!pl) return CM_E_INVALID;
+  if (float_per_cu < 1 || float_per_cu > 32 || dual_per_cu < 1 || dual_per_cu > 32)
+    return fail(pl->ctx, CM_E_INVALID, "launch shape outside [1, 32] workgroups per CU");
+  pl->blocks_per_cu = float_per_cu;
+  pl->blocks_per_cu_dual = dual_per_cu;
+  return CM_OK;
+}
+
+cm_status cm_plan_launch_shape(const cm_plan* pl, int32_t* float_per_cu, int32_t* dual_per_cu) {
+  if (!pl) return CM_E_INVALID;
+  if (float_per_cu) *float_per_cu = pl->blocks_per_cu;
+  if (dual_per_cu) *dual_per_cu = pl->blocks_per_cu_dual;
+  return CM_OK;
+}
+
 }  // extern "C"

@@ -87,3 +87,18 @@ def test_autotune_changes_no_result(setup):
         assert np.array_equal(a, b)
     for a, b in zip(_eager_float(s, s["qd"]), ref_f):
         assert np.array_equal(a, b)
+
+
+def test_launch_shape_setter(setup):
+    s = setup
+    plan = s["plan"]
+    ref = _eager(s, s["qd"])
+    keep = plan.launch_shape
+    plan.launch_shape = (3, 5)
+    assert plan.launch_shape == (3, 5)
+    for a, b in zip(_eager(s, s["qd"]), ref):
+        assert np.array_equal(a, b)
+    with pytest.raises(s["api"].CMError):
+        plan.launch_shape = (0, 5)
+    assert plan.launch_shape == (3, 5)
+    plan.launch_shape = keep
