@@ -166,9 +166,11 @@ cm_status cm_plan_stats(const cm_plan* plan, int64_t* stats8);
 
 /* Point-plane evaluations the narrow-phase kernels of the plan's last pass
  * performed (synchronous), counted per wave lane including lanes of partly
- * filled tiles and the support-plane bounds, after piece pruning; compare
- * with the dense count of cm_plan_stats [5] (times the evaluation passes). */
-cm_status cm_plan_work(const cm_plan* plan, int64_t* performed);
+ * filled tiles and the support-plane bounds, after piece pruning:
+ * performed2[0] for vertex contacts, performed2[1] for edge contacts (all
+ * trace steps); compare with cm_plan_stats [6] and (2 K + 1) x [7] (times the
+ * evaluation passes). */
+cm_status cm_plan_work(const cm_plan* plan, int64_t* performed2);
 
 /* Kernel timing with HIP events recorded on the launch stream around the
  * broad phase and each narrow-phase kernel of the plan's launches (off by

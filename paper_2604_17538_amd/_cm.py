@@ -82,7 +82,7 @@ cm_plan_destroy = _sig("cm_plan_destroy", I32, [P])
 cm_plan_info = _sig("cm_plan_info", I32, [P, ctypes.POINTER(I64), ctypes.POINTER(I64), ctypes.POINTER(I32)])
 cm_plan_offsets = _sig("cm_plan_offsets", I32, [P, P, P])
 cm_plan_stats = _sig("cm_plan_stats", I32, [P, P])
-cm_plan_work = _sig("cm_plan_work", I32, [P, ctypes.POINTER(I64)])
+cm_plan_work = _sig("cm_plan_work", I32, [P, P])
 cm_plan_set_timing = _sig("cm_plan_set_timing", I32, [P, I32])
 cm_plan_timing = _sig("cm_plan_timing", I32, [P, P])
 cm_contacts_fwd = _sig("cm_contacts_fwd", I32, [P, P, P, cm_groups, P, P])

@@ -305,11 +305,12 @@ class Plan:
         return dict(broad=float(ms[0]), narrow_fwd=float(ms[1]), narrow_tan=float(ms[2]),
                     narrow_adj=float(ms[3]), narrow_dual_adj=float(ms[4]))
 
-    def work(self) -> int:
-        """Point-plane evaluations performed by the last pass (cm_plan_work)."""
-        v = ctypes.c_int64()
-        self.ctx._check(_cm.cm_plan_work(self._h, ctypes.byref(v)), "cm_plan_work")
-        return int(v.value)
+    def work(self) -> tuple:
+        """Point-plane evaluations performed by the last pass for vertex and for
+        edge contacts (cm_plan_work)."""
+        v = np.zeros(2, np.int64)
+        self.ctx._check(_cm.cm_plan_work(self._h, _ptr(v)), "cm_plan_work")
+        return int(v[0]), int(v[1])
 
     def stats(self) -> dict:
         s = np.zeros(8, np.int64)

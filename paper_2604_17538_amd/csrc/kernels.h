@@ -99,7 +99,8 @@ struct NarrowArgs {
   int64_t tape_tiles;
   int32_t tape_nv;
   int64_t t_begin;        // first tile of this launch (recomputing adjoint)
-  unsigned long long* work;  // nullable: += point-plane evaluations performed (64 lanes per wave)
+  unsigned long long* work;  // nullable: [2] += point-plane evaluations performed for vertex and
+                             // edge contacts (64 lanes per wave)
 };
 
 struct FinArgs {

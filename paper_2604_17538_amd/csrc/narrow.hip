@@ -452,7 +452,7 @@ __global__ __launch_bounds__(256) void k_narrow(NarrowArgs a) {
   const int64_t rs = a.tape_tiles * kWave;
   const DevParams& P = a.P;
   constexpr bool HIST = ADJ || TAPE;  // Hessian and trace history
-  uint64_t work = 0;                  // point-plane evaluations per lane (wave-uniform)
+  uint64_t work[2] = {0, 0};          // point-plane evaluations per lane by contact kind (wave-uniform)
   // each pop returns a distinct tile, so a wave pops at most total + 1 times
   for (int64_t it = 0; it <= total; ++it) {
     uint32_t t0 = 0;
@@ -488,8 +488,8 @@ __global__ __launch_bounds__(256) void k_narrow(NarrowArgs a) {
     } else {
       // the store sweep writes the records of taped tiles
       float* tp = (!ADJ && TAPE && t < a.tape_tiles) ? a.tape : nullptr;
-      if (E0.kind == 0) vertex_fwd<T, HIST>(M, S, F, ci, P, ct, &work);
-      else edge_fwd<T, HIST>(M, S, F, ci, P, ct, tr, &work, tp, rs, slot);
+      if (E0.kind == 0) vertex_fwd<T, HIST>(M, S, F, ci, P, ct, &work[0]);
+      else edge_fwd<T, HIST>(M, S, F, ci, P, ct, tr, &work[1], tp, rs, slot);
       if (tp != nullptr) tape_store(ct, tp, rs, slot);
     }
     if (!ADJ) {
@@ -546,7 +546,10 @@ __global__ __launch_bounds__(256) void k_narrow(NarrowArgs a) {
       }
     }
   }
-  if (a.work != nullptr && l == 0 && work != 0) atomicAdd(a.work, (unsigned long long)(work * kWave));
+  if (a.work != nullptr && l == 0) {
+    if (work[0] != 0) atomicAdd(a.work, (unsigned long long)(work[0] * kWave));
+    if (work[1] != 0) atomicAdd(a.work + 1, (unsigned long long)(work[1] * kWave));
+  }
 }
 
 // ---------------------------------------------------------------- finalize --
@@ -771,7 +774,7 @@ static FinArgs fin_args(const FwdArgs& a, const float* partials, const float* di
 // left by an unrelated runtime call is cleared first.
 hipError_t launch_forward(const FwdArgs& a, hipStream_t s) {
   (void)hipGetLastError();
-  if (a.work) launch_fill_u32(reinterpret_cast<uint32_t*>(a.work), 0u, 2, s);
+  if (a.work) launch_fill_u32(reinterpret_cast<uint32_t*>(a.work), 0u, 4, s);
   launch_front(a, s);
   const int grid = a.n_cu * a.blocks_per_cu;
   narrow_launch<float, false, false>(narrow_args(a, a.partials, nullptr, a.dbg), grid, s, a.ev);
@@ -787,7 +790,7 @@ hipError_t launch_forward(const FwdArgs& a, hipStream_t s) {
 // per-query reduction.  T = df adds the tangents along `dir` (H v).
 template <class T> static hipError_t adjoint_impl(const FwdArgs& a, hipStream_t s, bool records) {
   (void)hipGetLastError();
-  if (a.work) launch_fill_u32(reinterpret_cast<uint32_t*>(a.work), 0u, 2, s);
+  if (a.work) launch_fill_u32(reinterpret_cast<uint32_t*>(a.work), 0u, 4, s);
   launch_front(a, s);
   const int grid = a.n_cu * (nT<T>() == 2 ? a.blocks_per_cu_dual : a.blocks_per_cu);
   const float* dir = a.dir;

@@ -804,10 +804,11 @@ cm_status cm_plan_offsets(const cm_plan* pl, int64_t* group_off, int64_t* contac
 
 cm_status cm_plan_work(const cm_plan* pl, int64_t* performed) {
   if (!pl || !performed) return CM_E_INVALID;
-  unsigned long long w = 0;
+  unsigned long long w[2] = {0, 0};
   CM_HIP(pl->ctx, hipDeviceSynchronize());
-  CM_HIP(pl->ctx, hipMemcpy(&w, pl->d_work, 8, hipMemcpyDeviceToHost));
-  *performed = int64_t(w);
+  CM_HIP(pl->ctx, hipMemcpy(w, pl->d_work, 16, hipMemcpyDeviceToHost));
+  performed[0] = int64_t(w[0]);
+  performed[1] = int64_t(w[1]);
   return CM_OK;
 }
 

@@ -1,0 +1,104 @@
+"""GPU parity on the large workload: 65536 pairs of 32-piece objects (pieces
+hulls of log-uniform [64, 1024] ellipsoid points; the objects drawn from a
+library of 2048), all in one plan and one cm_contacts_step (records, gradient
+w.r.t. both poses, H v), in the launch configuration the benchmark uses for
+this workload.  Four sampled queries are compared with the FP64 oracle's
+values stored in tests/golden/c4_oracle.json (written by
+tests/golden/c4_oracle.py, which calls only the oracle), and the same queries
+in a plan of their own must give bitwise the same results as inside the full
+batch.
+
+Tolerances as for the other workloads: positions and distances 1e-5 L_s,
+weights and normals 1e-4, gradients 1e-4 and H v 1e-3 relative, each
+derivative also allowed 4 times the query's FP32 spread."""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2604_17538_amd import workloads as W
+from tests import parity as PT
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+REL, REL_HVP, K_SPREAD = 1e-4, 1e-3, 4.0
+BUDGET = 256 << 30  # the benchmark's memory budget for this workload (a quarter holds the adjoint tape)
+
+
+def _log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def _ratio(a, b, floor, spread, rel):
+    nb = np.linalg.norm(b, axis=1)
+    allowed = np.maximum(rel * np.maximum(nb, floor), K_SPREAD * spread)
+    return np.linalg.norm(a - b, axis=1) / allowed
+
+
+@pytest.fixture(scope="module")
+def c4():
+    sys.path.insert(0, os.path.join(HERE, "golden"))
+    import c4_oracle as G
+    with open(os.path.join(HERE, "golden", "c4_oracle.json")) as f:
+        ref = json.load(f)
+    _log("c4: generating the workload")
+    w = W.config4(n_envs=ref["workload"]["n_envs"], library=ref["workload"]["library"])
+    sel = np.array(ref["sel"], np.int64)
+    assert G.input_digest(w, sel) == ref["input_sha256"], "the workload generator no longer gives the stored inputs"
+    return w, sel, ref
+
+
+def test_full_launch_sampled(c4):
+    import torch
+    from paper_2604_17538_amd import api
+    w, sel, ref = c4
+    ctx = api.Context(0, L_ref=w.L_ref, budget_bytes=BUDGET)
+    hs = ctx.build_objects(w.objects)
+    _log("c4: objects resident")
+    plan = ctx.plan(hs[w.qa], hs[w.qb])
+    _log("c4: plan of %d queries, %d groups, %d contacts" % (plan.n, plan.G, plan.C))
+    qd = plan.device_queries(w.poses)
+    goff_s = np.array(ref["group_off"], np.int64)
+    cot_s = W.cotangents(w.cot_seed, goff_s[-1])
+    dir_s = W.directions(w.cot_seed, len(sel))
+    rng = np.random.default_rng(7)
+    cot = rng.standard_normal((plan.G, 12)).astype(np.float32)
+    direc = rng.standard_normal((w.n, 12)).astype(np.float32)
+    for k, i in enumerate(sel):
+        assert plan.group_off[i + 1] - plan.group_off[i] == goff_s[k + 1] - goff_s[k]
+        cot[plan.group_off[i]:plan.group_off[i + 1]] = cot_s[goff_s[k]:goff_s[k + 1]]
+        direc[i] = dir_s[k]
+    cot_d = torch.tensor(np.ascontiguousarray(cot.T)).cuda()
+    dir_d = torch.tensor(direc).cuda()
+    out, grad, hv = plan.step(qd, cot_d, dir_d)
+    torch.cuda.synchronize()
+    _log("c4: step done")
+    g = out.cpu().numpy().T.astype(np.float64)
+    rows = np.concatenate([np.arange(plan.group_off[i], plan.group_off[i + 1]) for i in sel])
+    Ls = np.array(ref["scene_scale"])
+    err = PT.check_groups(g[rows], np.array(ref["records"]), np.repeat(Ls, np.diff(goff_s)), ctx.params.tau_blend)
+    _log("c4 records: %s" % err)
+    for k in ("pos", "logZ", "W", "n"):
+        assert err[k] <= 1.0, (k, err)
+    cq = np.sqrt(np.add.reduceat((cot_s.astype(np.float64) ** 2).sum(1), goff_s[:-1]))
+    floor = 1e-3 * cq * np.maximum(1.0, Ls)
+    gg, hh = grad.cpu().numpy()[sel].astype(np.float64), hv.cpu().numpy()[sel].astype(np.float64)
+    r = _ratio(gg, np.array(ref["grad"]), floor, np.array(ref["spread_grad"]), REL)
+    _log("c4 gradient: max error / allowed %.3f" % r.max())
+    assert r.max() <= 1.0, ("grad", r)
+    r = _ratio(hh, np.array(ref["hv"]), floor, np.array(ref["spread_hv"]), REL_HVP)
+    _log("c4 H v: max error / allowed %.3f" % r.max())
+    assert r.max() <= 1.0, ("hvp", r)
+    # the sampled queries alone: bitwise the same as inside the full batch
+    small = ctx.plan(hs[w.qa[sel]], hs[w.qb[sel]])
+    q1 = small.device_queries(w.poses[sel])
+    c1 = torch.tensor(np.ascontiguousarray(cot[rows].T)).cuda()
+    d1 = torch.tensor(direc[sel]).cuda()
+    o1, g1, h1 = small.step(q1, c1, d1)
+    torch.cuda.synchronize()
+    assert np.array_equal(o1.cpu().numpy().T, out.cpu().numpy().T[rows])
+    assert np.array_equal(g1.cpu().numpy(), grad.cpu().numpy()[sel])
+    assert np.array_equal(h1.cpu().numpy(), hv.cpu().numpy()[sel])
