@@ -191,6 +191,8 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-separate", action="store_true", help="skip timing the three separate calls")
+    ap.add_argument("--launch-shape", default=None,
+                    help="F,D: fixed persistent workgroups per CU for the float and dual sweeps (no autotuning)")
     ap.add_argument("--tune-sample", type=int, default=16384,
                     help="autotune on a plan of the first N pair-queries when the batch is larger")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -260,7 +262,11 @@ def main():
 
     # launch shapes picked by the autotuner (persistent workgroups per CU), one
     # for the sweeps in dual numbers (this step) and one for the float sweeps
-    if w.n <= args.tune_sample:
+    if args.launch_shape:
+        shape_f, shape = (int(v) for v in args.launch_shape.split(","))
+        plan.launch_shape = (shape_f, shape)
+        tuned_on = 0
+    elif w.n <= args.tune_sample:
         shape = plan.autotune(qd, cot_d, grad, dir_d, hv, stream)
         shape_f = plan.autotune(qd, cot_d, grad, stream=stream)
         tuned_on = w.n

@@ -235,12 +235,14 @@ CM_DEV void sdf_eval(const ObjDesc& o, const DevParams& P, const V3<T>* x, SdfRe
     const F4* sp = o.sub + int64_t(kSub) * k;
     V3<T> xl[NP];
     float m[NP];
-    V3<float> ref[NP];  // PREC: kappa n of the max plane
+    // PREC: the max plane, as an index into the piece's planes (>= 0) or its
+    // support subset (-1 - j); its kappa n is read once the passes are done
+    int jm[NP];
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
       xl[p] = x[p] - V3<float>{pd.cx, pd.cy, pd.cz};
       m[p] = -__builtin_inff();
-      ref[p] = {0.f, 0.f, 0.f};
+      jm[p] = -1;
     }
     // the support subset: a lower bound of the piece SDF, and for a piece of
     // at most kSub planes (the subset is all of them) already the LSE shift
@@ -254,7 +256,7 @@ CM_DEV void sdf_eval(const ObjDesc& o, const DevParams& P, const V3<T>* x, SdfRe
           if (PREC) {
             const bool up = a > m[p];
             m[p] = up ? a : m[p];
-            ref[p] = up ? V3<float>{q.x, q.y, q.z} : ref[p];
+            jm[p] = up ? -1 - j : jm[p];
           } else {
             m[p] = fmaxf(m[p], a);
           }
@@ -280,11 +282,20 @@ CM_DEV void sdf_eval(const ObjDesc& o, const DevParams& P, const V3<T>* x, SdfRe
           if (PREC) {
             const bool up = a > m[p];
             m[p] = up ? a : m[p];
-            ref[p] = up ? V3<float>{q.x, q.y, q.z} : ref[p];
+            jm[p] = up ? j : jm[p];
           } else {
             m[p] = fmaxf(m[p], a);
           }
         }
+      }
+    }
+    V3<float> ref[NP];  // PREC: kappa n of the max plane (first of equal ones)
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+      ref[p] = {0.f, 0.f, 0.f};
+      if (PREC && np > 0) {
+        const F4 q = jm[p] >= 0 ? pl[jm[p]] : sp[-1 - jm[p]];
+        ref[p] = {q.x, q.y, q.z};
       }
     }
     // pass 2: sums (PREC: of kappa (n - n_ref) and its outer products)
