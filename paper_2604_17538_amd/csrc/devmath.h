@@ -159,11 +159,58 @@ template <class T> struct SdfRes {
   Sym<T> H;
 };
 
+template <class T> struct IsDual { static constexpr bool value = false; };
+template <> struct IsDual<df> { static constexpr bool value = true; };
+
 // dot of a scaled plane (kappa n, kappa h) with a point relative to the piece centre
 CM_DEV float pdot(const F4& q, V3<float> x) { return fmaf(q.x, x.x, fmaf(q.y, x.y, fmaf(q.z, x.z, q.w))); }
 CM_DEV df pdot(const F4& q, V3<df> x) {
   return {fmaf(q.x, x.x.v, fmaf(q.y, x.y.v, fmaf(q.z, x.z.v, q.w))), fmaf(q.x, x.x.t, fmaf(q.y, x.y.t, q.z * x.z.t))};
 }
+
+// The same dots for a block of 4 consecutive planes at every lane's point, on
+// the matrix cores (v_mfma_f32_4x4x1_16b_f32: 16 blocks of 4 lanes, result i
+// of lane l = A(lane 4 (l / 4) + i) B(l) + C_i).  Lane l supplies plane l & 3
+// of the block as A and its own point as B, so result i is plane i at the
+// lane's point.  Accumulated in the order w, z, y, x, one rounding per step,
+// the values are those of pdot bit for bit (up to the sign of a zero).  The
+// operands are read across lanes: every lane of the wave executes these.
+typedef float f4v __attribute__((ext_vector_type(4)));
+CM_DEV f4v mdot(const F4& ql, V3<float> x) {
+  f4v a = {0.f, 0.f, 0.f, 0.f};
+  a = __builtin_amdgcn_mfma_f32_4x4x1f32(ql.w, 1.f, a, 0, 0, 0);
+  a = __builtin_amdgcn_mfma_f32_4x4x1f32(ql.z, x.z, a, 0, 0, 0);
+  a = __builtin_amdgcn_mfma_f32_4x4x1f32(ql.y, x.y, a, 0, 0, 0);
+  return __builtin_amdgcn_mfma_f32_4x4x1f32(ql.x, x.x, a, 0, 0, 0);
+}
+// kappa n . t for a tangent t (the dual part of pdot)
+CM_DEV f4v mdot_n(const F4& ql, V3<float> t) {
+  f4v a = {0.f, 0.f, 0.f, 0.f};
+  a = __builtin_amdgcn_mfma_f32_4x4x1f32(ql.z, t.z, a, 0, 0, 0);
+  a = __builtin_amdgcn_mfma_f32_4x4x1f32(ql.y, t.y, a, 0, 0, 0);
+  return __builtin_amdgcn_mfma_f32_4x4x1f32(ql.x, t.x, a, 0, 0, 0);
+}
+// this lane's plane of the block q[j .. j + 3] (the last plane repeated past n),
+// read through the global address space (plane data lives in device memory)
+typedef __attribute__((address_space(1))) const v4i* gv4p;
+CM_DEV F4 blk_plane(const F4* q, int j, int n) {
+  const v4i w = ((gv4p)q)[min(j + (int(threadIdx.x) & 3), n - 1)];
+  F4 r;
+  __builtin_memcpy(&r, &w, 16);
+  return r;
+}
+// plane values of a block at NP points: value and (dual scalars) tangent
+template <int NP, class T>
+CM_DEV void blk_vals(const F4& ql, const V3<T>* xl, f4v* av, f4v* at) {
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    av[p] = mdot(ql, val3(xl[p]));
+    if (IsDual<T>::value) at[p] = mdot_n(ql, V3<float>{tan_(xl[p].x), tan_(xl[p].y), tan_(xl[p].z)});
+  }
+}
+template <class T> CM_DEV T mkT(float v, float t);
+template <> CM_DEV float mkT<float>(float v, float) { return v; }
+template <> CM_DEV df mkT<df>(float v, float t) { return df{v, t}; }
 
 // SDF of a union of convex pieces at NP points per lane (Sec. III-A.2/3):
 //   phi_k = tau_cap LSE_j (n_kj . x + h_kj)          smooth intersection
@@ -187,8 +234,6 @@ CM_DEV df pdot(const F4& q, V3<df> x) {
 // accumulated without that cancellation: the normals of a piece relative to
 // the normal of its max plane, and the piece gradients with a weighted Welford
 // update of their running mean.
-template <class T> struct IsDual { static constexpr bool value = false; };
-template <> struct IsDual<df> { static constexpr bool value = true; };
 template <class T, class S> CM_DEV Sym<T> operator*(const Sym<T>& a, S s) {
   return {a.xx * s, a.yy * s, a.zz * s, a.xy * s, a.xz * s, a.yz * s}; }
 template <class T> CM_DEV Sym<T> operator+(const Sym<T>& a, const Sym<T>& b) {
@@ -238,9 +283,11 @@ CM_DEV void sdf_eval(const ObjDesc& o, const DevParams& P, const V3<T>* x, SdfRe
     // PREC: the max plane, as an index into the piece's planes (>= 0) or its
     // support subset (-1 - j); its kappa n is read once the passes are done
     int jm[NP];
+    V3<float> xl0[NP];  // their values
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
       xl[p] = x[p] - V3<float>{pd.cx, pd.cy, pd.cz};
+      xl0[p] = val3(xl[p]);
       m[p] = -__builtin_inff();
       jm[p] = -1;
     }
@@ -248,17 +295,25 @@ CM_DEV void sdf_eval(const ObjDesc& o, const DevParams& P, const V3<T>* x, SdfRe
     // at most kSub planes (the subset is all of them) already the LSE shift
     if (P.prune || np <= kSub) {
       if (work && P.prune) *work += uint64_t(ns * NP);  // the bound
-      for (int j = 0; j < ns; ++j) {
-        const F4 q = ldc(sp + j);
+      // (a block's repeats of the last plane never raise the max: equal values)
+      F4 qn = ns > 0 ? blk_plane(sp, 0, ns) : F4{0.f, 0.f, 0.f, 0.f};  // the next block's plane, loaded a block ahead
+      for (int j = 0; j < ns; j += 4) {
+        const F4 ql = qn;
+        qn = blk_plane(sp, j + 4 < ns ? j + 4 : j, ns);
+        f4v av[NP], at[NP];
+        blk_vals<NP, float>(ql, xl0, av, at);
 #pragma unroll
-        for (int p = 0; p < NP; ++p) {
-          const float a = pdot(q, val3(xl[p]));
-          if (PREC) {
-            const bool up = a > m[p];
-            m[p] = up ? a : m[p];
-            jm[p] = up ? -1 - j : jm[p];
-          } else {
-            m[p] = fmaxf(m[p], a);
+        for (int i = 0; i < 4; ++i) {
+#pragma unroll
+          for (int p = 0; p < NP; ++p) {
+            const float a = av[p][i];
+            if (PREC) {
+              const bool up = a > m[p];
+              m[p] = up ? a : m[p];
+              jm[p] = up ? -1 - (j + i) : jm[p];
+            } else {
+              m[p] = fmaxf(m[p], a);
+            }
           }
         }
       }
@@ -273,18 +328,24 @@ CM_DEV void sdf_eval(const ObjDesc& o, const DevParams& P, const V3<T>* x, SdfRe
     if (work) *work += uint64_t(np * NP);
     // pass 1: shift = max_j a_j (value only; LSE is shift-invariant)
     if (np > kSub) {
-#pragma unroll 4
-      for (int j = 0; j < np; ++j) {
-        const F4 q = ldc(pl + j);
+      F4 qn = blk_plane(pl, 0, np);
+      for (int j = 0; j < np; j += 4) {
+        const F4 ql = qn;
+        qn = blk_plane(pl, j + 4 < np ? j + 4 : j, np);
+        f4v av[NP], at[NP];
+        blk_vals<NP, float>(ql, xl0, av, at);
 #pragma unroll
-        for (int p = 0; p < NP; ++p) {
-          const float a = pdot(q, val3(xl[p]));
-          if (PREC) {
-            const bool up = a > m[p];
-            m[p] = up ? a : m[p];
-            jm[p] = up ? j : jm[p];
-          } else {
-            m[p] = fmaxf(m[p], a);
+        for (int i = 0; i < 4; ++i) {
+#pragma unroll
+          for (int p = 0; p < NP; ++p) {
+            const float a = av[p][i];
+            if (PREC) {
+              const bool up = a > m[p];
+              m[p] = up ? a : m[p];
+              jm[p] = up ? j + i : jm[p];
+            } else {
+              m[p] = fmaxf(m[p], a);
+            }
           }
         }
       }
@@ -294,7 +355,7 @@ CM_DEV void sdf_eval(const ObjDesc& o, const DevParams& P, const V3<T>* x, SdfRe
     for (int p = 0; p < NP; ++p) {
       ref[p] = {0.f, 0.f, 0.f};
       if (PREC && np > 0) {
-        const F4 q = jm[p] >= 0 ? pl[jm[p]] : sp[-1 - jm[p]];
+        const F4 q = jm[p] >= 0 ? pl[min(jm[p], np - 1)] : sp[min(-1 - jm[p], ns - 1)];
         ref[p] = {q.x, q.y, q.z};
       }
     }
@@ -308,12 +369,11 @@ CM_DEV void sdf_eval(const ObjDesc& o, const DevParams& P, const V3<T>* x, SdfRe
       if (MODE >= 1) G[p] = zero3<T>();
       if (MODE >= 2) N[p] = zsym<T>();
     }
-#pragma unroll 4
-    for (int j = 0; j < np; ++j) {
-      const F4 q = ldc(pl + j);
+    // plane j + i of a block (q: its wave-uniform copy) at the NP points
+    auto term = [&](const F4& q, const f4v* av, const f4v* at, int i) {
 #pragma unroll
       for (int p = 0; p < NP; ++p) {
-        const T e = ex2(pdot(q, xl[p]) - m[p]);
+        const T e = ex2(mkT<T>(av[p][i], IsDual<T>::value ? at[p][i] : 0.f) - m[p]);
         s[p] += e;
         if (MODE >= 1) {
           const float dx = PREC ? q.x - ref[p].x : q.x;
@@ -329,6 +389,23 @@ CM_DEV void sdf_eval(const ObjDesc& o, const DevParams& P, const V3<T>* x, SdfRe
           }
         }
       }
+    };
+    int j = 0;
+    F4 qn = np > 0 ? blk_plane(pl, 0, np) : F4{0.f, 0.f, 0.f, 0.f};
+    for (; j + 4 <= np; j += 4) {
+      const F4 ql = qn;
+      qn = blk_plane(pl, j + 4 < np ? j + 4 : j, np);
+      f4v av[NP], at[NP];
+      blk_vals<NP, T>(ql, xl, av, at);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) term(ldc(pl + j + i), av, at, i);
+    }
+    if (j < np) {  // the last, partial block
+      f4v av[NP], at[NP];
+      blk_vals<NP, T>(qn, xl, av, at);
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+        if (j + i < np) term(ldc(pl + j + i), av, at, i);
     }
     // combine the piece into the running smooth union
 #pragma unroll
