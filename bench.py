@@ -62,10 +62,13 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
+def measured_traffic(config="c2", pairs=None):
     """HBM bytes per launch of the dominant kernel from the committed counter
     summary (FETCH_SIZE and WRITE_SIZE scaled by a 1 GiB copy), or None when the
-    kernel sources changed since the counters were taken."""
+    kernel sources changed since the counters were taken or the workload is not
+    the one they were taken on (C2 at its full 16384 pair-queries)."""
+    if config != "c2" or pairs not in (None, 16384):
+        return None
     try:
         with open(TRAFFIC_PROFILE) as f:
             lines = f.read().splitlines()
@@ -331,7 +334,7 @@ def main():
     perf_achieved = perf_ops / (dom_ms * 1e-3)
     roofline = {"bound": "alu", "kernel": "k_narrow<df, forward, tape>", "achieved": round(achieved / 1e12, 3),
                 "peak": round(PEAK_LANE_OPS / 1e12, 3), "unit": "T lane-op/s (FP32 VALU)",
-                "frac": round(achieved / PEAK_LANE_OPS, 4), "traffic": measured_traffic(),
+                "frac": round(achieved / PEAK_LANE_OPS, 4), "traffic": measured_traffic(args.config, args.pairs),
                 "kernel_ms": round(dom_ms, 3), "alg_ops_per_launch": int(alg_ops),
                 "algorithmic_point_plane": int(st["pairs"]), "performed_point_plane": int(work_v + work_e),
                 "performed_achieved": round(perf_achieved / 1e12, 3),

@@ -246,6 +246,9 @@ template <class T> CM_DEV Sym<T> outer(V3<T> a) {
 template <int NP, int MODE, class T>
 CM_DEV void sdf_eval(const ObjDesc& o, const DevParams& P, const V3<T>* x, SdfRes<T>* r, uint64_t* work = nullptr) {
   constexpr bool PREC = MODE == 2 || (MODE == 1 && IsDual<T>::value);
+  // dot products on the matrix cores where each plane carries enough VALU work
+  // to hide their latency (second-order or dual terms); on the VALU otherwise
+  constexpr bool MF = PREC;
   float M[NP];
   T S[NP];
   V3<T> Ug[NP];           // sum u_k g_k (kappa folded out); PREC: running weighted mean of g_k
@@ -296,8 +299,15 @@ CM_DEV void sdf_eval(const ObjDesc& o, const DevParams& P, const V3<T>* x, SdfRe
     if (P.prune || np <= kSub) {
       if (work && P.prune) *work += uint64_t(ns * NP);  // the bound
       // (a block's repeats of the last plane never raise the max: equal values)
-      F4 qn = ns > 0 ? blk_plane(sp, 0, ns) : F4{0.f, 0.f, 0.f, 0.f};  // the next block's plane, loaded a block ahead
-      for (int j = 0; j < ns; j += 4) {
+      if (!MF) {
+        for (int j = 0; j < ns; ++j) {
+          const F4 q = ldc(sp + j);
+#pragma unroll
+          for (int p = 0; p < NP; ++p) m[p] = fmaxf(m[p], pdot(q, xl0[p]));
+        }
+      }
+      F4 qn = MF && ns > 0 ? blk_plane(sp, 0, ns) : F4{0.f, 0.f, 0.f, 0.f};  // the next block's plane, loaded a block ahead
+      for (int j = 0; MF && j < ns; j += 4) {
         const F4 ql = qn;
         qn = blk_plane(sp, j + 4 < ns ? j + 4 : j, ns);
         f4v av[NP], at[NP];
@@ -327,7 +337,15 @@ CM_DEV void sdf_eval(const ObjDesc& o, const DevParams& P, const V3<T>* x, SdfRe
     // point-plane evaluations performed by the wave (per lane)
     if (work) *work += uint64_t(np * NP);
     // pass 1: shift = max_j a_j (value only; LSE is shift-invariant)
-    if (np > kSub) {
+    if (np > kSub && !MF) {
+#pragma unroll 4
+      for (int j = 0; j < np; ++j) {
+        const F4 q = ldc(pl + j);
+#pragma unroll
+        for (int p = 0; p < NP; ++p) m[p] = fmaxf(m[p], pdot(q, xl0[p]));
+      }
+    }
+    if (np > kSub && MF) {
       F4 qn = blk_plane(pl, 0, np);
       for (int j = 0; j < np; j += 4) {
         const F4 ql = qn;
@@ -390,9 +408,23 @@ CM_DEV void sdf_eval(const ObjDesc& o, const DevParams& P, const V3<T>* x, SdfRe
         }
       }
     };
+    if (!MF) {
+#pragma unroll 4
+      for (int jj = 0; jj < np; ++jj) {
+        const F4 q = ldc(pl + jj);
+        f4v av[NP], at[NP];
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+          const T a = pdot(q, xl[p]);
+          av[p][0] = val(a);
+          at[p][0] = tan_(a);
+        }
+        term(q, av, at, 0);
+      }
+    }
     int j = 0;
-    F4 qn = np > 0 ? blk_plane(pl, 0, np) : F4{0.f, 0.f, 0.f, 0.f};
-    for (; j + 4 <= np; j += 4) {
+    F4 qn = MF && np > 0 ? blk_plane(pl, 0, np) : F4{0.f, 0.f, 0.f, 0.f};
+    for (; MF && j + 4 <= np; j += 4) {
       const F4 ql = qn;
       qn = blk_plane(pl, j + 4 < np ? j + 4 : j, np);
       f4v av[NP], at[NP];
@@ -400,7 +432,7 @@ CM_DEV void sdf_eval(const ObjDesc& o, const DevParams& P, const V3<T>* x, SdfRe
 #pragma unroll
       for (int i = 0; i < 4; ++i) term(ldc(pl + j + i), av, at, i);
     }
-    if (j < np) {  // the last, partial block
+    if (MF && j < np) {  // the last, partial block
       f4v av[NP], at[NP];
       blk_vals<NP, T>(qn, xl, av, at);
 #pragma unroll
