@@ -422,22 +422,37 @@ CM_DEV void sdf_eval(const ObjDesc& o, const DevParams& P, const V3<T>* x, SdfRe
         term(q, av, at, 0);
       }
     }
-    int j = 0;
-    F4 qn = MF && np > 0 ? blk_plane(pl, 0, np) : F4{0.f, 0.f, 0.f, 0.f};
-    for (; MF && j + 4 <= np; j += 4) {
-      const F4 ql = qn;
-      qn = blk_plane(pl, j + 4 < np ? j + 4 : j, np);
-      f4v av[NP], at[NP];
-      blk_vals<NP, T>(ql, xl, av, at);
+    if (MF && np > 0) {
+      // Two blocks per iteration with ping-pong buffers for the lane's plane
+      // (matrix-core operand, vector load) and the block's planes (SGPRs, scalar
+      // loads), each refilled one block ahead: no buffer is copied across the
+      // loop, so every load has a whole block of work to complete.  Indices past
+      // the piece are clamped to its last plane (never used).
+      auto blk = [&](const F4& ql, const F4* sq, int j0, int cnt) {
+        f4v av[NP], at[NP];
+        blk_vals<NP, T>(ql, xl, av, at);
 #pragma unroll
-      for (int i = 0; i < 4; ++i) term(ldc(pl + j + i), av, at, i);
-    }
-    if (MF && j < np) {  // the last, partial block
-      f4v av[NP], at[NP];
-      blk_vals<NP, T>(qn, xl, av, at);
+        for (int i = 0; i < 4; ++i)
+          if (i < cnt) term(sq[i], av, at, i);
+      };
+      auto fill = [&](F4& ql, F4* sq, int j0) {
+        ql = blk_plane(pl, j0, np);
 #pragma unroll
-      for (int i = 0; i < 3; ++i)
-        if (j + i < np) term(ldc(pl + j + i), av, at, i);
+        for (int i = 0; i < 4; ++i) sq[i] = ldc(pl + min(j0 + i, np - 1));
+      };
+      F4 qa, qb, sa[4], sb[4];
+      fill(qa, sa, 0);
+      fill(qb, sb, 4);
+      int j = 0;
+      for (; j + 8 <= np; j += 8) {
+        blk(qa, sa, j, 4);
+        fill(qa, sa, j + 8);
+        blk(qb, sb, j + 4, 4);
+        fill(qb, sb, j + 12);
+      }
+      // at most 7 planes left: block j in (qa, sa), block j + 4 in (qb, sb)
+      if (j < np) blk(qa, sa, j, min(np - j, 4));
+      if (j + 4 < np) blk(qb, sb, j + 4, np - j - 4);
     }
     // combine the piece into the running smooth union
 #pragma unroll
