@@ -346,10 +346,9 @@ CM_DEV void sdf_eval(const ObjDesc& o, const DevParams& P, const V3<T>* x, SdfRe
       }
     }
     if (np > kSub && MF) {
-      F4 qn = blk_plane(pl, 0, np);
-      for (int j = 0; j < np; j += 4) {
-        const F4 ql = qn;
-        qn = blk_plane(pl, j + 4 < np ? j + 4 : j, np);
+      // blocks of 4 in ping-pong pairs as in the second pass; the clamped
+      // repeats of the last plane come after it and never raise the max
+      auto blk = [&](const F4& ql, int j0) {
         f4v av[NP], at[NP];
         blk_vals<NP, float>(ql, xl0, av, at);
 #pragma unroll
@@ -360,13 +359,23 @@ CM_DEV void sdf_eval(const ObjDesc& o, const DevParams& P, const V3<T>* x, SdfRe
             if (PREC) {
               const bool up = a > m[p];
               m[p] = up ? a : m[p];
-              jm[p] = up ? j + i : jm[p];
+              jm[p] = up ? j0 + i : jm[p];
             } else {
               m[p] = fmaxf(m[p], a);
             }
           }
         }
+      };
+      F4 qa = blk_plane(pl, 0, np), qb = blk_plane(pl, 4, np);
+      int j = 0;
+      for (; j + 8 <= np; j += 8) {
+        blk(qa, j);
+        qa = blk_plane(pl, j + 8, np);
+        blk(qb, j + 4);
+        qb = blk_plane(pl, j + 12, np);
       }
+      if (j < np) blk(qa, j);
+      if (j + 4 < np) blk(qb, j + 4);
     }
     V3<float> ref[NP];  // PREC: kappa n of the max plane (first of equal ones)
 #pragma unroll
