@@ -306,23 +306,29 @@ CM_DEV void sdf_eval(const ObjDesc& o, const DevParams& P, const V3<T>* x, SdfRe
           for (int p = 0; p < NP; ++p) m[p] = fmaxf(m[p], pdot(q, xl0[p]));
         }
       }
-      F4 qn = MF && ns > 0 ? blk_plane(sp, 0, ns) : F4{0.f, 0.f, 0.f, 0.f};  // the next block's plane, loaded a block ahead
-      for (int j = 0; MF && j < ns; j += 4) {
-        const F4 ql = qn;
-        qn = blk_plane(sp, j + 4 < ns ? j + 4 : j, ns);
-        f4v av[NP], at[NP];
-        blk_vals<NP, float>(ql, xl0, av, at);
+      if (MF && ns > 0) {
+        // at most kSub / 4 blocks: every block's lane plane is loaded first
+        F4 qv[kSub / 4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
+        for (int b = 0; b < kSub / 4; ++b) qv[b] = blk_plane(sp, 4 * b, ns);
 #pragma unroll
-          for (int p = 0; p < NP; ++p) {
-            const float a = av[p][i];
-            if (PREC) {
-              const bool up = a > m[p];
-              m[p] = up ? a : m[p];
-              jm[p] = up ? -1 - (j + i) : jm[p];
-            } else {
-              m[p] = fmaxf(m[p], a);
+        for (int b = 0; b < kSub / 4; ++b) {
+          if (4 * b < ns) {
+            f4v av[NP], at[NP];
+            blk_vals<NP, float>(qv[b], xl0, av, at);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+#pragma unroll
+              for (int p = 0; p < NP; ++p) {
+                const float a = av[p][i];
+                if (PREC) {
+                  const bool up = a > m[p];
+                  m[p] = up ? a : m[p];
+                  jm[p] = up ? -1 - (4 * b + i) : jm[p];
+                } else {
+                  m[p] = fmaxf(m[p], a);
+                }
+              }
             }
           }
         }
@@ -338,12 +344,30 @@ CM_DEV void sdf_eval(const ObjDesc& o, const DevParams& P, const V3<T>* x, SdfRe
     if (work) *work += uint64_t(np * NP);
     // pass 1: shift = max_j a_j (value only; LSE is shift-invariant)
     if (np > kSub && !MF) {
-#pragma unroll 4
-      for (int j = 0; j < np; ++j) {
-        const F4 q = ldc(pl + j);
+      // ping-pong blocks of 4 planes in SGPRs, each refilled a block ahead
+      // (clamped repeats of the last plane never raise the max)
+      auto blk = [&](const F4* sq) {
 #pragma unroll
-        for (int p = 0; p < NP; ++p) m[p] = fmaxf(m[p], pdot(q, xl0[p]));
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int p = 0; p < NP; ++p) m[p] = fmaxf(m[p], pdot(sq[i], xl0[p]));
+      };
+      auto fill = [&](F4* sq, int j0) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) sq[i] = ldc(pl + min(j0 + i, np - 1));
+      };
+      F4 sa[4], sb[4];
+      fill(sa, 0);
+      fill(sb, 4);
+      int j = 0;
+      for (; j + 8 <= np; j += 8) {
+        blk(sa);
+        fill(sa, j + 8);
+        blk(sb);
+        fill(sb, j + 12);
       }
+      if (j < np) blk(sa);
+      if (j + 4 < np) blk(sb);
     }
     if (np > kSub && MF) {
       // blocks of 4 in ping-pong pairs as in the second pass; the clamped
@@ -417,19 +441,39 @@ CM_DEV void sdf_eval(const ObjDesc& o, const DevParams& P, const V3<T>* x, SdfRe
         }
       }
     };
-    if (!MF) {
-#pragma unroll 4
-      for (int jj = 0; jj < np; ++jj) {
-        const F4 q = ldc(pl + jj);
-        f4v av[NP], at[NP];
+    if (!MF && np > 0) {
+      // ping-pong blocks of 4 planes in SGPRs, as in the first pass
+      auto blk = [&](const F4* sq, int cnt) {
 #pragma unroll
-        for (int p = 0; p < NP; ++p) {
-          const T a = pdot(q, xl[p]);
-          av[p][0] = val(a);
-          at[p][0] = tan_(a);
+        for (int i = 0; i < 4; ++i) {
+          if (i < cnt) {
+            f4v av[NP], at[NP];
+#pragma unroll
+            for (int p = 0; p < NP; ++p) {
+              const T a = pdot(sq[i], xl[p]);
+              av[p][0] = val(a);
+              at[p][0] = tan_(a);
+            }
+            term(sq[i], av, at, 0);
+          }
         }
-        term(q, av, at, 0);
+      };
+      auto fill = [&](F4* sq, int j0) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) sq[i] = ldc(pl + min(j0 + i, np - 1));
+      };
+      F4 sa[4], sb[4];
+      fill(sa, 0);
+      fill(sb, 4);
+      int j = 0;
+      for (; j + 8 <= np; j += 8) {
+        blk(sa, 4);
+        fill(sa, j + 8);
+        blk(sb, 4);
+        fill(sb, j + 12);
       }
+      if (j < np) blk(sa, min(np - j, 4));
+      if (j + 4 < np) blk(sb, np - j - 4);
     }
     if (MF && np > 0) {
       // Two blocks per iteration with ping-pong buffers for the lane's plane
