@@ -306,7 +306,8 @@ def main():
     # the same outputs by the separate calls, and the forward + gradient step
     sep_ms = None if args.no_separate else timed(separate, 2)
     fg_ms = timed(fwd_grad, 1 if w.n > args.tune_sample else 2)
-    log("separate calls %s ms, forward + gradient step %.2f ms" % (sep_ms, fg_ms))
+    fw_ms = timed(lambda: plan.forward(qd, out=out, stream=stream), 1 if w.n > args.tune_sample else 2)
+    log("separate calls %s ms, forward + gradient step %.2f ms, forward %.2f ms" % (sep_ms, fg_ms, fw_ms))
     # the step replayed from a HIP graph of its launches
     graph = plan.graph(qd, cot_d, grad, dir_d, hv, out)
     graph_ms = timed(lambda: graph.launch(stream), max(args.steps, 1 if w.n > args.tune_sample else 2))
@@ -427,6 +428,8 @@ def main():
                          "tile": "one wave of 64 contacts", "tuned_on_pair_queries": tuned_on},
         "forward_gradient_step_ms": round(fg_ms, 3),
         "forward_gradient_value": round(w.n / (fg_ms * 1e-3), 1),
+        "forward_ms": round(fw_ms, 3),
+        "forward_value": round(w.n / (fw_ms * 1e-3), 1),
         "work": st,
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -246,9 +246,6 @@ template <class T> CM_DEV Sym<T> outer(V3<T> a) {
 template <int NP, int MODE, class T>
 CM_DEV void sdf_eval(const ObjDesc& o, const DevParams& P, const V3<T>* x, SdfRes<T>* r, uint64_t* work = nullptr) {
   constexpr bool PREC = MODE == 2 || (MODE == 1 && IsDual<T>::value);
-  // dot products on the matrix cores where each plane carries enough VALU work
-  // to hide their latency (second-order or dual terms); on the VALU otherwise
-  constexpr bool MF = PREC;
   float M[NP];
   T S[NP];
   V3<T> Ug[NP];           // sum u_k g_k (kappa folded out); PREC: running weighted mean of g_k
@@ -299,14 +296,7 @@ CM_DEV void sdf_eval(const ObjDesc& o, const DevParams& P, const V3<T>* x, SdfRe
     if (P.prune || np <= kSub) {
       if (work && P.prune) *work += uint64_t(ns * NP);  // the bound
       // (a block's repeats of the last plane never raise the max: equal values)
-      if (!MF) {
-        for (int j = 0; j < ns; ++j) {
-          const F4 q = ldc(sp + j);
-#pragma unroll
-          for (int p = 0; p < NP; ++p) m[p] = fmaxf(m[p], pdot(q, xl0[p]));
-        }
-      }
-      if (MF && ns > 0) {
+      if (ns > 0) {
         // at most kSub / 4 blocks: every block's lane plane is loaded first
         F4 qv[kSub / 4];
 #pragma unroll
@@ -343,33 +333,7 @@ CM_DEV void sdf_eval(const ObjDesc& o, const DevParams& P, const V3<T>* x, SdfRe
     // point-plane evaluations performed by the wave (per lane)
     if (work) *work += uint64_t(np * NP);
     // pass 1: shift = max_j a_j (value only; LSE is shift-invariant)
-    if (np > kSub && !MF) {
-      // ping-pong blocks of 4 planes in SGPRs, each refilled a block ahead
-      // (clamped repeats of the last plane never raise the max)
-      auto blk = [&](const F4* sq) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-          for (int p = 0; p < NP; ++p) m[p] = fmaxf(m[p], pdot(sq[i], xl0[p]));
-      };
-      auto fill = [&](F4* sq, int j0) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) sq[i] = ldc(pl + min(j0 + i, np - 1));
-      };
-      F4 sa[4], sb[4];
-      fill(sa, 0);
-      fill(sb, 4);
-      int j = 0;
-      for (; j + 8 <= np; j += 8) {
-        blk(sa);
-        fill(sa, j + 8);
-        blk(sb);
-        fill(sb, j + 12);
-      }
-      if (j < np) blk(sa);
-      if (j + 4 < np) blk(sb);
-    }
-    if (np > kSub && MF) {
+    if (np > kSub) {
       // blocks of 4 in ping-pong pairs as in the second pass; the clamped
       // repeats of the last plane come after it and never raise the max
       auto blk = [&](const F4& ql, int j0) {
@@ -441,41 +405,7 @@ CM_DEV void sdf_eval(const ObjDesc& o, const DevParams& P, const V3<T>* x, SdfRe
         }
       }
     };
-    if (!MF && np > 0) {
-      // ping-pong blocks of 4 planes in SGPRs, as in the first pass
-      auto blk = [&](const F4* sq, int cnt) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          if (i < cnt) {
-            f4v av[NP], at[NP];
-#pragma unroll
-            for (int p = 0; p < NP; ++p) {
-              const T a = pdot(sq[i], xl[p]);
-              av[p][0] = val(a);
-              at[p][0] = tan_(a);
-            }
-            term(sq[i], av, at, 0);
-          }
-        }
-      };
-      auto fill = [&](F4* sq, int j0) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) sq[i] = ldc(pl + min(j0 + i, np - 1));
-      };
-      F4 sa[4], sb[4];
-      fill(sa, 0);
-      fill(sb, 4);
-      int j = 0;
-      for (; j + 8 <= np; j += 8) {
-        blk(sa, 4);
-        fill(sa, j + 8);
-        blk(sb, 4);
-        fill(sb, j + 12);
-      }
-      if (j < np) blk(sa, min(np - j, 4));
-      if (j + 4 < np) blk(sb, np - j - 4);
-    }
-    if (MF && np > 0) {
+    if (np > 0) {
       // Two blocks per iteration with ping-pong buffers for the lane's plane
       // (matrix-core operand, vector load) and the block's planes (SGPRs, scalar
       // loads), each refilled one block ahead: no buffer is copied across the
