@@ -151,6 +151,7 @@ cm_status cm_object_grid(cm_context* ctx, cm_object obj, float* G, float* meta);
  * time from the device query array) and owns the scratch of the batched
  * persistent launch: broad-phase survivor bitmasks, the work queue of survivor
  * tiles (64 contacts of one piece, vertices or edges), per-tile partials. */
+/* n >= 1 (an empty batch is CM_E_INVALID); the context must own a device. */
 cm_status cm_plan_create(cm_context* ctx, const cm_query* host_queries, int32_t n, cm_plan** out);
 cm_status cm_plan_destroy(cm_plan* plan);
 /* Totals: groups G, contacts C (vertices + edges of both sides), queries n. */

@@ -130,6 +130,9 @@ def test_degenerate_and_invalid_inputs(cm):
     with pytest.raises(api.CMError) as e:  # a host-only context cannot run queries
         ctx.plan([h], [h])
     assert e.value.status == _cm.CM_E_INVALID
+    with pytest.raises(api.CMError) as e:  # an empty batch (checked before the device)
+        ctx.plan(np.zeros(0, np.uint32), np.zeros(0, np.uint32))
+    assert e.value.status == _cm.CM_E_INVALID
     bad = np.array([[0, 1]], np.int32)
     with pytest.raises(api.CMError):
         ctx.build_raw([0, 6], box.planes, [0, 1], box.verts[:1], [0, 1], bad)
