@@ -180,6 +180,49 @@ def serving_leg(api, W, rates, seconds):
     return out
 
 
+def sweep_leg(reps=10):
+    """Broad + narrow phase against narrow phase only (the design of Sec. V.4):
+    one pair of the 8-piece workload, 1024 translations of B along x linearly
+    spaced over [1, 2] times the x-extent of A's bounding box (identity
+    rotations), forward records of the batch timed with the broad phase on and
+    off for d_max at 0, 0.25, 0.5, 1 and 2 times its default."""
+    import torch
+    from paper_2604_17538_amd import api, workloads as W
+    w = W.config1(n_envs=1)
+    objs = [w.objects[0], w.objects[1]]
+    ext = float(np.ptp(objs[0].points[:, 0]))
+    n = 1024
+    poses = np.zeros((n, 14))
+    poses[:, 0] = 1.0
+    poses[:, 7] = 1.0
+    poses[:, 11] = np.linspace(1.0, 2.0, n) * ext
+    poses = W._f32(poses)
+    d0 = api.default_params(w.L_ref).d_max
+    stream = torch.cuda.current_stream()
+    rows = []
+    for f in (0.0, 0.25, 0.5, 1.0, 2.0):
+        for bp in (1, 0):
+            ctx = api.Context(0, L_ref=w.L_ref, d_max=d0 * f, broad_phase=bp)
+            hs = ctx.build_objects(objs)
+            plan = ctx.plan(np.repeat(hs[:1], n), np.repeat(hs[1:], n))
+            qd = plan.device_queries(poses)
+            out = plan.forward(qd, stream=stream)
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            for _ in range(reps):
+                plan.forward(qd, out=out, stream=stream)
+            b.record(stream)
+            torch.cuda.synchronize()
+            st = plan.stats()
+            rows.append({"d_max_factor": f, "broad_phase": bp, "ms": round(a.elapsed_time(b) / reps, 4),
+                         "surviving_contacts": st["surv_verts"] + st["surv_edges"],
+                         "contacts": st["verts"] + st["edges"]})
+            log("sweep %s" % rows[-1])
+            del plan, ctx
+    return {"pair_queries": n, "x_extent_A": round(ext, 5), "translation_factors": [1.0, 2.0], "rows": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -194,10 +237,13 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-separate", action="store_true", help="skip timing the three separate calls")
+    ap.add_argument("--no-tight", action="store_true", help="skip the step with the tighter edge bound")
     ap.add_argument("--launch-shape", default=None,
                     help="F,D: fixed persistent workgroups per CU for the float and dual sweeps (no autotuning)")
     ap.add_argument("--tune-sample", type=int, default=16384,
                     help="autotune on a plan of the first N pair-queries when the batch is larger")
+    ap.add_argument("--sweep", action="store_true",
+                    help="only the broad-phase sweep (broad + narrow vs narrow only over d_max); prints its own JSON line")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a device copy of 1 GiB three times (scale of the HBM traffic counters)")
     ap.add_argument("--serve-rates", default="2000,5000", help="Poisson request rates (req/s) for the serving leg")
@@ -221,6 +267,9 @@ def main():
         print(json.dumps({"copy_bytes_read": x.numel() * 4, "copy_bytes_written": y.numel() * 4, "dispatches": 3}))
         return
     from paper_2604_17538_amd import api, workloads as W
+    if args.sweep:
+        print(json.dumps({"sweep": sweep_leg()}), flush=True)
+        return
 
     w = build_workload(args.config, args.pairs)
     log("workload %s: %d pair-queries, %d objects" % (args.config, w.n, len(w.objects)))
@@ -313,6 +362,25 @@ def main():
     graph_ms = timed(lambda: graph.launch(stream), max(args.steps, 1 if w.n > args.tune_sample else 2))
     del graph
     log("graph replay %.2f ms" % graph_ms)
+
+    # the same step with the tighter edge bound of the broad phase (outputs are
+    # unchanged, only the candidate lists shrink), in a context of its own
+    tight = None
+    if not args.no_tight and args.config != "c4":  # (c4: a second plan would double ~80 GB of scratch)
+        ctx_t = api.Context(0, L_ref=w.L_ref, budget_bytes=int(budget_gb * (1 << 30)), edge_bound=1)
+        hs_t = ctx_t.build_objects(w.objects)
+        plan_t = ctx_t.plan(hs_t[w.qa], hs_t[w.qb])
+        plan_t.launch_shape = plan.launch_shape
+        qd_t = plan_t.device_queries(w.poses)
+        out_t, grad_t, hv_t = torch.empty_like(out), torch.empty_like(grad), torch.empty_like(hv)
+        t_ms = timed(lambda: plan_t.step(qd_t, cot_d, dir_d, out=out_t, grad=grad_t, hv=hv_t, stream=stream),
+                     max(args.steps, 1 if w.n > args.tune_sample else 2))
+        st_t = plan_t.stats()
+        tight = {"ms_per_step": round(t_ms, 3), "value": round(w.n / (t_ms * 1e-3), 1),
+                 "surviving_contacts": st_t["surv_verts"] + st_t["surv_edges"],
+                 "note": "edge bound max(max(lb1, lb2) - l, (lb1 + lb2 - l) / 2) instead of min(lb1, lb2) - l"}
+        log("tight edge bound %s" % tight)
+        del plan_t, qd_t, ctx_t, out_t, grad_t, hv_t
 
     # per-kernel timing of the step (events on the launch stream), untimed region
     plan.set_timing(True)
@@ -429,6 +497,7 @@ def main():
         "forward_gradient_step_ms": round(fg_ms, 3),
         "forward_gradient_value": round(w.n / (fg_ms * 1e-3), 1),
         "forward_ms": round(fw_ms, 3),
+        "tight_edge_bound": tight,
         "forward_value": round(w.n / (fw_ms * 1e-3), 1),
         "work": st,
         "roofline": roofline,

@@ -136,3 +136,44 @@ def test_full_batch_sampled():
     _check_records(g[rows], ref, "full batch")
     _check_derivs(grad.cpu().numpy()[sel].astype(np.float64), hv.cpu().numpy()[sel].astype(np.float64), ref,
                   "full batch")
+
+
+@pytest.mark.parametrize("variant", ["tight_edge_bound", "no_broad_phase"])
+def test_broad_phase_variants(small, variant):
+    """The broad phase changes which contacts are evaluated, never an output:
+    with the tighter edge bound (max(max(lb1, lb2) - l, (lb1 + lb2 - l) / 2))
+    the masks equal the oracle's under the same bound (bit-exact outside the
+    tie band) and filter at least as much as the paper's min form; with the
+    broad phase off every contact survives.  Records, gradient and H v stay
+    within the tolerances of the default oracle."""
+    import torch
+    from paper_2604_17538_amd import api
+    w, ref = small
+    kw = {"edge_bound": 1} if variant == "tight_edge_bound" else {"broad_phase": 0}
+    ctx = api.Context(0, L_ref=w.L_ref, **kw)
+    hs = ctx.build_objects(w.objects)
+    plan = ctx.plan(hs[w.qa], hs[w.qb])
+    qd = plan.device_queries(w.poses)
+    out, dbg = plan.forward(qd, debug=True)
+    cot_d = torch.tensor(np.ascontiguousarray(ref["cot"].T, np.float32)).cuda()
+    dir_d = torch.tensor(ref["dir"].astype(np.float32)).cuda()
+    out2, grad, hv = plan.step(qd, cot_d, dir_d)
+    torch.cuda.synchronize()
+    _check_records(out.cpu().numpy().T.astype(np.float64), ref, variant)
+    _check_records(out2.cpu().numpy().T.astype(np.float64), ref, variant + " step")
+    _check_derivs(grad.cpu().numpy().astype(np.float64), hv.cpu().numpy().astype(np.float64), ref, variant)
+    ex = [ctx.object_export(h) for h in hs]
+    perm_obj = [PT.contact_perm(ex[i], ref["objs"][i]) for i in range(len(hs))]
+    perm = PT.query_contact_perm(perm_obj, w.qa, w.qb, ref["coff"])
+    mask = dbg.cpu().numpy().T.astype(np.float64)[:, 0]
+    if variant == "no_broad_phase":
+        assert np.all(mask == 1)
+        return
+    prm1 = O.default_params(w.L_ref, edge_bound=1)
+    _, c1, _, _ = O.contacts(prm1, ref["objs"], w.qa, w.qb, w.poses, want_contacts=True, threads=16)
+    c1 = c1[perm]
+    band = (np.abs(c1[:, 12] - prm1.d_max) <= PT.BAND) | (c1[:, 13] <= PT.BAND)
+    assert not np.any((mask != c1[:, 0]) & ~band)
+    c0 = ref["c_o"][perm]
+    assert np.all(c1[:, 0] <= c0[:, 0])  # the tighter bound filters a superset
+    _log("%s: survivors %d of %d (paper's form %d)" % (variant, int(mask.sum()), len(mask), int(c0[:, 0].sum())))
