@@ -208,6 +208,16 @@ CM_DEV void blk_vals(const F4& ql, const V3<T>* xl, f4v* av, f4v* at) {
     if (IsDual<T>::value) at[p] = mdot_n(ql, V3<float>{tan_(xl[p].x), tan_(xl[p].y), tan_(xl[p].z)});
   }
 }
+// the same with the tangents given apart (xt: ln 2 times the points' tangents,
+// so that the tangent of 2^a is 2^a times the block's dot directly)
+template <int NP, bool DUAL>
+CM_DEV void blk_vals_t(const F4& ql, const V3<float>* x0, const V3<float>* xt, f4v* av, f4v* at) {
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    av[p] = mdot(ql, x0[p]);
+    if (DUAL) at[p] = mdot_n(ql, xt[p]);
+  }
+}
 template <class T> CM_DEV T mkT(float v, float t);
 template <> CM_DEV float mkT<float>(float v, float) { return v; }
 template <> CM_DEV df mkT<df>(float v, float t) { return df{v, t}; }
@@ -385,10 +395,15 @@ CM_DEV void sdf_eval(const ObjDesc& o, const DevParams& P, const V3<T>* x, SdfRe
       if (MODE >= 2) N[p] = zsym<T>();
     }
     // plane j + i of a block (q: its wave-uniform copy) at the NP points
+    constexpr bool DUAL = IsDual<T>::value;
+    V3<float> xt[NP];  // dual: ln 2 times the tangents of the points
+#pragma unroll
+    for (int p = 0; p < NP; ++p) xt[p] = V3<float>{tan_(xl[p].x), tan_(xl[p].y), tan_(xl[p].z)} * kLn2;
     auto term = [&](const F4& q, const f4v* av, const f4v* at, int i) {
 #pragma unroll
       for (int p = 0; p < NP; ++p) {
-        const T e = ex2(mkT<T>(av[p][i], IsDual<T>::value ? at[p][i] : 0.f) - m[p]);
+        const float ev = ex2(av[p][i] - m[p]);
+        const T e = mkT<T>(ev, DUAL ? ev * at[p][i] : 0.f);  // 2^a and its tangent ln 2 a' 2^a
         s[p] += e;
         if (MODE >= 1) {
           const float dx = PREC ? q.x - ref[p].x : q.x;
@@ -413,7 +428,7 @@ CM_DEV void sdf_eval(const ObjDesc& o, const DevParams& P, const V3<T>* x, SdfRe
       // the piece are clamped to its last plane (never used).
       auto blk = [&](const F4& ql, const F4* sq, int j0, int cnt) {
         f4v av[NP], at[NP];
-        blk_vals<NP, T>(ql, xl, av, at);
+        blk_vals_t<NP, DUAL>(ql, xl0, xt, av, at);
 #pragma unroll
         for (int i = 0; i < 4; ++i)
           if (i < cnt) term(sq[i], av, at, i);
