@@ -202,6 +202,14 @@ cm_status cm_contacts_bwd(cm_context* ctx, cm_plan* plan, const cm_query* q_dev,
  * written to hv [n][12]; grad (nullable) receives the gradient. */
 cm_status cm_hvp(cm_context* ctx, cm_plan* plan, const cm_query* q_dev, cm_groups cot, const float* dir, float* hv,
                  float* grad, void* stream);
+/* Jacobian-vector product of the group records (Sec. IV-D outputs) along the
+ * pose direction dir (device float [n][12], the xi of cm_contacts_bwd): out
+ * receives the records, out_tangent (same layout) their derivatives
+ * d y_g / d xi . dir, from one forward sweep in dual numbers.  Twelve calls
+ * with the unit directions give the blended Jacobian of every record.  All
+ * buffers are caller-owned device memory; CM_E_INVALID on a null argument. */
+cm_status cm_contacts_jvp(cm_context* ctx, cm_plan* plan, const cm_query* q_dev, cm_groups out,
+                          cm_groups out_tangent, const float* dir, void* stream);
 
 /* ---------------------------------------------------------------- serving --
  * A background scheduler admits requests while the device memory they need

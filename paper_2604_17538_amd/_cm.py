@@ -88,6 +88,7 @@ cm_plan_timing = _sig("cm_plan_timing", I32, [P, P])
 cm_contacts_fwd = _sig("cm_contacts_fwd", I32, [P, P, P, cm_groups, P, P])
 cm_contacts_bwd = _sig("cm_contacts_bwd", I32, [P, P, P, cm_groups, P, P])
 cm_hvp = _sig("cm_hvp", I32, [P, P, P, cm_groups, P, P, P, P])
+cm_contacts_jvp = _sig("cm_contacts_jvp", I32, [P, P, P, cm_groups, cm_groups, P, P])
 cm_contacts_step = _sig("cm_contacts_step", I32, [P, P, P, cm_groups, cm_groups, P, P, P, P])
 cm_graph_create = _sig("cm_graph_create", I32, [P, P, P, cm_groups, cm_groups, P, P, P, PP])
 cm_graph_launch = _sig("cm_graph_launch", I32, [P, P])
@@ -105,7 +106,8 @@ EXPORTED = ["cm_default_params", "cm_init", "cm_shutdown", "cm_last_error", "cm_
             "cm_build_pieces_raw", "cm_release_object", "cm_object_info", "cm_object_export", "cm_object_grid",
             "cm_plan_create", "cm_plan_destroy", "cm_plan_info", "cm_plan_offsets", "cm_plan_stats", "cm_plan_work",
             "cm_plan_set_timing", "cm_plan_timing",
-            "cm_contacts_fwd", "cm_contacts_bwd", "cm_hvp", "cm_contacts_step", "cm_graph_create", "cm_graph_launch",
+            "cm_contacts_fwd", "cm_contacts_bwd", "cm_hvp", "cm_contacts_jvp",
+            "cm_contacts_step", "cm_graph_create", "cm_graph_launch",
             "cm_graph_destroy", "cm_plan_autotune", "cm_plan_set_launch_shape", "cm_plan_launch_shape",
             "cm_submit", "cm_poll", "cm_wait", "cm_serve_stats",
             "cm_serve_latencies"]

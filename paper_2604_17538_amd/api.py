@@ -295,6 +295,19 @@ class Plan:
         self.ctx._check(st, "cm_hvp")
         return hv
 
+    def jvp(self, q_dev, direction, out=None, out_t=None, stream=None):
+        """Records [12, G] and their derivatives along `direction` [n, 12]
+        (cm_contacts_jvp)."""
+        torch = _torch()
+        if out is None:
+            out = torch.empty((12, self.G), dtype=torch.float32, device=q_dev.device)
+        if out_t is None:
+            out_t = torch.empty((12, self.G), dtype=torch.float32, device=q_dev.device)
+        st = _cm.cm_contacts_jvp(self.ctx.handle, self._h, ctypes.c_void_p(q_dev.data_ptr()), groups_struct(out),
+                                 groups_struct(out_t), ctypes.c_void_p(direction.data_ptr()), _stream_ptr(stream))
+        self.ctx._check(st, "cm_contacts_jvp")
+        return out, out_t
+
     def set_timing(self, enable: bool = True):
         self.ctx._check(_cm.cm_plan_set_timing(self._h, int(enable)), "cm_plan_set_timing")
 

@@ -52,6 +52,7 @@ struct FwdArgs {
   const I2* gent;       // per group: (vertex entry, edge entry)
   int64_t G;
   OutPtrs out;
+  OutPtrs out_t;        // tangents of the records along dir (Jacobian-vector product)
   float* dbg;           // nullable
   int64_t C;
   int32_t n_cu;
@@ -115,6 +116,7 @@ struct FinArgs {
   const QueryDev* Q;
   DevParams P;
   OutPtrs out;
+  OutPtrs out_t;
   OutPtrs cot;
   float* gscratch;
   const float* dir;
@@ -129,5 +131,7 @@ hipError_t launch_forward(const FwdArgs& a, hipStream_t s);
 // records: also write the group records a.out (from the same sweep)
 hipError_t launch_backward(const FwdArgs& a, hipStream_t s, bool records = false);
 hipError_t launch_hvp(const FwdArgs& a, hipStream_t s, bool records = false);
+// records and their tangents along dir (one forward sweep in dual numbers)
+hipError_t launch_jvp(const FwdArgs& a, hipStream_t s);
 
 }  // namespace cm

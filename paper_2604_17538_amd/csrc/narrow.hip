@@ -625,7 +625,8 @@ template <class T> CM_DEV BlendT<T> group_blend(const FinArgs& a, int64_t g) {
 
 // WHAT 0: write the group records.  WHAT 1: write the per-piece adjoint seeds
 // for the cotangent `cot` (n_bar = cot_n, m_bar through the normalisation).
-// WHAT 2: both (the records are the value parts).
+// WHAT 2: both (the records are the value parts).  WHAT 3 (dual numbers): the
+// records and, to out_t, their tangents along the direction.
 template <class T, int WHAT>
 __global__ __launch_bounds__(256) void k_finalize(FinArgs a) {
   const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -639,7 +640,7 @@ __global__ __launch_bounds__(256) void k_finalize(FinArgs a) {
   const T d = b.d * iz, W = b.f * iz;
   const T logZ = logT(b.Z) + b.L;
   const int64_t G = a.G;
-  if (WHAT == 0 || WHAT == 2) {
+  if (WHAT == 0 || WHAT == 2 || WHAT == 3) {
     a.out.p[g] = val(p.x); a.out.p[G + g] = val(p.y); a.out.p[2 * G + g] = val(p.z);
     a.out.n[g] = val(n.x); a.out.n[G + g] = val(n.y); a.out.n[2 * G + g] = val(n.z);
     a.out.q[g] = val(q.x); a.out.q[G + g] = val(q.y); a.out.q[2 * G + g] = val(q.z);
@@ -647,7 +648,15 @@ __global__ __launch_bounds__(256) void k_finalize(FinArgs a) {
     a.out.W[g] = val(W);
     a.out.logZ[g] = val(logZ);
   }
-  if (WHAT >= 1) {
+  if (WHAT == 3) {
+    a.out_t.p[g] = tan_(p.x); a.out_t.p[G + g] = tan_(p.y); a.out_t.p[2 * G + g] = tan_(p.z);
+    a.out_t.n[g] = tan_(n.x); a.out_t.n[G + g] = tan_(n.y); a.out_t.n[2 * G + g] = tan_(n.z);
+    a.out_t.q[g] = tan_(q.x); a.out_t.q[G + g] = tan_(q.y); a.out_t.q[2 * G + g] = tan_(q.z);
+    a.out_t.d[g] = tan_(d);
+    a.out_t.W[g] = tan_(W);
+    a.out_t.logZ[g] = tan_(logZ);
+  }
+  if (WHAT == 1 || WHAT == 2) {
     const V3<float> cp{a.cot.p[g], a.cot.p[G + g], a.cot.p[2 * G + g]};
     const V3<float> cn{a.cot.n[g], a.cot.n[G + g], a.cot.n[2 * G + g]};
     const V3<float> cq{a.cot.q[g], a.cot.q[G + g], a.cot.q[2 * G + g]};
@@ -766,7 +775,8 @@ static FinArgs fin_args(const FwdArgs& a, const float* partials, const float* di
   FinArgs fa{};
   fa.G = a.G; fa.gent = a.gent; fa.tile_off = a.tile_off; fa.filt = a.filt; fa.partials = partials;
   fa.part_off = a.part_off; fa.q_runs = a.q_runs;
-  fa.ents = a.ents; fa.Q = a.Q; fa.P = a.P; fa.out = a.out; fa.cot = a.cot; fa.gscratch = a.gscratch; fa.dir = dir;
+  fa.ents = a.ents; fa.Q = a.Q; fa.P = a.P; fa.out = a.out; fa.out_t = a.out_t; fa.cot = a.cot;
+  fa.gscratch = a.gscratch; fa.dir = dir;
   return fa;
 }
 
@@ -809,6 +819,17 @@ template <class T> static hipError_t adjoint_impl(const FwdArgs& a, hipStream_t 
   narrow_launch<T, true, false>(nb, grid, s, a.ev, !tape, true);
   hipLaunchKernelGGL((k_reduce<T>), dim3(unsigned(cdiv(a.n, 256))), dim3(256), 0, s, fin_args(a, a.partials, dir),
                      a.bpartials, a.group_off, a.n, a.grad, a.hv);
+  return hipGetLastError();
+}
+
+hipError_t launch_jvp(const FwdArgs& a, hipStream_t s) {
+  (void)hipGetLastError();
+  if (a.work) launch_fill_u32(reinterpret_cast<uint32_t*>(a.work), 0u, 4, s);
+  launch_front(a, s);
+  const int grid = a.n_cu * a.blocks_per_cu_dual;
+  narrow_launch<df, false, false>(narrow_args(a, a.partials, a.dir, nullptr), grid, s, a.ev);
+  hipLaunchKernelGGL((k_finalize<df, 3>), dim3(unsigned(cdiv(a.G, 256))), dim3(256), 0, s,
+                     fin_args(a, a.partials, a.dir));
   return hipGetLastError();
 }
 

@@ -928,6 +928,19 @@ cm_status cm_hvp(cm_context* ctx, cm_plan* pl, const cm_query* q, cm_groups cot,
   return CM_OK;
 }
 
+cm_status cm_contacts_jvp(cm_context* ctx, cm_plan* pl, const cm_query* q, cm_groups out, cm_groups out_t,
+                          const float* dir, void* stream) {
+  if (!ctx || !pl || pl->ctx != ctx || !q || !dir || !valid_groups(out) || !valid_groups(out_t))
+    return fail(ctx, CM_E_INVALID, "bad arguments");
+  FwdArgs a = fwd_args(ctx, pl, q, out, nullptr);
+  a.out_t = OutPtrs{out_t.p, out_t.n, out_t.d, out_t.q, out_t.W, out_t.logZ};
+  a.dir = dir;
+  pl->timed_mask = (1u << kTBroad) | (1u << kTNarrowTan);
+  hipError_t e = launch_jvp(a, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(ctx, e, "jvp launch");
+  return CM_OK;
+}
+
 cm_status cm_contacts_step(cm_context* ctx, cm_plan* pl, const cm_query* q, cm_groups out, cm_groups cot,
                            float* grad, const float* dir, float* hv, void* stream) {
   if (!ctx || !pl || pl->ctx != ctx || !q || !grad || !valid_groups(cot) || (dir != nullptr) != (hv != nullptr))
