@@ -410,6 +410,19 @@ def main():
                 "performed_frac": round(perf_achieved / PEAK_LANE_OPS, 4)}
     log("roofline %s" % roofline)
 
+    # the forward pass alone (records only): its narrow-phase kernel against the same peak
+    plan.set_timing(True)
+    plan.forward(qd, out=out, stream=stream)
+    torch.cuda.synchronize()
+    fwd_k = plan.timing()["narrow_fwd"]
+    plan.set_timing(False)
+    fv, fe = OPS["forward"]
+    f_ops = st["vertex_pairs"] * fv + st["edge_pairs"] * fe
+    forward_roofline = {"bound": "alu", "kernel": "k_narrow<float, forward>", "kernel_ms": round(fwd_k, 3),
+                        "achieved": round(f_ops / (fwd_k * 1e-3) / 1e12, 3), "unit": "T lane-op/s (FP32 VALU)",
+                        "frac": round(f_ops / (fwd_k * 1e-3) / PEAK_LANE_OPS, 4), "alg_ops_per_launch": int(f_ops)}
+    log("forward roofline %s" % forward_roofline)
+
     # plain per-pair launch: same kernels, one pair-query per launch
     plain = None
     if not args.no_plain:
@@ -497,6 +510,7 @@ def main():
         "forward_gradient_step_ms": round(fg_ms, 3),
         "forward_gradient_value": round(w.n / (fg_ms * 1e-3), 1),
         "forward_ms": round(fw_ms, 3),
+        "forward_roofline": forward_roofline,
         "tight_edge_bound": tight,
         "forward_value": round(w.n / (fw_ms * 1e-3), 1),
         "work": st,
