@@ -252,7 +252,8 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU: pair-queries are independent and the path has no "
-              "cross-GPU step; run with --gpus 1 (sharding across GPUs is described in DESIGN.md)",
+              "cross-GPU step; run with --gpus 1 (several GPUs would each run their own share of the "
+              "pair-queries, with no communication)",
               file=sys.stderr)
         sys.exit(2)
 
