@@ -610,13 +610,20 @@ cm_status plan_host(cm_context* ctx, const cm_query* hq, int32_t n, cm_plan* pl,
   // mesh side, whose survivors share tiles; costliest runs first, so their tiles
   // head the work queue, pieces in order within a run
   const int64_t R = 4 * int64_t(n);
+  const size_t E0 = pl->ents.size();
   std::vector<double> rcost(static_cast<size_t>(R), 0.0);
-  std::vector<std::vector<int64_t>> members(static_cast<size_t>(R));
-  for (size_t i = 0; i < pl->ents.size(); ++i) {
-    const Entry& e = pl->ents[i];
-    const int64_t r = 4 * int64_t(e.query) + 2 * e.dir + e.kind;
+  // members of each run by a counting pass (in generation order within a run)
+  std::vector<int64_t> rstart(static_cast<size_t>(R) + 1, 0), rmem(E0);
+  auto run_of = [](const Entry& e) { return 4 * int64_t(e.query) + 2 * e.dir + e.kind; };
+  for (size_t i = 0; i < E0; ++i) {
+    const int64_t r = run_of(pl->ents[i]);
     rcost[size_t(r)] += cost[i];
-    members[size_t(r)].push_back(int64_t(i));
+    rstart[size_t(r) + 1]++;
+  }
+  for (int64_t r = 0; r < R; ++r) rstart[size_t(r) + 1] += rstart[size_t(r)];
+  {
+    std::vector<int64_t> fill(rstart.begin(), rstart.end() - 1);
+    for (size_t i = 0; i < E0; ++i) rmem[size_t(fill[size_t(run_of(pl->ents[i]))]++)] = int64_t(i);
   }
   std::vector<int64_t> rorder(static_cast<size_t>(R));
   std::iota(rorder.begin(), rorder.end(), 0);
@@ -626,12 +633,13 @@ cm_status plan_host(cm_context* ctx, const cm_query* hq, int32_t n, cm_plan* pl,
   pl->run_off.assign(size_t(R) + 1, 0);
   pl->q_runs.assign(size_t(R), 0);
   pl->ent_run.clear();
+  pl->ent_run.reserve(E0);
   pl->gent.assign(size_t(pl->G), I2{0, 0});
   for (int64_t k = 0; k < R; ++k) {
     const int64_t r = rorder[size_t(k)];
     pl->q_runs[size_t(r)] = int32_t(k);
-    for (int64_t i : members[size_t(r)]) {
-      const Entry& e = pl->ents[size_t(i)];
+    for (int64_t m = rstart[size_t(r)]; m < rstart[size_t(r) + 1]; ++m) {
+      const Entry& e = pl->ents[size_t(rmem[size_t(m)])];
       I2& ge = pl->gent[size_t(e.group)];
       if (e.kind == 0) ge.x = int32_t(sorted.size()); else ge.y = int32_t(sorted.size());
       sorted.push_back(e);
@@ -674,12 +682,17 @@ size_t plan_layout(cm_plan* pl, char* b) {
   const size_t o_bp = take(4 * size_t(kStride) * size_t(W));
   const size_t o_goff = take(8 * size_t(pl->n + 1));
   const size_t o_gt = take(4 * 12 * size_t(pl->n));
-  // the adjoint tape, for as many tiles as a quarter of the memory budget holds
-  // (dual values); tiles past it are recomputed by the adjoint
+  // the adjoint tape (dual values), for a quarter of the bitmask words as tiles
+  // plus the partly filled last tile of each run: the broad phase leaves far
+  // fewer tiles than words (a few per cent of the contacts survive), and sizing
+  // for every word would make each request reserve ten times the memory it
+  // uses; at most a quarter of the memory budget.  Tiles past the tape are
+  // recomputed by the adjoint.
   const int st = pl->ctx->prm.st_iters;
-  const int64_t tape_slot_bytes = int64_t(2 * 4 * tape_values(st));
+  const int64_t tape_slot_bytes = int64_t(std::max(pl->tape_kind, 1) * 4 * tape_values(st));
   const int64_t budget_tiles = int64_t(pl->ctx->budget / 4) / (tape_slot_bytes * kWave);
-  pl->tape_tiles = (st <= kMaxTraceAdj) ? std::min<int64_t>(W, budget_tiles) : 0;
+  const int64_t want_tiles = std::min<int64_t>(W, W / 4 + pl->R);
+  pl->tape_tiles = (st <= kMaxTraceAdj && pl->tape_kind > 0) ? std::min<int64_t>(want_tiles, budget_tiles) : 0;
   const size_t o_tape = take(size_t(tape_slot_bytes) * kWave * size_t(pl->tape_tiles));
   if (b) {
     pl->d_ents = reinterpret_cast<Entry*>(b + o_ents);
@@ -922,6 +935,7 @@ cm_status cm_hvp(cm_context* ctx, cm_plan* pl, const cm_query* q, cm_groups cot,
   a.grad = grad ? grad : pl->d_gradtmp;
   a.hv = hv;
   a.dir = dir;
+  if (pl->tape_kind < 2) { a.tape = nullptr; a.tape_tiles = 0; }  // a float tape: recompute
   pl->timed_mask = (1u << kTBroad) | (1u << kTNarrowTan) | (1u << kTNarrowDualAdj);
   hipError_t e = launch_hvp(a, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(ctx, e, "hvp launch");
@@ -953,6 +967,7 @@ cm_status cm_contacts_step(cm_context* ctx, cm_plan* pl, const cm_query* q, cm_g
   a.grad = grad;
   a.hv = hv;
   a.dir = dir;
+  if (dir && pl->tape_kind < 2) { a.tape = nullptr; a.tape_tiles = 0; }  // a float tape: recompute
   hipError_t e;
   if (dir) {
     pl->timed_mask = (1u << kTBroad) | (1u << kTNarrowTan) | (1u << kTNarrowDualAdj);

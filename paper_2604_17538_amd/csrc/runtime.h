@@ -111,6 +111,9 @@ struct cm_plan {
   float* d_tape = nullptr;       // adjoint tape (see kernels.h)
   unsigned long long* d_work = nullptr;  // point-plane evaluations of the last pass
   int64_t tape_tiles = 0;
+  // what the tape holds per row: 0 nothing (the plan never runs an adjoint),
+  // 1 float values (float adjoints only), 2 dual values (any adjoint)
+  int32_t tape_kind = 2;
   int32_t blocks_per_cu = 8;       // persistent workgroups per CU, float sweeps (cm_plan_autotune)
   int32_t blocks_per_cu_dual = 8;  // the same for the sweeps in dual numbers
   bool timing = false;

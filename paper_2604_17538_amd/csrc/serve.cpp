@@ -83,10 +83,14 @@ namespace {
 
 // Device bytes a request needs inside a batch: its share of the plan scratch
 // (entries, bitmask, partials, ...) plus its input and output buffers.
-size_t request_bytes(const cm_plan& pl, bool grad) {
-  size_t b = plan_layout(const_cast<cm_plan*>(&pl), nullptr);
-  b += 64 * size_t(pl.n) + 48 * size_t(pl.G);              // queries, outputs
-  if (grad) b += b + 48 * size_t(pl.G) + 48 * size_t(pl.n);  // adjoint plan, cotangents, gradients
+size_t request_bytes(cm_plan& pl, bool grad) {
+  pl.tape_kind = 0;  // the forward plan keeps no tape
+  size_t b = plan_layout(&pl, nullptr);
+  b += 64 * size_t(pl.n) + 48 * size_t(pl.G);  // queries, outputs
+  if (grad) {
+    pl.tape_kind = 1;  // the adjoint plan: a tape of float values
+    b += plan_layout(&pl, nullptr) + 64 * size_t(pl.n) + 48 * size_t(pl.G) + 48 * size_t(pl.n);
+  }
   return b;
 }
 
@@ -122,11 +126,13 @@ cm_status launch_batch(cm_context* ctx, Slot& s) {
   s.n = int64_t(qa.size());
   s.ng = int64_t(qg.size());
   s.pf.reset(new cm_plan);
+  s.pf->tape_kind = 0;  // forward only
   size_t bf = 0, bg = 0;
   cm_status st = plan_host(ctx, qa.data(), int32_t(s.n), s.pf.get(), &bf);
   if (st != CM_OK) return st;
   if (s.ng) {
     s.pg.reset(new cm_plan);
+    s.pg->tape_kind = 1;  // float adjoint only
     st = plan_host(ctx, qg.data(), int32_t(s.ng), s.pg.get(), &bg);
     if (st != CM_OK) return st;
   } else {

@@ -148,3 +148,35 @@ def test_step_records_gradient(c0g):
     torch.cuda.synchronize()
     assert hv is None
     _check_step(c0g, out, grad, None)
+
+
+def test_adjoint_past_the_tape(c0g):
+    """A context whose memory budget holds a tape for only a few hundred tiles:
+    the adjoint recomputes the forward sweep for the tiles past it.  Gradient
+    and H v (separate calls and the one-pass step) stay within the tolerances
+    of the oracle; the log reports whether they are bitwise those of the
+    fully taped plan."""
+    import torch
+    from paper_2604_17538_amd import api
+    w = W.config0()
+    ctx = api.Context(0, L_ref=w.L_ref, budget_bytes=16 << 20)
+    hs = ctx.build_objects(w.objects)
+    plan = ctx.plan(hs[w.qa], hs[w.qb])
+    qd = plan.device_queries(w.poses)
+    grad = plan.backward(qd, c0g["cot_d"])
+    grad2 = torch.empty_like(grad)
+    hv = plan.hvp(qd, c0g["cot_d"], c0g["dir_d"], grad=grad2)
+    out, g3, h3 = plan.step(qd, c0g["cot_d"], c0g["dir_d"])
+    torch.cuda.synchronize()
+    tiles = plan.stats()["tiles"]
+    _step("tape overflow: %d tiles; bitwise equal to the taped plan: grad %s, H v %s" % (
+        tiles, np.array_equal(grad.cpu().numpy(), c0g["grad"].astype(np.float32)),
+        np.array_equal(hv.cpu().numpy(), c0g["hv"].astype(np.float32))))
+    assert tiles > 4 * 240  # most tiles lie past a tape of about 240 tiles
+    for gg in (grad, grad2, g3):
+        r = _ratio(gg.cpu().numpy().astype(np.float64), c0g["g_o"], c0g["floor"], c0g["dg"])
+        assert r.max() <= 1.0, ("grad", r.max())
+    for hh in (hv, h3):
+        r = _ratio(hh.cpu().numpy().astype(np.float64), c0g["hv_o"], c0g["floor"], c0g["dh"], REL_HVP)
+        assert r.max() <= 1.0, ("hvp", r.max())
+    _check_step(c0g, out, g3, h3)
