@@ -231,6 +231,7 @@ def main():
     ap.add_argument("--config", default="c2", choices=["c0", "c1", "c2", "c4"])
     ap.add_argument("--pairs", type=int, default=None, help="batch size override (default: the config's)")
     ap.add_argument("--budget-gb", type=float, default=None, help="device-memory budget (default per workload)")
+    ap.add_argument("--no-prune", action="store_true", help="evaluate every piece (no piece pruning)")
     ap.add_argument("--cpu-sample", type=int, default=16)
     ap.add_argument("--plain-sample", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -275,7 +276,7 @@ def main():
     w = build_workload(args.config, args.pairs)
     log("workload %s: %d pair-queries, %d objects" % (args.config, w.n, len(w.objects)))
     budget_gb = args.budget_gb or BUDGET_GB[args.config]
-    ctx = api.Context(0, L_ref=w.L_ref, budget_bytes=int(budget_gb * (1 << 30)))
+    ctx = api.Context(0, L_ref=w.L_ref, budget_bytes=int(budget_gb * (1 << 30)), prune_pieces=0 if args.no_prune else 1)
     hs = ctx.build_objects(w.objects)
     torch.cuda.synchronize()
     log("objects resident")
