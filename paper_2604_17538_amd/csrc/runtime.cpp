@@ -235,8 +235,11 @@ static void finish_host(ObjHost& o) {
   o.n_planes = o.n_verts = o.n_edges = 0;
   o.radius = 0;
   o.centres.assign(3 * o.pieces.size(), 0.0);
+  o.counts.assign(2 * o.pieces.size(), 0);
   for (size_t k = 0; k < o.pieces.size(); ++k) {
     const PieceGeom& g = o.pieces[k];
+    o.counts[2 * k] = int32_t(g.n_verts());
+    o.counts[2 * k + 1] = int32_t(g.n_edges());
     o.n_planes += int64_t(g.n_planes());
     o.n_verts += int64_t(g.n_verts());
     o.n_edges += int64_t(g.n_edges());
@@ -557,14 +560,30 @@ namespace cm {
 cm_status plan_host(cm_context* ctx, const cm_query* hq, int32_t n, cm_plan* pl, size_t* dev_bytes) {
   pl->ctx = ctx;
   pl->n = n;
+  pl->W = 0;
   pl->group_off.assign(size_t(n) + 1, 0);
   pl->contact_off.assign(size_t(n) + 1, 0);
   pl->qa.resize(size_t(n));
   pl->qb.resize(size_t(n));
-  std::vector<double> cost;
+  // scratch kept across calls on this thread: planning a batch of tens of
+  // thousands of queries touches tens of MB, and fresh allocations would take
+  // a page fault on every page again (the serving thread plans every batch)
+  thread_local std::vector<Entry> gen;  // entries in generation order
+  thread_local std::vector<double> cost, rcost;
+  thread_local std::vector<int64_t> rstart, rmem, rorder, fill;
+  gen.clear();
+  cost.clear();
   const int K2 = 2 * ctx->prm.st_iters + 1;
   {
     std::lock_guard<std::mutex> lk(ctx->mu);
+    size_t n_ent = 0;  // 2 entries (vertices, edges) per piece of either side
+    for (int32_t i = 0; i < n; ++i) {
+      const ObjHost* A = get_obj(ctx, hq[i].a);
+      const ObjHost* B = get_obj(ctx, hq[i].b);
+      if (A && B) n_ent += 2 * (A->pieces.size() + B->pieces.size());
+    }
+    gen.reserve(n_ent);
+    cost.reserve(n_ent);
     for (int32_t i = 0; i < n; ++i) {
       const ObjHost* A = get_obj(ctx, hq[i].a);
       const ObjHost* B = get_obj(ctx, hq[i].b);
@@ -579,15 +598,16 @@ cm_status plan_host(cm_context* ctx, const cm_query* hq, int32_t n, cm_plan* pl,
       for (int dir = 0; dir < 2; ++dir) {
         const ObjHost* Mo = dir ? B : A;
         const ObjHost* So = dir ? A : B;
-        for (size_t k = 0; k < Mo->pieces.size(); ++k) {
-          const PieceGeom& g = Mo->pieces[k];
+        const size_t Km = Mo->pieces.size();
+        const int32_t* cnt = Mo->counts.data();
+        for (size_t k = 0; k < Km; ++k) {
           const int64_t group = pl->group_off[size_t(i)] + (dir ? ga : 0) + int64_t(k);
           for (int kind = 0; kind < 2; ++kind) {
             Entry e{};
             e.query = i;
             e.group = int32_t(group);
             e.piece = int32_t(k);
-            e.count = int32_t(kind ? g.n_edges() : g.n_verts());
+            e.count = cnt[2 * k + size_t(kind)];
             e.word_off = pl->W;
             e.contact_base = cbase;
             e.dir = dir;
@@ -596,7 +616,7 @@ cm_status plan_host(cm_context* ctx, const cm_query* hq, int32_t n, cm_plan* pl,
             e.sdf_obj = int32_t(dir ? hq[i].a : hq[i].b);
             pl->W += (e.count + kWave - 1) / kWave;
             cbase += e.count;
-            pl->ents.push_back(e);
+            gen.push_back(e);
             cost.push_back(double(e.count) * double(So->n_planes) * (kind ? K2 : 1));
           }
         }
@@ -610,44 +630,41 @@ cm_status plan_host(cm_context* ctx, const cm_query* hq, int32_t n, cm_plan* pl,
   // mesh side, whose survivors share tiles; costliest runs first, so their tiles
   // head the work queue, pieces in order within a run
   const int64_t R = 4 * int64_t(n);
-  const size_t E0 = pl->ents.size();
-  std::vector<double> rcost(static_cast<size_t>(R), 0.0);
+  const size_t E0 = gen.size();
+  rcost.assign(static_cast<size_t>(R), 0.0);
   // members of each run by a counting pass (in generation order within a run)
-  std::vector<int64_t> rstart(static_cast<size_t>(R) + 1, 0), rmem(E0);
+  rstart.assign(static_cast<size_t>(R) + 1, 0);
+  rmem.resize(E0);
   auto run_of = [](const Entry& e) { return 4 * int64_t(e.query) + 2 * e.dir + e.kind; };
   for (size_t i = 0; i < E0; ++i) {
-    const int64_t r = run_of(pl->ents[i]);
+    const int64_t r = run_of(gen[i]);
     rcost[size_t(r)] += cost[i];
     rstart[size_t(r) + 1]++;
   }
   for (int64_t r = 0; r < R; ++r) rstart[size_t(r) + 1] += rstart[size_t(r)];
-  {
-    std::vector<int64_t> fill(rstart.begin(), rstart.end() - 1);
-    for (size_t i = 0; i < E0; ++i) rmem[size_t(fill[size_t(run_of(pl->ents[i]))]++)] = int64_t(i);
-  }
-  std::vector<int64_t> rorder(static_cast<size_t>(R));
+  fill.assign(rstart.begin(), rstart.end() - 1);
+  for (size_t i = 0; i < E0; ++i) rmem[size_t(fill[size_t(run_of(gen[i]))]++)] = int64_t(i);
+  rorder.resize(static_cast<size_t>(R));
   std::iota(rorder.begin(), rorder.end(), 0);
   std::stable_sort(rorder.begin(), rorder.end(), [&](int64_t a, int64_t b) { return rcost[size_t(a)] > rcost[size_t(b)]; });
-  std::vector<Entry> sorted;
-  sorted.reserve(pl->ents.size());
+  pl->ents.resize(E0);
   pl->run_off.assign(size_t(R) + 1, 0);
   pl->q_runs.assign(size_t(R), 0);
-  pl->ent_run.clear();
-  pl->ent_run.reserve(E0);
+  pl->ent_run.assign(E0, 0);
   pl->gent.assign(size_t(pl->G), I2{0, 0});
+  size_t pos = 0;
   for (int64_t k = 0; k < R; ++k) {
     const int64_t r = rorder[size_t(k)];
     pl->q_runs[size_t(r)] = int32_t(k);
-    for (int64_t m = rstart[size_t(r)]; m < rstart[size_t(r) + 1]; ++m) {
-      const Entry& e = pl->ents[size_t(rmem[size_t(m)])];
+    for (int64_t m = rstart[size_t(r)]; m < rstart[size_t(r) + 1]; ++m, ++pos) {
+      const Entry& e = gen[size_t(rmem[size_t(m)])];
       I2& ge = pl->gent[size_t(e.group)];
-      if (e.kind == 0) ge.x = int32_t(sorted.size()); else ge.y = int32_t(sorted.size());
-      sorted.push_back(e);
-      pl->ent_run.push_back(int32_t(k));
+      if (e.kind == 0) ge.x = int32_t(pos); else ge.y = int32_t(pos);
+      pl->ents[pos] = e;
+      pl->ent_run[pos] = int32_t(k);
     }
-    pl->run_off[size_t(k) + 1] = int64_t(sorted.size());
+    pl->run_off[size_t(k) + 1] = int64_t(pos);
   }
-  pl->ents.swap(sorted);
   pl->E = int64_t(pl->ents.size());
   pl->R = R;
   pl->nb = (std::max(pl->E, pl->R) + 1023) / 1024;

@@ -46,6 +46,7 @@ struct ObjHost {
   bool alive = false;
   std::vector<PieceGeom> pieces;
   std::vector<double> centres;  // 3 per piece
+  std::vector<int32_t> counts;  // per piece: vertices, edges (compact, for planning)
   int64_t n_planes = 0, n_verts = 0, n_edges = 0;
   double radius = 0;
   void* dmem = nullptr;

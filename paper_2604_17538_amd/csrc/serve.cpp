@@ -125,18 +125,18 @@ cm_status launch_batch(cm_context* ctx, Slot& s) {
   }
   s.n = int64_t(qa.size());
   s.ng = int64_t(qg.size());
-  s.pf.reset(new cm_plan);
+  // the slot's plans are reused batch after batch (their host tables keep
+  // their capacity); the slot is free only once its previous batch completed
+  if (!s.pf) s.pf.reset(new cm_plan);
   s.pf->tape_kind = 0;  // forward only
   size_t bf = 0, bg = 0;
   cm_status st = plan_host(ctx, qa.data(), int32_t(s.n), s.pf.get(), &bf);
   if (st != CM_OK) return st;
   if (s.ng) {
-    s.pg.reset(new cm_plan);
+    if (!s.pg) s.pg.reset(new cm_plan);
     s.pg->tape_kind = 1;  // float adjoint only
     st = plan_host(ctx, qg.data(), int32_t(s.ng), s.pg.get(), &bg);
     if (st != CM_OK) return st;
-  } else {
-    s.pg.reset();
   }
   s.G = s.pf->G;
   s.Gg = s.ng ? s.pg->G : 0;
