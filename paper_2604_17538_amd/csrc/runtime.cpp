@@ -665,6 +665,17 @@ cm_status plan_host(cm_context* ctx, const cm_query* hq, int32_t n, cm_plan* pl,
     }
     pl->run_off[size_t(k) + 1] = int64_t(pos);
   }
+  // keep the scratch for batches of the serving size only (a plan of millions
+  // of entries would otherwise hold hundreds of MB on this thread until exit)
+  if (gen.capacity() > (size_t(1) << 21)) {
+    std::vector<Entry>().swap(gen);
+    std::vector<double>().swap(cost);
+    std::vector<double>().swap(rcost);
+    std::vector<int64_t>().swap(rstart);
+    std::vector<int64_t>().swap(rmem);
+    std::vector<int64_t>().swap(rorder);
+    std::vector<int64_t>().swap(fill);
+  }
   pl->E = int64_t(pl->ents.size());
   pl->R = R;
   pl->nb = (std::max(pl->E, pl->R) + 1023) / 1024;
