@@ -155,3 +155,14 @@ def test_raw_object_round_trip(cm):
     P, V, E = _geom_sets(ex["planes"], ex["verts"], ex["edges"])
     Pb, Vb, Eb = _geom_sets(box.planes, box.verts, box.edges)
     assert V == Vb and E == Eb
+
+
+def test_new_entry_points_reject_null_arguments(cm):
+    """The Jacobian-vector product and the launch-shape calls validate their
+    arguments before touching a device."""
+    api, _cm = cm
+    ctx = api.Context(-1, L_ref=1.0)
+    empty = _cm.cm_groups()
+    assert _cm.cm_contacts_jvp(ctx.handle, None, None, empty, empty, None, None) == _cm.CM_E_INVALID
+    assert _cm.cm_plan_set_launch_shape(None, 4, 4) == _cm.CM_E_INVALID
+    assert _cm.cm_plan_launch_shape(None, None, None) == _cm.CM_E_INVALID
