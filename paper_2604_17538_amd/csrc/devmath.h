@@ -208,14 +208,29 @@ CM_DEV void blk_vals(const F4& ql, const V3<T>* xl, f4v* av, f4v* at) {
     if (IsDual<T>::value) at[p] = mdot_n(ql, V3<float>{tan_(xl[p].x), tan_(xl[p].y), tan_(xl[p].z)});
   }
 }
-// the same with the tangents given apart (xt: ln 2 times the points' tangents,
-// so that the tangent of 2^a is 2^a times the block's dot directly)
+// the same dots with a per-point constant c added first (c = -shift: the
+// exponent a - m comes out of the chain, accumulated as (h + c) + z + y + x)
+CM_DEV f4v mdot_c(const F4& ql, V3<float> x, const f4v& c) {
+  f4v a = __builtin_amdgcn_mfma_f32_4x4x1f32(ql.w, 1.f, c, 0, 0, 0);
+  a = __builtin_amdgcn_mfma_f32_4x4x1f32(ql.z, x.z, a, 0, 0, 0);
+  a = __builtin_amdgcn_mfma_f32_4x4x1f32(ql.y, x.y, a, 0, 0, 0);
+  return __builtin_amdgcn_mfma_f32_4x4x1f32(ql.x, x.x, a, 0, 0, 0);
+}
+// plane values of a block at NP points; with dual numbers already shifted,
+// a - m (nm: -m per point in all 4 slots), and their tangents (xt: ln 2 times
+// the points' tangents, so that the tangent of 2^(a - m) is 2^(a - m) times the
+// block's dot directly)
 template <int NP, bool DUAL>
-CM_DEV void blk_vals_t(const F4& ql, const V3<float>* x0, const V3<float>* xt, f4v* av, f4v* at) {
+CM_DEV void blk_vals_t(const F4& ql, const V3<float>* x0, const f4v* nm, const V3<float>* xt, f4v* av,
+                       f4v* at) {
 #pragma unroll
   for (int p = 0; p < NP; ++p) {
-    av[p] = mdot(ql, x0[p]);
-    if (DUAL) at[p] = mdot_n(ql, xt[p]);
+    if (DUAL) {
+      av[p] = mdot_c(ql, x0[p], nm[p]);
+      at[p] = mdot_n(ql, xt[p]);
+    } else {
+      av[p] = mdot(ql, x0[p]);  // float sweeps: shift on the VALU (fewer registers)
+    }
   }
 }
 template <class T> CM_DEV T mkT(float v, float t);
@@ -397,12 +412,16 @@ CM_DEV void sdf_eval(const ObjDesc& o, const DevParams& P, const V3<T>* x, SdfRe
     // plane j + i of a block (q: its wave-uniform copy) at the NP points
     constexpr bool DUAL = IsDual<T>::value;
     V3<float> xt[NP];  // dual: ln 2 times the tangents of the points
+    f4v nm[NP];        // -m, the shift of the exponents
 #pragma unroll
-    for (int p = 0; p < NP; ++p) xt[p] = V3<float>{tan_(xl[p].x), tan_(xl[p].y), tan_(xl[p].z)} * kLn2;
+    for (int p = 0; p < NP; ++p) {
+      xt[p] = V3<float>{tan_(xl[p].x), tan_(xl[p].y), tan_(xl[p].z)} * kLn2;
+      if (DUAL) nm[p] = f4v{-m[p], -m[p], -m[p], -m[p]};
+    }
     auto term = [&](const F4& q, const f4v* av, const f4v* at, int i) {
 #pragma unroll
       for (int p = 0; p < NP; ++p) {
-        const float ev = ex2(av[p][i] - m[p]);
+        const float ev = ex2(DUAL ? av[p][i] : av[p][i] - m[p]);  // (dual: the chain subtracted m)
         const T e = mkT<T>(ev, DUAL ? ev * at[p][i] : 0.f);  // 2^a and its tangent ln 2 a' 2^a
         s[p] += e;
         if (MODE >= 1) {
@@ -428,7 +447,7 @@ CM_DEV void sdf_eval(const ObjDesc& o, const DevParams& P, const V3<T>* x, SdfRe
       // the piece are clamped to its last plane (never used).
       auto blk = [&](const F4& ql, const F4* sq, int j0, int cnt) {
         f4v av[NP], at[NP];
-        blk_vals_t<NP, DUAL>(ql, xl0, xt, av, at);
+        blk_vals_t<NP, DUAL>(ql, xl0, nm, xt, av, at);
 #pragma unroll
         for (int i = 0; i < 4; ++i)
           if (i < cnt) term(sq[i], av, at, i);
