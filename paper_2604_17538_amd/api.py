@@ -1,7 +1,8 @@
 """Python API over the C ABI (include/cm.h): contexts, resident objects, plans,
 and launches on torch-managed device memory and streams.
 
-PyTorch is used for device memory, streams and autograd plumbing only; every
+PyTorch is used for device memory and streams only (gradients come from the
+library's adjoint entry points, not from torch.autograd); every
 step of the contact pipeline runs in libcm.so's gfx950 kernels.
 """
 from __future__ import annotations
