@@ -336,8 +336,8 @@ def main():
         plan.launch_shape = (shape_f, shape)
         del tp, tq, tc, tg
         tuned_on = ns
-    log("autotuned launch shape (on %d pair-queries): %d workgroups per CU (dual sweeps), %d (float sweeps)"
-        % (tuned_on, shape, shape_f))
+    how = ("autotuned on %d pair-queries" % tuned_on) if tuned_on else "set by --launch-shape"
+    log("launch shape (%s): %d workgroups per CU (dual sweeps), %d (float sweeps)" % (how, shape, shape_f))
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
