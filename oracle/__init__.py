@@ -79,7 +79,7 @@ def lib():
         L.orc_lower_bound.argtypes = [I32, P]
         L.orc_sdf.argtypes = [I32, P, I64, P, P, P, P]
         L.orc_edge_point_sphere.argtypes = [P, P, D, P, P, P, P, P]
-        L.orc_edge_point.argtypes = [I32, P, P, P, P]
+        L.orc_edge_point.argtypes = [I32, P, P, P, P, P]
         L.orc_transition.argtypes = [P, D, P]
         L.orc_softclip.argtypes = [D, D, D, D, P]
         L.orc_n_groups.restype = I64
@@ -89,6 +89,7 @@ def lib():
         L.orc_contacts.argtypes = [P, I64, P, P, P, P, P, P, P, I32]
         L.orc_groups_at_xi.argtypes = [P, I32, I32, P, P, P]
         L.orc_grad_hvp.argtypes = [P, I64, P, P, P, P, P, P, P, P, I32]
+        L.orc_jvp.argtypes = [P, I64, P, P, P, P, P, P, P, I32]
         _lib = L
     return _lib
 
@@ -147,11 +148,13 @@ class Obj:
         lib().orc_sdf(self.h, ctypes.byref(prm), n, _p(x), _p(phi), _p(g), _p(H))
         return phi, g, H.reshape(n, 3, 3)
 
-    def edge_point(self, prm: Params, xI, xII):
-        pe = np.zeros(3)
+    def edge_point(self, prm: Params, xI, xII, arc_lengths: bool = False):
+        """E-SDF point of the edge xI -> xII (object frame); with arc_lengths
+        also the softclipped (alpha', beta')."""
+        pe, ab = np.zeros(3), np.zeros(2)
         lib().orc_edge_point(self.h, ctypes.byref(prm), _p(_c(xI, np.float64)), _p(_c(xII, np.float64)),
-                             _p(pe))
-        return pe
+                             _p(pe), _p(ab))
+        return (pe, ab[0], ab[1]) if arc_lengths else pe
 
     def __del__(self):
         try:
@@ -237,6 +240,21 @@ def grad_hvp(prm: Params, objs, qa, qb, poses, cot, direction: Optional[np.ndarr
     lib().orc_grad_hvp(ctypes.byref(prm), n, _p(qa_h), _p(qb_h), _p(poses), _p(goff), _p(cot), _p(d),
                        _p(grad), _p(hv), int(threads))
     return (grad, hv) if direction is not None else grad
+
+
+def jvp(prm: Params, objs, qa, qb, poses, direction, threads: int = 0):
+    """Group records [G,12] and their derivatives along `direction` [n,12]
+    (the pose perturbation xi of grad_hvp), and the group offsets."""
+    qa_h = _c([objs[i].h for i in qa], np.int32)
+    qb_h = _c([objs[i].h for i in qb], np.int32)
+    poses = _c(poses, np.float64).reshape(-1, 14)
+    goff, _ = layout(objs, qa, qb)
+    d = _c(direction, np.float64).reshape(-1, 12)
+    assert len(d) == len(qa_h)
+    groups, tang = np.zeros((goff[-1], 12)), np.zeros((goff[-1], 12))
+    lib().orc_jvp(ctypes.byref(prm), len(qa_h), _p(qa_h), _p(qb_h), _p(poses), _p(goff), _p(d), _p(groups),
+                  _p(tang), int(threads))
+    return groups, tang, goff
 
 
 FP32_UNIT_ROUNDOFF = 2.0 ** -24

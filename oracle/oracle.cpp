@@ -677,11 +677,14 @@ void orc_edge_point_sphere(const Params* prm, const double* c, double R, const d
   pe[0] = p.x; pe[1] = p.y; pe[2] = p.z; *alpha = a; *beta = b;
 }
 
-// E-SDF point of an edge against an object's SDF (object frame).
-void orc_edge_point(int32_t h, const Params* prm, const double* xI, const double* xII, double* pe) {
+// E-SDF point of an edge against an object's SDF (object frame); ab
+// (nullable) receives the softclipped arc lengths (alpha', beta').
+void orc_edge_point(int32_t h, const Params* prm, const double* xI, const double* xII, double* pe, double* ab) {
   SdfFn<double> fn{&obj(h), prm};
-  V3<double> p = edge_point(fn, cvt<double>(xI), cvt<double>(xII), *prm);
+  double a = 0, b = 0;
+  V3<double> p = edge_point(fn, cvt<double>(xI), cvt<double>(xII), *prm, &a, &b);
   pe[0] = p.x; pe[1] = p.y; pe[2] = p.z;
+  if (ab) { ab[0] = a; ab[1] = b; }
 }
 
 // Transition f_t and its first two derivatives at phi (hyper-dual).
@@ -737,6 +740,34 @@ void orc_groups_at_xi(const Params* prm, int32_t a, int32_t b, const double* pos
   std::vector<GroupOut<double>> out;
   query(obj(a), obj(b), PA, PB, *prm, out, nullptr);
   for (size_t g = 0; g < out.size(); ++g) put(out[g], groups + 12 * g);
+}
+
+// Jacobian-vector product of the group records: y and dy/dxi . dir at xi = 0
+// (one tangent slot seeded with dir; first derivatives of I + W + W^2/2 at
+// zero are those of the exponential).  groups, tangents: [sum groups][12].
+void orc_jvp(const Params* prm, int64_t n, const int32_t* qa, const int32_t* qb, const double* poses,
+             const int64_t* group_off, const double* dir, double* groups, double* tangents, int32_t n_threads) {
+#ifdef _OPENMP
+  if (n_threads > 0) omp_set_num_threads(n_threads);
+#pragma omp parallel for schedule(dynamic, 1)
+#endif
+  for (int64_t i = 0; i < n; ++i) {
+    const double* ps = poses + 14 * i;
+    M3<double> RA = quat_to_R(ps), RB = quat_to_R(ps + 7);
+    typedef Dual<double, 1> D;
+    D xi[12];
+    for (int k = 0; k < 12; ++k) { xi[k] = D(0.0); xi[k].d[0] = dir[12 * i + k]; }
+    Pose<D> PA = perturbed<D>(RA, ps + 4, xi, xi + 3, true);
+    Pose<D> PB = perturbed<D>(RB, ps + 11, xi + 6, xi + 9, true);
+    std::vector<GroupOut<D>> out;
+    query(obj(qa[i]), obj(qb[i]), PA, PB, *prm, out, nullptr);
+    for (size_t g = 0; g < out.size(); ++g)
+      for (int k = 0; k < 12; ++k) {
+        const D& c = comp(out[g], k);
+        groups[12 * (group_off[i] + int64_t(g)) + k] = c.v;
+        tangents[12 * (group_off[i] + int64_t(g)) + k] = c.d[0];
+      }
+  }
 }
 
 // Gradient of L = <c, y> w.r.t. xi = (w_A, v_A, w_B, v_B) at xi = 0 and,

@@ -510,3 +510,144 @@ def test_gradient_of_invariant_outputs_is_orthogonal_to_global_twists(oracle_mod
             om, t = rng.standard_normal(3), rng.standard_normal(3)
             xi = np.r_[om, np.cross(om, tA) + t, om, np.cross(om, tB) + t]
             assert abs(grad[i] @ xi) <= 1e-9 * (np.abs(grad[i]).sum() * np.abs(xi).sum() + 1)
+
+
+# ---------------------------------------- E-SDF at finite K: half-space pin --
+def _half_space(O, n, h):
+    """Raw one-piece object whose SDF is the single plane n.x + h (exactly
+    linear: a one-term log-sum-exp is its term)."""
+    return O.Obj([0, 1], [list(n) + [h]], [0, 1], [[0.0, 0.0, -1.0]], [0, 0], np.zeros((0, 2), np.int32))
+
+
+@pytest.mark.parametrize("K", [1, 2, 3])
+def test_sphere_trace_half_space_closed_form(oracle_mod, K):
+    """phi(x) = z.  An edge leaving the plane's outside at height phi0 with
+    n.e = c in (-1, 0): phi at the k-th iterate is phi0 + c alpha_k, the gate is
+    1 (tau_s -> 0), so alpha_{k+1} = (1 + c) alpha_k + phi0 and
+    alpha_K = phi0 (1 - (1 + c)^K) / (-c) (Sec. IV-B.2, iterate evaluated at
+    the current point).  The other corner lies inside and does not move.
+    Checked on both ends (the edge reversed) and through a whole query: the
+    edge contact's raw phi is the height of the edge point."""
+    O = oracle_mod
+    plane = _half_space(O, (0.0, 0.0, 1.0), 0.0)
+    prm = O.default_params(1.0, tau_st=1e-12, tau_clip=1e-12, st_iters=K)
+    phi0, c, L = 0.1, -0.5, 1.0
+    e = np.array([np.sqrt(1 - c * c), 0.0, c])
+    xI = np.array([0.3, -0.2, phi0])
+    xII = xI + L * e                      # phi(xII) = phi0 + c L < 0: inside
+    aK = phi0 * (1 - (1 + c) ** K) / (-c)
+    pe, a, b = plane.edge_point(prm, xI, xII, arc_lengths=True)
+    # (a corner that does not move keeps the softclip's bias tau_clip ln 2 ~ 7e-13)
+    assert abs(a - aK) < 1e-14 and abs(b) < 1e-12
+    assert np.allclose(pe, 0.5 * (xI + aK * e + xII), atol=1e-12)
+    pe2, a2, b2 = plane.edge_point(prm, xII, xI, arc_lengths=True)   # the approaching corner is now x_II
+    assert abs(a2) < 1e-12 and abs(b2 - aK) < 1e-14
+    assert np.allclose(pe2, pe, atol=1e-12)
+    # not phi at the corner each step (K phi0), and not K - 1 or K + 1 steps
+    for wrong in (K * phi0, phi0 * (1 - (1 + c) ** (K - 1)) / (-c), phi0 * (1 - (1 + c) ** (K + 1)) / (-c)):
+        if abs(wrong - aK) > 1e-9:
+            assert abs(a - wrong) > 1e-9
+    # the same edge as the mesh of a query against the plane (identity poses, no broad phase)
+    mesh = O.Obj([0, 1], [[0.0, 0.0, 1.0, -5.0]], [0, 2], [xI, xII], [0, 1], [[0, 1]])
+    prm_q = O.default_params(1.0, tau_st=1e-12, tau_clip=1e-12, st_iters=K, broad_phase=False)
+    ident = [1, 0, 0, 0, 0, 0, 0]
+    g, cts, goff, coff = O.contacts(prm_q, [mesh, plane], [0], [1], [ident + ident], want_contacts=True)
+    edge_rec = cts[2]                      # vertices xI, xII, then the edge
+    assert edge_rec[11] == 1.0 and abs(edge_rec[10] - pe[2]) < 1e-12
+
+
+# --------------------------------------------- oracle hull from point clouds --
+def _check_hull(O, pts, nP, nV, nE, planes=None):
+    pl, vs, es = O.geometry.piece_geometry(np.asarray(pts, np.float64))
+    assert (len(pl), len(vs), len(es)) == (nP, nV, nE)
+    assert len(vs) - len(es) + len(pl) == 2                      # Euler
+    assert np.allclose(np.linalg.norm(pl[:, :3], axis=1), 1.0, atol=1e-14)
+    assert np.all(vs @ pl[:, :3].T + pl[:, 3] <= 1e-12)           # every vertex inside every plane
+    on = np.abs(vs @ pl[:, :3].T + pl[:, 3]) < 1e-12
+    assert np.all(on.sum(0) >= 3)                                 # every plane carries a face
+    for a, b in es:                                               # a feature edge joins two faces
+        assert np.count_nonzero(on[a] & on[b]) == 2
+    if planes is not None:
+        got = sorted(map(tuple, np.round(pl, 12)))
+        want = sorted(map(tuple, np.round(np.asarray(planes, np.float64), 12)))
+        assert got == want
+    return pl, vs, es
+
+
+def test_oracle_hull_of_polytopes_with_coplanar_points(oracle_mod):
+    """The oracle's own hull of point clouds with coplanar facets (Sec. III-A.3
+    planes; Sec. IV-A vertices and edges): a box sampled with points inside its
+    faces merges to 6 planes, 8 vertices, 12 feature edges; a triangular prism
+    gives 5 / 6 / 9 and an octahedron 8 / 6 / 12; a box whose face centre is
+    raised by 1e-4 keeps the 4 new planes apart (no merge beyond the tolerance)."""
+    O = oracle_mod
+    rng = np.random.default_rng(3)
+    corners = np.array([[x, y, z] for x in (-0.5, 0.5) for y in (-0.5, 0.5) for z in (-0.5, 0.5)])
+    face_pts = []
+    for ax in range(3):
+        for s in (-0.5, 0.5):
+            p = rng.uniform(-0.45, 0.45, (6, 3))
+            p[:, ax] = s
+            face_pts.append(p)
+    box = np.concatenate([corners] + face_pts)
+    box_planes = [[s * (ax == 0), s * (ax == 1), s * (ax == 2), -0.5] for ax in range(3) for s in (-1.0, 1.0)]
+    _check_hull(O, box, 6, 8, 12, box_planes)
+    tri = np.array([[0.0, 0.0], [1.0, 0.0], [0.2, 0.9]])
+    prism = np.concatenate([np.c_[tri, np.zeros(3)], np.c_[tri, np.ones(3)],
+                            [[0.5 * (tri[0, 0] + tri[1, 0]), 0.5 * (tri[0, 1] + tri[1, 1]), 0.5]]])  # inside a side face
+    _check_hull(O, prism, 5, 6, 9)
+    octa = np.concatenate([np.eye(3), -np.eye(3)]) * 0.7
+    s = 0.7 / np.sqrt(3)
+    _check_hull(O, octa, 8, 6, 12, [[a * np.sqrt(1 / 3), b * np.sqrt(1 / 3), c * np.sqrt(1 / 3), -s]
+                                    for a in (-1, 1) for b in (-1, 1) for c in (-1, 1)])
+    tent = np.concatenate([corners, [[0.0, 0.0, 0.5 + 1e-4]]])
+    _check_hull(O, tent, 9, 9, 16)
+
+
+def test_oracle_pieces_of_the_workloads_are_polytopes(oracle_mod):
+    """Every oracle piece of the config-0 to config-2 workloads (a sample of
+    the larger two) has V - E + F = 2 and unit outward planes holding all its
+    vertices."""
+    O = oracle_mod
+    objs = list(W.config0(n_poses=2).objects) + list(W.config1(n_envs=4).objects) + list(W.config2(n_pairs=4).objects)
+    n = 0
+    for o in objs:
+        if not hasattr(o, "points"):
+            continue
+        for k in range(len(o.offsets) - 1):
+            pl, vs, es = O.geometry.piece_geometry(o.points[o.offsets[k]:o.offsets[k + 1]])
+            assert len(vs) - len(es) + len(pl) == 2
+            assert np.allclose(np.linalg.norm(pl[:, :3], axis=1), 1.0, atol=1e-12)
+            assert np.all(vs @ pl[:, :3].T + pl[:, 3] <= 1e-9)
+            n += 1
+    assert n >= 40
+
+
+# ------------------------------------------------- Jacobian-vector product --
+def test_jvp_matches_central_differences_and_gradient(oracle_mod):
+    """orc_jvp (one dual slot seeded with the direction) against central
+    differences of the records at the Rodrigues-perturbed poses (h = 1e-6, a
+    path with no dual numbers), and <c, J v> against the gradient's g . v."""
+    O = oracle_mod
+    w = W.config0(n_poses=6)
+    prm = O.default_params(w.L_ref)
+    objs = [O.from_workload_object(o) for o in w.objects]
+    for o in objs:
+        o.build_grid(prm)
+    sel = np.r_[0:3, 6:9]
+    d = W.directions(5, len(sel))
+    y, t, goff = O.jvp(prm, objs, w.qa[sel], w.qb[sel], w.poses[sel], d)
+    y0, _ = O.contacts(prm, objs, w.qa[sel], w.qb[sel], w.poses[sel])
+    assert np.allclose(y, y0, rtol=1e-12, atol=1e-14)   # (dual division rounds as a * (1 / b))
+    h = 1e-6
+    for k, i in enumerate(sel):
+        A, B = objs[w.qa[i]], objs[w.qb[i]]
+        yp = O.groups_at_xi(prm, A, B, w.poses[i], h * d[k])
+        ym = O.groups_at_xi(prm, A, B, w.poses[i], -h * d[k])
+        fd = (yp - ym) / (2 * h)
+        tk = t[goff[k]:goff[k + 1]]
+        assert np.abs(tk - fd).max() <= 1e-7 * max(1.0, np.abs(fd).max())
+    cot = W.cotangents(5, goff[-1])
+    grad = O.grad_hvp(prm, objs, w.qa[sel], w.qb[sel], w.poses[sel], cot)
+    lhs = np.add.reduceat((cot * t).sum(1), goff[:-1])
+    assert np.allclose(lhs, (grad * d).sum(1), rtol=1e-10, atol=1e-12)
