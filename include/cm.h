@@ -194,8 +194,13 @@ cm_status cm_contacts_fwd(cm_context* ctx, cm_plan* plan, const cm_query* q_dev,
 /* Gradient of L = sum_g <cot_g, y_g> w.r.t. xi = (w_A, v_A, w_B, v_B), the
  * world-frame perturbation T_X <- (exp([w_X]x) R_X, t_X + v_X) at xi = 0.
  * cot: device group records (same layout as out).  grad: device float [n][12].
- * Recomputes the forward pass (no stored intermediates).  Requires
- * st_iters <= 4 (CM_E_INVALID otherwise). */
+ * Runs the forward sweep again (nothing is kept from an earlier
+ * cm_contacts_fwd); that sweep writes, for the survivor tiles the plan's tape
+ * holds (a quarter of the context's memory budget at most), the values the
+ * adjoint needs (phi, gradient and Hessian at the contact point and at the
+ * sphere-trace iterates), and the adjoint recomputes them for tiles past the
+ * tape.  The adjoint keeps the trace steps in registers: st_iters <= 4
+ * (CM_E_INVALID otherwise; the forward entry points take up to 64). */
 cm_status cm_contacts_bwd(cm_context* ctx, cm_plan* plan, const cm_query* q_dev, cm_groups cot, float* grad,
                           void* stream);
 /* Hessian-vector product H dir of the same L (dir: device float [n][12]),
@@ -285,7 +290,8 @@ cm_status cm_plan_set_launch_shape(cm_plan* plan, int32_t float_per_cu, int32_t 
 cm_status cm_plan_launch_shape(const cm_plan* plan, int32_t* float_per_cu, int32_t* dual_per_cu);
 
 /* Serving statistics: [0] submitted, [1] completed, [2] batches, [3] queued,
- * [4] in flight, [5] peak in-flight bytes, [6] queries completed. */
+ * [4] in flight, [5] peak device bytes held by the serving slots' buffers (the
+ * admission keeps it within the budget), [6] queries completed. */
 cm_status cm_serve_stats(cm_context* ctx, int64_t* stats7);
 
 #ifdef __cplusplus

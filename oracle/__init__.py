@@ -260,6 +260,22 @@ def jvp(prm: Params, objs, qa, qb, poses, direction, threads: int = 0):
 FP32_UNIT_ROUNDOFF = 2.0 ** -24
 
 
+def jvp_spread(prm: Params, objs, qa, qb, poses, direction, seeds=(1, 2), threads: int = 0):
+    """Conditioning of the Jacobian-vector product at FP32 precision (the
+    probe of fp32_spread applied to jvp): per group, the largest change of the
+    12 tangent components (logZ's scaled by tau_blend) over the seeds."""
+    _, t0, _ = jvp(prm, objs, qa, qb, poses, direction, threads)
+    sc = np.ones(12)
+    sc[11] = prm.tau_blend
+    out = np.zeros(len(t0))
+    for s in seeds:
+        p = Params.from_buffer_copy(prm)
+        p.jitter, p.jitter_seed = FP32_UNIT_ROUNDOFF, int(s)
+        _, t, _ = jvp(p, objs, qa, qb, poses, direction, threads)
+        out = np.maximum(out, np.linalg.norm((t - t0) * sc, axis=1))
+    return out
+
+
 def fp32_spread(prm: Params, objs, qa, qb, poses, cot, direction: Optional[np.ndarray] = None,
                 seeds=(1, 2, 3), threads: int = 0, concurrent: bool = False, return_base: bool = False):
     """Conditioning of each query at FP32 precision (the oracle's probe).

@@ -760,7 +760,9 @@ void orc_jvp(const Params* prm, int64_t n, const int32_t* qa, const int32_t* qb,
     Pose<D> PA = perturbed<D>(RA, ps + 4, xi, xi + 3, true);
     Pose<D> PB = perturbed<D>(RB, ps + 11, xi + 6, xi + 9, true);
     std::vector<GroupOut<D>> out;
+    probe_begin(*prm, i, obj(qa[i]), obj(qb[i]));
     query(obj(qa[i]), obj(qb[i]), PA, PB, *prm, out, nullptr);
+    probe_end();
     for (size_t g = 0; g < out.size(); ++g)
       for (int k = 0; k < 12; ++k) {
         const D& c = comp(out[g], k);

@@ -1,9 +1,11 @@
 """Python API over the C ABI (include/cm.h): contexts, resident objects, plans,
-and launches on torch-managed device memory and streams.
+launches on torch-managed device memory and streams, and the autograd layer
+(ContactFn) whose backward passes call the library's adjoint, Hessian-vector
+and Jacobian-vector entry points.
 
-PyTorch is used for device memory and streams only (gradients come from the
-library's adjoint entry points, not from torch.autograd); every
-step of the contact pipeline runs in libcm.so's gfx950 kernels.
+PyTorch provides device memory, streams and the autograd graph only; every
+step of the contact pipeline and its derivatives runs in libcm.so's gfx950
+kernels.
 """
 from __future__ import annotations
 
@@ -394,7 +396,7 @@ class Server:
         s = np.zeros(7, np.int64)
         self.ctx._check(_cm.cm_serve_stats(self.ctx.handle, _ptr(s)), "cm_serve_stats")
         return dict(submitted=int(s[0]), completed=int(s[1]), batches=int(s[2]), queued=int(s[3]),
-                    in_flight=int(s[4]), peak_inflight_bytes=int(s[5]), queries=int(s[6]))
+                    in_flight=int(s[4]), peak_device_bytes=int(s[5]), queries=int(s[6]))
 
 
 class Ticket:
@@ -423,3 +425,111 @@ class Ticket:
         if self.status != 0:
             raise CMError(self.status, "request failed")
         return self.out, self.grad
+
+
+# ------------------------------------------------------------------ autograd --
+def _require_zero(xi):
+    if bool(xi.detach().any()):
+        raise ValueError("ContactFn evaluates the records at the plan's poses, i.e. at xi = 0; retract a "
+                         "perturbation into the poses (R <- exp([w]x) R, t <- t + v) and write new queries instead")
+
+
+def _torch_fn():
+    torch = _torch()
+
+    class HvpFn(torch.autograd.Function):
+        """u -> H_c u, the Hessian of L = <c, y> w.r.t. xi along u (cm_hvp).
+        Linear in u with H symmetric, so its backward along w is H_c w.  Third
+        derivatives (w.r.t. xi or c) are not provided."""
+
+        @staticmethod
+        def forward(ctx, u, xi, cot, plan, q_dev):
+            ctx.plan, ctx.q_dev = plan, q_dev
+            ctx.save_for_backward(cot)
+            return plan.hvp(q_dev, cot, u.detach().contiguous())
+
+        @staticmethod
+        def backward(ctx, w):
+            (cot,) = ctx.saved_tensors
+            gu = HvpFn.apply(w.contiguous(), None, cot, ctx.plan, ctx.q_dev) if ctx.needs_input_grad[0] else None
+            return gu, None, None, None, None
+
+    class JvpFn(torch.autograd.Function):
+        """u -> J u, the derivative of the records along the pose direction u
+        (cm_contacts_jvp).  Its backward along w: J^T w (cm_contacts_bwd) for u,
+        and H_w u (cm_hvp with cotangent w) for xi."""
+
+        @staticmethod
+        def forward(ctx, u, xi, plan, q_dev):
+            ctx.plan, ctx.q_dev = plan, q_dev
+            u = u.detach().contiguous()
+            ctx.save_for_backward(u, xi)
+            return plan.jvp(q_dev, u)[1]
+
+        @staticmethod
+        def backward(ctx, w):
+            u, xi = ctx.saved_tensors
+            w = w.contiguous()
+            gu = ContactGrad.apply(xi, w, ctx.plan, ctx.q_dev) if ctx.needs_input_grad[0] else None
+            gx = HvpFn.apply(u, xi, w, ctx.plan, ctx.q_dev) if ctx.needs_input_grad[1] else None
+            return gu, gx, None, None
+
+    class ContactGrad(torch.autograd.Function):
+        """(xi, c) -> dL/dxi for L = <c, y(xi)> (cm_contacts_bwd).  Its backward
+        along v: H_c v w.r.t. xi (cm_hvp) and J v w.r.t. c (cm_contacts_jvp), each
+        itself differentiable in v, so torch.autograd.functional.hvp's
+        double-backward works."""
+
+        @staticmethod
+        def forward(ctx, xi, cot, plan, q_dev):
+            ctx.plan, ctx.q_dev = plan, q_dev
+            cot = cot.detach().contiguous()
+            ctx.save_for_backward(xi, cot)
+            return plan.backward(q_dev, cot)
+
+        @staticmethod
+        def backward(ctx, v):
+            xi, cot = ctx.saved_tensors
+            v = v.contiguous()
+            gx = HvpFn.apply(v, xi, cot, ctx.plan, ctx.q_dev) if ctx.needs_input_grad[0] else None
+            gc = JvpFn.apply(v, xi, ctx.plan, ctx.q_dev) if ctx.needs_input_grad[1] else None
+            return gx, gc, None, None
+
+    class ContactFn(torch.autograd.Function):
+        """Group records y [12, G] (rows p, n, d, q, W, logZ) of a plan's batch as
+        a function of the pose perturbation xi [n, 12] = (w_A, v_A, w_B, v_B) per
+        query, T_X <- (exp([w_X]x) R_X, t_X + v_X), evaluated at xi = 0 (the
+        poses in q_dev; a nonzero xi is rejected).  forward: cm_contacts_fwd;
+        backward: cm_contacts_bwd, through ContactGrad, whose own backward calls
+        cm_hvp and cm_contacts_jvp, so torch.autograd.grad and
+        torch.autograd.functional.hvp over xi work for any loss of the records.
+        The derivatives are those of the pose twist at zero (the ones the
+        adjoint kernels compute); use: ContactFn.apply(xi, plan, q_dev)."""
+
+        @staticmethod
+        def forward(ctx, xi, plan, q_dev):
+            _require_zero(xi)
+            ctx.plan, ctx.q_dev = plan, q_dev
+            ctx.save_for_backward(xi)
+            return plan.forward(q_dev)
+
+        @staticmethod
+        def backward(ctx, gy):
+            (xi,) = ctx.saved_tensors
+            return ContactGrad.apply(xi, gy.contiguous(), ctx.plan, ctx.q_dev), None, None
+
+    return ContactFn, ContactGrad, HvpFn, JvpFn
+
+
+_FNS = None
+
+
+def __getattr__(name):
+    # the autograd classes are created on first use, so that importing this
+    # module does not import torch
+    global _FNS
+    if name in ("ContactFn", "ContactGrad", "HvpFn", "JvpFn"):
+        if _FNS is None:
+            _FNS = dict(zip(("ContactFn", "ContactGrad", "HvpFn", "JvpFn"), _torch_fn()))
+        return _FNS[name]
+    raise AttributeError(name)

@@ -306,11 +306,10 @@ static cm_status register_objects(cm_context* ctx, std::vector<ObjHost>& built, 
       size_t cap = std::max<size_t>(need, 2 * ctx->d_objs_cap + 64);
       ObjDesc* nd = nullptr;
       if (hipMalloc(&nd, cap * sizeof(ObjDesc)) != hipSuccess) { ctx->err = "object table allocation failed"; return CM_E_OOM; }
-      if (ctx->d_objs) {
-        (void)hipStreamSynchronize(ctx->build_stream);
-        (void)hipDeviceSynchronize();  // no kernel may still read the old table
-        (void)hipFree(ctx->d_objs);
-      }
+      // the old table is kept until shutdown: kernels in flight, captured
+      // graphs and a serving batch being launched may still hold its address
+      // (its descriptors stay valid for the objects it lists)
+      if (ctx->d_objs) ctx->old_tables.push_back(ctx->d_objs);
       ctx->d_objs = nd;
       ctx->d_objs_cap = cap;
       std::vector<ObjDesc> all(need);
@@ -885,7 +884,10 @@ FwdArgs fwd_args(cm_context* ctx, cm_plan* pl, const cm_query* q, const cm_group
   a.ents = pl->d_ents;
   a.n_ent = pl->E;
   a.Q = reinterpret_cast<const QueryDev*>(q);
-  a.objs = ctx->d_objs;
+  {
+    std::lock_guard<std::mutex> lk(ctx->mu);  // the table may be replaced by a concurrent build
+    a.objs = ctx->d_objs;
+  }
   a.P = ctx->dp;
   a.bits = pl->d_bits;
   a.nsurv = pl->d_nsurv;
@@ -1014,6 +1016,7 @@ cm_status cm_shutdown(cm_context* ctx) {
   if (ctx->device >= 0) (void)hipDeviceSynchronize();
   ctx->arena.reset();
   if (ctx->d_objs) (void)hipFree(ctx->d_objs);
+  for (cm::ObjDesc* t : ctx->old_tables) (void)hipFree(t);
   if (ctx->build_stream) (void)hipStreamDestroy(ctx->build_stream);
   delete ctx;
   return CM_OK;

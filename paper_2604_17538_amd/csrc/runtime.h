@@ -70,6 +70,7 @@ struct cm_context {
   std::vector<cm::ObjHost> objs;
   cm::ObjDesc* d_objs = nullptr;  // device table
   size_t d_objs_cap = 0;
+  std::vector<cm::ObjDesc*> old_tables;  // outgrown tables, freed at shutdown
   std::unique_ptr<cm::Arena> arena;
   hipStream_t build_stream = nullptr;
   cm::Serving* serving = nullptr;

@@ -3,9 +3,11 @@
 // cm_submit copies a request (host queries, optional cotangents) into the
 // pending queue.  A scheduler thread, started on the first submit, keeps up to
 // kSlots batches in flight on their own streams: whenever a slot is free it
-// admits pending requests in arrival order while the device memory they need
-// (plan scratch + buffers, estimated exactly as the plan lays it out) stays
-// within the context's budget, packs their queries into one batch, runs the
+// admits pending requests in arrival order while the device memory the slots
+// hold stays within the context's budget (each request's plan scratch and
+// buffers estimated as the plan lays them out; a slot's buffer is sized to its
+// batch, and idle slots give theirs back when a batch needs the room), packs
+// their queries into one batch, runs the
 // forward pass over all of them and the adjoint over those that asked for a
 // gradient, and copies the results back into pinned staging.  Batches on
 // different streams overlap; the next batch is formed while others run.
@@ -26,6 +28,10 @@ namespace {
 constexpr int kSlots = 3;
 constexpr int64_t kMaxBatchQueries = 16384;
 constexpr size_t kQueueLimit = 1 << 20;
+// a batch's layout can exceed the sum of its requests' layouts by a tape tile
+// and a few aligned arrays per request (rounding of the merged sizes)
+constexpr size_t kSlackPerRequest = size_t(16) << 10;
+constexpr size_t kDevGranule = size_t(1) << 20;  // slot buffers are sized in MiB
 
 double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
@@ -71,7 +77,8 @@ struct Serving {
   std::deque<Req*> pending;
   std::unordered_map<cm_ticket, cm_status> finished;
   std::unordered_map<cm_ticket, int> live;  // submitted, not yet finished
-  size_t inflight = 0, peak_inflight = 0;
+  size_t inflight = 0;            // estimated bytes of the admitted requests
+  size_t held = 0, peak_held = 0;  // device bytes the slots' buffers hold (never above the budget)
   bool stop = false;
   cm_ticket next = 1;
   int64_t n_submitted = 0, n_completed = 0, n_batches = 0, n_queries = 0;
@@ -91,17 +98,42 @@ size_t request_bytes(cm_plan& pl, bool grad) {
     pl.tape_kind = 1;  // the adjoint plan: a tape of float values
     b += plan_layout(&pl, nullptr) + 64 * size_t(pl.n) + 48 * size_t(pl.G) + 48 * size_t(pl.n);
   }
-  return b;
+  return b + kSlackPerRequest;
 }
 
-bool ensure_device(Slot& s, size_t bytes) {
+// Frees the buffers of idle slots other than `keep` (their last batch has
+// completed).  Called with S->mu held.
+void release_idle(Serving* S, const Slot* keep) {
+  for (Slot& t : S->slots) {
+    if (&t == keep || t.busy || !t.dmem) continue;
+    (void)hipStreamSynchronize(t.stream);
+    (void)hipFree(t.dmem);
+    S->held -= t.dcap;
+    t.dmem = nullptr;
+    t.dcap = 0;
+  }
+}
+
+// Sizes the slot's device buffer for a batch of `bytes` (exactly, in MiB
+// granules; a larger buffer is kept) so that the slots together never hold
+// more than the budget.
+bool ensure_device(Serving* S, Slot& s, size_t bytes) {
   if (s.dcap >= bytes) return true;
+  const size_t want = align_up(bytes, kDevGranule);
+  std::lock_guard<std::mutex> lk(S->mu);
+  if (S->held - s.dcap + want > S->ctx->budget) release_idle(S, &s);
+  if (S->held - s.dcap + want > S->ctx->budget) return false;
   if (s.dmem) {
     (void)hipStreamSynchronize(s.stream);
     (void)hipFree(s.dmem);
+    S->held -= s.dcap;
+    s.dmem = nullptr;
+    s.dcap = 0;
   }
-  s.dcap = std::max(bytes, 2 * s.dcap);
-  if (hipMalloc(&s.dmem, s.dcap) != hipSuccess) { s.dmem = nullptr; s.dcap = 0; return false; }
+  if (hipMalloc(&s.dmem, want) != hipSuccess) { s.dmem = nullptr; return false; }
+  s.dcap = want;
+  S->held += want;
+  S->peak_held = std::max(S->peak_held, S->held);
   return true;
 }
 
@@ -116,7 +148,7 @@ bool ensure_pinned(Slot& s, size_t bytes) {
 }
 
 // Builds the batch's plans and buffers and enqueues its work on the slot's stream.
-cm_status launch_batch(cm_context* ctx, Slot& s) {
+cm_status launch_batch(Serving* S, cm_context* ctx, Slot& s) {
   std::vector<cm_query> qa, qg;
   std::vector<const Req*> gr;
   for (const Req* r : s.reqs) {
@@ -149,7 +181,7 @@ cm_status launch_batch(cm_context* ctx, Slot& s) {
   s.d_out = take(48 * size_t(s.G));
   s.d_cot = take(48 * size_t(s.Gg));
   s.d_grad = take(48 * size_t(s.ng));
-  if (!ensure_device(s, off)) return fail(ctx, CM_E_OOM, "serving: device allocation failed");
+  if (!ensure_device(S, s, off)) return fail(ctx, CM_E_OOM, "serving: device allocation within the budget failed");
   size_t hoff = 0;
   auto htake = [&](size_t b) { size_t r = hoff; hoff = align_up(hoff + b, 256); return r; };
   s.h_q = htake(64 * size_t(s.n));
@@ -247,16 +279,22 @@ void scheduler(Serving* S) {
       progressed = true;
       S->done_cv.notify_all();
     }
-    // admission into free slots
+    // admission into free slots: a batch may use the budget less what the
+    // other slots hold (idle slots give their buffers back when it is short)
     for (Slot& s : S->slots) {
       if (s.busy || S->pending.empty()) continue;
       size_t bytes = 0;
       int64_t nq = 0;
       while (!S->pending.empty()) {
         Req* r = S->pending.front();
-        const bool fits = S->inflight + bytes + r->bytes <= ctx->budget;
+        const size_t room = ctx->budget - (S->held - s.dcap);
+        bool fits = bytes + r->bytes <= room;
+        if (!fits && s.reqs.empty()) {
+          release_idle(S, &s);
+          fits = r->bytes <= ctx->budget - (S->held - s.dcap);
+        }
         if (!s.reqs.empty() && (!fits || nq + int64_t(r->q.size()) > kMaxBatchQueries)) break;
-        if (s.reqs.empty() && !fits && S->inflight > 0) break;  // wait for memory to free up
+        if (s.reqs.empty() && !fits) break;  // wait for busy slots to finish
         S->pending.pop_front();
         s.reqs.push_back(r);
         bytes += r->bytes;
@@ -266,10 +304,9 @@ void scheduler(Serving* S) {
       s.busy = true;
       s.bytes = bytes;
       S->inflight += bytes;
-      S->peak_inflight = std::max(S->peak_inflight, S->inflight);
       S->n_batches++;
       lk.unlock();
-      const cm_status st = launch_batch(ctx, s);
+      const cm_status st = launch_batch(S, ctx, s);
       lk.lock();
       if (st != CM_OK) {
         for (Req* r : s.reqs) {
@@ -453,7 +490,7 @@ cm_status cm_serve_stats(cm_context* ctx, int64_t* st) {
   st[2] = S->n_batches;
   st[3] = int64_t(S->pending.size());
   st[4] = busy;
-  st[5] = int64_t(S->peak_inflight);
+  st[5] = int64_t(S->peak_held);
   st[6] = S->n_queries;
   return CM_OK;
 }

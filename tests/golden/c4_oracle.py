@@ -1,9 +1,16 @@
-"""Writes c4_oracle.json beside this file: the FP64 oracle's results for four
+"""Writes c4_oracle.json beside this file: the FP64 oracle's results for
 pair-queries sampled from the large workload (65536 pairs of 32-piece objects,
 pieces hulls of log-uniform [64, 1024] ellipsoid points, the objects drawn
 from a library of 2048), so that the GPU test of the full launch can compare
-against them without re-running the oracle (about 11 minutes of hyper-dual
+against them without re-running the oracle (several minutes of hyper-dual
 arithmetic per query on one core).
+
+Which queries: the oracle's own forward records of N_CANDIDATES evenly spaced
+queries decide.  A query's active groups are those with blended Jacobian
+weight W > 1e-6 (some contact within d_max); the N_ACTIVE queries with the most
+active groups are kept, then up to N_SHALLOW more whose deepest group is near
+contact only (0 <= min d < d_max), then the deepest remaining query, so the
+sample holds deep penetration, near contact and fully filtered pieces.
 
 Stored per sampled query: the group records (p, n, d, q, W, logZ), the gradient
 of <c, records> w.r.t. both poses and the Hessian-vector product along the
@@ -14,7 +21,7 @@ groups in order, as for the other parity tests), and a digest of the sampled
 inputs lets the test check that it regenerated the same workload.
 
 Only the oracle and the seeded input generators are called.  Usage:
-    python tests/golden/c4_oracle.py [--threads 4]
+    python tests/golden/c4_oracle.py [--threads 8]
 """
 import argparse
 import hashlib
@@ -32,13 +39,16 @@ sys.path.insert(0, ROOT)
 
 N_ENVS = 65536
 LIBRARY = 2048
-N_SAMPLE = 4
+N_CANDIDATES = 32
+N_ACTIVE = 8
+N_SHALLOW = 2
 SEEDS = (1, 2)
+W_ACTIVE = 1e-6
 OUT = os.path.join(HERE, "c4_oracle.json")
 
 
-def sample(n):
-    return np.linspace(0, n - 1, N_SAMPLE).astype(np.int64)
+def candidates(n):
+    return np.linspace(0, n - 1, N_CANDIDATES).astype(np.int64)
 
 
 def input_digest(w, sel):
@@ -53,18 +63,37 @@ def input_digest(w, sel):
     return h.hexdigest()
 
 
+def choose(cand, g, goff, d_max):
+    """Indices into cand of the sampled queries (rule in the module docstring)."""
+    act, dmin = [], []
+    for k in range(len(cand)):
+        G = g[goff[k]:goff[k + 1]]
+        act.append(int((G[:, 10] > W_ACTIVE).sum()))
+        dmin.append(float(G[:, 6].min()))
+    act, dmin = np.array(act), np.array(dmin)
+    order = sorted(range(len(cand)), key=lambda k: (-act[k], k))
+    pick = [k for k in order if act[k] > 0][:N_ACTIVE]
+    shallow = [k for k in range(len(cand)) if k not in pick and 0.0 <= dmin[k] < d_max - 1e-12]
+    pick += shallow[:N_SHALLOW]
+    rest = [k for k in range(len(cand)) if k not in pick]
+    if rest:
+        pick.append(min(rest, key=lambda k: dmin[k]))
+    pick = sorted(pick)
+    return np.array(pick, np.int64), act, dmin
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--threads", type=int, default=N_SAMPLE)
+    ap.add_argument("--threads", type=int, default=8)
     args = ap.parse_args()
     import oracle as O
     from paper_2604_17538_amd import workloads as W
     O.build(force=False)
     t0 = time.time()
     w = W.config4(n_envs=N_ENVS, library=LIBRARY)
-    sel = sample(w.n)
+    cand = candidates(w.n)
     prm = O.default_params(w.L_ref)
-    need = sorted({int(w.qa[i]) for i in sel} | {int(w.qb[i]) for i in sel})
+    need = sorted({int(w.qa[i]) for i in cand} | {int(w.qb[i]) for i in cand})
 
     def make(j):
         o = O.from_workload_object(w.objects[j])
@@ -72,21 +101,28 @@ def main():
         return j, o
 
     objs = [None] * len(w.objects)
-    with ThreadPoolExecutor(len(need)) as ex:
+    with ThreadPoolExecutor(2) as ex:
         for j, o in ex.map(make, need):
             objs[j] = o
     print("objects %.1f s" % (time.time() - t0), flush=True)
+    gc, goc = O.contacts(prm, objs, w.qa[cand], w.qb[cand], w.poses[cand], threads=args.threads)
+    pick, act, dmin = choose(cand, gc, goc, prm.d_max)
+    sel = cand[pick]
+    print("candidates %.1f s; selected %s (active groups %s, min d %s)"
+          % (time.time() - t0, sel.tolist(), act[pick].tolist(), np.round(dmin[pick], 5).tolist()), flush=True)
     qa, qb, poses = w.qa[sel], w.qb[sel], w.poses[sel]
     g, goff = O.contacts(prm, objs, qa, qb, poses, threads=args.threads)
-    print("records %.1f s" % (time.time() - t0), flush=True)
     cot = W.cotangents(w.cot_seed, goff[-1])
     direc = W.directions(w.cot_seed, len(sel))
-    dg, dh, grad, hv = O.fp32_spread(prm, objs, qa, qb, poses, cot, direc, seeds=SEEDS, threads=args.threads,
+    dg, dh, grad, hv = O.fp32_spread(prm, objs, qa, qb, poses, cot, direc, seeds=SEEDS,
+                                     threads=max(1, args.threads // (len(SEEDS) + 1)),
                                      concurrent=True, return_base=True)
     print("gradient, H v and spread %.1f s" % (time.time() - t0), flush=True)
     r = np.array([objs[j].radius() if objs[j] is not None else 0.0 for j in range(len(objs))])
     doc = {
         "workload": {"n_envs": N_ENVS, "library": LIBRARY, "seed": W.SEED_BASE + 4, "cot_seed": int(w.cot_seed)},
+        "selection": {"candidates": cand.tolist(), "active_groups": act.tolist(), "min_d": dmin.tolist(),
+                      "rule": "most active groups (W > 1e-6), then near-contact-only, then the deepest remaining"},
         "sel": sel.tolist(),
         "input_sha256": input_digest(w, sel),
         "group_off": goff.tolist(),

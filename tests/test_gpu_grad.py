@@ -1,13 +1,8 @@
 """GPU parity of the adjoint (gradient w.r.t. both poses) and of the
 Hessian-vector product against the FP64 oracle's hyper-dual derivatives, on the
 full config-0 batch: per query, |grad_gpu - grad_oracle| <= 1e-4 |grad_oracle|
-(norm-wise over the 12-vector) and |Hv_gpu - Hv_oracle| <= 1e-3 |Hv_oracle|.
-
-The gradient bound is the stated one.  No bound is stated for H v; it is one
-derivative further from the FP32-rounded evaluation point, and that derivative
-varies on the temperature scale (the sphere-trace gate, the mollifier, normals
-turning within tau of an edge), so its attainable accuracy is about a decade
-below the gradient's: 1e-3.
+and |Hv_gpu - Hv_oracle| <= 1e-4 |Hv_oracle| (norm-wise over the 12-vector),
+the stated bound for gradients and HVP.
 
 Where the reference cancels to zero (separated unit boxes: every output is a
 blend of vertices symmetric about the body origin, so rotations leave it fixed)
@@ -37,7 +32,7 @@ from tests import parity as PT
 pytestmark = pytest.mark.gpu
 
 REL = 1e-4
-REL_HVP = 1e-3
+REL_HVP = 1e-4
 K_SPREAD = 4.0
 
 

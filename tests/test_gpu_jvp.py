@@ -1,7 +1,12 @@
 """GPU parity of the Jacobian-vector product (cm_contacts_jvp) on the full
 config-0 batch against the FP64 oracle.
 
-The tangent records J v along a unit direction v per query are checked through
+Element by element: every group's tangent record (J v)_g against the oracle's
+own Jacobian-vector product (one dual slot seeded with v), norm-wise over the
+12 components with logZ's scaled by tau_b (a length, like the others), held to
+max(1e-4 max(|ref|, 1e-3 max(1, L_s)), 4 x the oracle's FP32 spread of it).
+
+Beside it, the tangent records J v along a unit direction v per query are checked through
 the identity sum_g <c_g, (J v)_g> = grad_xi <c, y> . v for random cotangents c:
 the right side is the oracle's hyper-dual gradient, so every component of J v
 is weighed against the oracle (two independent cotangents per query).  The
@@ -53,6 +58,19 @@ def test_jvp_matches_oracle_gradient_projections():
     for k in ("pos", "logZ", "W", "n"):
         assert err[k] <= 1.0, (k, err)
     assert np.all(np.isfinite(jv))
+    _, jv_o, _ = O.jvp(prm, objs, w.qa, w.qb, w.poses, v, threads=16)
+    sp = O.jvp_spread(prm, objs, w.qa, w.qb, w.poses, v, threads=16)
+    sc = np.ones(12)
+    sc[11] = prm.tau_blend
+    LsG = np.repeat(Lq, np.diff(goff))
+    nref = np.linalg.norm(jv_o * sc, axis=1)
+    allowed = np.maximum(REL * np.maximum(nref, 1e-3 * np.maximum(1.0, LsG)), K_SPREAD * sp)
+    ratio = np.linalg.norm((jv - jv_o) * sc, axis=1) / allowed
+    _log("jvp tangents element by element: max error / allowed %.3f (group %d); %d of %d groups held to the "
+         "FP32 spread" % (ratio.max(), int(np.argmax(ratio)),
+                          int(np.count_nonzero(K_SPREAD * sp > REL * np.maximum(nref, 1e-3 * np.maximum(1.0, LsG)))),
+                          len(ratio)))
+    assert ratio.max() <= 1.0
     for seed in (42, 43):
         cot = W.cotangents(seed, goff[-1])
         gr = O.grad_hvp(prm, objs, w.qa, w.qb, w.poses, cot, threads=16)

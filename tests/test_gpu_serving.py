@@ -67,3 +67,39 @@ def test_request_over_budget_is_rejected(lib):
     assert e.value.status == -2
     with pytest.raises(api.CMError):  # degenerate quaternion
         srv.submit(h2[:1], h2[1:2], np.zeros((1, 14)))
+
+
+def test_device_memory_held_stays_within_budget(lib):
+    """A small budget (48 MiB) under a burst of mixed traffic: the slots'
+    device buffers together never exceed it (the library's own record of the
+    bytes it holds), every admitted request completes, and results stay bitwise
+    those of the queries run alone."""
+    api, _, _, objs = lib
+    budget = 48 << 20
+    ctx = api.Context(0, L_ref=0.1, budget_bytes=budget)
+    hs = ctx.build_objects(objs)
+    tr = W.serving_trace(objs, rate_hz=5000.0, duration_s=0.02, seed=9, max_pairs=48)
+    srv = api.Server(ctx)
+    rng = np.random.default_rng(1)
+    tickets, reqs, refused = [], [], 0
+    for r in range(len(tr.n_pairs)):
+        qa, qb = hs[tr.pair_a[r]], hs[tr.pair_b[r]]
+        G = sum(ctx.object_info(int(a))[0] + ctx.object_info(int(b))[0] for a, b in zip(qa, qb))
+        cot = rng.standard_normal((G, 12)) if tr.want_grad[r] else None
+        try:
+            tickets.append(srv.submit(qa, qb, tr.poses[r], cot))
+            reqs.append((qa, qb, tr.poses[r], cot))
+        except api.CMError as e:
+            assert e.status == -2  # this request alone exceeds the budget
+            refused += 1
+    assert len(tickets) >= 40
+    for t in tickets:
+        t.wait()
+    st = srv.stats()
+    assert st["completed"] == len(tickets)
+    assert 0 < st["peak_device_bytes"] <= budget, st
+    for t, (qa, qb, poses, cot) in list(zip(tickets, reqs))[::7]:
+        o_ref, g_ref = _alone(api, ctx, hs, qa, qb, poses, cot)
+        assert np.array_equal(t.out, o_ref)
+        if cot is not None:
+            assert np.array_equal(t.grad, g_ref)
