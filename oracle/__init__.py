@@ -90,6 +90,15 @@ def lib():
         L.orc_groups_at_xi.argtypes = [P, I32, I32, P, P, P]
         L.orc_grad_hvp.argtypes = [P, I64, P, P, P, P, P, P, P, P, I32]
         L.orc_jvp.argtypes = [P, I64, P, P, P, P, P, P, P, I32]
+        L.orc_object_set_tris.argtypes = [I32, P, P]
+        L.orc_build_spline.argtypes = [I32, P]
+        L.orc_spline.argtypes = [I32, P, P]
+        L.orc_spline_edge_bound.restype = D
+        L.orc_spline_edge_bound.argtypes = [I32, P, P]
+        L.orc_spline_eval.argtypes = [I32, I64, P, P, P, P, P]
+        L.orc_ground_truth.argtypes = [I32, I64, P, P]
+        L.orc_spline_operator.argtypes = [I32, P]
+        L.orc_spline_from_values.argtypes = [I32, P, P, P, I64, P, P, P, P]
         _lib = L
     return _lib
 
@@ -156,6 +165,52 @@ class Obj:
                              _p(pe), _p(ab))
         return (pe, ab[0], ab[1]) if arc_lengths else pe
 
+    def set_triangles(self, tri_off, tris):
+        """Boundary triangles of the pieces (tri_off [n_pieces + 1], tris [T, 9]),
+        needed by the spline SDF's ground truth."""
+        self.tri_off = _c(tri_off, np.int64)
+        self.tris = _c(tris, np.float64).reshape(-1, 9)
+        lib().orc_object_set_tris(self.h, _p(self.tri_off), _p(self.tris))
+
+    def build_spline(self, prm: Params):
+        """Fits the cubic-spline SDF and normal (Sec. III-B) over the object's
+        grid box (grid_res cells per axis); the SDF side of every later query,
+        and the voxel grid built after it, then use the spline."""
+        if not hasattr(self, "tris"):
+            self.set_triangles(*_triangles_of(self))
+        lib().orc_build_spline(self.h, ctypes.byref(prm))
+
+    def spline(self):
+        """(n, origin [3], spacing [3], coefficients [4, n+3, n+3, n+3] of phi,
+        n_x, n_y, n_z)."""
+        meta = np.zeros(8)
+        lib().orc_spline(self.h, _p(meta), None)
+        n = int(meta[0])
+        C = np.zeros((4, n + 3, n + 3, n + 3))
+        lib().orc_spline(self.h, _p(meta), _p(C))
+        return n, meta[1:4].copy(), meta[4:7].copy(), C
+
+    def spline_edge_bound(self, x1, x2):
+        """Lower bound of the spline SDF over the segment x1 -> x2 (its grid)."""
+        return lib().orc_spline_edge_bound(self.h, _p(_c(x1, np.float64)), _p(_c(x2, np.float64)))
+
+    def spline_eval(self, x):
+        """phi [n], normal [n, 3], grad phi [n, 3], Jacobian of the normal [n, 3, 3]."""
+        x = _c(x, np.float64).reshape(-1, 3)
+        n = len(x)
+        phi, nr, g, J = np.zeros(n), np.zeros((n, 3)), np.zeros((n, 3)), np.zeros((n, 9))
+        lib().orc_spline_eval(self.h, n, _p(x), _p(phi), _p(nr), _p(g), _p(J))
+        return phi, nr, g, J.reshape(n, 3, 3)
+
+    def ground_truth(self, x):
+        """Ground-truth SDF [n] and normal [n, 3] of Sec. III-B.2 at points x."""
+        if not hasattr(self, "tris"):
+            self.set_triangles(*_triangles_of(self))
+        x = _c(x, np.float64).reshape(-1, 3)
+        out = np.zeros((len(x), 4))
+        lib().orc_ground_truth(self.h, len(x), _p(x), _p(out))
+        return out[:, 0], out[:, 1:]
+
     def __del__(self):
         try:
             lib().orc_object_free(self.h)
@@ -164,7 +219,39 @@ class Obj:
 
 
 def from_points(offsets, points) -> Obj:
-    return Obj(*geometry.object_geometry(np.asarray(offsets), np.asarray(points, np.float64)))
+    o = Obj(*geometry.object_geometry(np.asarray(offsets), np.asarray(points, np.float64)))
+    offsets = np.asarray(offsets)
+    tris = [geometry.piece_triangles(np.asarray(points, np.float64)[offsets[k]:offsets[k + 1]])
+            for k in range(len(offsets) - 1)]
+    o.set_triangles(np.concatenate([[0], np.cumsum([len(t) for t in tris])]), np.concatenate(tris))
+    return o
+
+
+def _triangles_of(o: Obj):
+    """Boundary triangles of an object given by explicit planes and vertices."""
+    tris = [geometry.raw_piece_triangles(o.planes[o.plane_off[k]:o.plane_off[k + 1]],
+                                         o.verts[o.vert_off[k]:o.vert_off[k + 1]]) for k in range(o.n_pieces)]
+    return np.concatenate([[0], np.cumsum([len(t) for t in tris])]), np.concatenate(tris)
+
+
+def spline_from_values(values, origin, spacing, x):
+    """The oracle's tensor-product cubic spline (natural end conditions) fitted to
+    values [4, n+1, n+1, n+1] at the corners of the box origin + [0, n] spacing,
+    evaluated at points x: (s_0 [N], (s_1, s_2, s_3) [N, 3], grad s_0 [N, 3])."""
+    v = _c(values, np.float64)
+    n = v.shape[1] - 1
+    x = _c(x, np.float64).reshape(-1, 3)
+    phi, nr, g = np.zeros(len(x)), np.zeros((len(x), 3)), np.zeros((len(x), 3))
+    lib().orc_spline_from_values(n, _p(_c(origin, np.float64)), _p(_c(spacing, np.float64)), _p(v), len(x),
+                                 _p(x), _p(phi), _p(nr), _p(g))
+    return phi, nr, g
+
+
+def spline_operator(n: int) -> np.ndarray:
+    """The oracle's 1-D interpolation operator M [(n+3), (n+1)]: coefficients = M values."""
+    M = np.zeros((n + 3, n + 1))
+    lib().orc_spline_operator(int(n), _p(M))
+    return M
 
 
 def from_workload_object(o) -> Obj:

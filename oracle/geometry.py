@@ -76,6 +76,37 @@ def piece_geometry(points: np.ndarray):
     return np.array(planes, np.float64), verts, E
 
 
+def piece_triangles(points: np.ndarray) -> np.ndarray:
+    """Boundary triangles [T, 9] of the hull of `points` (qhull's facets), for the
+    ground truth of the spline SDF."""
+    pts = np.asarray(points, np.float64)
+    hull = ConvexHull(pts)
+    return pts[hull.simplices].reshape(-1, 9)
+
+
+def raw_piece_triangles(planes: np.ndarray, verts: np.ndarray, tol: float = 1e-9) -> np.ndarray:
+    """Boundary triangles [T, 9] of a piece given explicitly by planes and
+    vertices: per plane, its vertices (within tol of it) ordered by angle about
+    their mean and joined as a fan."""
+    tris = []
+    scale = max(1.0, float(np.abs(verts).max()))
+    for n0, n1, n2, h in planes:
+        n = np.array([n0, n1, n2]) / np.linalg.norm([n0, n1, n2])
+        hh = h / np.linalg.norm([n0, n1, n2])
+        on = verts[np.abs(verts @ n + hh) < tol * scale]
+        if len(on) < 3:
+            continue
+        c = on.mean(0)
+        u = on[0] - c
+        u /= np.linalg.norm(u)
+        v = np.cross(n, u)
+        order = np.argsort(np.arctan2((on - c) @ v, (on - c) @ u))
+        ring = on[order]
+        for k in range(1, len(ring) - 1):
+            tris.append(np.concatenate([ring[0], ring[k], ring[k + 1]]))
+    return np.array(tris, np.float64).reshape(-1, 9)
+
+
 def object_geometry(offsets, points):
     """Per-piece hull geometry of an object given as point clouds.
 

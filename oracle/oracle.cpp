@@ -25,6 +25,10 @@
 //   O8  softmax blending per convex piece                       [Sec. IV-D.1-3]
 //   O9  both directions (SDF and mesh roles swapped)            [Sec. III, first paragraph]
 //   O10 derivatives w.r.t. world-frame pose perturbations       (project addition)
+//   S1  spline SDF: ground-truth SDF and normal of the pieces at the corners
+//       of a voxel grid, cubic-spline coefficients by 1-D solves along each
+//       axis, 64-term evaluation, a separate spline for the normal    [Sec. III-B.1/2]
+//   S2  voxel lower bounds of a spline SDF (B-spline convex hull)   (reading, see DESIGN)
 #include <algorithm>
 #include <array>
 #include <cmath>
@@ -178,6 +182,7 @@ struct Piece {
   std::vector<double> planes;  // 4 per plane: (n_x, n_y, n_z, h); inside where n.x + h <= 0
   std::vector<double> verts;   // 3 per vertex, object frame
   std::vector<int32_t> edges;  // 2 per edge, piece-local vertex indices
+  std::vector<double> tris;    // 9 per boundary triangle (only for the spline's ground truth)
   size_t n_planes() const { return planes.size() / 4; }
   size_t n_verts() const { return verts.size() / 3; }
   size_t n_edges() const { return edges.size() / 2; }
@@ -185,11 +190,22 @@ struct Piece {
 struct Grid {
   int n = 0;
   double origin[3] = {0, 0, 0}, h[3] = {0, 0, 0}, r = 0;
-  std::vector<double> G;  // phi at voxel centres, index (i * n + j) * n + k
+  std::vector<double> G;  // phi at voxel centres, index (i * n + j) * n + k (spline: its lower bound there)
+  bool spline = false;    // the grid of a spline SDF (S2)
+};
+// Cubic-spline SDF of an object (Sec. III-B): n intervals per axis over the
+// box [a, a + n h]; coefficients c[f] of phi (f = 0) and of the normal's three
+// components (f = 1..3) at (n + 3)^3 basis functions, index (i (n+3) + j) (n+3) + k.
+struct Spline {
+  int n = 0;
+  double a[3] = {0, 0, 0}, h[3] = {0, 0, 0};
+  std::vector<double> c[4];
 };
 struct Object {
   std::vector<Piece> pieces;
   Grid grid;
+  bool has_spline = false;
+  Spline spl;
 };
 
 std::mutex g_mu;
@@ -292,31 +308,294 @@ template <class T> T softclip(const T& x, const T& a, const T& b, double tau) {
   return a + softplus(x - a, tau) - softplus(x - b, tau);
 }
 
+
+// ------------------------------------------------------ S1 spline SDF --
+// The ground truth of Sec. III-B.2 needs the closest point of the piece's
+// surface: inside a convex piece it lies on the nearest facet plane, outside
+// on one of its boundary triangles.
+inline V3<double> closest_on_segment(const V3<double>& x, const V3<double>& a, const V3<double>& b) {
+  const V3<double> d = b - a;
+  const double dd = dot(d, d);
+  double t = dd > 0 ? dot(x - a, d) / dd : 0.0;
+  t = std::min(1.0, std::max(0.0, t));
+  return a + d * t;
+}
+// Closest point of the triangle t[0..8] to x: the projection onto its plane when
+// that lies inside (barycentric coordinates >= 0), else the closest of the three
+// sides' closest points.
+inline V3<double> closest_on_triangle(const V3<double>& x, const double* t) {
+  const V3<double> p0{t[0], t[1], t[2]}, p1{t[3], t[4], t[5]}, p2{t[6], t[7], t[8]};
+  const V3<double> e1 = p1 - p0, e2 = p2 - p0, r = x - p0;
+  const double a11 = dot(e1, e1), a12 = dot(e1, e2), a22 = dot(e2, e2);
+  const double b1 = dot(r, e1), b2 = dot(r, e2);
+  const double det = a11 * a22 - a12 * a12;
+  if (det > 0) {
+    const double u = (b1 * a22 - b2 * a12) / det, v = (a11 * b2 - a12 * b1) / det;
+    if (u >= 0 && v >= 0 && u + v <= 1) return p0 + e1 * u + e2 * v;
+  }
+  const V3<double> c[3] = {closest_on_segment(x, p0, p1), closest_on_segment(x, p1, p2),
+                           closest_on_segment(x, p2, p0)};
+  int best = 0;
+  double bd = 1e300;
+  for (int k = 0; k < 3; ++k) {
+    const V3<double> d = x - c[k];
+    if (dot(d, d) < bd) { bd = dot(d, d); best = k; }
+  }
+  return c[best];
+}
+
+// Exact SDF of a convex piece at x and the vector x - proj(x) from the closest
+// surface point: inside, the largest plane value a_j* (<= 0) and a_j* n_j*;
+// outside, the distance to the closest point over the boundary triangles.
+inline double piece_exact(const Piece& pc, const V3<double>& x, V3<double>& diff) {
+  double m = -1e300;
+  size_t jm = 0;
+  for (size_t j = 0; j < pc.n_planes(); ++j) {
+    const double* p = &pc.planes[4 * j];
+    const double a = x.x * p[0] + x.y * p[1] + x.z * p[2] + p[3];
+    if (a > m) { m = a; jm = j; }
+  }
+  if (m <= 0) {
+    const double* p = &pc.planes[4 * jm];
+    diff = V3<double>{p[0], p[1], p[2]} * m;
+    return m;
+  }
+  double best = 1e300;
+  for (size_t t = 0; t < pc.tris.size() / 9; ++t) {
+    const V3<double> d = x - closest_on_triangle(x, &pc.tris[9 * t]);
+    if (dot(d, d) < best) { best = dot(d, d); diff = d; }
+  }
+  return std::sqrt(best);
+}
+
+// Ground-truth SDF and normal of the object (Sec. III-B.2), the union of its
+// pieces: phi = min_k phi_k and, from the minimising piece, the unit direction
+// sign(phi) (x - proj(x)) / |x - proj(x)|: outside (x - proj) / phi, inside and
+// on the surface the outward normal of the nearest facet (the limit of the
+// paper's (x - proj) / (|x - proj| + eps) as eps -> 0, defined on the surface too).
+inline void ground_truth(const Object& o, const V3<double>& x, double* out4) {
+  double phi = 1e300;
+  V3<double> diff{0, 0, 0}, nin{0, 0, 0};
+  for (const Piece& pc : o.pieces) {
+    V3<double> d{0, 0, 0};
+    const double p = piece_exact(pc, x, d);
+    if (p < phi) {
+      phi = p;
+      diff = d;
+      if (p <= 0) {  // inside: the nearest facet's normal, found again by its value
+        double m = -1e300;
+        for (size_t j = 0; j < pc.n_planes(); ++j) {
+          const double* q = &pc.planes[4 * j];
+          const double a = x.x * q[0] + x.y * q[1] + x.z * q[2] + q[3];
+          if (a > m) { m = a; nin = V3<double>{q[0], q[1], q[2]}; }
+        }
+      }
+    }
+  }
+  const V3<double> n = phi > 0 ? diff * (1.0 / std::sqrt(dot(diff, diff))) : nin;
+  out4[0] = phi; out4[1] = n.x; out4[2] = n.y; out4[3] = n.z;
+}
+
+// 1-D interpolation operator (Sec. III-B.1): coefficients c_0..c_{n+2} of
+// s(t) = sum_m c_m u(t - m + 1), t in node units, from the values f_0..f_n at
+// the nodes, c = M f.  The square system is s(t_i) = c_i + 4 c_{i+1} + c_{i+2}
+// = f_i (i = 0..n) and the natural end conditions s''(t_0) = s''(t_n) = 0,
+// i.e. c_0 - 2 c_1 + c_2 = 0 and c_n - 2 c_{n+1} + c_{n+2} = 0; M is the first
+// n + 1 columns of its inverse (Gauss-Jordan with partial pivoting).
+inline std::vector<double> spline_operator(int n) {
+  const int m = n + 3;
+  std::vector<double> A(size_t(m) * m, 0.0), I(size_t(m) * m, 0.0);
+  auto at = [m](std::vector<double>& X, int r, int c) -> double& { return X[size_t(r) * m + c]; };
+  for (int i = 0; i <= n; ++i) { at(A, i, i) = 1; at(A, i, i + 1) = 4; at(A, i, i + 2) = 1; }
+  at(A, n + 1, 0) = 1; at(A, n + 1, 1) = -2; at(A, n + 1, 2) = 1;
+  at(A, n + 2, n) = 1; at(A, n + 2, n + 1) = -2; at(A, n + 2, n + 2) = 1;
+  for (int i = 0; i < m; ++i) at(I, i, i) = 1;
+  for (int col = 0; col < m; ++col) {
+    int piv = col;
+    for (int r = col + 1; r < m; ++r)
+      if (std::fabs(at(A, r, col)) > std::fabs(at(A, piv, col))) piv = r;
+    for (int k = 0; k < m; ++k) { std::swap(at(A, col, k), at(A, piv, k)); std::swap(at(I, col, k), at(I, piv, k)); }
+    const double d = at(A, col, col);
+    for (int k = 0; k < m; ++k) { at(A, col, k) /= d; at(I, col, k) /= d; }
+    for (int r = 0; r < m; ++r) {
+      const double f = at(A, r, col);
+      if (r == col || f == 0) continue;
+      for (int k = 0; k < m; ++k) { at(A, r, k) -= f * at(A, col, k); at(I, r, k) -= f * at(I, col, k); }
+    }
+  }
+  std::vector<double> M(size_t(m) * (n + 1));
+  for (int r = 0; r < m; ++r)
+    for (int k = 0; k <= n; ++k) M[size_t(r) * (n + 1) + k] = at(I, r, k);
+  return M;
+}
+
+// The box of an object's voxel grid and spline: the vertex AABB grown by
+// grid_margin + grid_margin_rel * (bounding radius), n = grid_res cells per axis.
+inline void object_box(const Object& o, const Params& prm, double* origin, double* h) {
+  double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+  double rad = 0;
+  for (const Piece& pc : o.pieces)
+    for (size_t i = 0; i < pc.n_verts(); ++i) {
+      const double* v = &pc.verts[3 * i];
+      for (int a = 0; a < 3; ++a) { lo[a] = std::min(lo[a], v[a]); hi[a] = std::max(hi[a], v[a]); }
+      rad = std::max(rad, std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]));
+    }
+  const double margin = prm.grid_margin + prm.grid_margin_rel * rad;
+  for (int a = 0; a < 3; ++a) {
+    origin[a] = lo[a] - margin;
+    h[a] = (hi[a] - lo[a] + 2 * margin) / prm.grid_res;
+  }
+}
+
+// S1: the ground truth at the (n + 1)^3 corners of the box, then the
+// coefficients of the four splines by the 1-D operator along z, y and x in
+// turn (the tensor-product interpolant; Sec. III-B.1).
+// Coefficients of the four splines from values [4][(n+1)^3] at the corners
+// (index (i (n+1) + j) (n+1) + k).
+void fit_spline(Spline& sp, const std::vector<double>& f) {
+  const int n = sp.n, n1 = n + 1, m = n + 3;
+  const std::vector<double> M = spline_operator(n);
+  for (int c = 0; c < 4; ++c) {
+    const double* F = &f[size_t(c) * n1 * n1 * n1];
+    std::vector<double> z(size_t(n1) * n1 * m), y(size_t(n1) * m * m);
+    sp.c[c].assign(size_t(m) * m * m, 0.0);
+    for (int i = 0; i < n1; ++i)
+      for (int j = 0; j < n1; ++j)
+        for (int r = 0; r < m; ++r) {
+          double s = 0;
+          for (int k = 0; k < n1; ++k) s += M[size_t(r) * n1 + k] * F[(size_t(i) * n1 + j) * n1 + k];
+          z[(size_t(i) * n1 + j) * m + r] = s;
+        }
+    for (int i = 0; i < n1; ++i)
+      for (int r = 0; r < m; ++r)
+        for (int q = 0; q < m; ++q) {
+          double s = 0;
+          for (int j = 0; j < n1; ++j) s += M[size_t(r) * n1 + j] * z[(size_t(i) * n1 + j) * m + q];
+          y[(size_t(i) * m + r) * m + q] = s;
+        }
+    for (int r = 0; r < m; ++r)
+      for (int q = 0; q < m; ++q)
+        for (int p = 0; p < m; ++p) {
+          double s = 0;
+          for (int i = 0; i < n1; ++i) s += M[size_t(r) * n1 + i] * y[(size_t(i) * m + q) * m + p];
+          sp.c[c][(size_t(r) * m + q) * m + p] = s;
+        }
+  }
+}
+
+void build_spline(Object& o, const Params& prm) {
+  Spline& sp = o.spl;
+  const int n = prm.grid_res;
+  sp.n = n;
+  object_box(o, prm, sp.a, sp.h);
+  const int n1 = n + 1;
+  std::vector<double> f(size_t(4) * n1 * n1 * n1);
+#ifdef _OPENMP
+#pragma omp parallel for collapse(2) schedule(dynamic, 1)
+#endif
+  for (int i = 0; i < n1; ++i)
+    for (int j = 0; j < n1; ++j)
+      for (int k = 0; k < n1; ++k) {
+        const V3<double> x{sp.a[0] + i * sp.h[0], sp.a[1] + j * sp.h[1], sp.a[2] + k * sp.h[2]};
+        double g[4];
+        ground_truth(o, x, g);
+        for (int c = 0; c < 4; ++c) f[((size_t(c) * n1 + i) * n1 + j) * n1 + k] = g[c];
+      }
+  fit_spline(sp, f);
+  o.has_spline = true;
+}
+
+template <class T> T clamp_to(const T& x, double lo, double hi) {
+  if (val(x) < lo) return T(lo);
+  if (val(x) > hi) return T(hi);
+  return x;
+}
+// The four basis functions that are nonzero in a cell, at the offset w in
+// [0, 1] into it: u(w + 1), u(w), u(w - 1), u(w - 2) of Sec. III-B.1.
+template <class T> void cell_weights(const T& w, T* b) {
+  const T v = 1.0 - w;
+  b[0] = v * v * v;
+  b[1] = 4.0 - 6.0 * w * w + 3.0 * w * w * w;
+  b[2] = 4.0 - 6.0 * v * v + 3.0 * v * v * v;
+  b[3] = w * w * w;
+}
+// S1 evaluation at x (object frame): the 64 nonzero terms of each spline.
+// Outside the box phi continues as s_phi(pi(x)) + |x - pi(x)| and the normal as
+// s_n(pi(x)), pi(x) the closest point of the box (reading, see DESIGN).
+template <class T> void spline_eval(const Spline& sp, const V3<T>& x, T& phi, V3<T>& nrm) {
+  const T xs[3] = {x.x, x.y, x.z};
+  T w[3][4];
+  int i0[3];
+  T out2(0.0);
+  bool outside = false;
+  for (int a = 0; a < 3; ++a) {
+    const double lo = sp.a[a], hi = sp.a[a] + sp.n * sp.h[a];
+    const T pa = clamp_to(xs[a], lo, hi);
+    if (val(xs[a]) < lo || val(xs[a]) > hi) {
+      const T d = xs[a] - pa;
+      out2 = out2 + d * d;
+      outside = true;
+    }
+    const T t = (pa - lo) * (1.0 / sp.h[a]);
+    const int i = std::min(std::max(int(std::floor(val(t))), 0), sp.n - 1);
+    i0[a] = i;
+    cell_weights(t - double(i), w[a]);
+  }
+  const size_t m = size_t(sp.n) + 3;
+  T acc[4] = {T(0.0), T(0.0), T(0.0), T(0.0)};
+  for (int p = 0; p < 4; ++p)
+    for (int q = 0; q < 4; ++q)
+      for (int r = 0; r < 4; ++r) {
+        const T wt = w[0][p] * w[1][q] * w[2][r];
+        const size_t idx = (size_t(i0[0] + p) * m + size_t(i0[1] + q)) * m + size_t(i0[2] + r);
+        for (int c = 0; c < 4; ++c) acc[c] += wt * sp.c[c][idx];
+      }
+  phi = outside ? acc[0] + sqrt(out2) : acc[0];
+  nrm = V3<T>{acc[1], acc[2], acc[3]};
+}
+
+// The SDF side of a contact, for either representation: phi alone, and phi
+// with the contact normal (planes: the normalised gradient; spline: the
+// separately fitted normal spline, Sec. III-B.2).
+template <class T> T object_phi(const Object& o, const V3<T>& x, const Params& prm) {
+  T phi;
+  if (o.has_spline) {
+    V3<T> n;
+    spline_eval(o.spl, x, phi, n);
+    probe(phi, true);
+  } else {
+    V3<T> g;
+    object_sdf(o, x, prm, phi, g);
+  }
+  return phi;
+}
+template <class T> void object_phi_normal(const Object& o, const V3<T>& x, const Params& prm, T& phi, V3<T>& n) {
+  if (o.has_spline) {
+    spline_eval(o.spl, x, phi, n);
+    probe(phi, true);
+    probe3(n, false);
+  } else {
+    V3<T> g;
+    object_sdf(o, x, prm, phi, g);
+    n = normal_of(g, prm);
+  }
+}
+
 // ------------------------------------------------------------------ O4 grid --
 void build_grid(Object& o, const Params& prm) {
-  double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
-  for (const Piece& pc : o.pieces)
-    for (size_t i = 0; i < pc.n_verts(); ++i)
-      for (int a = 0; a < 3; ++a) {
-        lo[a] = std::min(lo[a], pc.verts[3 * i + a]);
-        hi[a] = std::max(hi[a], pc.verts[3 * i + a]);
-      }
-  double rad = 0;  // bounding radius about the object origin
-  for (const Piece& pc : o.pieces)
-    for (size_t i = 0; i < pc.n_verts(); ++i)
-      rad = std::max(rad, std::sqrt(pc.verts[3 * i] * pc.verts[3 * i] + pc.verts[3 * i + 1] * pc.verts[3 * i + 1] +
-                                    pc.verts[3 * i + 2] * pc.verts[3 * i + 2]));
-  const double margin = prm.grid_margin + prm.grid_margin_rel * rad;
   Grid& g = o.grid;
   g.n = prm.grid_res;
+  object_box(o, prm, g.origin, g.h);
   double r2 = 0;
-  for (int a = 0; a < 3; ++a) {
-    g.origin[a] = lo[a] - margin;
-    g.h[a] = (hi[a] - lo[a] + 2 * margin) / g.n;
-    r2 += g.h[a] * g.h[a];
-  }
+  for (int a = 0; a < 3; ++a) r2 += g.h[a] * g.h[a];
   g.r = 0.5 * std::sqrt(r2);  // circumradius of a voxel
   g.G.assign(size_t(g.n) * g.n * g.n, 0.0);
+  // S2: a spline SDF is not a true distance (no 1-Lipschitz bound), so its
+  // voxels (the spline's own cells) store a lower bound of the spline over the
+  // cell instead: the three 1-D bases of a cell are >= 0 and each sums to 6, so
+  // s is 216 times a convex combination of the 64 coefficients the cell
+  // reaches, and s >= 216 min of them.
+  g.spline = o.has_spline;
 #ifdef _OPENMP
 #pragma omp parallel for collapse(2) schedule(dynamic, 4)
 #endif
@@ -325,9 +604,20 @@ void build_grid(Object& o, const Params& prm) {
       for (int k = 0; k < g.n; ++k) {
         V3<double> c{g.origin[0] + (i + 0.5) * g.h[0], g.origin[1] + (j + 0.5) * g.h[1],
                      g.origin[2] + (k + 0.5) * g.h[2]};
-        double phi; V3<double> gr;
-        object_sdf(o, c, prm, phi, gr);
-        g.G[(size_t(i) * g.n + j) * g.n + k] = phi;
+        const size_t v = (size_t(i) * g.n + j) * g.n + k;
+        if (o.has_spline) {
+          const size_t m = size_t(g.n) + 3;
+          double lo = 1e300;
+          for (int p = 0; p < 4; ++p)
+            for (int q = 0; q < 4; ++q)
+              for (int r = 0; r < 4; ++r)
+                lo = std::min(lo, o.spl.c[0][(size_t(i + p) * m + size_t(j + q)) * m + size_t(k + r)]);
+          g.G[v] = 216.0 * lo;
+        } else {
+          double phi; V3<double> gr;
+          object_sdf(o, c, prm, phi, gr);
+          g.G[v] = phi;
+        }
       }
 }
 
@@ -350,7 +640,41 @@ inline double lower_bound(const Grid& g, const V3<double>& x, double* face_dist 
   }
   double Gc = g.G[(size_t(idx[0]) * g.n + idx[1]) * g.n + idx[2]];
   if (face_dist) *face_dist = fd;
+  if (g.spline) {
+    // S2: the cell's bound holds at pi(x), the closest point of the box (whose
+    // cell is the clamped one), and outside the box phi = s(pi(x)) + |x - pi(x)|
+    double o2 = 0;
+    for (int a = 0; a < 3; ++a) {
+      const double lo = g.origin[a], hi = g.origin[a] + g.n * g.h[a];
+      const double d = xs[a] < lo ? lo - xs[a] : (xs[a] > hi ? xs[a] - hi : 0.0);
+      o2 += d * d;
+    }
+    return Gc + std::sqrt(o2);
+  }
   return Gc - std::max(g.r, std::sqrt(d2));
+}
+
+// S2 for an edge x1 -> x2 against a spline SDF: every point of the segment lies
+// in its bounding box, whose closest points of the grid box lie in the cells
+// of the clamped index range, so phi >= (least cell bound over that range) +
+// (distance from the bounding box to the grid box).
+inline double spline_edge_bound(const Grid& g, const V3<double>& x1, const V3<double>& x2) {
+  const double a[3] = {x1.x, x1.y, x1.z}, b[3] = {x2.x, x2.y, x2.z};
+  int lo[3], hi[3];
+  double gap2 = 0;
+  for (int k = 0; k < 3; ++k) {
+    const double mn = std::min(a[k], b[k]), mx = std::max(a[k], b[k]);
+    lo[k] = std::min(std::max(int(std::floor((mn - g.origin[k]) / g.h[k])), 0), g.n - 1);
+    hi[k] = std::min(std::max(int(std::floor((mx - g.origin[k]) / g.h[k])), 0), g.n - 1);
+    const double blo = g.origin[k], bhi = g.origin[k] + g.n * g.h[k];
+    const double d = mx < blo ? blo - mx : (mn > bhi ? mn - bhi : 0.0);
+    gap2 += d * d;
+  }
+  double m = 1e300;
+  for (int i = lo[0]; i <= hi[0]; ++i)
+    for (int j = lo[1]; j <= hi[1]; ++j)
+      for (int k = lo[2]; k <= hi[2]; ++k) m = std::min(m, g.G[(size_t(i) * g.n + j) * g.n + k]);
+  return m + std::sqrt(gap2);
 }
 
 // ------------------------------------------------------------- O6 E-SDF --
@@ -467,7 +791,7 @@ template <class T> struct Pose { M3<T> R; V3<T> t; };
 
 template <class T> struct SdfFn {
   const Object* o; const Params* prm;
-  T operator()(const V3<T>& x) const { T phi; V3<T> g; object_sdf(*o, x, *prm, phi, g); return phi; }
+  T operator()(const V3<T>& x) const { return object_phi(*o, x, *prm); }
 };
 
 // One direction: vertices and edges of `mesh` against the SDF of `sdf`.
@@ -492,9 +816,9 @@ void direction(const Object& mesh, const Object& sdf, const Pose<T>& PM, const P
       if (bp && bound >= prm.d_max) {
         cs.push_back(filtered(Pw[i], prm));
       } else {
-        T phi; V3<T> g;
-        object_sdf(sdf, xs[i], prm, phi, g);
-        V3<T> Nw = mul(PS.R, normal_of(g, prm));
+        T phi; V3<T> nS;
+        object_phi_normal(sdf, xs[i], prm, phi, nS);
+        V3<T> Nw = mul(PS.R, nS);
         cs.push_back(mollify(phi, Nw, Pw[i], Pw[i], prm));
       }
       cs.back().kind = 0;
@@ -517,6 +841,7 @@ void direction(const Object& mesh, const Object& sdf, const Pose<T>& PM, const P
         // phi >= max(max(la, lb) - L, (la + lb - L) / 2).
         double lb = prm.edge_bound == 0 ? std::min(la, lbb) - L
                                         : std::max(std::max(la, lbb) - L, 0.5 * (la + lbb - L));
+        if (sdf.grid.spline) lb = spline_edge_bound(sdf.grid, a, b);
         ebound = lb;
         if (lb >= prm.d_max) {
           cs.push_back(filtered(rest, prm));
@@ -526,9 +851,9 @@ void direction(const Object& mesh, const Object& sdf, const Pose<T>& PM, const P
       }
       V3<T> pe = edge_point(fn, xs[i0], xs[i1], prm);
       probe3(pe, true);
-      T phi; V3<T> g;
-      object_sdf(sdf, pe, prm, phi, g);
-      V3<T> Nw = mul(PS.R, normal_of(g, prm));
+      T phi; V3<T> nS;
+      object_phi_normal(sdf, pe, prm, phi, nS);
+      V3<T> Nw = mul(PS.R, nS);
       V3<T> pw = mul(PS.R, pe) + PS.t;
       cs.push_back(mollify(phi, Nw, pw, rest, prm)); cs.back().kind = 1;
       if (bp) { cs.back().bound = ebound; cs.back().face_dist = efd; }
@@ -637,6 +962,83 @@ void orc_object_free(int32_t h) {
 }
 
 void orc_build_grid(int32_t h, const Params* prm) { build_grid(*g_objects.at(size_t(h)), *prm); }
+
+// Boundary triangles of each piece (9 doubles each, tri_off[n_pieces + 1]),
+// used only by the spline's ground truth.
+void orc_object_set_tris(int32_t h, const int64_t* tri_off, const double* tris) {
+  Object& o = *g_objects.at(size_t(h));
+  for (size_t k = 0; k < o.pieces.size(); ++k)
+    o.pieces[k].tris.assign(tris + 9 * tri_off[k], tris + 9 * tri_off[k + 1]);
+}
+
+// S1: fits the object's spline SDF (then its voxel grid follows the spline).
+void orc_build_spline(int32_t h, const Params* prm) { build_spline(*g_objects.at(size_t(h)), *prm); }
+
+// meta: n, origin (3), spacing (3); coeffs [4][(n+3)^3] may be null.
+void orc_spline(int32_t h, double* meta, double* coeffs) {
+  const Spline& sp = obj(h).spl;
+  meta[0] = sp.n;
+  for (int a = 0; a < 3; ++a) { meta[1 + a] = sp.a[a]; meta[4 + a] = sp.h[a]; }
+  if (coeffs)
+    for (int c = 0; c < 4; ++c) std::copy(sp.c[c].begin(), sp.c[c].end(), coeffs + size_t(c) * sp.c[c].size());
+}
+
+// S2 edge bound of the segment x1 -> x2 against the object's spline grid.
+double orc_spline_edge_bound(int32_t h, const double* x1, const double* x2) {
+  return spline_edge_bound(obj(h).grid, cvt<double>(x1), cvt<double>(x2));
+}
+
+// The spline's phi, normal (n x 3), gradient of phi (n x 3) and Jacobian of the
+// normal (n x 9, row a = d n_a / dx) at n points.
+void orc_spline_eval(int32_t h, int64_t n, const double* x, double* phi, double* nrm, double* grad, double* jac) {
+  const Spline& sp = obj(h).spl;
+  typedef Dual<double, 3> D3;
+  for (int64_t i = 0; i < n; ++i) {
+    V3<D3> xd{D3(x[3 * i]), D3(x[3 * i + 1]), D3(x[3 * i + 2])};
+    xd.x.d[0] = 1; xd.y.d[1] = 1; xd.z.d[2] = 1;
+    D3 p; V3<D3> nn;
+    spline_eval(sp, xd, p, nn);
+    phi[i] = p.v;
+    const D3* c[3] = {&nn.x, &nn.y, &nn.z};
+    for (int a = 0; a < 3; ++a) {
+      if (nrm) nrm[3 * i + a] = c[a]->v;
+      if (grad) grad[3 * i + a] = p.d[a];
+      if (jac) for (int b = 0; b < 3; ++b) jac[9 * i + 3 * a + b] = c[a]->d[b];
+    }
+  }
+}
+
+// Ground truth (phi, n) of Sec. III-B.2 at n points (n x 4).
+void orc_ground_truth(int32_t h, int64_t n, const double* x, double* out4) {
+  for (int64_t i = 0; i < n; ++i) ground_truth(obj(h), cvt<double>(x + 3 * i), out4 + 4 * i);
+}
+
+// The spline fitted to values [4][(n+1)^3] given at the corners of the box
+// [a, a + n h] (no object), evaluated at n_pts points: phi, normal spline,
+// gradient of phi.
+void orc_spline_from_values(int32_t n, const double* a, const double* h, const double* values, int64_t n_pts,
+                            const double* x, double* phi, double* nrm, double* grad) {
+  Spline sp;
+  sp.n = n;
+  for (int k = 0; k < 3; ++k) { sp.a[k] = a[k]; sp.h[k] = h[k]; }
+  fit_spline(sp, std::vector<double>(values, values + size_t(4) * (n + 1) * (n + 1) * (n + 1)));
+  typedef Dual<double, 3> D3;
+  for (int64_t i = 0; i < n_pts; ++i) {
+    V3<D3> xd{D3(x[3 * i]), D3(x[3 * i + 1]), D3(x[3 * i + 2])};
+    xd.x.d[0] = 1; xd.y.d[1] = 1; xd.z.d[2] = 1;
+    D3 p; V3<D3> nn;
+    spline_eval(sp, xd, p, nn);
+    phi[i] = p.v;
+    if (nrm) { nrm[3 * i] = nn.x.v; nrm[3 * i + 1] = nn.y.v; nrm[3 * i + 2] = nn.z.v; }
+    if (grad) for (int k = 0; k < 3; ++k) grad[3 * i + k] = p.d[k];
+  }
+}
+
+// The 1-D interpolation operator M [(n+3) x (n+1)].
+void orc_spline_operator(int32_t n, double* M) {
+  const std::vector<double> m = spline_operator(n);
+  std::copy(m.begin(), m.end(), M);
+}
 
 // meta: origin[3], h[3], r, n.  G may be null.
 void orc_grid(int32_t h, double* G, double* meta) {

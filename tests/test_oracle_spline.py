@@ -1,0 +1,214 @@
+"""Pins of the oracle's spline SDF (Sec. III-B) against what the mathematics
+and independent library routines fix, CPU only.
+
+* The 1-D interpolation with natural end conditions equals scipy's
+  CubicSpline(bc_type="natural") at arbitrary points, values and derivatives
+  (a function varying along one axis, constant along the others).
+* The 3-D tensor-product spline of a non-separable function equals successive
+  1-D natural-spline interpolation with scipy along z, then y, then x, at
+  arbitrary points; affine functions are reproduced exactly.
+* The ground truth of Sec. III-B.2 equals the closed-form SDF of a box (inside,
+  and outside in face, edge and corner regions) and of a union of two boxes
+  outside; its normal is the unit gradient of that SDF.
+* The voxel bounds of a spline SDF (the B-spline convex hull: 216 times the
+  least coefficient a cell reaches) never exceed the spline inside the cell,
+  nor along a segment; with them the broad phase changes no output bit.
+* The spline of a unit box approaches the box SDF away from its edges, and the
+  derivatives of a query through the spline SDF match central differences.
+"""
+import numpy as np
+import pytest
+from scipy.interpolate import CubicSpline
+
+import oracle as O
+from paper_2604_17538_amd import workloads as W
+
+
+def _grid(n, a, h):
+    ax = [a[k] + h[k] * np.arange(n + 1) for k in range(3)]
+    return ax, np.meshgrid(*ax, indexing="ij")
+
+
+def test_1d_natural_spline_matches_scipy(oracle_mod):
+    rng = np.random.default_rng(0)
+    n, a, h = 9, np.array([-0.3, 0.1, 0.2]), np.array([0.07, 0.05, 0.11])
+    ax, (X, Y, Z) = _grid(n, a, h)
+    f1 = rng.standard_normal(n + 1)
+    vals = np.zeros((4, n + 1, n + 1, n + 1))
+    vals[0] = f1[:, None, None]
+    x = np.column_stack([rng.uniform(a[0], a[0] + n * h[0], 200), rng.uniform(a[1], a[1] + n * h[1], 200),
+                         rng.uniform(a[2], a[2] + n * h[2], 200)])
+    phi, _, g = O.spline_from_values(vals, a, h, x)
+    cs = CubicSpline(ax[0], f1, bc_type="natural")
+    assert np.abs(phi - cs(x[:, 0])).max() < 1e-12
+    assert np.abs(g[:, 0] - cs(x[:, 0], 1)).max() < 1e-10
+    assert np.abs(g[:, 1:]).max() < 1e-10
+    # at the nodes the spline interpolates
+    xn = np.column_stack([ax[0], np.full(n + 1, a[1] + 2 * h[1]), np.full(n + 1, a[2] + 3 * h[2])])
+    assert np.abs(O.spline_from_values(vals, a, h, xn)[0] - f1).max() < 1e-12
+
+
+def test_3d_tensor_spline_matches_successive_scipy(oracle_mod):
+    rng = np.random.default_rng(1)
+    n, a, h = 7, np.array([0.0, -1.0, 0.5]), np.array([0.3, 0.25, 0.2])
+    ax, (X, Y, Z) = _grid(n, a, h)
+    F = np.sin(2 * X + Y) * np.cos(3 * Z - X * Y) + X * Y * Z
+    vals = np.zeros((4, n + 1, n + 1, n + 1))
+    vals[0] = F
+    vals[2] = np.exp(-X * X - Z)  # a second field through the same operator
+    x = np.column_stack([rng.uniform(a[k], a[k] + n * h[k], 60) for k in range(3)])
+    phi, nr, _ = O.spline_from_values(vals, a, h, x)
+
+    def successive(V, p):
+        gz = np.array([[CubicSpline(ax[2], V[i, j], bc_type="natural")(p[2]) for j in range(n + 1)]
+                       for i in range(n + 1)])
+        gy = np.array([CubicSpline(ax[1], gz[i], bc_type="natural")(p[1]) for i in range(n + 1)])
+        return CubicSpline(ax[0], gy, bc_type="natural")(p[0])
+
+    ref0 = np.array([successive(F, p) for p in x])
+    ref2 = np.array([successive(vals[2], p) for p in x])
+    assert np.abs(phi - ref0).max() < 1e-11
+    assert np.abs(nr[:, 1] - ref2).max() < 1e-11
+
+
+def test_affine_reproduced_exactly(oracle_mod):
+    rng = np.random.default_rng(2)
+    n, a, h = 6, np.array([0.1, 0.2, 0.3]), np.array([0.1, 0.2, 0.15])
+    _, (X, Y, Z) = _grid(n, a, h)
+    c = rng.standard_normal(4)
+    vals = np.zeros((4, n + 1, n + 1, n + 1))
+    vals[0] = c[0] + c[1] * X + c[2] * Y + c[3] * Z
+    x = np.column_stack([rng.uniform(a[k], a[k] + n * h[k], 100) for k in range(3)])
+    phi, _, g = O.spline_from_values(vals, a, h, x)
+    assert np.abs(phi - (c[0] + x @ c[1:])).max() < 1e-12
+    assert np.abs(g - c[1:]).max() < 1e-10
+    # outside the box the value continues with the distance to the box
+    xo = np.array([[a[0] - 0.2, a[1] + 0.3, a[2] + 0.2], [a[0] + 0.3, a[1] + n * h[1] + 0.4, a[2] + n * h[2] + 0.3]])
+    p = np.clip(xo, a, a + n * h)
+    phi_o = O.spline_from_values(vals, a, h, xo)[0]
+    assert np.allclose(phi_o, c[0] + p @ c[1:] + np.linalg.norm(xo - p, axis=1), atol=1e-12)
+
+
+def _box_sdf(x, b):
+    q = np.abs(x) - b
+    out = np.linalg.norm(np.maximum(q, 0), axis=1)
+    ins = np.minimum(q.max(1), 0)
+    return out + ins
+
+
+def test_ground_truth_box_closed_form(oracle_mod):
+    w = W.config0(n_poses=2)
+    box = O.from_workload_object(w.objects[0])  # unit box [-1/2, 1/2]^3, explicit planes
+    rng = np.random.default_rng(3)
+    x = rng.uniform(-1.2, 1.2, (4000, 3))
+    phi, nrm = box.ground_truth(x)
+    ref = _box_sdf(x, 0.5)
+    assert np.abs(phi - ref).max() < 1e-12
+    # the normal: gradient of the box SDF by central differences
+    e = 1e-7
+    gfd = np.column_stack([(_box_sdf(x + e * np.eye(3)[k], 0.5) - _box_sdf(x - e * np.eye(3)[k], 0.5)) / (2 * e)
+                           for k in range(3)])
+    far = np.abs(ref) > 1e-3
+    # away from the medial axis inside (ties between faces) the gradient is unique
+    q = np.sort(np.abs(x), axis=1)
+    unique = (ref > 0) | (q[:, 2] - q[:, 1] > 1e-3)
+    sel = far & unique
+    assert np.abs(nrm[sel] - gfd[sel]).max() < 1e-6
+    # outside in edge and corner regions too
+    assert ((np.abs(x) > 0.5).sum(1) >= 2).sum() > 500
+
+
+def test_ground_truth_union_of_boxes(oracle_mod):
+    # two overlapping boxes: outside the union the distance is the smaller box distance
+    pts = []
+    for c, b in (((0.0, 0.0, 0.0), (0.5, 0.3, 0.2)), ((0.4, 0.2, 0.1), (0.3, 0.4, 0.25))):
+        s = np.array(np.meshgrid(*[[-1, 1]] * 3, indexing="ij")).reshape(3, -1).T
+        pts.append(np.array(c) + s * np.array(b))
+    o = O.from_points(np.array([0, 8, 16]), np.concatenate(pts))
+    rng = np.random.default_rng(4)
+    x = rng.uniform(-1.5, 1.5, (3000, 3))
+    d1 = _box_sdf(x - np.array([0.0, 0.0, 0.0]), np.array([0.5, 0.3, 0.2]))
+    d2 = _box_sdf(x - np.array([0.4, 0.2, 0.1]), np.array([0.3, 0.4, 0.25]))
+    phi, _ = o.ground_truth(x)
+    out = np.minimum(d1, d2) > 0
+    assert out.sum() > 1000
+    assert np.abs(phi[out] - np.minimum(d1, d2)[out]).max() < 1e-12
+    assert np.abs(phi[~out] - np.minimum(d1, d2)[~out]).max() < 1e-12  # min of the pieces' SDFs
+
+
+@pytest.fixture(scope="module")
+def spline_pair(oracle_mod):
+    w = W.config1(n_envs=3)
+    prm = O.default_params(w.L_ref, grid_margin_rel=0.0)
+    objs = [O.from_workload_object(o) for o in w.objects]
+    for o in objs:
+        o.build_spline(prm)
+        o.build_grid(prm)
+    return w, prm, objs
+
+
+def test_cell_bounds_below_spline(spline_pair):
+    w, prm, objs = spline_pair
+    o = objs[0]
+    n, a, h, _ = o.spline()
+    G, org, hh, _ = o.grid()
+    assert np.allclose(org, a) and np.allclose(hh, h) and G.shape == (n, n, n)
+    rng = np.random.default_rng(5)
+    x = rng.uniform(a - 0.3 * n * h, a + 1.3 * n * h, (20000, 3))
+    phi = o.spline_eval(x)[0]
+    lb = np.array([o.lower_bound(p) for p in x])
+    assert (phi >= lb - 1e-12).all()
+    # and tight enough to filter: most far points are filtered
+    assert (lb >= prm.d_max).mean() > 0.5
+    for _ in range(200):
+        p1 = rng.uniform(a, a + n * h)
+        p2 = p1 + rng.normal(size=3) * 0.03
+        t = np.linspace(0, 1, 101)[:, None]
+        seg = p1 + t * (p2 - p1)
+        assert o.spline_eval(seg)[0].min() >= o.spline_edge_bound(p1, p2) - 1e-12
+
+
+def test_spline_broad_phase_changes_nothing(spline_pair):
+    w, prm, objs = spline_pair
+    g1, c1, _, _ = O.contacts(prm, objs, w.qa, w.qb, w.poses, want_contacts=True)
+    prm0 = O.default_params(w.L_ref, grid_margin_rel=0.0, broad_phase=0)
+    g0 = O.contacts(prm0, objs, w.qa, w.qb, w.poses)[0]
+    assert np.array_equal(g0, g1)
+    assert 0.0 < c1[:, 0].mean() < 0.2  # the bounds filter most contacts
+
+
+def test_spline_of_box_approaches_box_sdf(oracle_mod):
+    w = W.config0(n_poses=2)
+    box = O.from_workload_object(w.objects[0])
+    prm = O.default_params(1.0, grid_margin_rel=0.0, grid_res=48)
+    box.build_spline(prm)
+    rng = np.random.default_rng(6)
+    x = rng.uniform(-0.55, 0.55, (5000, 3))
+    # near the faces, away from edges and the medial axis, the SDF is affine and
+    # the spline (cell size 1.2 / 48) reproduces it up to the kinks' reach
+    q = np.sort(np.abs(x), axis=1)
+    sel = (q[:, 2] > 0.45) & (q[:, 1] < 0.3)
+    phi, nrm, g, _ = box.spline_eval(x[sel])
+    assert np.abs(phi - _box_sdf(x[sel], 0.5)).max() < 2e-3
+    assert np.abs(np.abs(nrm).max(1) - 1).max() < 0.05
+
+
+def test_spline_query_derivatives_match_central_differences(spline_pair):
+    w, prm, objs = spline_pair
+    sel = [0, 1, 2]
+    goff, _ = O.layout(objs, w.qa[sel], w.qb[sel])
+    rng = np.random.default_rng(7)
+    cot = rng.standard_normal((goff[-1], 12))
+    d = rng.standard_normal((len(sel), 12))
+    grad, hv = O.grad_hvp(prm, objs, w.qa[sel], w.qb[sel], w.poses[sel], cot, d)
+    hstep = 1e-6
+    for k, i in enumerate(sel):
+        A, B = objs[w.qa[i]], objs[w.qb[i]]
+        c = cot[goff[k]:goff[k + 1]]
+        fd = np.zeros(12)
+        for j in range(12):
+            e = np.zeros(12)
+            e[j] = hstep
+            fd[j] = ((O.groups_at_xi(prm, A, B, w.poses[i], e) * c).sum()
+                     - (O.groups_at_xi(prm, A, B, w.poses[i], -e) * c).sum()) / (2 * hstep)
+        assert np.linalg.norm(fd - grad[k]) <= 1e-5 * max(np.linalg.norm(grad[k]), 1e-8) + 1e-9
