@@ -158,11 +158,13 @@ def start_cpu_child(config, pairs, cot, direc, threads):
     spec = dict(config=config, pairs=pairs, sample=sample, grad=grad, threads=threads,
                 cot=cot.tolist() if grad else None,
                 dir=direc[:sample].tolist() if grad else None)
+    import tempfile
     env = dict(os.environ, OMP_NUM_THREADS=str(threads))
-    p = subprocess.Popen([sys.executable, os.path.abspath(__file__), "--cpu-child"], stdin=subprocess.PIPE,
+    fd, path = tempfile.mkstemp(suffix=".json", prefix="cm_cpu_child_")
+    with os.fdopen(fd, "w") as f:
+        json.dump(spec, f)
+    p = subprocess.Popen([sys.executable, os.path.abspath(__file__), "--cpu-child", path],
                          stdout=subprocess.PIPE, text=True, env=env, cwd=HERE)
-    p.stdin.write(json.dumps(spec))
-    p.stdin.close()
     return p, spec
 
 
@@ -508,10 +510,13 @@ def main():
                     help="only run a device copy of 1 GiB three times (scale of the HBM traffic counters)")
     ap.add_argument("--serve-rates", default="2000,5000,10000,20000", help="Poisson request rates (req/s)")
     ap.add_argument("--serve-seconds", type=float, default=2.0)
-    ap.add_argument("--cpu-child", action="store_true", help=argparse.SUPPRESS)
+    ap.add_argument("--cpu-child", default=None, help=argparse.SUPPRESS)
     args = ap.parse_args()
     if args.cpu_child:
-        cpu_child(json.loads(sys.stdin.read()))
+        with open(args.cpu_child) as f:
+            spec = json.load(f)
+        os.unlink(args.cpu_child)
+        cpu_child(spec)
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:

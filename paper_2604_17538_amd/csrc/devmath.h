@@ -110,6 +110,39 @@ CM_DEV M3<float> quat_R(const float* q) {
   return R;
 }
 
+// Both bodies' rotations and the mesh -> SDF-frame transform of one direction
+// of a query, formed in FP64 and rounded once to FP32: R_M, R_S, R_rel =
+// R_S^T R_M and t_rel = R_S^T (t_M - t_S).  In FP32 each entry would be rounded
+// several times (normalisation, products, the composition), and position
+// errors reach the second derivatives amplified by 1 / tau.
+struct Frame32 {
+  float RM[9], RS[9], Rrel[9], tM[3], tS[3], trel[3];
+};
+CM_DEV void quat_R64(const float* q, double* R) {
+  const double w0 = q[0], x0 = q[1], y0 = q[2], z0 = q[3];
+  const double n = 1.0 / sqrt(w0 * w0 + x0 * x0 + y0 * y0 + z0 * z0);
+  const double w = w0 * n, x = x0 * n, y = y0 * n, z = z0 * n;
+  R[0] = 1.0 - 2.0 * (y * y + z * z); R[1] = 2.0 * (x * y - w * z); R[2] = 2.0 * (x * z + w * y);
+  R[3] = 2.0 * (x * y + w * z); R[4] = 1.0 - 2.0 * (x * x + z * z); R[5] = 2.0 * (y * z - w * x);
+  R[6] = 2.0 * (x * z - w * y); R[7] = 2.0 * (y * z + w * x); R[8] = 1.0 - 2.0 * (x * x + y * y);
+}
+CM_DEV Frame32 frame32(const float* qM, const float* tM, const float* qS, const float* tS) {
+  double RM[9], RS[9];
+  quat_R64(qM, RM);
+  quat_R64(qS, RS);
+  Frame32 f;
+  for (int i = 0; i < 9; ++i) { f.RM[i] = float(RM[i]); f.RS[i] = float(RS[i]); }
+  const double d[3] = {double(tM[0]) - double(tS[0]), double(tM[1]) - double(tS[1]), double(tM[2]) - double(tS[2])};
+  for (int i = 0; i < 3; ++i) {
+    f.tM[i] = tM[i];
+    f.tS[i] = tS[i];
+    f.trel[i] = float(RS[i] * d[0] + RS[3 + i] * d[1] + RS[6 + i] * d[2]);
+    for (int j = 0; j < 3; ++j)
+      f.Rrel[3 * i + j] = float(RS[i] * RM[j] + RS[3 + i] * RM[3 + j] + RS[6 + i] * RM[6 + j]);
+  }
+  return f;
+}
+
 // --------------------------------------------------------- smooth operators --
 // sigma(z) = 1 / (1 + exp(-z))  (Sec. II)
 template <class T> CM_DEV T sigmoidT(T z) {

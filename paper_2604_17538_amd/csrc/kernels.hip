@@ -21,15 +21,12 @@ struct Frame {
   V3<float> tM, tS, trel;
 };
 CM_DEV Frame make_frame(const QueryDev& q, int dir) {
+  const Frame32 f = dir ? frame32(q.qb, q.tb, q.qa, q.ta) : frame32(q.qa, q.ta, q.qb, q.tb);
   Frame F;
-  const M3<float> RA = quat_R(q.qa), RB = quat_R(q.qb);
-  const V3<float> tA{q.ta[0], q.ta[1], q.ta[2]}, tB{q.tb[0], q.tb[1], q.tb[2]};
-  F.RM = dir ? RB : RA;
-  F.RS = dir ? RA : RB;
-  F.tM = dir ? tB : tA;
-  F.tS = dir ? tA : tB;
-  F.Rrel = mulMTM(F.RS, F.RM);
-  F.trel = mulMT(F.RS, F.tM - F.tS);
+  for (int i = 0; i < 9; ++i) { F.RM.m[i] = f.RM[i]; F.RS.m[i] = f.RS[i]; F.Rrel.m[i] = f.Rrel[i]; }
+  F.tM = {f.tM[0], f.tM[1], f.tM[2]};
+  F.tS = {f.tS[0], f.tS[1], f.tS[2]};
+  F.trel = {f.trel[0], f.trel[1], f.trel[2]};
   return F;
 }
 

@@ -79,6 +79,8 @@ CM_DEV void body_pose(const float* q, const float* t, const float* d6, M3<df>* R
   }
   *tt = {df{t[0], d6[3]}, df{t[1], d6[4]}, df{t[2], d6[5]}};
 }
+CM_DEV void setv(float& a, float v) { a = v; }
+CM_DEV void setv(df& a, float v) { a.v = v; }
 template <class T> CM_DEV FrameT<T> frame_t(const QueryDev& q, int dir, const float* d12) {
   M3<T> RA, RB;
   V3<T> tA, tB;
@@ -89,8 +91,13 @@ template <class T> CM_DEV FrameT<T> frame_t(const QueryDev& q, int dir, const fl
   F.RS = dir ? RA : RB;
   F.tM = dir ? tB : tA;
   F.tS = dir ? tA : tB;
+  // the value parts once rounded from FP64 (tangents: products of FP32 values)
+  const Frame32 f = dir ? frame32(q.qb, q.tb, q.qa, q.ta) : frame32(q.qa, q.ta, q.qb, q.tb);
+  for (int i = 0; i < 9; ++i) { setv(F.RM.m[i], f.RM[i]); setv(F.RS.m[i], f.RS[i]); }
   F.Rrel = mulMTM(F.RS, F.RM);
   F.trel = mulMT(F.RS, F.tM - F.tS);
+  for (int i = 0; i < 9; ++i) setv(F.Rrel.m[i], f.Rrel[i]);
+  setv(F.trel.x, f.trel[0]); setv(F.trel.y, f.trel[1]); setv(F.trel.z, f.trel[2]);
   return F;
 }
 
