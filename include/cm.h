@@ -191,6 +191,22 @@ cm_status cm_plan_timing(const cm_plan* plan, float* ms5);
  * cm_object_export. */
 cm_status cm_contacts_fwd(cm_context* ctx, cm_plan* plan, const cm_query* q_dev, cm_groups out, float* contact_dbg,
                           void* stream);
+/* For callers that cannot allocate device memory at call time (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * forward pass of cm_contacts_fwd (same kernels, same records, bitwise, at the
+ * plan's launch shape) with all launch scratch -- survivor bitmasks, counts and
+ * offsets, filtered sums, the tile counter, blend partials -- in one fixed
+ * 64 MiB device array of the library (one per GPU, held until the process
+ * ends) instead of the plan's memory.  The call allocates nothing; the plan
+ * (created beforehand) supplies its uploaded tables, the caller the queries
+ * and output records as for cm_contacts_fwd.  CM_E_INVALID, with nothing
+ * launched, when the batch needs more than 64 MiB of launch scratch (about
+ * (W + E) * 128 bytes for W survivor words and E entries: split the batch
+ * into smaller plans).  Every call on a GPU shares that GPU's array: calls that
+ * overlap in time on one GPU (other streams, other threads) race and must be
+ * serialised by the caller.  No debug output, timing or work counters. */
+cm_status cm_contacts_fwd_noalloc(cm_context* ctx, cm_plan* plan, const cm_query* q_dev, cm_groups out,
+                                  void* stream);
 /* Gradient of L = sum_g <cot_g, y_g> w.r.t. xi = (w_A, v_A, w_B, v_B), the
  * world-frame perturbation T_X <- (exp([w_X]x) R_X, t_X + v_X) at xi = 0.
  * cot: device group records (same layout as out).  grad: device float [n][12].

@@ -86,6 +86,7 @@ cm_plan_work = _sig("cm_plan_work", I32, [P, P])
 cm_plan_set_timing = _sig("cm_plan_set_timing", I32, [P, I32])
 cm_plan_timing = _sig("cm_plan_timing", I32, [P, P])
 cm_contacts_fwd = _sig("cm_contacts_fwd", I32, [P, P, P, cm_groups, P, P])
+cm_contacts_fwd_noalloc = _sig("cm_contacts_fwd_noalloc", I32, [P, P, P, cm_groups, P])
 cm_contacts_bwd = _sig("cm_contacts_bwd", I32, [P, P, P, cm_groups, P, P])
 cm_hvp = _sig("cm_hvp", I32, [P, P, P, cm_groups, P, P, P, P])
 cm_contacts_jvp = _sig("cm_contacts_jvp", I32, [P, P, P, cm_groups, cm_groups, P, P])
@@ -106,7 +107,7 @@ EXPORTED = ["cm_default_params", "cm_init", "cm_shutdown", "cm_last_error", "cm_
             "cm_build_pieces_raw", "cm_release_object", "cm_object_info", "cm_object_export", "cm_object_grid",
             "cm_plan_create", "cm_plan_destroy", "cm_plan_info", "cm_plan_offsets", "cm_plan_stats", "cm_plan_work",
             "cm_plan_set_timing", "cm_plan_timing",
-            "cm_contacts_fwd", "cm_contacts_bwd", "cm_hvp", "cm_contacts_jvp",
+            "cm_contacts_fwd", "cm_contacts_fwd_noalloc", "cm_contacts_bwd", "cm_hvp", "cm_contacts_jvp",
             "cm_contacts_step", "cm_graph_create", "cm_graph_launch",
             "cm_graph_destroy", "cm_plan_autotune", "cm_plan_set_launch_shape", "cm_plan_launch_shape",
             "cm_submit", "cm_poll", "cm_wait", "cm_serve_stats",

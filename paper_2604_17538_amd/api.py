@@ -226,6 +226,15 @@ class Plan:
         self.ctx._check(st, "cm_contacts_fwd")
         return (out, dbg) if debug else out
 
+    def forward_noalloc(self, q_dev, out, stream=None):
+        """The forward records into the caller's `out` [12, G] with the launch
+        scratch in the library's fixed device array (cm_contacts_fwd_noalloc):
+        nothing is allocated by this call."""
+        st = _cm.cm_contacts_fwd_noalloc(self.ctx.handle, self._h, ctypes.c_void_p(q_dev.data_ptr()),
+                                         groups_struct(out), _stream_ptr(stream))
+        self.ctx._check(st, "cm_contacts_fwd_noalloc")
+        return out
+
     def backward(self, q_dev, cot, grad=None, stream=None):
         torch = _torch()
         if grad is None:

@@ -391,6 +391,8 @@ cm_status cm_init(int32_t device, const cm_params* params, size_t mem_budget_byt
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) != hipSuccess) { delete ctx; return CM_E_HIP; }
     ctx->n_cu = prop.multiProcessorCount;
+    // device address of the fixed launch scratch of cm_contacts_fwd_noalloc
+    if (static_scratch_setup(device) != hipSuccess) { delete ctx; return CM_E_HIP; }
     if (hipStreamCreateWithFlags(&ctx->build_stream, hipStreamNonBlocking) != hipSuccess) { delete ctx; return CM_E_HIP; }
     ctx->arena.reset(new Arena(size_t(256) << 20));
   }

@@ -131,4 +131,5 @@ cm_status plan_host(cm_context* ctx, const cm_query* hq, int32_t n, cm_plan* pl,
 size_t plan_layout(cm_plan* pl, char* base);
 cm_status plan_bind(cm_plan* pl, void* dmem, hipStream_t s);
 FwdArgs fwd_args(cm_context* ctx, cm_plan* pl, const cm_query* q, const cm_groups& out, float* dbg);
+hipError_t static_scratch_setup(int device);  // noalloc.hip
 }  // namespace cm
