@@ -7,9 +7,10 @@
 // hold stays within the context's budget (each request's plan scratch and
 // buffers estimated as the plan lays them out; a slot's buffer is sized to its
 // batch, and idle slots give theirs back when a batch needs the room), packs
-// their queries into one batch, runs the
-// forward pass over all of them and the adjoint over those that asked for a
-// gradient, and copies the results back into pinned staging.  Batches on
+// their queries into one batch, runs the forward pass over the forward-only
+// requests and the gradient pass (one forward sweep that also writes the
+// records, and the adjoint) over those that asked for a gradient, and copies
+// the results back into pinned staging.  Batches on
 // different streams overlap; the next batch is formed while others run.
 // Completion is detected with events; results are scattered to the callers'
 // buffers and the tickets are marked done.  A query's results depend only on
@@ -59,11 +60,11 @@ struct Slot {
   size_t pcap = 0;
   bool busy = false;
   std::vector<Req*> reqs;
-  std::unique_ptr<cm_plan> pf, pg;  // forward plan (all queries), adjoint plan (gradient requests)
+  std::unique_ptr<cm_plan> pf, pg;  // forward plan (forward-only requests), adjoint plan (gradient requests)
   size_t bytes = 0;
   // offsets into dmem / pinned
-  size_t d_q = 0, d_qg = 0, d_out = 0, d_cot = 0, d_grad = 0, d_pf = 0, d_pg = 0;
-  size_t h_q = 0, h_qg = 0, h_out = 0, h_cot = 0, h_grad = 0;
+  size_t d_q = 0, d_qg = 0, d_out = 0, d_outg = 0, d_cot = 0, d_grad = 0, d_pf = 0, d_pg = 0;
+  size_t h_q = 0, h_qg = 0, h_out = 0, h_outg = 0, h_cot = 0, h_grad = 0;
   int64_t n = 0, ng = 0, G = 0, Gg = 0;
 };
 
@@ -89,15 +90,14 @@ struct Serving {
 namespace {
 
 // Device bytes a request needs inside a batch: its share of the plan scratch
-// (entries, bitmask, partials, ...) plus its input and output buffers.
+// (entries, bitmask, partials, ...) plus its input and output buffers.  A
+// forward request joins the forward plan (no tape); a gradient request joins
+// the adjoint plan (a tape of float values), whose forward sweep also writes
+// its records, and brings cotangents and a gradient buffer.
 size_t request_bytes(cm_plan& pl, bool grad) {
-  pl.tape_kind = 0;  // the forward plan keeps no tape
-  size_t b = plan_layout(&pl, nullptr);
-  b += 64 * size_t(pl.n) + 48 * size_t(pl.G);  // queries, outputs
-  if (grad) {
-    pl.tape_kind = 1;  // the adjoint plan: a tape of float values
-    b += plan_layout(&pl, nullptr) + 64 * size_t(pl.n) + 48 * size_t(pl.G) + 48 * size_t(pl.n);
-  }
+  pl.tape_kind = grad ? 1 : 0;
+  size_t b = plan_layout(&pl, nullptr) + 64 * size_t(pl.n) + 48 * size_t(pl.G);  // plan, queries, records
+  if (grad) b += 48 * size_t(pl.G) + 48 * size_t(pl.n);                        // cotangents, gradient
   return b + kSlackPerRequest;
 }
 
@@ -152,25 +152,28 @@ cm_status launch_batch(Serving* S, cm_context* ctx, Slot& s) {
   std::vector<cm_query> qa, qg;
   std::vector<const Req*> gr;
   for (const Req* r : s.reqs) {
-    qa.insert(qa.end(), r->q.begin(), r->q.end());
     if (r->grad) { qg.insert(qg.end(), r->q.begin(), r->q.end()); gr.push_back(r); }
+    else qa.insert(qa.end(), r->q.begin(), r->q.end());
   }
   s.n = int64_t(qa.size());
   s.ng = int64_t(qg.size());
   // the slot's plans are reused batch after batch (their host tables keep
   // their capacity); the slot is free only once its previous batch completed
-  if (!s.pf) s.pf.reset(new cm_plan);
-  s.pf->tape_kind = 0;  // forward only
   size_t bf = 0, bg = 0;
-  cm_status st = plan_host(ctx, qa.data(), int32_t(s.n), s.pf.get(), &bf);
-  if (st != CM_OK) return st;
+  cm_status st = CM_OK;
+  if (s.n) {
+    if (!s.pf) s.pf.reset(new cm_plan);
+    s.pf->tape_kind = 0;  // forward only
+    st = plan_host(ctx, qa.data(), int32_t(s.n), s.pf.get(), &bf);
+    if (st != CM_OK) return st;
+  }
   if (s.ng) {
     if (!s.pg) s.pg.reset(new cm_plan);
     s.pg->tape_kind = 1;  // float adjoint only
     st = plan_host(ctx, qg.data(), int32_t(s.ng), s.pg.get(), &bg);
     if (st != CM_OK) return st;
   }
-  s.G = s.pf->G;
+  s.G = s.n ? s.pf->G : 0;
   s.Gg = s.ng ? s.pg->G : 0;
   size_t off = 0;
   auto take = [&](size_t b) { size_t r = off; off = align_up(off + b, 256); return r; };
@@ -179,6 +182,7 @@ cm_status launch_batch(Serving* S, cm_context* ctx, Slot& s) {
   s.d_q = take(64 * size_t(s.n));
   s.d_qg = take(64 * size_t(s.ng));
   s.d_out = take(48 * size_t(s.G));
+  s.d_outg = take(48 * size_t(s.Gg));
   s.d_cot = take(48 * size_t(s.Gg));
   s.d_grad = take(48 * size_t(s.ng));
   if (!ensure_device(S, s, off)) return fail(ctx, CM_E_OOM, "serving: device allocation within the budget failed");
@@ -187,6 +191,7 @@ cm_status launch_batch(Serving* S, cm_context* ctx, Slot& s) {
   s.h_q = htake(64 * size_t(s.n));
   s.h_qg = htake(64 * size_t(s.ng));
   s.h_out = htake(48 * size_t(s.G));
+  s.h_outg = htake(48 * size_t(s.Gg));
   s.h_cot = htake(48 * size_t(s.Gg));
   s.h_grad = htake(48 * size_t(s.ng));
   if (!ensure_pinned(s, hoff)) return fail(ctx, CM_E_OOM, "serving: pinned allocation failed");
@@ -204,30 +209,36 @@ cm_status launch_batch(Serving* S, cm_context* ctx, Slot& s) {
     }
   }
   hipStream_t st_ = s.stream;
-  if (hipMemcpyAsync(d + s.d_q, s.pinned + s.h_q, 64 * size_t(s.n), hipMemcpyHostToDevice, st_) != hipSuccess)
-    return fail(ctx, CM_E_HIP, "serving: upload failed");
-  if ((st = plan_bind(s.pf.get(), d + s.d_pf, st_)) != CM_OK) return st;
-  float* out = reinterpret_cast<float*>(d + s.d_out);
-  const int64_t G = s.G;
-  cm_groups og{out, out + 3 * G, out + 6 * G, out + 7 * G, out + 10 * G, out + 11 * G};
-  FwdArgs a = fwd_args(ctx, s.pf.get(), reinterpret_cast<const cm_query*>(d + s.d_q), og, nullptr);
-  if (launch_forward(a, st_) != hipSuccess) return fail(ctx, CM_E_HIP, "serving: forward launch failed");
+  if (s.n) {
+    if (hipMemcpyAsync(d + s.d_q, s.pinned + s.h_q, 64 * size_t(s.n), hipMemcpyHostToDevice, st_) != hipSuccess)
+      return fail(ctx, CM_E_HIP, "serving: upload failed");
+    if ((st = plan_bind(s.pf.get(), d + s.d_pf, st_)) != CM_OK) return st;
+    float* out = reinterpret_cast<float*>(d + s.d_out);
+    const int64_t G = s.G;
+    cm_groups og{out, out + 3 * G, out + 6 * G, out + 7 * G, out + 10 * G, out + 11 * G};
+    FwdArgs a = fwd_args(ctx, s.pf.get(), reinterpret_cast<const cm_query*>(d + s.d_q), og, nullptr);
+    if (launch_forward(a, st_) != hipSuccess) return fail(ctx, CM_E_HIP, "serving: forward launch failed");
+    if (hipMemcpyAsync(s.pinned + s.h_out, d + s.d_out, 48 * size_t(s.G), hipMemcpyDeviceToHost, st_) != hipSuccess)
+      return fail(ctx, CM_E_HIP, "serving: download failed");
+  }
   if (s.ng) {
     if (hipMemcpyAsync(d + s.d_qg, s.pinned + s.h_qg, 64 * size_t(s.ng), hipMemcpyHostToDevice, st_) != hipSuccess ||
         hipMemcpyAsync(d + s.d_cot, s.pinned + s.h_cot, 48 * size_t(s.Gg), hipMemcpyHostToDevice, st_) != hipSuccess)
       return fail(ctx, CM_E_HIP, "serving: upload failed");
     if ((st = plan_bind(s.pg.get(), d + s.d_pg, st_)) != CM_OK) return st;
     float* c = reinterpret_cast<float*>(d + s.d_cot);
+    float* og_ = reinterpret_cast<float*>(d + s.d_outg);
     const int64_t Gg = s.Gg;
-    FwdArgs b = fwd_args(ctx, s.pg.get(), reinterpret_cast<const cm_query*>(d + s.d_qg), cm_groups{}, nullptr);
+    // records and gradient from one forward sweep and one adjoint
+    cm_groups ogg{og_, og_ + 3 * Gg, og_ + 6 * Gg, og_ + 7 * Gg, og_ + 10 * Gg, og_ + 11 * Gg};
+    FwdArgs b = fwd_args(ctx, s.pg.get(), reinterpret_cast<const cm_query*>(d + s.d_qg), ogg, nullptr);
     b.cot = OutPtrs{c, c + 3 * Gg, c + 6 * Gg, c + 7 * Gg, c + 10 * Gg, c + 11 * Gg};
     b.grad = reinterpret_cast<float*>(d + s.d_grad);
-    if (launch_backward(b, st_) != hipSuccess) return fail(ctx, CM_E_HIP, "serving: adjoint launch failed");
-    if (hipMemcpyAsync(s.pinned + s.h_grad, d + s.d_grad, 48 * size_t(s.ng), hipMemcpyDeviceToHost, st_) != hipSuccess)
+    if (launch_backward(b, st_, true) != hipSuccess) return fail(ctx, CM_E_HIP, "serving: adjoint launch failed");
+    if (hipMemcpyAsync(s.pinned + s.h_grad, d + s.d_grad, 48 * size_t(s.ng), hipMemcpyDeviceToHost, st_) != hipSuccess ||
+        hipMemcpyAsync(s.pinned + s.h_outg, d + s.d_outg, 48 * size_t(s.Gg), hipMemcpyDeviceToHost, st_) != hipSuccess)
       return fail(ctx, CM_E_HIP, "serving: download failed");
   }
-  if (hipMemcpyAsync(s.pinned + s.h_out, d + s.d_out, 48 * size_t(s.G), hipMemcpyDeviceToHost, st_) != hipSuccess)
-    return fail(ctx, CM_E_HIP, "serving: download failed");
   if (hipEventRecord(s.done, st_) != hipSuccess) return fail(ctx, CM_E_HIP, "serving: event record failed");
   return CM_OK;
 }
@@ -235,15 +246,20 @@ cm_status launch_batch(Serving* S, cm_context* ctx, Slot& s) {
 // Scatters a finished batch's results to the callers' buffers.
 void scatter(Slot& s) {
   const float* out = reinterpret_cast<const float*>(s.pinned + s.h_out);
+  const float* outg = reinterpret_cast<const float*>(s.pinned + s.h_outg);
   const float* grad = reinterpret_cast<const float*>(s.pinned + s.h_grad);
-  int64_t g0 = 0, qg0 = 0;
+  int64_t g0 = 0, gg0 = 0, qg0 = 0;
   for (Req* r : s.reqs) {
-    for (int64_t g = 0; g < r->G; ++g)
-      for (int k = 0; k < 12; ++k) r->out_groups[12 * g + k] = out[k * s.G + g0 + g];
-    g0 += r->G;
     if (r->grad) {
+      for (int64_t g = 0; g < r->G; ++g)
+        for (int k = 0; k < 12; ++k) r->out_groups[12 * g + k] = outg[k * s.Gg + gg0 + g];
+      gg0 += r->G;
       std::memcpy(r->out_grad, grad + 12 * qg0, 48 * r->q.size());
       qg0 += int64_t(r->q.size());
+    } else {
+      for (int64_t g = 0; g < r->G; ++g)
+        for (int k = 0; k < 12; ++k) r->out_groups[12 * g + k] = out[k * s.G + g0 + g];
+      g0 += r->G;
     }
   }
 }

@@ -1,7 +1,9 @@
 """GPU tests of the serving loop: every request's results equal those of the
 same queries run alone through a plan (bitwise: reductions are per query and
 in a fixed order), for mixed forward / forward+gradient traffic arriving while
-earlier batches are on the device; admission respects the memory budget."""
+earlier batches are on the device; admission respects the memory budget.  A
+gradient request's records come from the sweep that also feeds its adjoint
+(cm_contacts_step), not from a second forward pass."""
 import numpy as np
 import pytest
 
@@ -21,14 +23,19 @@ def lib():
 
 
 def _alone(api, ctx, hs, qa, qb, poses, cot):
+    """The same queries in a plan of their own: records by the forward pass for
+    a forward request; records and gradient from one sweep (cm_contacts_step,
+    as the server runs a gradient request) for a gradient request."""
     import torch
     plan = ctx.plan(qa, qb)
     qd = plan.device_queries(poses)
-    out = plan.forward(qd)
     grad = None
-    if cot is not None:
+    if cot is None:
+        out = plan.forward(qd)
+    else:
         cd = torch.tensor(np.ascontiguousarray(cot.T, np.float32)).contiguous().cuda()
-        grad = plan.backward(qd, cd).cpu().numpy()
+        out, g, _ = plan.step(qd, cd)
+        grad = g.cpu().numpy()
     torch.cuda.synchronize()
     return out.cpu().numpy().T, grad
 
