@@ -20,8 +20,16 @@ ones of paper_2604_17538_amd.workloads (cotangents over the sampled queries'
 groups in order, as for the other parity tests), and a digest of the sampled
 inputs lets the test check that it regenerated the same workload.
 
+Also stored: the FP32 spread of every record component (the change of the
+records when every intermediate an FP32 evaluation rounds is perturbed by one
+rounding, oracle seeds 1, 2 and 3; the max over seeds): a blended W made of
+contacts in the transition band moves by far more than 1e-4 of itself under
+such perturbations, so no FP32 evaluation can be held tighter there.
+
 Only the oracle and the seeded input generators are called.  Usage:
     python tests/golden/c4_oracle.py [--threads 8]
+    python tests/golden/c4_oracle.py --record-spread   (adds the record spread
+        to an existing c4_oracle.json of the same workload)
 """
 import argparse
 import hashlib
@@ -82,10 +90,53 @@ def choose(cand, g, goff, d_max):
     return np.array(pick, np.int64), act, dmin
 
 
+REC_SEEDS = (1, 2, 3)
+
+
+def record_spread(O, prm, objs, qa, qb, poses, threads):
+    """Per group and component, the largest change of the records over the
+    probe seeds (max |records(seed) - records|), [G, 12]."""
+    g0, _ = O.contacts(prm, objs, qa, qb, poses, threads=threads)
+    sp = np.zeros_like(g0)
+    for s in REC_SEEDS:
+        p = O.Params.from_buffer_copy(prm)
+        p.jitter, p.jitter_seed = O.FP32_UNIT_ROUNDOFF, int(s)
+        g, _ = O.contacts(p, objs, qa, qb, poses, threads=threads)
+        sp = np.maximum(sp, np.abs(g - g0))
+    return g0, sp
+
+
+def add_record_spread(threads):
+    import oracle as O
+    from paper_2604_17538_amd import workloads as W
+    O.build(force=False)
+    with open(OUT) as f:
+        doc = json.load(f)
+    w = W.config4(n_envs=N_ENVS, library=LIBRARY)
+    sel = np.array(doc["sel"], np.int64)
+    assert input_digest(w, sel) == doc["input_sha256"]
+    prm = O.default_params(w.L_ref)
+    objs = [None] * len(w.objects)
+    for j in sorted({int(w.qa[i]) for i in sel} | {int(w.qb[i]) for i in sel}):
+        objs[j] = O.from_workload_object(w.objects[j])
+        objs[j].build_grid(prm)
+    g0, sp = record_spread(O, prm, objs, w.qa[sel], w.qb[sel], w.poses[sel], threads)
+    assert np.array_equal(g0, np.array(doc["records"])), "the oracle no longer gives the stored records"
+    doc["spread_records"] = sp.tolist()
+    doc["record_spread_seeds"] = list(REC_SEEDS)
+    with open(OUT, "w") as f:
+        json.dump(doc, f, indent=0)
+    print("added the record spread to %s" % OUT, flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--threads", type=int, default=8)
+    ap.add_argument("--record-spread", action="store_true")
     args = ap.parse_args()
+    if args.record_spread:
+        add_record_spread(args.threads)
+        return
     import oracle as O
     from paper_2604_17538_amd import workloads as W
     O.build(force=False)
@@ -118,6 +169,7 @@ def main():
                                      threads=max(1, args.threads // (len(SEEDS) + 1)),
                                      concurrent=True, return_base=True)
     print("gradient, H v and spread %.1f s" % (time.time() - t0), flush=True)
+    _, rsp = record_spread(O, prm, objs, qa, qb, poses, args.threads)
     r = np.array([objs[j].radius() if objs[j] is not None else 0.0 for j in range(len(objs))])
     doc = {
         "workload": {"n_envs": N_ENVS, "library": LIBRARY, "seed": W.SEED_BASE + 4, "cot_seed": int(w.cot_seed)},
@@ -133,6 +185,8 @@ def main():
         "spread_hv": dh.tolist(),
         "scene_scale": (r[qa] + r[qb]).tolist(),
         "spread_seeds": list(SEEDS),
+        "spread_records": rsp.tolist(),
+        "record_spread_seeds": list(REC_SEEDS),
     }
     with open(OUT, "w") as f:
         json.dump(doc, f, indent=0)
