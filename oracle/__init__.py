@@ -90,6 +90,8 @@ def lib():
         L.orc_groups_at_xi.argtypes = [P, I32, I32, P, P, P]
         L.orc_grad_hvp.argtypes = [P, I64, P, P, P, P, P, P, P, P, I32]
         L.orc_jvp.argtypes = [P, I64, P, P, P, P, P, P, P, I32]
+        L.orc_project.argtypes = [P, I64, P, P, P, P, P, P, I32]
+        L.orc_assign_edges.argtypes = [I32, P]
         L.orc_object_set_tris.argtypes = [I32, P, P]
         L.orc_build_spline.argtypes = [I32, P]
         L.orc_spline.argtypes = [I32, P, P]
@@ -130,7 +132,16 @@ class Obj:
         return len(self.plane_off) - 1
 
     def n_contacts(self):
-        return len(self.verts) + len(self.edges)
+        return len(self.verts) + len(self.edges) + int(getattr(self, "n_xedges", 0))
+
+    def assign_edges(self):
+        """Sec. IV-D.1: every piece also takes the edges of other pieces that
+        cross it (their contacts then count in its group too).  Returns the
+        number each piece collected."""
+        counts = np.zeros(self.n_pieces, np.int64)
+        lib().orc_assign_edges(self.h, _p(counts))
+        self.n_xedges = int(counts.sum())
+        return counts
 
     def radius(self):
         return float(np.sqrt((self.verts ** 2).sum(1)).max())
@@ -327,6 +338,21 @@ def grad_hvp(prm: Params, objs, qa, qb, poses, cot, direction: Optional[np.ndarr
     lib().orc_grad_hvp(ctypes.byref(prm), n, _p(qa_h), _p(qb_h), _p(poses), _p(goff), _p(cot), _p(d),
                        _p(grad), _p(hv), int(threads))
     return (grad, hv) if direction is not None else grad
+
+
+def project(prm: Params, objs, qa, qb, poses, points, threads: int = 0):
+    """Isosurface projection (Sec. IV-A): every group's point [G, 3] (world)
+    moved to p - phi(p) n(p) of the SDF its group was evaluated against."""
+    qa_h = _c([objs[i].h for i in qa], np.int32)
+    qb_h = _c([objs[i].h for i in qb], np.int32)
+    poses = _c(poses, np.float64).reshape(-1, 14)
+    goff, _ = layout(objs, qa, qb)
+    pin = _c(points, np.float64).reshape(-1, 3)
+    assert len(pin) == goff[-1]
+    out = np.zeros_like(pin)
+    lib().orc_project(ctypes.byref(prm), len(qa_h), _p(qa_h), _p(qb_h), _p(poses), _p(goff), _p(pin), _p(out),
+                      int(threads))
+    return out
 
 
 def jvp(prm: Params, objs, qa, qb, poses, direction, threads: int = 0):

@@ -183,6 +183,9 @@ struct Piece {
   std::vector<double> verts;   // 3 per vertex, object frame
   std::vector<int32_t> edges;  // 2 per edge, piece-local vertex indices
   std::vector<double> tris;    // 9 per boundary triangle (only for the spline's ground truth)
+  std::vector<double> xedges;  // 6 per edge of another piece that crosses this one (both
+                               // endpoints, object frame), in its group too (Sec. IV-D.1)
+  size_t n_xedges() const { return xedges.size() / 6; }
   size_t n_planes() const { return planes.size() / 4; }
   size_t n_verts() const { return verts.size() / 3; }
   size_t n_edges() const { return edges.size() / 2; }
@@ -308,6 +311,47 @@ template <class T> T softclip(const T& x, const T& a, const T& b, double tau) {
   return a + softplus(x - a, tau) - softplus(x - b, tau);
 }
 
+
+// --------------------------------------------------- edge assignment --
+// Sec. IV-D.1: a vertex belongs to the convex piece it lies in (here: its own
+// piece), an edge to every piece it intersects.  Besides its own piece, an edge
+// of piece k joins piece j != k when the segment keeps a part of positive length
+// (> 1e-9 of the object's scale) inside j's hull: the segment a + t (b - a),
+// t in [0, 1], clipped by each half-space n.x + h <= 0 of j.
+inline bool segment_crosses_piece(const Piece& pj, const double* a, const double* b, double tol) {
+  double t0 = 0.0, t1 = 1.0;
+  for (size_t i = 0; i < pj.n_planes(); ++i) {
+    const double* q = &pj.planes[4 * i];
+    const double ca = q[0] * a[0] + q[1] * a[1] + q[2] * a[2] + q[3];
+    const double cb = q[0] * b[0] + q[1] * b[1] + q[2] * b[2] + q[3];
+    if (ca > 0 && cb > 0) return false;
+    if (ca > 0) t0 = std::max(t0, ca / (ca - cb));
+    if (cb > 0) t1 = std::min(t1, ca / (ca - cb));
+  }
+  const double L = std::sqrt((b[0] - a[0]) * (b[0] - a[0]) + (b[1] - a[1]) * (b[1] - a[1]) + (b[2] - a[2]) * (b[2] - a[2]));
+  return (t1 - t0) * L > tol;
+}
+void assign_edges(Object& o) {
+  double scale = 1e-300;
+  for (const Piece& pc : o.pieces)
+    for (double v : pc.verts) scale = std::max(scale, std::fabs(v));
+  for (size_t j = 0; j < o.pieces.size(); ++j) {
+    Piece& pj = o.pieces[j];
+    pj.xedges.clear();
+    for (size_t k = 0; k < o.pieces.size(); ++k) {
+      if (k == j) continue;
+      const Piece& pk = o.pieces[k];
+      for (size_t e = 0; e < pk.n_edges(); ++e) {
+        const double* a = &pk.verts[3 * size_t(pk.edges[2 * e])];
+        const double* b = &pk.verts[3 * size_t(pk.edges[2 * e + 1])];
+        if (segment_crosses_piece(pj, a, b, 1e-9 * scale)) {
+          pj.xedges.insert(pj.xedges.end(), a, a + 3);
+          pj.xedges.insert(pj.xedges.end(), b, b + 3);
+        }
+      }
+    }
+  }
+}
 
 // ------------------------------------------------------ S1 spline SDF --
 // The ground truth of Sec. III-B.2 needs the closest point of the piece's
@@ -858,6 +902,36 @@ void direction(const Object& mesh, const Object& sdf, const Pose<T>& PM, const P
       cs.push_back(mollify(phi, Nw, pw, rest, prm)); cs.back().kind = 1;
       if (bp) { cs.back().bound = ebound; cs.back().face_dist = efd; }
     }
+    // edges of other pieces that cross this one (Sec. IV-D.1), the same E-SDF
+    for (size_t k = 0; k < pc.n_xedges(); ++k) {
+      V3<T> W0 = mul(PM.R, cvt<T>(&pc.xedges[6 * k])) + PM.t, W1 = mul(PM.R, cvt<T>(&pc.xedges[6 * k + 3])) + PM.t;
+      V3<T> x0 = mulT(PS.R, W0 - PS.t), x1 = mulT(PS.R, W1 - PS.t);
+      probe3(x0, true);
+      probe3(x1, true);
+      V3<T> rest = (W0 + W1) * 0.5;
+      if (bp) {
+        V3<double> a = vval(x0), b = vval(x1);
+        V3<double> dv = b - a;
+        double L = std::sqrt(dot(dv, dv));
+        double la = lower_bound(sdf.grid, a), lbb = lower_bound(sdf.grid, b);
+        double lb = prm.edge_bound == 0 ? std::min(la, lbb) - L
+                                        : std::max(std::max(la, lbb) - L, 0.5 * (la + lbb - L));
+        if (sdf.grid.spline) lb = spline_edge_bound(sdf.grid, a, b);
+        if (lb >= prm.d_max) {
+          cs.push_back(filtered(rest, prm));
+          cs.back().kind = 1;
+          continue;
+        }
+      }
+      V3<T> pe = edge_point(fn, x0, x1, prm);
+      probe3(pe, true);
+      T phi; V3<T> nS;
+      object_phi_normal(sdf, pe, prm, phi, nS);
+      V3<T> Nw = mul(PS.R, nS);
+      V3<T> pw = mul(PS.R, pe) + PS.t;
+      cs.push_back(mollify(phi, Nw, pw, rest, prm));
+      cs.back().kind = 1;
+    }
     std::vector<double> w;
     out.push_back(blend(cs, prm, dbg ? &w : nullptr));
     if (dbg) {
@@ -928,7 +1002,7 @@ Pose<T> perturbed(const M3<double>& R0, const double* t0, const T* w, const T* v
 size_t n_groups(const Object& A, const Object& B) { return A.pieces.size() + B.pieces.size(); }
 size_t n_contacts(const Object& o) {
   size_t c = 0;
-  for (const Piece& p : o.pieces) c += p.n_verts() + p.n_edges();
+  for (const Piece& p : o.pieces) c += p.n_verts() + p.n_edges() + p.n_xedges();
   return c;
 }
 
@@ -962,6 +1036,14 @@ void orc_object_free(int32_t h) {
 }
 
 void orc_build_grid(int32_t h, const Params* prm) { build_grid(*g_objects.at(size_t(h)), *prm); }
+
+// Sec. IV-D.1 edge assignment: each piece also collects the edges of the other
+// pieces that cross it; returns the number collected per piece (counts[n_pieces]).
+void orc_assign_edges(int32_t h, int64_t* counts) {
+  Object& o = *g_objects.at(size_t(h));
+  assign_edges(o);
+  for (size_t k = 0; k < o.pieces.size(); ++k) counts[k] = int64_t(o.pieces[k].n_xedges());
+}
 
 // Boundary triangles of each piece (9 doubles each, tri_off[n_pieces + 1]),
 // used only by the spline's ground truth.
@@ -1171,6 +1253,36 @@ void orc_jvp(const Params* prm, int64_t n, const int32_t* qa, const int32_t* qb,
         groups[12 * (group_off[i] + int64_t(g)) + k] = c.v;
         tangents[12 * (group_off[i] + int64_t(g)) + k] = c.d[0];
       }
+  }
+}
+
+// Isosurface projection (Sec. IV-A, last paragraph): each group's point
+// p_in[g] (world) moved onto the zero level set of the SDF it was evaluated
+// against, proj(p) = p - phi(p) n(p) in that object's frame (A's groups
+// against B's SDF, B's against A's).  points: [sum groups][3].
+void orc_project(const Params* prm, int64_t n, const int32_t* qa, const int32_t* qb, const double* poses,
+                 const int64_t* group_off, const double* p_in, double* p_out, int32_t n_threads) {
+#ifdef _OPENMP
+  if (n_threads > 0) omp_set_num_threads(n_threads);
+#pragma omp parallel for schedule(dynamic, 1)
+#endif
+  for (int64_t i = 0; i < n; ++i) {
+    const double* ps = poses + 14 * i;
+    const Object& A = obj(qa[i]);
+    const Object& B = obj(qb[i]);
+    for (int64_t g = group_off[i]; g < group_off[i + 1]; ++g) {
+      const bool a_side = g - group_off[i] < int64_t(A.pieces.size());
+      const Object& S = a_side ? B : A;
+      const double* qs = a_side ? ps + 7 : ps;
+      const M3<double> R = quat_to_R(qs);
+      const V3<double> t{qs[4], qs[5], qs[6]};
+      const V3<double> x = mulT(R, cvt<double>(p_in + 3 * g) - t);
+      double phi;
+      V3<double> nS;
+      object_phi_normal(S, x, *prm, phi, nS);
+      const V3<double> pw = mul(R, x - nS * phi) + t;
+      p_out[3 * g] = pw.x; p_out[3 * g + 1] = pw.y; p_out[3 * g + 2] = pw.z;
+    }
   }
 }
 

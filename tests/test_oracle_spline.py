@@ -212,3 +212,63 @@ def test_spline_query_derivatives_match_central_differences(spline_pair):
             fd[j] = ((O.groups_at_xi(prm, A, B, w.poses[i], e) * c).sum()
                      - (O.groups_at_xi(prm, A, B, w.poses[i], -e) * c).sum()) / (2 * hstep)
         assert np.linalg.norm(fd - grad[k]) <= 1e-5 * max(np.linalg.norm(grad[k]), 1e-8) + 1e-9
+
+
+def _unit_box_pair():
+    w = W.config0(n_poses=2)
+    return [O.from_workload_object(w.objects[0]), O.from_workload_object(w.objects[1])]
+
+
+def test_projection_box_closed_form(oracle_mod):
+    """Sec. IV-A: proj(p) = p - phi(p) n(p).  With tau -> 0 the plane SDF of a
+    box is exact in its face regions, so a point near a face moves straight onto
+    it; A's group points are projected onto B's surface and B's onto A's."""
+    objs = _unit_box_pair()
+    prm = O.default_params(1.0, tau_cap=1e-5, tau_cup=1e-5)
+    rng = np.random.default_rng(8)
+    poses = np.zeros((1, 14))
+    poses[0, 0] = 1.0
+    poses[0, 7] = 1.0
+    poses[0, 11:14] = [3.0, 0.0, 0.0]  # B at x = 3
+    for side in range(2):
+        c = np.array([3.0, 0.0, 0.0]) if side == 0 else np.zeros(3)  # the SDF body's centre
+        pts = np.zeros((2, 3))
+        # a point near the SDF body's +z face (group of this side), the other group left at its centre
+        pts[side] = c + [rng.uniform(-0.3, 0.3), rng.uniform(-0.3, 0.3), 0.5 + rng.uniform(-0.04, 0.04)]
+        pts[1 - side] = [10.0, 10.0, 10.0]
+        out = O.project(prm, objs, np.array([0]), np.array([1]), poses, pts)
+        ref = pts[side].copy()
+        ref[2] = c[2] + 0.5
+        assert np.abs(out[side] - ref).max() < 1e-9
+
+
+def test_projection_lands_on_the_level_set(spline_pair):
+    """For spline and plane SDFs alike the projected point's phi is second order
+    in the original phi (Newton's step along a normal of length ~ 1)."""
+    w, prm, objs = spline_pair
+    prm_p = O.default_params(w.L_ref, grid_margin_rel=0.0)
+    objs_p = [O.from_workload_object(o) for o in w.objects[:2]]
+    for ob, pr, spl in ((objs[:2], prm, True), (objs_p, prm_p, False)):
+        A, B = ob
+        rng = np.random.default_rng(9)
+        sel = np.array([0])
+        goff, _ = O.layout(ob, [0], [1])
+        phis, phis_after = [], []
+        for _ in range(40):
+            # start from B's vertices near A's surface: points of B's groups (its SDF is A's)
+            pts = np.zeros((goff[-1], 3))
+            v = B.verts[rng.integers(len(B.verts))]
+            pts[:] = v
+            pose = w.poses[sel].copy()
+            pose[0, :] = [1, 0, 0, 0, 0, 0, 0, 1, 0, 0, 0, 0, 0, 0]
+            # B at identity too: the points are in both frames the same
+            out = O.project(pr, ob, np.array([0]), np.array([1]), pose, pts)
+            g = A.n_pieces  # B's first group is evaluated against A
+            before = A.spline_eval(pts[g:g + 1])[0][0] if spl else A.sdf(pr, pts[g:g + 1])[0][0]
+            after = A.spline_eval(out[g:g + 1])[0][0] if spl else A.sdf(pr, out[g:g + 1])[0][0]
+            if abs(before) < 0.2 * w.L_ref:
+                phis.append(abs(before))
+                phis_after.append(abs(after))
+        phis, phis_after = np.array(phis), np.array(phis_after)
+        assert len(phis) > 10
+        assert np.median(phis_after / np.maximum(phis, 1e-12)) < 0.2
