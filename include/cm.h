@@ -83,6 +83,28 @@ typedef struct {
   int32_t prune_pieces; /* 1: skip, per wave, pieces whose union weight is provably
                            below 2^-28 at all its points (results equal within
                            FP32 rounding); 0: every piece at every point */
+  int32_t sdf_kind;     /* SDF representation of every object of the context (the
+                           paper's two alternatives, Sec. III):
+                           0: smooth union of smooth intersections of the pieces'
+                              hull half-spaces (Sec. III-A.2/3);
+                           1: cubic spline (Sec. III-B): the ground-truth SDF and
+                              normal of the pieces (closest point on their hulls,
+                              phi = min over pieces) sampled at the (grid_res + 1)^3
+                              corners of the grid box, natural cubic-spline
+                              coefficients by 1-D solves along each axis, and a
+                              separately fitted normal spline; the contact normal is
+                              the normal spline's value.  Outside the box phi
+                              continues as s(pi(x)) + |x - pi(x)|.  The broad phase
+                              bounds the spline over each cell by 216 times its
+                              least coefficient there (B-spline convex hull); the
+                              grid margins set the box (grid_margin_rel = 0 keeps it
+                              tight).  No adjoint tape: the adjoint recomputes. */
+  int32_t edge_assign;  /* edge assignment for blending (Sec. IV-D.1): 0: an edge
+                           counts in its own piece's group only; 1: also in the group
+                           of every other piece of its object it crosses (a part of
+                           positive length, > 1e-9 of the object's scale, inside that
+                           piece's hull), after the piece's own edges.  Vertices stay
+                           with their own piece.  cm_object_export lists own edges. */
 } cm_params;
 
 /* A pair-query: objects and poses (body -> world). 64 bytes. */
@@ -146,6 +168,11 @@ cm_status cm_object_export(cm_context* ctx, cm_object obj, int64_t* plane_off, d
 /* Copies the object's voxel grid to the host (synchronous): G [n^3] (index
  * (i * n + j) * n + k) and meta = origin (3), spacing (3), circumradius, n. */
 cm_status cm_object_grid(cm_context* ctx, cm_object obj, float* G, float* meta);
+/* Copies a spline object's coefficients to the host (synchronous; contexts
+ * with sdf_kind = 1): coef [(n+3)^3][4] (phi, n_x, n_y, n_z; index
+ * (i (n+3) + j) (n+3) + k; may be NULL) and meta = n, box origin (3), cell
+ * size (3).  Its grid (cm_object_grid) holds the per-cell lower bounds. */
+cm_status cm_object_spline(cm_context* ctx, cm_object obj, float* coef, float* meta);
 
 /* A plan fixes the objects of a batch of n pair-queries (poses are read at run
  * time from the device query array) and owns the scratch of the batched
@@ -231,6 +258,17 @@ cm_status cm_hvp(cm_context* ctx, cm_plan* plan, const cm_query* q_dev, cm_group
  * buffers are caller-owned device memory; CM_E_INVALID on a null argument. */
 cm_status cm_contacts_jvp(cm_context* ctx, cm_plan* plan, const cm_query* q_dev, cm_groups out,
                           cm_groups out_tangent, const float* dir, void* stream);
+
+/* Isosurface projection of contact points (Sec. IV-A, last paragraph): the
+ * collision mesh and the SDF's zero level set differ slightly, and a contact
+ * point p found on the mesh is moved onto the level set by
+ * proj(p) = p - phi(p) n(p), with phi and n those of the SDF the point's group
+ * was evaluated against (groups of A: B's SDF; groups of B: A's), in that
+ * body's frame.  p_in, p_out: device float [3][G] (SoA rows x, y, z; world
+ * frame; typically the records' p), one point per group of the plan; may
+ * alias.  Forward only (no derivatives).  Asynchronous on `stream`. */
+cm_status cm_project_points(cm_context* ctx, cm_plan* plan, const cm_query* q_dev, const float* p_in, float* p_out,
+                            void* stream);
 
 /* ---------------------------------------------------------------- serving --
  * A background scheduler admits requests while the device memory they need

@@ -36,7 +36,8 @@ class cm_params(ctypes.Structure):
     _fields_ = [(n, ctypes.c_float) for n in
                 ("tau_cap", "tau_cup", "tau_st", "tau_clip", "tau_blend", "d_max", "eps_t", "eps_n",
                  "grid_margin", "grid_margin_rel")] + \
-               [(n, ctypes.c_int32) for n in ("st_iters", "grid_res", "curve", "broad_phase", "edge_bound", "prune_pieces")]
+               [(n, ctypes.c_int32) for n in ("st_iters", "grid_res", "curve", "broad_phase", "edge_bound", "prune_pieces",
+                                              "sdf_kind", "edge_assign")]
 
 
 class cm_groups(ctypes.Structure):
@@ -77,6 +78,7 @@ cm_object_info = _sig("cm_object_info", I32, [P, U32, ctypes.POINTER(I32), ctype
                                               ctypes.POINTER(I64), ctypes.POINTER(I64)])
 cm_object_export = _sig("cm_object_export", I32, [P, U32, P, P, P, P, P, P])
 cm_object_grid = _sig("cm_object_grid", I32, [P, U32, P, P])
+cm_object_spline = _sig("cm_object_spline", I32, [P, U32, P, P])
 cm_plan_create = _sig("cm_plan_create", I32, [P, P, I32, PP])
 cm_plan_destroy = _sig("cm_plan_destroy", I32, [P])
 cm_plan_info = _sig("cm_plan_info", I32, [P, ctypes.POINTER(I64), ctypes.POINTER(I64), ctypes.POINTER(I32)])
@@ -90,6 +92,7 @@ cm_contacts_fwd_noalloc = _sig("cm_contacts_fwd_noalloc", I32, [P, P, P, cm_grou
 cm_contacts_bwd = _sig("cm_contacts_bwd", I32, [P, P, P, cm_groups, P, P])
 cm_hvp = _sig("cm_hvp", I32, [P, P, P, cm_groups, P, P, P, P])
 cm_contacts_jvp = _sig("cm_contacts_jvp", I32, [P, P, P, cm_groups, cm_groups, P, P])
+cm_project_points = _sig("cm_project_points", I32, [P, P, P, P, P, P])
 cm_contacts_step = _sig("cm_contacts_step", I32, [P, P, P, cm_groups, cm_groups, P, P, P, P])
 cm_graph_create = _sig("cm_graph_create", I32, [P, P, P, cm_groups, cm_groups, P, P, P, PP])
 cm_graph_launch = _sig("cm_graph_launch", I32, [P, P])
@@ -104,10 +107,10 @@ cm_serve_stats = _sig("cm_serve_stats", I32, [P, P])
 cm_serve_latencies = _sig("cm_serve_latencies", I32, [P, P, I64, ctypes.POINTER(I64)])
 
 EXPORTED = ["cm_default_params", "cm_init", "cm_shutdown", "cm_last_error", "cm_build_pieces", "cm_build_objects",
-            "cm_build_pieces_raw", "cm_release_object", "cm_object_info", "cm_object_export", "cm_object_grid",
+            "cm_build_pieces_raw", "cm_release_object", "cm_object_info", "cm_object_export", "cm_object_grid", "cm_object_spline",
             "cm_plan_create", "cm_plan_destroy", "cm_plan_info", "cm_plan_offsets", "cm_plan_stats", "cm_plan_work",
             "cm_plan_set_timing", "cm_plan_timing",
-            "cm_contacts_fwd", "cm_contacts_fwd_noalloc", "cm_contacts_bwd", "cm_hvp", "cm_contacts_jvp",
+            "cm_contacts_fwd", "cm_contacts_fwd_noalloc", "cm_contacts_bwd", "cm_hvp", "cm_contacts_jvp", "cm_project_points",
             "cm_contacts_step", "cm_graph_create", "cm_graph_launch",
             "cm_graph_destroy", "cm_plan_autotune", "cm_plan_set_launch_shape", "cm_plan_launch_shape",
             "cm_submit", "cm_poll", "cm_wait", "cm_serve_stats",

@@ -151,6 +151,16 @@ class Context:
         self._check(_cm.cm_object_grid(self._h, int(h), _ptr(G), _ptr(meta)), "cm_object_grid")
         return G.reshape(n, n, n), meta[:3].astype(np.float64), meta[3:6].astype(np.float64), float(meta[6])
 
+    def object_spline(self, h: int):
+        """A spline object's (n, box origin [3], cell size [3], coefficients
+        [4, n+3, n+3, n+3] of phi, n_x, n_y, n_z) (contexts with sdf_kind = 1)."""
+        meta = np.zeros(7, np.float32)
+        self._check(_cm.cm_object_spline(self._h, int(h), None, _ptr(meta)), "cm_object_spline")
+        n = int(meta[0])
+        C = np.zeros(((n + 3) ** 3, 4), np.float32)
+        self._check(_cm.cm_object_spline(self._h, int(h), _ptr(C), _ptr(meta)), "cm_object_spline")
+        return n, meta[1:4].astype(np.float64), meta[4:7].astype(np.float64), C.T.reshape(4, n + 3, n + 3, n + 3)
+
     def plan(self, qa, qb) -> "Plan":
         return Plan(self, qa, qb)
 
@@ -225,6 +235,19 @@ class Plan:
                                  _stream_ptr(stream))
         self.ctx._check(st, "cm_contacts_fwd")
         return (out, dbg) if debug else out
+
+    def project(self, q_dev, points, out=None, stream=None):
+        """Isosurface projection (cm_project_points) of one point per group,
+        points [3, G] (world; e.g. the records' first three rows)."""
+        torch = _torch()
+        pin = points.contiguous()
+        if out is None:
+            out = torch.empty_like(pin)
+        st = _cm.cm_project_points(self.ctx.handle, self._h, ctypes.c_void_p(q_dev.data_ptr()),
+                                   ctypes.c_void_p(pin.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                   _stream_ptr(stream))
+        self.ctx._check(st, "cm_project_points")
+        return out
 
     def forward_noalloc(self, q_dev, out, stream=None):
         """The forward records into the caller's `out` [12, G] with the launch

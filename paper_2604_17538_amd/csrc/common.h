@@ -13,6 +13,13 @@ constexpr int kMaxPieces = 4096;   // pieces per object (index fits 16 bits)
 constexpr int kSub = 16;           // support planes per piece (lower bound of its SDF)
 constexpr float kPruneTau = 20.f;  // a piece this many tau_cup above the union's minimum has weight < 2^-28
 
+// SDF representations of an object (the paper's two alternatives, Sec. III):
+// the smooth union of smooth intersections of half-spaces (one convex piece
+// each), or a cubic spline fitted to the ground-truth SDF with a separately
+// fitted normal spline.
+constexpr int32_t kRepPlanes = 0;
+constexpr int32_t kRepSpline = 1;
+
 // Per piece of a resident object (device).  Planes of the piece are stored
 // relative to `centre` and pre-scaled by kappa = log2(e) / tau_cap, so the
 // piece's log-sum-exp runs in base 2 with the temperature folded in.
@@ -44,8 +51,11 @@ struct ObjDesc {
   float ginv[3];          // 1 / voxel size
   float gr;               // voxel circumradius
   int32_t gn;             // voxels per axis
-  int32_t pad;
-  const F4* sub;          // [n_pieces][kSub] support planes (scaled like planes), min(kSub, plane_count) used
+  int32_t rep;            // SDF representation: kRepPlanes or kRepSpline
+  // kRepPlanes: [n_pieces][kSub] support planes (scaled like planes), min(kSub,
+  // plane_count) used.  kRepSpline: the spline coefficients, (gn + 3)^3 float4
+  // (phi, n_x, n_y, n_z) over the grid's box (its cells are the grid's voxels)
+  const F4* sub;
 };
 static_assert(sizeof(ObjDesc) == 128, "ObjDesc layout");
 

@@ -546,6 +546,153 @@ CM_DEV void sdf_eval(const ObjDesc& o, const DevParams& P, const V3<T>* x, SdfRe
   }
 }
 
+// ------------------------------------------------------- spline SDF --
+// Cubic-spline SDF of an object (Sec. III-B.1/2): over the box of its voxel grid
+// (origin gorg, n = gn cells of size gh per axis) the spline of phi and the
+// separately fitted spline of the normal share (n + 3)^3 basis functions, whose
+// coefficients (phi, n_x, n_y, n_z) are one float4 each (`sub` of a spline
+// object), index (i (n + 3) + j) (n + 3) + k.  At a point, 4 basis functions
+// per axis are nonzero: 64 gathers of 16 bytes, the 4 z-neighbours contiguous.
+// Outside the box phi continues as s(pi(x)) + |x - pi(x)| and the normal as
+// s_n(pi(x)), pi the closest point of the box.
+template <class T> struct SplRes {
+  T phi;
+  V3<T> g;   // grad phi (GRAD)
+  V3<T> n;   // normal spline (NRM)
+  M3<T> J;   // its Jacobian, row a = d n_a / dx (JAC)
+};
+// The 4 basis functions nonzero in a cell at offset w in [0, 1] (u(w + 1),
+// u(w), u(w - 1), u(w - 2) with u of Sec. III-B.1) and their derivatives in w.
+template <class T> CM_DEV void cell_basis(T w, T* b, T* db) {
+  const T v = cst<T>(1.f) - w;
+  const T w2 = w * w, v2 = v * v;
+  b[0] = v2 * v;
+  b[1] = w2 * (3.f * w - 6.f) + 4.f;
+  b[2] = v2 * (3.f * v - 6.f) + 4.f;
+  b[3] = w2 * w;
+  db[0] = v2 * -3.f;
+  db[1] = w * (9.f * w - 12.f);
+  db[2] = v * (12.f - 9.f * v);
+  db[3] = w2 * 3.f;
+}
+template <bool GRAD, bool NRM, bool JAC, class T>
+CM_DEV void spline_eval(const ObjDesc& o, const V3<T>& x, SplRes<T>& r) {
+  const int n = o.gn, m = n + 3;
+  const T xs[3] = {x.x, x.y, x.z};
+  T b[3][4], db[3][4];
+  int i0[3];
+  T out2 = cst<T>(0.f);
+  T dd[3] = {cst<T>(0.f), cst<T>(0.f), cst<T>(0.f)};  // x - pi(x)
+  float dsc[3];  // d t / d x, 0 for a clamped axis (s(pi(x)) does not move with it)
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    T t = (xs[a] - o.gorg[a]) * o.ginv[a];
+    dsc[a] = o.ginv[a];
+    const float tv = val(t);
+    if (!(tv >= 0.f) || tv > float(n)) {
+      const float lim = tv > float(n) ? float(n) : 0.f;
+      const T d = xs[a] - (o.gorg[a] + lim * o.gh[a]);
+      out2 = out2 + d * d;
+      dd[a] = d;
+      t = cst<T>(lim);
+      dsc[a] = 0.f;
+    }
+    const int i = min(max(int(floorf(val(t))), 0), n - 1);
+    i0[a] = i;
+    cell_basis(t - float(i), b[a], db[a]);
+  }
+  T phi = cst<T>(0.f);
+  V3<T> g = zero3<T>(), nr = zero3<T>();
+  M3<T> J;
+  if (JAC)
+#pragma unroll
+    for (int i = 0; i < 9; ++i) J.m[i] = cst<T>(0.f);
+  const F4* cf = o.sub;
+  // one x-slab of 16 coefficients per iteration (the x weights picked by the
+  // uniform counter), so that at most 16 gathers are in flight per lane
+#pragma unroll 1
+  for (int p = 0; p < 4; ++p) {
+    const T bx = p == 0 ? b[0][0] : (p == 1 ? b[0][1] : (p == 2 ? b[0][2] : b[0][3]));
+    const T dbx = p == 0 ? db[0][0] : (p == 1 ? db[0][1] : (p == 2 ? db[0][2] : db[0][3]));
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const T wpq = bx * b[1][q];
+      const T wdx = dbx * b[1][q], wdy = bx * db[1][q];
+      const F4* row = cf + (int64_t(i0[0] + p) * m + (i0[1] + q)) * m + i0[2];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const F4 c = row[k];
+        const T w = wpq * b[2][k];
+        phi = fmaT(c.x, w, phi);
+        if (NRM) { nr.x = fmaT(c.y, w, nr.x); nr.y = fmaT(c.z, w, nr.y); nr.z = fmaT(c.w, w, nr.z); }
+        if (GRAD || JAC) {
+          const T wx = wdx * b[2][k], wy = wdy * b[2][k], wz = wpq * db[2][k];
+          if (GRAD) { g.x = fmaT(c.x, wx, g.x); g.y = fmaT(c.x, wy, g.y); g.z = fmaT(c.x, wz, g.z); }
+          if (JAC) {
+            J.m[0] = fmaT(c.y, wx, J.m[0]); J.m[1] = fmaT(c.y, wy, J.m[1]); J.m[2] = fmaT(c.y, wz, J.m[2]);
+            J.m[3] = fmaT(c.z, wx, J.m[3]); J.m[4] = fmaT(c.z, wy, J.m[4]); J.m[5] = fmaT(c.z, wz, J.m[5]);
+            J.m[6] = fmaT(c.w, wx, J.m[6]); J.m[7] = fmaT(c.w, wy, J.m[7]); J.m[8] = fmaT(c.w, wz, J.m[8]);
+          }
+        }
+      }
+    }
+  }
+  const bool outside = val(out2) > 0.f;
+  const T dl = outside ? sqrtT(out2) : cst<T>(0.f);
+  r.phi = phi + dl;
+  if (GRAD) {
+    r.g = {g.x * dsc[0], g.y * dsc[1], g.z * dsc[2]};
+    if (outside) r.g = r.g + V3<T>{dd[0], dd[1], dd[2]} * (cst<T>(1.f) / dl);
+  }
+  if (NRM) r.n = nr;
+  if (JAC)
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) r.J.m[3 * a + c] = J.m[3 * a + c] * dsc[c];
+}
+
+// Spline broad phase (B-spline convex hull): the grid of a spline object
+// stores, per cell, 216 times the least coefficient of phi the cell reaches, a
+// lower bound of the spline over the cell; a point's bound is its clamped
+// cell's plus its distance outside the box.
+CM_DEV float spline_lb(const ObjDesc& o, V3<float> x) {
+  const int n = o.gn;
+  const float xs[3] = {x.x, x.y, x.z};
+  int id[3];
+  float o2 = 0.f;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const float lo = o.gorg[a], hi = o.gorg[a] + float(n) * o.gh[a];
+    const float d = xs[a] < lo ? lo - xs[a] : (xs[a] > hi ? xs[a] - hi : 0.f);
+    o2 = fmaf(d, d, o2);
+    id[a] = min(max(int(floorf((xs[a] - lo) * o.ginv[a])), 0), n - 1);
+  }
+  return o.grid[(id[0] * n + id[1]) * n + id[2]] + sqrtf(o2);
+}
+// The same bound over a segment: the least cell bound over the clamped cell
+// range of its bounding box plus the box's distance outside the grid box.
+CM_DEV float spline_edge_lb(const ObjDesc& o, V3<float> x1, V3<float> x2) {
+  const int n = o.gn;
+  const float a1[3] = {x1.x, x1.y, x1.z}, a2[3] = {x2.x, x2.y, x2.z};
+  int lo[3], hi[3];
+  float o2 = 0.f;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const float mn = fminf(a1[a], a2[a]), mx = fmaxf(a1[a], a2[a]);
+    const float blo = o.gorg[a], bhi = o.gorg[a] + float(n) * o.gh[a];
+    const float d = mx < blo ? blo - mx : (mn > bhi ? mn - bhi : 0.f);
+    o2 = fmaf(d, d, o2);
+    lo[a] = min(max(int(floorf((mn - blo) * o.ginv[a])), 0), n - 1);
+    hi[a] = min(max(int(floorf((mx - blo) * o.ginv[a])), 0), n - 1);
+  }
+  float m = __builtin_inff();
+  for (int i = lo[0]; i <= hi[0]; ++i)
+    for (int j = lo[1]; j <= hi[1]; ++j)
+      for (int k = lo[2]; k <= hi[2]; ++k) m = fminf(m, o.grid[(i * n + j) * n + k]);
+  return m + sqrtf(o2);
+}
+
 // Lower bound of phi from the voxel grid (Sec. IV-C.2): the stored phi at the
 // centre of the voxel the point falls into (clamped to the grid) minus
 // max(circumradius, distance to that centre).

@@ -72,6 +72,8 @@ struct FwdArgs {
   float* tape;          // [2 * tape_nv][tape_tiles * 64] (nullable)
   int64_t tape_tiles;   // tiles [0, tape_tiles) are taped; the rest is recomputed
   int32_t tape_nv;
+  int32_t rep;          // SDF representation of every SDF-side object (kRepPlanes / kRepSpline);
+                        // spline SDFs keep no tape (tape == nullptr)
 };
 
 // Kernels timed with events when a plan has timing enabled.
@@ -101,7 +103,8 @@ struct NarrowArgs {
   int32_t tape_nv;
   int64_t t_begin;        // first tile of this launch (recomputing adjoint)
   unsigned long long* work;  // nullable: [2] += point-plane evaluations performed for vertex and
-                             // edge contacts (64 lanes per wave)
+                             // edge contacts (64 lanes per wave); spline SDFs: 64 terms per evaluation
+  int32_t rep;               // see FwdArgs
 };
 
 struct FinArgs {
@@ -124,6 +127,26 @@ struct FinArgs {
 
 hipError_t launch_grid_build(const ObjDesc* objs, const int32_t* ids, int32_t n_ids, int32_t grid_res,
                              const DevParams& P, hipStream_t s);
+
+// One object's spline fit (spline.hip): its collision geometry in FP64 and
+// where the results go.
+struct SplJob {
+  const double* planes;   // [P][4] unit outward n, h (n.x + h <= 0 inside), object frame
+  const int4* pieces;     // per piece: plane begin, plane count, segment begin, segment count
+  const double* segs;     // [E][6] feature edges as segments (both endpoints)
+  int32_t n_pieces;
+  int32_t pad;
+  double org[3], h[3];    // grid box: corners org + (i, j, k) h, i, j, k in [0, n]
+  F4* coef;               // out: [(n + 3)^3] (phi, n_x, n_y, n_z) coefficients
+  float* grid;            // out: [n^3] per cell lower bound of the spline
+};
+// GT at the corners, three solve passes, pack; work_a and work_b hold
+// n_jobs * work_stride doubles each, work_stride >= 4 (n + 3)^3.
+hipError_t launch_spline_build(const SplJob* d_jobs, int n_jobs, int n, double* work_a, double* work_b,
+                               int64_t work_stride, hipStream_t s);
+// isosurface projection of group points (p_in, p_out: SoA [3][G], world)
+hipError_t launch_project(const QueryDev* Q, const ObjDesc* objs, const int64_t* group_off, int32_t n,
+                          const DevParams& P, const float* pin, float* pout, int64_t G, hipStream_t s);
 // broad phase + tile scan (shared by every pass)
 void launch_front(const FwdArgs& a, hipStream_t s);
 void launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);

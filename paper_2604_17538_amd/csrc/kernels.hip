@@ -38,6 +38,7 @@ __global__ __launch_bounds__(256) void k_grid_build(const ObjDesc* __restrict__ 
   const int oi = uni(int(blockIdx.x) / blocks_per_obj);
   const int obj = uni(ids[oi]);
   const ObjDesc o = ldc(objs + obj);
+  if (o.rep != kRepPlanes) return;  // a spline object's cell bounds come with its fit
   const int n = o.gn;
   const int n3 = n * n * n;
   const int v0 = (int(blockIdx.x) % blocks_per_obj) * 256 + int(threadIdx.x);
@@ -83,13 +84,15 @@ __global__ __launch_bounds__(256) void k_broad(const Entry* __restrict__ ents, i
       if (E.kind == 0) {
         const V3<float> v = vert(M, pd.vert_begin + cc);
         const V3<float> x = mulM(F.Rrel, v) + F.trel;
-        surv = !P.broad_phase || grid_lb(S, x) < P.d_max;
+        surv = !P.broad_phase || (S.rep == kRepSpline ? spline_lb(S, x) : grid_lb(S, x)) < P.d_max;
         prest = mulM(F.RM, v) + F.tM;
       } else {
         const I2 ed = M.edges[pd.edge_begin + cc];
         const V3<float> v0 = vert(M, ed.x), v1 = vert(M, ed.y);
         const V3<float> x0 = mulM(F.Rrel, v0) + F.trel, x1 = mulM(F.Rrel, v1) + F.trel;
-        if (P.broad_phase) {
+        if (P.broad_phase && S.rep == kRepSpline) {
+          surv = spline_edge_lb(S, x0, x1) < P.d_max;
+        } else if (P.broad_phase) {
           const V3<float> dv = x1 - x0;
           const float L = sqrtf(dot(dv, dv));
           const float la = grid_lb(S, x0), lb = grid_lb(S, x1);
@@ -214,6 +217,63 @@ __global__ void k_entry_parts(const int64_t* __restrict__ run_off, const int32_t
   const int64_t rs = surv_off[run_off[ent_run[e]]];
   const int64_t a = surv_off[e] - rs, b = surv_off[e + 1] - rs;
   npart[e] = b > a ? int32_t((b - 1) / kWave - a / kWave + 1) : 0;
+}
+
+// ------------------------------------------------------ isosurface projection --
+// Sec. IV-A, last paragraph: contact points found on the collision mesh are
+// moved onto the SDF's zero level set, proj(p) = p - phi(p) n(p), in the frame of
+// the SDF each group was evaluated against (A's groups: B's SDF; B's groups:
+// A's).  One wave per (query, direction); its lanes take that direction's
+// groups (every lane runs the SDF evaluation, whose piece loop is wave-uniform).
+__global__ __launch_bounds__(256) void k_project(const QueryDev* __restrict__ Q, const ObjDesc* __restrict__ objs,
+                                                 const int64_t* __restrict__ group_off, int32_t n, DevParams P,
+                                                 const float* __restrict__ pin, float* __restrict__ pout, int64_t G) {
+  const int l = lane();
+  const int64_t wave = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+  if (wave >= 2 * int64_t(n)) return;
+  const int qi = int(wave >> 1), dir = int(wave & 1);
+  const QueryDev q = ldc(Q + qi);
+  const ObjDesc A = ldc(objs + q.a);
+  const ObjDesc S = ldc(objs + (dir ? q.a : q.b));
+  const int64_t gq = group_off[qi], gn = group_off[qi + 1] - gq;
+  const int64_t g0 = gq + (dir ? A.n_pieces : 0);
+  const int64_t ng = dir ? gn - A.n_pieces : int64_t(A.n_pieces);
+  const Frame32 f = dir ? frame32(q.qb, q.tb, q.qa, q.ta) : frame32(q.qa, q.ta, q.qb, q.tb);
+  for (int64_t base = 0; base < ng; base += kWave) {
+    const bool valid = base + l < ng;
+    const int64_t g = g0 + (valid ? base + l : 0);
+    const V3<float> d{pin[g] - f.tS[0], pin[G + g] - f.tS[1], pin[2 * G + g] - f.tS[2]};
+    const V3<float> x{f.RS[0] * d.x + f.RS[3] * d.y + f.RS[6] * d.z, f.RS[1] * d.x + f.RS[4] * d.y + f.RS[7] * d.z,
+                      f.RS[2] * d.x + f.RS[5] * d.y + f.RS[8] * d.z};
+    float phi;
+    V3<float> nS;
+    if (S.rep == kRepSpline) {
+      SplRes<float> r;
+      spline_eval<false, true, false, float>(S, x, r);
+      phi = r.phi;
+      nS = r.n;
+    } else {
+      SdfRes<float> r;
+      sdf_eval<1, 1, float>(S, P, &x, &r);
+      phi = r.phi;
+      nS = r.g * (1.f / sqrtf(dot(r.g, r.g) + P.eps_n2));
+    }
+    const V3<float> y = x - nS * phi;
+    if (valid) {
+      pout[g] = f.RS[0] * y.x + f.RS[1] * y.y + f.RS[2] * y.z + f.tS[0];
+      pout[G + g] = f.RS[3] * y.x + f.RS[4] * y.y + f.RS[5] * y.z + f.tS[1];
+      pout[2 * G + g] = f.RS[6] * y.x + f.RS[7] * y.y + f.RS[8] * y.z + f.tS[2];
+    }
+  }
+}
+
+hipError_t launch_project(const QueryDev* Q, const ObjDesc* objs, const int64_t* group_off, int32_t n,
+                          const DevParams& P, const float* pin, float* pout, int64_t G, hipStream_t s) {
+  (void)hipGetLastError();
+  const int64_t threads = 2 * int64_t(n) * kWave;
+  hipLaunchKernelGGL(k_project, dim3(unsigned((threads + 255) / 256)), dim3(256), 0, s, Q, objs, group_off, n, P, pin,
+                     pout, G);
+  return hipGetLastError();
 }
 
 __global__ void k_fill_u32(uint32_t* p, uint32_t v, int64_t n) {

@@ -105,8 +105,9 @@ template <class T> CM_DEV FrameT<T> frame_t(const QueryDev& q, int dir, const fl
 template <class T> struct CF {
   T phi;
   V3<T> g;      // grad phi at the contact point (SDF frame)
-  Sym<T> H;     // Hessian of phi there (adjoint only)
-  T sg;         // sqrt(|g|^2 + eps_n^2)
+  Sym<T> H;     // Hessian of phi there (adjoint only; plane SDFs)
+  M3<T> J;      // Jacobian of the normal spline there (adjoint only; spline SDFs)
+  T sg;         // sqrt(|g|^2 + eps_n^2) (plane SDFs)
   V3<T> nS;     // normal, SDF frame
   V3<T> N;      // normal, world
   V3<T> p;      // contact point, world
@@ -115,9 +116,13 @@ template <class T> struct CF {
   T d;          // mollified depth
 };
 
-template <class T> CM_DEV void finish_contact(CF<T>& c, const FrameT<T>& F, const DevParams& P) {
-  c.sg = sqrtT(dot(c.g, c.g) + P.eps_n2);
-  c.nS = c.g * (cst<T>(1.f) / c.sg);
+// The contact normal: for plane SDFs the normalised gradient (set here), for
+// spline SDFs the normal spline's value (set by the evaluation, Sec. III-B.2).
+template <class T, int REP> CM_DEV void finish_contact(CF<T>& c, const FrameT<T>& F, const DevParams& P) {
+  if (REP == kRepPlanes) {
+    c.sg = sqrtT(dot(c.g, c.g) + P.eps_n2);
+    c.nS = c.g * (cst<T>(1.f) / c.sg);
+  }
   c.N = mulM(F.RS, c.nS);
   // C2 transition (Sec. IV-C.1): quintic smoothstep and its derivative
   const T s = (P.d_max - c.phi) * P.inv_eps_t;
@@ -133,21 +138,56 @@ template <class T> CM_DEV void finish_contact(CF<T>& c, const FrameT<T>& F, cons
   c.d = c.f * c.phi + (cst<T>(1.f) - c.f) * P.d_max;
 }
 
+// SDF evaluations for either representation.  Trace points: phi at NP points
+// (GRAD: and its gradient, for the adjoint).  Spline evaluations count 64
+// terms of work each.
+template <int REP, int NP, bool GRAD, class T>
+CM_DEV void sdf_points(const ObjDesc& S, const DevParams& P, const V3<T>* x, SdfRes<T>* r, uint64_t* work) {
+  if (REP == kRepPlanes) {
+    sdf_eval<NP, GRAD ? 1 : 0, T>(S, P, x, r, work);
+  } else {
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+      SplRes<T> q;
+      spline_eval<GRAD, false, false, T>(S, x[p], q);
+      r[p].phi = q.phi;
+      if (GRAD) r[p].g = q.g;
+    }
+    if (work) *work += uint64_t(64 * NP);
+  }
+}
+// The contact point: phi and what the normal needs (plane SDFs: the gradient;
+// spline SDFs: the normal spline); HIST: also what the adjoint needs (the
+// Hessian of phi, or the gradient of phi and the normal spline's Jacobian).
+template <int REP, bool HIST, class T>
+CM_DEV void sdf_contact(const ObjDesc& S, const DevParams& P, const V3<T>& x, CF<T>& c, uint64_t* work) {
+  if (REP == kRepPlanes) {
+    SdfRes<T> r;
+    sdf_eval<1, HIST ? 2 : 1, T>(S, P, &x, &r, work);
+    c.phi = r.phi;
+    c.g = r.g;
+    if (HIST) c.H = r.H;
+  } else {
+    SplRes<T> q;
+    spline_eval<HIST, true, HIST, T>(S, x, q);
+    c.phi = q.phi;
+    if (HIST) { c.g = q.g; c.J = q.J; }
+    c.nS = q.n;
+    if (work) *work += 64;
+  }
+}
+
 // Vertex-SDF contact (Sec. IV-B): the vertex itself is the contact point.
-// HIST: also the Hessian (for the adjoint).
-template <class T, bool HIST>
+// HIST: also what the adjoint needs.
+template <class T, bool HIST, int REP>
 CM_DEV void vertex_fwd(const ObjDesc& M, const ObjDesc& S, const FrameT<T>& F, int vi, const DevParams& P,
                        CF<T>& c, uint64_t* work) {
   const V3<float> v = vert(M, vi);
   V3<T> x = mulMc(F.Rrel, v) + F.trel;
-  SdfRes<T> r;
-  sdf_eval<1, HIST ? 2 : 1, T>(S, P, &x, &r, work);
-  c.phi = r.phi;
-  c.g = r.g;
-  if (HIST) c.H = r.H;
+  sdf_contact<REP, HIST, T>(S, P, x, c, work);
   c.p = mulMc(F.RM, v) + F.tM;
   c.prest = c.p;
-  finish_contact(c, F, P);
+  finish_contact<T, REP>(c, F, P);
 }
 
 // The same contact rebuilt from its tape record (phi, gradient, Hessian).
@@ -161,7 +201,7 @@ CM_DEV void vertex_load(const ObjDesc& M, const FrameT<T>& F, int vi, const DevP
          tget<T>(tp, rs, 7, slot), tget<T>(tp, rs, 8, slot), tget<T>(tp, rs, 9, slot)};
   c.p = mulMc(F.RM, v) + F.tM;
   c.prest = c.p;
-  finish_contact(c, F, P);
+  finish_contact<T, kRepPlanes>(c, F, P);
 }
 
 // Sphere-trace history kept for the adjoint.
@@ -196,11 +236,11 @@ CM_DEV void edge_point(Trace<T>& tr, T al, T be, const DevParams& P) {
   tr.pe = (tr.x0 + tr.e * tr.ac + tr.x1 - tr.e * tr.bc) * 0.5f;
 }
 
-template <class T>
+template <class T, int REP>
 CM_DEV void edge_contact(const ObjDesc& M, const FrameT<T>& F, const DevParams& P, const Trace<T>& tr, CF<T>& c) {
   c.p = mulM(F.RS, tr.pe) + F.tS;
   c.prest = mulMc(F.RM, (tr.v0 + tr.v1) * 0.5f) + F.tM;
-  finish_contact(c, F, P);
+  finish_contact<T, REP>(c, F, P);
 }
 
 // Edge-SDF contact (Sec. IV-B.2, Fig. e_s): trace both corners towards each
@@ -209,7 +249,7 @@ CM_DEV void edge_contact(const ObjDesc& M, const FrameT<T>& F, const DevParams& 
 // midpoint of the two points.  HIST: keep the trace and the Hessian; with a
 // tape (tp != nullptr) the trace steps go to the tape as they are computed
 // instead of being kept.
-template <class T, bool HIST>
+template <class T, bool HIST, int REP>
 CM_DEV void edge_fwd(const ObjDesc& M, const ObjDesc& S, const FrameT<T>& F, int ei, const DevParams& P, CF<T>& c,
                      Trace<T>& tr, uint64_t* work, float* tp = nullptr, int64_t rs = 0, int64_t slot = 0) {
   edge_setup(M, F, ei, tr);
@@ -220,7 +260,7 @@ CM_DEV void edge_fwd(const ObjDesc& M, const ObjDesc& S, const FrameT<T>& F, int
       if (k < P.st_iters) {
         V3<T> xs[2] = {tr.x0 + tr.e * al, tr.x1 - tr.e * be};
         SdfRes<T> r[2];
-        sdf_eval<2, 1, T>(S, P, xs, r, work);
+        sdf_points<REP, 2, true, T>(S, P, xs, r, work);
         if (tp != nullptr) {
           const int v = kTapeFixed + kTapeStep * k;
           tput(tp, rs, v, slot, r[0].phi);
@@ -240,18 +280,14 @@ CM_DEV void edge_fwd(const ObjDesc& M, const ObjDesc& S, const FrameT<T>& F, int
     for (int k = 0; k < P.st_iters; ++k) {
       V3<T> xs[2] = {tr.x0 + tr.e * al, tr.x1 - tr.e * be};
       SdfRes<T> r[2];
-      sdf_eval<2, 0, T>(S, P, xs, r, work);
+      sdf_points<REP, 2, false, T>(S, P, xs, r, work);
       al = al + sigmoidT(r[0].phi * P.inv_tau_st) * r[0].phi;
       be = be + sigmoidT(r[1].phi * P.inv_tau_st) * r[1].phi;
     }
   }
   edge_point(tr, al, be, P);
-  SdfRes<T> r;
-  sdf_eval<1, HIST ? 2 : 1, T>(S, P, &tr.pe, &r, work);
-  c.phi = r.phi;
-  c.g = r.g;
-  if (HIST) c.H = r.H;
-  edge_contact(M, F, P, tr, c);
+  sdf_contact<REP, HIST, T>(S, P, tr.pe, c, work);
+  edge_contact<T, REP>(M, F, P, tr, c);
 }
 
 // The same contact rebuilt from its tape record: the trace steps replayed from
@@ -279,7 +315,7 @@ CM_DEV void edge_load(const ObjDesc& M, const FrameT<T>& F, int ei, const DevPar
   c.g = tget3<T>(tp, rs, 1, slot);
   c.H = {tget<T>(tp, rs, 4, slot), tget<T>(tp, rs, 5, slot), tget<T>(tp, rs, 6, slot),
          tget<T>(tp, rs, 7, slot), tget<T>(tp, rs, 8, slot), tget<T>(tp, rs, 9, slot)};
-  edge_contact(M, F, P, tr, c);
+  edge_contact<T, kRepPlanes>(M, F, P, tr, c);
 }
 
 // Writes the contact-point part of a tape record (the trace steps of an edge
@@ -357,22 +393,24 @@ CM_DEV void blend_moll_adj(const CF<T>& c, const GAdj<T>& a, const DevParams& P,
   prb = pcb * omf;
 }
 
-// Through n_S = g / sqrt(|g|^2 + eps^2), N = R_S n_S and phi: adjoint of the
-// contact point in the SDF frame, x_bar = phi_bar grad phi + H g_bar.
-template <class T>
+// Through N = R_S n_S and phi: adjoint of the contact point in the SDF frame.
+// Plane SDFs, n_S = g / sqrt(|g|^2 + eps^2): x_bar = phi_bar grad phi + H g_bar.
+// Spline SDFs, n_S the normal spline: x_bar = phi_bar grad phi + J^T n_S_bar.
+template <class T, int REP>
 CM_DEV V3<T> point_adj(const CF<T>& c, const FrameT<T>& F, T phib, V3<T> Nb, PoseGrad<T>& G) {
   G.wS = G.wS + cross(c.N, Nb);
   const V3<T> nSb = mulMT(F.RS, Nb);
+  if (REP == kRepSpline) return c.g * phib + mulMT(c.J, nSb);
   const V3<T> gb = (nSb - c.nS * dot(c.nS, nSb)) * (cst<T>(1.f) / c.sg);
   return c.g * phib + mulS(c.H, gb);
 }
 
-template <class T>
+template <class T, int REP>
 CM_DEV void vertex_adj(const CF<T>& c, const FrameT<T>& F, const GAdj<T>& a, const DevParams& P, PoseGrad<T>& G) {
   T phib;
   V3<T> Nb, pb, prb;
   blend_moll_adj(c, a, P, phib, Nb, pb, prb);
-  const V3<T> xb = point_adj(c, F, phib, Nb, G);
+  const V3<T> xb = point_adj<T, REP>(c, F, phib, Nb, G);
   const V3<T> xbw = mulM(F.RS, xb);
   const V3<T> Pb = pb + prb + xbw;  // p = p_rest = R_M v + t_M; x = R_S^T (p - t_S)
   G.wM = G.wM + cross(c.p - F.tM, Pb);
@@ -420,13 +458,13 @@ CM_DEV void trace_adj(const Trace<T>& tr, V3<T> peb, const DevParams& P, V3<T>& 
   x0b = x0b - db;
 }
 
-template <class T>
+template <class T, int REP>
 CM_DEV void edge_adj(const CF<T>& c, const Trace<T>& tr, const FrameT<T>& F, const GAdj<T>& a, const DevParams& P,
                      PoseGrad<T>& G) {
   T phib;
   V3<T> Nb, pb, prb;
   blend_moll_adj(c, a, P, phib, Nb, pb, prb);
-  const V3<T> xb = point_adj(c, F, phib, Nb, G);
+  const V3<T> xb = point_adj<T, REP>(c, F, phib, Nb, G);
   // p = R_S p^e + t_S
   G.wS = G.wS + cross(c.p - F.tS, pb);
   G.vS = G.vS + pb;
@@ -450,8 +488,9 @@ CM_DEV void edge_adj(const CF<T>& c, const Trace<T>& tr, const FrameT<T>& F, con
 //                              tape records of tiles [0, tape_tiles)
 //   ADJ = true,  TAPE = true   adjoint of tiles [0, tape_tiles) from the tape
 //   ADJ = true,  TAPE = false  adjoint of tiles [t_begin, total), recomputing
-template <class T, bool ADJ, bool TAPE>
+template <class T, bool ADJ, bool TAPE, int REP>
 __global__ __launch_bounds__(256) void k_narrow(NarrowArgs a) {
+  static_assert(REP == kRepPlanes || !TAPE, "spline SDFs recompute instead of taping");
   const int l = lane();
   const int64_t total = a.tile_off[a.n_run];
   const int64_t t_end = (ADJ && TAPE) ? min(total, a.tape_tiles) : total;
@@ -489,15 +528,17 @@ __global__ __launch_bounds__(256) void k_narrow(NarrowArgs a) {
     CF<T> ct;
     Trace<T> tr;
     const int64_t slot = t * kWave + l;
-    if (ADJ && TAPE) {
+    if constexpr (ADJ && TAPE) {
       if (E0.kind == 0) vertex_load<T>(M, F, ci, P, a.tape, rs, slot, ct);
       else edge_load<T>(M, F, ci, P, a.tape, rs, slot, ct, tr);
     } else {
       // the store sweep writes the records of taped tiles
       float* tp = (!ADJ && TAPE && t < a.tape_tiles) ? a.tape : nullptr;
-      if (E0.kind == 0) vertex_fwd<T, HIST>(M, S, F, ci, P, ct, &work[0]);
-      else edge_fwd<T, HIST>(M, S, F, ci, P, ct, tr, &work[1], tp, rs, slot);
-      if (tp != nullptr) tape_store(ct, tp, rs, slot);
+      if (E0.kind == 0) vertex_fwd<T, HIST, REP>(M, S, F, ci, P, ct, &work[0]);
+      else edge_fwd<T, HIST, REP>(M, S, F, ci, P, ct, tr, &work[1], tp, rs, slot);
+      if constexpr (TAPE) {
+        if (tp != nullptr) tape_store(ct, tp, rs, slot);
+      }
     }
     if (!ADJ) {
       // online softmax over l_i = -d_c,i / tau_b, one partial per piece present
@@ -534,8 +575,8 @@ __global__ __launch_bounds__(256) void k_narrow(NarrowArgs a) {
     } else {
       const GAdj<T> ga = load_gadj<T>(a.gscratch + int64_t(E.group) * kGStride);
       PoseGrad<T> G{zero3<T>(), zero3<T>(), zero3<T>(), zero3<T>()};
-      if (E0.kind == 0) vertex_adj(ct, F, ga, P, G);
-      else edge_adj(ct, tr, F, ga, P, G);
+      if (E0.kind == 0) vertex_adj<T, REP>(ct, F, ga, P, G);
+      else edge_adj<T, REP>(ct, tr, F, ga, P, G);
       // (w_A, v_A, w_B, v_B): all lanes of a tile belong to one query
       const V3<T> g4[4] = {E0.dir ? G.wS : G.wM, E0.dir ? G.vS : G.vM, E0.dir ? G.wM : G.wS,
                            E0.dir ? G.vM : G.vS};
@@ -764,7 +805,12 @@ static void narrow_launch(const NarrowArgs& na, int grid, hipStream_t s, hipEven
   launch_fill_u32(na.counter, 0u, 1, s);
   const int slot = nT<T>() == 1 ? (ADJ ? kTNarrowAdj : kTNarrowFwd) : (ADJ ? kTNarrowDualAdj : kTNarrowTan);
   if (ev && first) (void)hipEventRecord(ev[2 * slot], s);
-  hipLaunchKernelGGL((k_narrow<T, ADJ, TAPE>), dim3(unsigned(grid)), dim3(256), 0, s, na);
+  if (na.rep == kRepSpline) {
+    if constexpr (!TAPE) hipLaunchKernelGGL((k_narrow<T, ADJ, false, kRepSpline>), dim3(unsigned(grid)), dim3(256), 0,
+                                            s, na);
+  } else {
+    hipLaunchKernelGGL((k_narrow<T, ADJ, TAPE, kRepPlanes>), dim3(unsigned(grid)), dim3(256), 0, s, na);
+  }
   if (ev && last) (void)hipEventRecord(ev[2 * slot + 1], s);
 }
 
@@ -776,6 +822,7 @@ static NarrowArgs narrow_args(const FwdArgs& a, float* partials, const float* di
   na.dbg = dbg; na.C = a.C;
   na.tape = a.tape; na.tape_tiles = a.tape_tiles; na.tape_nv = a.tape_nv; na.t_begin = 0;
   na.work = a.work;
+  na.rep = a.rep;
   return na;
 }
 static FinArgs fin_args(const FwdArgs& a, const float* partials, const float* dir) {

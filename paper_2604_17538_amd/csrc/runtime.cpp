@@ -42,6 +42,8 @@ bool valid_params(const cm_params& p, std::string* why) {
   if (p.curve < 0 || p.curve > 2) { *why = "curve must be 0, 1 or 2"; return false; }
   if (!(p.grid_margin >= 0.f) || !(p.grid_margin_rel >= 0.f)) { *why = "grid margins must be >= 0"; return false; }
   if (p.prune_pieces < 0 || p.prune_pieces > 1) { *why = "prune_pieces must be 0 or 1"; return false; }
+  if (p.sdf_kind < 0 || p.sdf_kind > 1) { *why = "sdf_kind must be 0 (planes) or 1 (spline)"; return false; }
+  if (p.edge_assign < 0 || p.edge_assign > 1) { *why = "edge_assign must be 0 or 1"; return false; }
   return true;
 }
 
@@ -114,9 +116,12 @@ void Arena::release(int chunk_id) {
 struct Packed {
   std::vector<char> bytes;
   size_t off_planes, off_sub, off_pieces, off_vx, off_vy, off_vz, off_edges, off_grid;
+  size_t off_coef;  // spline coefficients (spline objects)
   int32_t K, P, V, E;
   float gorg[3], gh[3], ginv[3], gr;
+  double gorg64[3], gh64[3];  // the grid box in FP64 (the spline fit's corners)
   int32_t gn;
+  int32_t rep;
 };
 
 static void pack_object(const ObjHost& o, const cm_params& prm, Packed* pk) {
@@ -136,6 +141,8 @@ static void pack_object(const ObjHost& o, const cm_params& prm, Packed* pk) {
   pk->off_vz = take(4 * size_t(pk->V));
   pk->off_edges = take(8 * size_t(pk->E));
   pk->off_grid = take(4 * size_t(gn) * gn * gn);
+  pk->rep = prm.sdf_kind == 1 ? kRepSpline : kRepPlanes;
+  pk->off_coef = pk->rep == kRepSpline ? take(16 * size_t(gn + 3) * (gn + 3) * (gn + 3)) : 0;
   pk->bytes.assign(off, 0);
   F4* planes = reinterpret_cast<F4*>(pk->bytes.data() + pk->off_planes);
   F4* sub = reinterpret_cast<F4*>(pk->bytes.data() + pk->off_sub);
@@ -145,6 +152,8 @@ static void pack_object(const ObjHost& o, const cm_params& prm, Packed* pk) {
   float* vz = reinterpret_cast<float*>(pk->bytes.data() + pk->off_vz);
   I2* edges = reinterpret_cast<I2*>(pk->bytes.data() + pk->off_edges);
   int32_t pb = 0, vb = 0, eb = 0;
+  std::vector<int32_t> vbase(size_t(pk->K) + 1, 0);  // object-level first vertex of each piece
+  for (int32_t k = 0; k < pk->K; ++k) vbase[size_t(k) + 1] = vbase[size_t(k)] + int32_t(o.pieces[size_t(k)].n_verts());
   double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
   for (int32_t k = 0; k < pk->K; ++k) {
     const PieceGeom& g = o.pieces[size_t(k)];
@@ -154,7 +163,8 @@ static void pack_object(const ObjHost& o, const cm_params& prm, Packed* pk) {
     d.cx = float(c[0]); d.cy = float(c[1]); d.cz = float(c[2]);
     d.plane_begin = pb; d.plane_count = int32_t(g.n_planes());
     d.vert_begin = vb; d.vert_count = int32_t(g.n_verts());
-    d.edge_begin = eb; d.edge_count = int32_t(g.n_edges());
+    const std::vector<int32_t>& xe = o.xedges[size_t(k)];
+    d.edge_begin = eb; d.edge_count = int32_t(g.n_edges() + xe.size() / 2);
     // the centre as stored in FP32 is the one the kernels subtract
     const double cf[3] = {double(d.cx), double(d.cy), double(d.cz)};
     double rin = 1e300;
@@ -196,6 +206,13 @@ static void pack_object(const ObjHost& o, const cm_params& prm, Packed* pk) {
     }
     for (size_t e = 0; e < g.n_edges(); ++e)
       edges[eb + int32_t(e)] = I2{vb + g.edges[2 * e], vb + g.edges[2 * e + 1]};
+    // crossing edges of other pieces (Sec. IV-D.1), after the piece's own
+    for (size_t x = 0; x < xe.size() / 2; ++x) {
+      const PieceGeom& gk = o.pieces[size_t(xe[2 * x])];
+      const size_t e = size_t(xe[2 * x + 1]);
+      const int32_t vk = vbase[size_t(xe[2 * x])];
+      edges[eb + int32_t(g.n_edges() + x)] = I2{vk + gk.edges[2 * e], vk + gk.edges[2 * e + 1]};
+    }
     pb += d.plane_count; vb += d.vert_count; eb += d.edge_count;
   }
   // voxel grid over the vertex AABB grown by margin + margin_rel * radius
@@ -206,6 +223,8 @@ static void pack_object(const ObjHost& o, const cm_params& prm, Packed* pk) {
     const double h = (hi[a] - lo[a] + 2 * margin) / gn;
     pk->gorg[a] = float(org);
     pk->gh[a] = float(h);
+    pk->gorg64[a] = org;
+    pk->gh64[a] = h;
     pk->ginv[a] = float(1.0 / h);
     r2 += h * h;
   }
@@ -227,22 +246,67 @@ static ObjDesc make_desc(const Packed& pk, char* base) {
   for (int a = 0; a < 3; ++a) { d.gorg[a] = pk.gorg[a]; d.gh[a] = pk.gh[a]; d.ginv[a] = pk.ginv[a]; }
   d.gr = pk.gr;
   d.gn = pk.gn;
+  d.rep = pk.rep;
+  if (pk.rep == kRepSpline) d.sub = reinterpret_cast<const F4*>(base + pk.off_coef);
   return d;
 }
 
+// Edge assignment (Sec. IV-D.1): an edge belongs to every convex piece it
+// intersects.  Besides its own piece, edge e of piece k joins piece j when the
+// segment, clipped by j's half-spaces (parameter interval [t_in, t_out] of
+// a + t (b - a)), keeps a part longer than 1e-9 of the object's scale.
+static void cross_edges(ObjHost& o) {
+  double scale = 1e-300;
+  for (const PieceGeom& g : o.pieces)
+    for (double v : g.verts) scale = std::max(scale, std::fabs(v));
+  const double tol = 1e-9 * scale;
+  o.xedges.assign(o.pieces.size(), {});
+  for (size_t j = 0; j < o.pieces.size(); ++j) {
+    const PieceGeom& pj = o.pieces[j];
+    for (size_t k = 0; k < o.pieces.size(); ++k) {
+      if (k == j) continue;
+      const PieceGeom& pk = o.pieces[k];
+      for (size_t e = 0; e < pk.n_edges(); ++e) {
+        const double* a = &pk.verts[3 * size_t(pk.edges[2 * e])];
+        const double* b = &pk.verts[3 * size_t(pk.edges[2 * e + 1])];
+        double t_in = 0.0, t_out = 1.0;
+        bool miss = false;
+        for (size_t i = 0; i < pj.n_planes() && !miss; ++i) {
+          const double* q = &pj.planes[4 * i];
+          const double fa = q[0] * a[0] + q[1] * a[1] + q[2] * a[2] + q[3];
+          const double fb = q[0] * b[0] + q[1] * b[1] + q[2] * b[2] + q[3];
+          if (fa > 0 && fb > 0) miss = true;
+          else if (fa > 0) t_in = std::max(t_in, fa / (fa - fb));
+          else if (fb > 0) t_out = std::min(t_out, fa / (fa - fb));
+        }
+        if (miss) continue;
+        const double L = std::sqrt((b[0] - a[0]) * (b[0] - a[0]) + (b[1] - a[1]) * (b[1] - a[1]) +
+                                   (b[2] - a[2]) * (b[2] - a[2]));
+        if ((t_out - t_in) * L > tol) {
+          o.xedges[j].push_back(int32_t(k));
+          o.xedges[j].push_back(int32_t(e));
+        }
+      }
+    }
+  }
+}
+
 // Fills the derived host data of an object whose pieces are set.
-static void finish_host(ObjHost& o) {
+static void finish_host(ObjHost& o, bool assign_crossing) {
+  if (assign_crossing) cross_edges(o);
+  else o.xedges.assign(o.pieces.size(), {});
   o.n_planes = o.n_verts = o.n_edges = 0;
   o.radius = 0;
   o.centres.assign(3 * o.pieces.size(), 0.0);
   o.counts.assign(2 * o.pieces.size(), 0);
   for (size_t k = 0; k < o.pieces.size(); ++k) {
     const PieceGeom& g = o.pieces[k];
+    const int32_t nx = int32_t(o.xedges[k].size() / 2);
     o.counts[2 * k] = int32_t(g.n_verts());
-    o.counts[2 * k + 1] = int32_t(g.n_edges());
+    o.counts[2 * k + 1] = int32_t(g.n_edges()) + nx;
     o.n_planes += int64_t(g.n_planes());
     o.n_verts += int64_t(g.n_verts());
-    o.n_edges += int64_t(g.n_edges());
+    o.n_edges += int64_t(g.n_edges()) + nx;
     double c[3] = {0, 0, 0};
     for (size_t i = 0; i < g.n_verts(); ++i) {
       for (int a = 0; a < 3; ++a) c[a] += g.verts[3 * i + size_t(a)];
@@ -251,6 +315,76 @@ static void finish_host(ObjHost& o) {
     }
     for (int a = 0; a < 3; ++a) o.centres[3 * k + size_t(a)] = g.n_verts() ? c[a] / double(g.n_verts()) : 0.0;
   }
+}
+
+// Spline fits of freshly registered objects (Sec. III-B), on the device in
+// chunks: their FP64 collision geometry (planes, feature edges as segments) is
+// uploaded to scratch, the fit writes the coefficients and cell bounds into each
+// object's memory, and the scratch is freed.
+static cm_status fit_splines(cm_context* ctx, const std::vector<Packed>& packs, const std::vector<int32_t>& ids) {
+  const int n = ctx->prm.grid_res, m = n + 3;
+  const int64_t stride = 4 * int64_t(m) * m * m;
+  const size_t chunk = 64;
+  for (size_t c0 = 0; c0 < ids.size(); c0 += chunk) {
+    const size_t cn = std::min(chunk, ids.size() - c0);
+    std::vector<double> planes, segs;
+    std::vector<int32_t> pieces;  // int4 per piece
+    std::vector<size_t> pl_off(cn), pc_off(cn), sg_off(cn);
+    for (size_t i = 0; i < cn; ++i) {
+      const ObjHost& o = ctx->objs[size_t(ids[c0 + i])];
+      pl_off[i] = planes.size();
+      pc_off[i] = pieces.size();
+      sg_off[i] = segs.size();
+      int32_t pb = 0, eb = 0;
+      for (const PieceGeom& g : o.pieces) {
+        planes.insert(planes.end(), g.planes.begin(), g.planes.end());
+        for (size_t e = 0; e < g.n_edges(); ++e)
+          for (int k = 0; k < 2; ++k)
+            for (int a = 0; a < 3; ++a) segs.push_back(g.verts[3 * size_t(g.edges[2 * e + size_t(k)]) + size_t(a)]);
+        pieces.insert(pieces.end(), {pb, int32_t(g.n_planes()), eb, int32_t(g.n_edges())});
+        pb += int32_t(g.n_planes());
+        eb += int32_t(g.n_edges());
+      }
+    }
+    const size_t b_pl = align_up(8 * planes.size(), 256), b_sg = align_up(8 * segs.size(), 256);
+    const size_t b_pc = align_up(4 * pieces.size(), 256), b_job = align_up(sizeof(SplJob) * cn, 256);
+    const size_t b_work = 8 * size_t(stride) * cn;
+    char* d = nullptr;
+    if (hipMalloc(&d, b_pl + b_sg + b_pc + b_job + 2 * b_work) != hipSuccess)
+      return fail(ctx, CM_E_OOM, "spline fit scratch allocation failed");
+    double* d_pl = reinterpret_cast<double*>(d);
+    double* d_sg = reinterpret_cast<double*>(d + b_pl);
+    int32_t* d_pc = reinterpret_cast<int32_t*>(d + b_pl + b_sg);
+    SplJob* d_job = reinterpret_cast<SplJob*>(d + b_pl + b_sg + b_pc);
+    double* wa = reinterpret_cast<double*>(d + b_pl + b_sg + b_pc + b_job);
+    double* wb = wa + stride * int64_t(cn);
+    std::vector<SplJob> jobs(cn);
+    for (size_t i = 0; i < cn; ++i) {
+      const ObjHost& o = ctx->objs[size_t(ids[c0 + i])];
+      const Packed& pk = packs[c0 + i];
+      SplJob& j = jobs[i];
+      j.planes = d_pl + pl_off[i];
+      j.pieces = reinterpret_cast<const int4*>(d_pc + pc_off[i]);
+      j.segs = d_sg + sg_off[i];
+      j.n_pieces = int32_t(o.pieces.size());
+      j.pad = 0;
+      for (int a = 0; a < 3; ++a) { j.org[a] = pk.gorg64[a]; j.h[a] = pk.gh64[a]; }
+      j.coef = const_cast<F4*>(o.desc.sub);
+      j.grid = const_cast<float*>(o.desc.grid);
+    }
+    hipError_t e = hipMemcpyAsync(d_pl, planes.data(), 8 * planes.size(), hipMemcpyHostToDevice, ctx->build_stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(d_sg, segs.data(), 8 * segs.size(), hipMemcpyHostToDevice, ctx->build_stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(d_pc, pieces.data(), 4 * pieces.size(), hipMemcpyHostToDevice, ctx->build_stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(d_job, jobs.data(), sizeof(SplJob) * cn, hipMemcpyHostToDevice, ctx->build_stream);
+    if (e == hipSuccess) e = launch_spline_build(d_job, int(cn), n, wa, wb, stride, ctx->build_stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->build_stream);
+    (void)hipFree(d);
+    if (e != hipSuccess) return hip_fail(ctx, e, "spline fit");
+  }
+  return CM_OK;
 }
 
 // Uploads host-built objects, refreshes the device table and builds their grids.
@@ -340,6 +474,7 @@ static cm_status register_objects(cm_context* ctx, std::vector<ObjHost>& built, 
   hipError_t e = hipStreamSynchronize(ctx->build_stream);
   (void)hipFree(d_ids);
   if (e != hipSuccess) return hip_fail(ctx, e, "grid build");
+  if (ctx->prm.sdf_kind == 1) return fit_splines(ctx, packs, ids);
   return CM_OK;
 }
 
@@ -434,7 +569,7 @@ cm_status cm_build_objects(cm_context* ctx, int32_t n_objects, const int64_t* ob
             if (st != 0) { status = st; break; }
             serialize_piece(&g, ctx->prm.curve);
           }
-          finish_host(o);
+          finish_host(o, ctx->prm.edge_assign != 0);
         }
       });
     for (auto& t : th) t.join();
@@ -478,7 +613,7 @@ cm_status cm_build_pieces_raw(cm_context* ctx, int32_t n_pieces, const int64_t* 
     }
     serialize_piece(&g, ctx->prm.curve);
   }
-  finish_host(o);
+  finish_host(o, ctx->prm.edge_assign != 0);
   return register_objects(ctx, built, out);
 }
 
@@ -532,6 +667,25 @@ cm_status cm_object_export(cm_context* ctx, cm_object obj, int64_t* plane_off, d
   return CM_OK;
 }
 
+cm_status cm_object_spline(cm_context* ctx, cm_object obj, float* coef, float* meta) {
+  if (!ctx || !meta) return fail(ctx, CM_E_INVALID, "null argument");
+  ObjHost* o;
+  {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    o = get_obj(ctx, obj);
+    if (!o) { ctx->err = "unknown object"; return CM_E_NOTFOUND; }
+  }
+  if (ctx->prm.sdf_kind != 1 || ctx->device < 0) return fail(ctx, CM_E_INVALID, "not a spline object on a device");
+  const int n = o->desc.gn;
+  meta[0] = float(n);
+  for (int a = 0; a < 3; ++a) { meta[1 + a] = o->desc.gorg[a]; meta[4 + a] = o->desc.gh[a]; }
+  if (coef) {
+    const size_t m = size_t(n) + 3;
+    CM_HIP(ctx, hipMemcpy(coef, o->desc.sub, 16 * m * m * m, hipMemcpyDeviceToHost));
+  }
+  return CM_OK;
+}
+
 cm_status cm_object_grid(cm_context* ctx, cm_object obj, float* G, float* meta) {
   if (!ctx) return CM_E_INVALID;
   ObjDesc d;
@@ -555,6 +709,12 @@ cm_status cm_object_grid(cm_context* ctx, cm_object obj, float* G, float* meta) 
 }  // extern "C"
 
 namespace cm {
+
+// Terms of one SDF evaluation against an object: its planes, or the 64
+// coefficients of a spline evaluation.
+static double sdf_terms(const cm_context* ctx, const ObjHost& o) {
+  return ctx->prm.sdf_kind == 1 ? 64.0 : double(o.n_planes);
+}
 
 // Host tables of a plan (entries sorted by estimated cost, group -> entries)
 // and the size of its device scratch.  Takes ctx->mu.
@@ -618,7 +778,7 @@ cm_status plan_host(cm_context* ctx, const cm_query* hq, int32_t n, cm_plan* pl,
             pl->W += (e.count + kWave - 1) / kWave;
             cbase += e.count;
             gen.push_back(e);
-            cost.push_back(double(e.count) * double(So->n_planes) * (kind ? K2 : 1));
+            cost.push_back(double(e.count) * sdf_terms(ctx, *So) * (kind ? K2 : 1));
           }
         }
       }
@@ -721,7 +881,9 @@ size_t plan_layout(cm_plan* pl, char* b) {
   const int64_t tape_slot_bytes = int64_t(std::max(pl->tape_kind, 1) * 4 * tape_values(st));
   const int64_t budget_tiles = int64_t(pl->ctx->budget / 4) / (tape_slot_bytes * kWave);
   const int64_t want_tiles = std::min<int64_t>(W, W / 4 + pl->R);
-  pl->tape_tiles = (st <= kMaxTraceAdj && pl->tape_kind > 0) ? std::min<int64_t>(want_tiles, budget_tiles) : 0;
+  // (spline SDFs keep no tape: an evaluation is 64 gathers, cheap to repeat)
+  pl->tape_tiles = (st <= kMaxTraceAdj && pl->tape_kind > 0 && pl->ctx->prm.sdf_kind == 0)
+                       ? std::min<int64_t>(want_tiles, budget_tiles) : 0;
   const size_t o_tape = take(size_t(tape_slot_bytes) * kWave * size_t(pl->tape_tiles));
   if (b) {
     pl->d_ents = reinterpret_cast<Entry*>(b + o_ents);
@@ -869,7 +1031,7 @@ cm_status cm_plan_stats(const cm_plan* pl, int64_t* st) {  // 8 entries
   }
   for (size_t i = 0; i < ns.size(); ++i) {
     const Entry& e = pl->ents[i];
-    const double P = double(pl->ctx->objs[size_t(e.sdf_obj)].n_planes);
+    const double P = sdf_terms(pl->ctx, pl->ctx->objs[size_t(e.sdf_obj)]);
     if (e.kind == 0) { sv += ns[i]; nv += e.count; pairs += double(ns[i]) * P; vpairs += double(ns[i]) * P; }
     else { se += ns[i]; ne += e.count; pairs += double(ns[i]) * P * K2; epairs += double(ns[i]) * P; }
   }
@@ -924,6 +1086,7 @@ FwdArgs fwd_args(cm_context* ctx, cm_plan* pl, const cm_query* q, const cm_group
   a.tape = pl->d_tape;
   a.tape_tiles = pl->d_tape ? pl->tape_tiles : 0;
   a.tape_nv = tape_values(ctx->prm.st_iters);
+  a.rep = ctx->prm.sdf_kind == 1 ? kRepSpline : kRepPlanes;
   return a;
 }
 }  // namespace cm
@@ -984,6 +1147,20 @@ cm_status cm_contacts_jvp(cm_context* ctx, cm_plan* pl, const cm_query* q, cm_gr
   pl->timed_mask = (1u << kTBroad) | (1u << kTNarrowTan);
   hipError_t e = launch_jvp(a, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(ctx, e, "jvp launch");
+  return CM_OK;
+}
+
+cm_status cm_project_points(cm_context* ctx, cm_plan* pl, const cm_query* q, const float* p_in, float* p_out,
+                            void* stream) {
+  if (!ctx || !pl || pl->ctx != ctx || !q || !p_in || !p_out) return fail(ctx, CM_E_INVALID, "bad arguments");
+  const ObjDesc* objs;
+  {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    objs = ctx->d_objs;
+  }
+  hipError_t e = launch_project(reinterpret_cast<const QueryDev*>(q), objs, pl->d_group_off, pl->n, ctx->dp, p_in,
+                                p_out, pl->G, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(ctx, e, "projection launch");
   return CM_OK;
 }
 

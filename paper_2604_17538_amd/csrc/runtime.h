@@ -46,7 +46,10 @@ struct ObjHost {
   bool alive = false;
   std::vector<PieceGeom> pieces;
   std::vector<double> centres;  // 3 per piece
-  std::vector<int32_t> counts;  // per piece: vertices, edges (compact, for planning)
+  std::vector<int32_t> counts;  // per piece: vertices, edges incl. crossing edges (compact, for planning)
+  // per piece: edges of other pieces that cross it, as (piece, edge) pairs
+  // (edge assignment of Sec. IV-D.1; empty unless cm_params.edge_assign)
+  std::vector<std::vector<int32_t>> xedges;
   int64_t n_planes = 0, n_verts = 0, n_edges = 0;
   double radius = 0;
   void* dmem = nullptr;
