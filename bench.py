@@ -260,6 +260,121 @@ def sweep_leg(reps=10):
     return {"pair_queries": n, "x_extent_A": round(ext, 5), "translation_factors": [1.0, 2.0], "rows": rows}
 
 
+def curve_study_leg(n_pairs=1024, reps=5):
+    """Serialization study (Sec. IV-C.3): the vertices and edges of each piece
+    ordered along no curve, a Morton (Z-order) curve or a Hilbert curve.  For the
+    8-piece workload: the fraction of mixed chunks (consecutive contacts of one
+    piece and kind, 32 or 64 at a time, that the broad phase partly accepts and
+    partly filters: the divergence the paper's ordering targets), and the broad
+    and narrow phase times of the forward pass (events on the launch stream)."""
+    import torch
+    from paper_2604_17538_amd import api, workloads as W
+    w = W.config1(n_envs=n_pairs)
+    stream = torch.cuda.current_stream()
+    rows = []
+    for curve, name in ((0, "none"), (1, "morton"), (2, "hilbert")):
+        ctx = api.Context(0, L_ref=w.L_ref, curve=curve)
+        hs = ctx.build_objects(w.objects)
+        plan = ctx.plan(hs[w.qa], hs[w.qb])
+        qd = plan.device_queries(w.poses)
+        out, dbg = plan.forward(qd, debug=True, stream=stream)
+        torch.cuda.synchronize()
+        mask = dbg[0].cpu().numpy() > 0.5
+        # segment boundaries: per query, A's pieces then B's; per piece vertices then edges
+        ex = {}
+        seg_len = []
+        for a, b in zip(w.qa, w.qb):
+            for j in (a, b):
+                if j not in ex:
+                    e = ctx.object_export(hs[j])
+                    ex[j] = np.stack([np.diff(e["vert_off"]), np.diff(e["edge_off"])], 1).ravel()
+                seg_len.append(ex[j])
+        seg_len = np.concatenate(seg_len)
+        seg = np.repeat(np.arange(len(seg_len)), seg_len)
+        pos = np.arange(len(seg)) - np.repeat(np.cumsum(seg_len) - seg_len, seg_len)
+        res = {"curve": name}
+        for width in (32, 64):
+            key = seg.astype(np.int64) * 1_000_000 + pos // width
+            _, inv = np.unique(key, return_inverse=True)
+            acc = np.bincount(inv, weights=mask.astype(np.float64))
+            cnt = np.bincount(inv)
+            mixed = (acc > 0) & (acc < cnt)
+            res["mixed_chunks_%d" % width] = round(float(mixed.mean()), 4)
+        plan.set_timing(True)
+        tb, tn = [], []
+        for _ in range(reps):
+            plan.forward(qd, out=out, stream=stream)
+            torch.cuda.synchronize()
+            t = plan.timing()
+            tb.append(t["broad"])
+            tn.append(t["narrow_fwd"])
+        res.update(broad_ms=round(float(np.median(tb)), 4), narrow_ms=round(float(np.median(tn)), 4),
+                   survivors=round(float(mask.mean()), 4))
+        rows.append(res)
+        log("curve study %s" % res)
+        del plan, ctx, dbg
+        torch.cuda.empty_cache()
+    return {"workload": "c1: %d pair-queries of 8-piece objects, forward" % n_pairs, "rows": rows}
+
+
+def spline_leg(n_pairs=2048, reps=5):
+    """The spline SDF representation (Sec. III-B) on the 8-piece workload:
+    every object's SDF a cubic spline over a 32^3-cell box (with a fitted normal
+    spline), fitted on the device at registration.  Times the forward records
+    and the step (records + gradient + H v) of the batch, beside the plane
+    representation on the same batch; a spline evaluation gathers 64
+    coefficients of 16 bytes."""
+    import torch
+    from paper_2604_17538_amd import api, workloads as W
+    w = W.config1(n_envs=n_pairs)
+    stream = torch.cuda.current_stream()
+    out = {"workload": "c1: %d pair-queries of 8-piece objects" % n_pairs}
+    for name, kw in (("spline", dict(sdf_kind=1, grid_margin_rel=0.0)), ("planes", {})):
+        ctx = api.Context(0, L_ref=w.L_ref, **kw)
+        torch.cuda.synchronize()
+        t0 = time.time()
+        hs = ctx.build_objects(w.objects)
+        torch.cuda.synchronize()
+        t_build = time.time() - t0
+        plan = ctx.plan(hs[w.qa], hs[w.qb])
+        qd = plan.device_queries(w.poses)
+        cot = torch.tensor(np.ascontiguousarray(W.cotangents(5, plan.G).T, np.float32)).cuda()
+        direc = torch.tensor(W.directions(5, w.n).astype(np.float32)).cuda()
+        o = plan.forward(qd, stream=stream)
+        res = {}
+        for what, fn in (("forward", lambda: plan.forward(qd, out=o, stream=stream)),
+                         ("step", lambda: plan.step(qd, cot, direc, stream=stream))):
+            fn()
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            for _ in range(reps):
+                fn()
+            b.record(stream)
+            torch.cuda.synchronize()
+            ms = a.elapsed_time(b) / reps
+            res[what + "_ms"] = round(ms, 3)
+            res[what + "_value"] = round(w.n / (ms * 1e-3), 1)
+        plan.set_timing(True)
+        plan.forward(qd, out=o, stream=stream)
+        torch.cuda.synchronize()
+        k_ms = plan.timing()["narrow_fwd"]
+        wv, we = plan.work()
+        plan.set_timing(False)
+        st = plan.stats()
+        res.update(build_s=round(t_build, 2), narrow_fwd_ms=round(k_ms, 3),
+                   surviving_contacts=st["surv_verts"] + st["surv_edges"])
+        if name == "spline":
+            evals = (wv + we) / 64
+            res.update(evaluations=int(evals), evaluations_per_s=round(evals / (k_ms * 1e-3), 1),
+                       gather_GBps=round(evals * 64 * 16 / (k_ms * 1e-3) / 1e9, 1))
+        out[name] = res
+        log("spline leg %s %s" % (name, res))
+        del plan, ctx
+        torch.cuda.empty_cache()
+    return out
+
+
 def golden_c4():
     """Stored FP64 oracle values of sampled queries of the large workload."""
     path = os.path.join(HERE, "tests", "golden", "c4_oracle.json")
@@ -371,9 +486,12 @@ def step_leg(api, W, config, pairs, budget_gb, args, steps, warmup, golden=None,
     wall = time.time() - t_wall
     ms = e0.elapsed_time(e1) / steps
     log("timed %d steps: %.2f ms/step (wall %.2f s)" % (steps, ms, wall))
+    # the step's outputs (every timed step gives the same), kept apart from the
+    # buffers the other legs reuse
+    step_out = (out.clone(), grad.clone(), hv.clone())
     res = dict(w=w, ctx=ctx, hs=hs, plan=plan, qd=qd, cot=cot, direc=direc, cot_d=cot_d, dir_d=dir_d,
                out=out, grad=grad, hv=hv, ms=ms, wall=wall, shape=shape, shape_f=shape_f, tuned_on=tuned_on,
-               step=step, timed=timed, stream=stream)
+               step=step, timed=timed, stream=stream, step_out=step_out)
     # the step's outputs now are those of every timed step (deterministic launches)
     if golden is not None:
         sel = np.array(golden["sel"], np.int64)
@@ -471,8 +589,9 @@ def step_leg(api, W, config, pairs, budget_gb, args, steps, warmup, golden=None,
 
         pms = timed(plain_pass, 1)
         # the plain launches give the same results as the batched step (bitwise)
-        same = all(torch.equal(o1, out[:, plan.group_off[i]:plan.group_off[i + 1]]) and torch.equal(gr1[0], grad[i])
-                   and torch.equal(hv1[0], hv[i]) for i, (p1, q1, c1, d1, o1, gr1, hv1) in enumerate(plans))
+        so, sg, sh = step_out
+        same = all(torch.equal(o1, so[:, plan.group_off[i]:plan.group_off[i + 1]]) and torch.equal(gr1[0], sg[i])
+                   and torch.equal(hv1[0], sh[i]) for i, (p1, q1, c1, d1, o1, gr1, hv1) in enumerate(plans))
         step()
         torch.cuda.synchronize()
         res["plain"] = {"sample": ns, "ms": round(pms, 3), "value": round(ns / (pms * 1e-3), 1),
@@ -506,6 +625,9 @@ def main():
                     help="autotune on a plan of the first N pair-queries when the batch is larger")
     ap.add_argument("--sweep", action="store_true",
                     help="only the broad-phase sweep (broad + narrow vs narrow only over d_max); prints its own JSON line")
+    ap.add_argument("--no-spline", action="store_true", help="skip the spline-representation leg")
+    ap.add_argument("--curve-study", action="store_true",
+                    help="only the serialization study (no curve / Morton / Hilbert); prints its own JSON line")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a device copy of 1 GiB three times (scale of the HBM traffic counters)")
     ap.add_argument("--serve-rates", default="2000,5000,10000,20000", help="Poisson request rates (req/s)")
@@ -538,6 +660,9 @@ def main():
     from paper_2604_17538_amd import api, workloads as W
     if args.sweep:
         print(json.dumps({"sweep": sweep_leg()}), flush=True)
+        return
+    if args.curve_study:
+        print(json.dumps({"curve_study": curve_study_leg()}), flush=True)
         return
 
     cfg = args.config
@@ -578,9 +703,9 @@ def main():
         log("tight edge bound %s" % tight)
         del plan_t, qd_t, ctx_t, o_t, g_t, h_t
 
-    out_h = r["out"].cpu().numpy().T.astype(np.float64)
-    grad_h = r["grad"].cpu().numpy().astype(np.float64)
-    hv_h = r["hv"].cpu().numpy().astype(np.float64)
+    out_h = r["step_out"][0].cpu().numpy().T.astype(np.float64)
+    grad_h = r["step_out"][1].cpu().numpy().astype(np.float64)
+    hv_h = r["step_out"][2].cpu().numpy().astype(np.float64)
     config_line = {"workload": "%s: %d pair-queries, forward + gradient (both poses) + HVP per step" % (cfg, w.n),
                    "pair_queries": w.n, "groups": plan.G, "contacts": plan.C, "step": "cm_contacts_step",
                    "budget_gb": budget_gb}
@@ -611,6 +736,10 @@ def main():
         log("secondary %s" % secondary)
         del r2
         torch.cuda.empty_cache()
+
+    spline = None
+    if not args.no_spline:
+        spline = spline_leg()
 
     serving = None
     if not args.no_serving:
@@ -657,7 +786,7 @@ def main():
     }
     line.update(line_extra)
     line.update({"roofline": roofline, "cpu_baseline": cpu, "plain_launch": plain, "parity": parity,
-                 "secondary": secondary, "serving": serving})
+                 "secondary": secondary, "spline": spline, "serving": serving})
     if plain:
         line["vs_plain_launch"] = round(value / plain["value"], 2)
     print(json.dumps(line), flush=True)
