@@ -43,7 +43,8 @@ class Params(ctypes.Structure):
                 ("tau_cap", "tau_cup", "tau_st", "tau_clip", "tau_blend", "d_max", "eps_t", "eps_n",
                  "grid_margin", "grid_margin_rel")] + \
                [(n, ctypes.c_int32) for n in ("st_iters", "grid_res", "broad_phase", "edge_bound")] + \
-               [("jitter", ctypes.c_double), ("jitter_seed", ctypes.c_int32), ("pad_", ctypes.c_int32)]
+               [("jitter", ctypes.c_double), ("jitter_seed", ctypes.c_int32), ("pad_", ctypes.c_int32)] + \
+               [("tau_t", ctypes.c_double), ("tau_disc", ctypes.c_double)]
 
 
 def default_params(L_ref: float = 0.1, broad_phase: bool = True, **kw) -> Params:
@@ -53,11 +54,13 @@ def default_params(L_ref: float = 0.1, broad_phase: bool = True, **kw) -> Params
     tau_b = 0.02 L_ref; d_max = 0.05 L_ref; eps_t = 0.025 L_ref; eps_n = 1e-6;
     K = 3 sphere-trace steps; 32^3 voxel grid over the vertex AABB grown by
     0.1 L_ref + 1.0 * (object radius); the paper's min-form edge bound.
+    Primitive SDFs: tau_t = 0.01 (soft clip of the spline parameter to (0, 1)),
+    tau_disc = 1e-3 (softplus and sigmoid of the cubic's discriminant).
     """
     p = Params(tau_cap=0.01 * L_ref, tau_cup=0.01 * L_ref, tau_st=0.01 * L_ref, tau_clip=0.01 * L_ref,
                tau_blend=0.02 * L_ref, d_max=0.05 * L_ref, eps_t=0.025 * L_ref, eps_n=1e-6,
                grid_margin=0.1 * L_ref, grid_margin_rel=1.0, st_iters=3, grid_res=32,
-               broad_phase=int(broad_phase), edge_bound=0)
+               broad_phase=int(broad_phase), edge_bound=0, tau_t=0.01, tau_disc=1e-3)
     for k, v in kw.items():
         setattr(p, k, v)
     return p
@@ -101,6 +104,9 @@ def lib():
         L.orc_ground_truth.argtypes = [I32, I64, P, P]
         L.orc_spline_operator.argtypes = [I32, P]
         L.orc_spline_from_values.argtypes = [I32, P, P, P, I64, P, P, P, P]
+        L.orc_object_set_prims.argtypes = [I32, I32, P, P, P]
+        L.orc_prims_eval.argtypes = [I32, P, I64, P, P, P]
+        L.orc_xpsq_roots.argtypes = [I32, I32, P, I64, P, P]
         _lib = L
     return _lib
 
@@ -182,6 +188,30 @@ class Obj:
         self.tri_off = _c(tri_off, np.int64)
         self.tris = _c(tris, np.float64).reshape(-1, 9)
         lib().orc_object_set_tris(self.h, _p(self.tri_off), _p(self.tris))
+
+    def set_prims(self, rec, plane_off, planes):
+        """The object's SDF side becomes primitives (Sec. III-A): rec [n, 32]
+        records (see orc_object_set_prims), half-spaces planes[plane_off[i]:
+        plane_off[i + 1]] [*, 4] in each PSQ frame.  Its pieces stay the mesh side."""
+        self.prim_rec = _c(rec, np.float64).reshape(-1, 32)
+        self.prim_plane_off = _c(plane_off, np.int64)
+        self.prim_planes = _c(planes, np.float64).reshape(-1, 4)
+        lib().orc_object_set_prims(self.h, len(self.prim_rec), _p(self.prim_rec), _p(self.prim_plane_off),
+                                   _p(self.prim_planes))
+
+    def prims_eval(self, prm: Params, x):
+        """Primitive SDF phi [n] and its gradient [n, 3] at object-frame points."""
+        x = _c(x, np.float64).reshape(-1, 3)
+        phi, g = np.zeros(len(x)), np.zeros((len(x), 3))
+        lib().orc_prims_eval(self.h, ctypes.byref(prm), len(x), _p(x), _p(phi), _p(g))
+        return phi, g
+
+    def xpsq_roots(self, prm: Params, k: int, x):
+        """The three projection parameters t* [n, 3] of primitive k (an XPSQ)."""
+        x = _c(x, np.float64).reshape(-1, 3)
+        t = np.zeros((len(x), 3))
+        lib().orc_xpsq_roots(self.h, int(k), ctypes.byref(prm), len(x), _p(x), _p(t))
+        return t
 
     def build_spline(self, prm: Params):
         """Fits the cubic-spline SDF and normal (Sec. III-B) over the object's

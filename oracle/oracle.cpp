@@ -93,6 +93,21 @@ ORC_DUAL inline Dual<T, N> log1p(const Dual<T, N>& a) {
   Dual<T, N> r; r.v = log1p(a.v); T inv = T(1.0) / (a.v + 1.0); for (int i = 0; i < N; ++i) r.d[i] = a.d[i] * inv; return r; }
 ORC_DUAL inline Dual<T, N> sqrt(const Dual<T, N>& a) {
   Dual<T, N> r; r.v = sqrt(a.v); T inv = T(0.5) / r.v; for (int i = 0; i < N; ++i) r.d[i] = a.d[i] * inv; return r; }
+using std::cbrt; using std::cos; using std::sin; using std::atan2;
+// cbrt'(v) = 1 / (3 cbrt(v)^2); cos' = -sin; sin' = cos
+ORC_DUAL inline Dual<T, N> cbrt(const Dual<T, N>& a) {
+  Dual<T, N> r; r.v = cbrt(a.v); T inv = T(1.0) / (r.v * r.v * 3.0); for (int i = 0; i < N; ++i) r.d[i] = a.d[i] * inv; return r; }
+ORC_DUAL inline Dual<T, N> cos(const Dual<T, N>& a) {
+  Dual<T, N> r; r.v = cos(a.v); T m = -sin(a.v); for (int i = 0; i < N; ++i) r.d[i] = a.d[i] * m; return r; }
+ORC_DUAL inline Dual<T, N> sin(const Dual<T, N>& a) {
+  Dual<T, N> r; r.v = sin(a.v); T m = cos(a.v); for (int i = 0; i < N; ++i) r.d[i] = a.d[i] * m; return r; }
+// atan2(y, x): d = (x dy - y dx) / (x^2 + y^2)
+ORC_DUAL inline Dual<T, N> atan2(const Dual<T, N>& y, const Dual<T, N>& x) {
+  Dual<T, N> r; r.v = atan2(y.v, x.v); T inv = T(1.0) / (x.v * x.v + y.v * y.v);
+  for (int i = 0; i < N; ++i) r.d[i] = (x.v * y.d[i] - y.v * x.d[i]) * inv;
+  return r; }
+// x^e = exp(e log x) (x > 0)
+template <class T, class E> inline T powr(const T& x, const E& e) { return exp(e * log(x)); }
 
 // ----------------------------------------------------------------- vectors --
 template <class T> struct V3 { T x, y, z; };
@@ -138,6 +153,10 @@ struct Params {
   double jitter;        // FP32 conditioning probe: relative size of the injected perturbations (0: off)
   int32_t jitter_seed;  // its seed
   int32_t pad_;
+  // primitive SDFs: temperature of the soft clip of the spline parameter t to
+  // (0, 1), and of the softplus / sigmoid of the cubic's discriminant (both
+  // dimensionless)
+  double tau_t, tau_disc;
 };
 
 // ------------------------------------------------ FP32 conditioning probe --
@@ -204,11 +223,23 @@ struct Spline {
   double a[3] = {0, 0, 0}, h[3] = {0, 0, 0};
   std::vector<double> c[4];
 };
+// A primitive of the primitive-based SDF representation (Sec. III-A.1, 3-5).
+struct Prim {
+  int kind = 0;  // 0: PSQ at a fixed pose; 1: XPSQ (a PSQ swept along a quadratic spline)
+  int op = 0;    // how it joins the primitives before it: 0 union, 1 subtraction, 2 intersection
+  double c[3] = {0, 0, 0}, R[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};  // PSQ: centre, rotation (PSQ -> object)
+  double p[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};                      // XPSQ: control points p1, p2, p3
+  double a0[3] = {1, 1, 1}, a1[3] = {1, 1, 1};  // SQ scales at t = 0 and t = 1 (PSQ: a0)
+  double e0[2] = {1, 1}, e1[2] = {1, 1};        // SQ exponents (eps1, eps2) at t = 0 and t = 1
+  std::vector<double> planes;                   // 4 per half-space (n, h) in the PSQ frame
+};
 struct Object {
   std::vector<Piece> pieces;
   Grid grid;
   bool has_spline = false;
   Spline spl;
+  bool has_prims = false;  // SDF side: the primitives (the pieces stay the mesh side)
+  std::vector<Prim> prims;
 };
 
 std::mutex g_mu;
@@ -309,6 +340,145 @@ template <class T> T softplus(const T& x, double tau) {
 // Sec. II: s_clip(x, a, b) = a + s_+(x - a) - s_+(x - b).
 template <class T> T softclip(const T& x, const T& a, const T& b, double tau) {
   return a + softplus(x - a, tau) - softplus(x - b, tau);
+}
+
+// ------------------------------------------------------ primitive SDFs --
+// Regulariser of the superquadric's powers: every squared coordinate q^2 enters
+// as q^2 + delta^2 (q relative to its scale), so that each power is smooth on the
+// coordinate planes; the radius as sqrt(|x|^2 + (delta a_min)^2).
+constexpr double kSqDelta = 1e-3;
+
+// Superquadric (Sec. III-A.1): f(x) = ((x/a_x)^(2/e2) + (y/a_y)^(2/e2))^(e2/e1)
+// + (z/a_z)^(2/e1), e1 = eps1, e2 = eps2.  Its SDF read as the radial distance
+// |x| (1 - f(x)^(-e1/2)): the point's distance to where the ray from the centre
+// through it crosses f = 1 (f is homogeneous of degree 2/e1 along rays); exact
+// for a sphere.
+template <class T> T sq_sdf(const V3<T>& x, const T a[3], const T e[2]) {
+  const double d2 = kSqDelta * kSqDelta;
+  const T X = x.x / a[0], Y = x.y / a[1], Z = x.z / a[2];
+  const T fxy = powr(X * X + d2, 1.0 / e[1]) + powr(Y * Y + d2, 1.0 / e[1]);
+  const T f = powr(fxy, e[1] / e[0]) + powr(Z * Z + d2, 1.0 / e[0]);
+  T amin = a[0];
+  if (val(a[1]) < val(amin)) amin = a[1];
+  if (val(a[2]) < val(amin)) amin = a[2];
+  const T r = sqrt(dot(x, x) + amin * amin * d2);
+  return r * (1.0 - powr(f, e[0] * -0.5));
+}
+
+// LSE of values with temperature tau (Sec. II): the smooth maximum.
+template <class T> T lse(const std::vector<T>& v, double tau) {
+  double m = -std::numeric_limits<double>::infinity();
+  for (const T& x : v) m = std::max(m, val(x));
+  T s(0.0);
+  for (const T& x : v) s += exp((x - m) / tau);
+  return m + tau * log(s);
+}
+
+// PSQ (Sec. III-A.3): smooth intersection of the SQ and the half-spaces, in
+// the PSQ frame.
+template <class T> T psq_sdf(const Prim& pr, const V3<T>& xs, const T a[3], const T e[2], const Params& prm) {
+  std::vector<T> v;
+  v.push_back(sq_sdf(xs, a, e));
+  for (size_t j = 0; j + 3 < pr.planes.size(); j += 4) {
+    const double* q = &pr.planes[j];
+    v.push_back(xs.x * q[0] + xs.y * q[1] + xs.z * q[2] + q[3]);
+  }
+  return v.size() == 1 ? v[0] : lse(v, prm.tau_cap);
+}
+
+// The three spline parameters t* of a point's projection onto the XPSQ's
+// quadratic spline p(t) = (1-t)^2 p1 + 2t(1-t) p2 + t^2 p3 (Sec. III-A.5):
+// d/dt |x - p(t)|^2 / 2 = (p(t) - x) . p'(t) is the cubic
+// 2|A|^2 t^3 + 3 A.B t^2 + (|B|^2 + 2 A.(p1 - x)) t + B.(p1 - x), A = p1 - 2 p2 + p3,
+// B = 2 (p2 - p1); divided by 2|A|^2 and shifted t = s - a2/3 it reads
+// s^3 + P s + Q = 0 with discriminant Delta = -(4 P^3 + 27 Q^2).  Both of
+// Cardano's branches are always taken: one real root from Delta^- = -s_+(-Delta),
+// s = cbrt(-Q/2 + sqrt(-Delta^-/108)) + cbrt(-Q/2 - sqrt(-Delta^-/108)); three from
+// Delta^+ = s_+(Delta) through the cube roots of -Q/2 +- i sqrt(Delta^+/108),
+// s_k = 2 r^(1/3) cos((theta + 2 pi k) / 3), r = sqrt(Q^2/4 + Delta^+/108),
+// theta = atan2(sqrt(Delta^+/108), -Q/2).  Every root is soft-clipped to (0, 1)
+// and t*_k = [Delta < 0] t^- + [Delta > 0] t^+_k with sigmoid brackets.
+template <class T> void xpsq_roots(const Prim& pr, const V3<T>& x, const Params& prm, T t[3]) {
+  const V3<double> P1{pr.p[0], pr.p[1], pr.p[2]}, P2{pr.p[3], pr.p[4], pr.p[5]}, P3{pr.p[6], pr.p[7], pr.p[8]};
+  const V3<double> A = P1 - P2 * 2.0 + P3, B = (P2 - P1) * 2.0;
+  const V3<T> C0{T(P1.x) - x.x, T(P1.y) - x.y, T(P1.z) - x.z};
+  const double AA = dot(A, A);
+  const double a2 = 1.5 * dot(A, B) / AA;
+  const T a1 = (dot(B, B) + 2.0 * (C0.x * A.x + C0.y * A.y + C0.z * A.z)) / (2.0 * AA);
+  const T a0 = (C0.x * B.x + C0.y * B.y + C0.z * B.z) / (2.0 * AA);
+  const T P = a1 - a2 * a2 / 3.0;
+  const T Q = a0 - a1 * (a2 / 3.0) + 2.0 * a2 * a2 * a2 / 27.0;
+  const T Delta = -(4.0 * P * P * P + 27.0 * Q * Q);
+  const double tau = prm.tau_disc, tiny = 1e-20;  // (keeps sqrt differentiable where s_+ underflows)
+  const T u = Q * -0.5;
+  const T Dm = softplus(-Delta, tau) / 108.0, Dp = softplus(Delta, tau) / 108.0;
+  const T sm = sqrt(Dm + tiny);
+  const T s_one = cbrt(u + sm) + cbrt(u - sm);
+  const T r = sqrt(u * u + Dp), th = atan2(sqrt(Dp + tiny), u), rr = cbrt(r);
+  const T w_one = sigmoid(-Delta / tau), w_three = sigmoid(Delta / tau);
+  const T zero(0.0), one(1.0);
+  const T t_one = softclip(s_one - a2 / 3.0, zero, one, prm.tau_t);
+  for (int k = 0; k < 3; ++k) {
+    const T sk = 2.0 * rr * cos((th + 2.0 * M_PI * k) / 3.0);
+    t[k] = w_one * t_one + w_three * softclip(sk - a2 / 3.0, zero, one, prm.tau_t);
+  }
+}
+
+// XPSQ (Sec. III-A.4/5): the PSQ placed at each of the three projection
+// parameters -- centre p(t), frame R(t) = [N(t), b, T(t)] (the Frenet frame of
+// the planar spline: unit tangent T = p'/|p'|, binormal b along B x A, constant
+// for a quadratic, N = b x T; the SQ's z-axis runs along the spline), scales and
+// exponents linear in t, half-spaces fixed in the PSQ frame -- and the smooth
+// minimum of the three PSQ SDFs.
+template <class T> T xpsq_sdf(const Prim& pr, const V3<T>& x, const Params& prm) {
+  T t[3];
+  xpsq_roots(pr, x, prm, t);
+  const V3<double> P1{pr.p[0], pr.p[1], pr.p[2]}, P2{pr.p[3], pr.p[4], pr.p[5]}, P3{pr.p[6], pr.p[7], pr.p[8]};
+  const V3<double> A = P1 - P2 * 2.0 + P3, B = (P2 - P1) * 2.0;
+  V3<double> bn{B.y * A.z - B.z * A.y, B.z * A.x - B.x * A.z, B.x * A.y - B.y * A.x};
+  bn = bn * (1.0 / std::sqrt(dot(bn, bn)));
+  std::vector<T> neg(3);
+  for (int k = 0; k < 3; ++k) {
+    const T& tk = t[k];
+    const T w0 = (1.0 - tk) * (1.0 - tk), w1 = 2.0 * tk * (1.0 - tk), w2 = tk * tk;
+    const V3<T> pt{w0 * P1.x + w1 * P2.x + w2 * P3.x, w0 * P1.y + w1 * P2.y + w2 * P3.y,
+                   w0 * P1.z + w1 * P2.z + w2 * P3.z};
+    const V3<T> dp{2.0 * tk * A.x + B.x, 2.0 * tk * A.y + B.y, 2.0 * tk * A.z + B.z};
+    const T il = 1.0 / sqrt(dot(dp, dp));
+    const V3<T> Tn = dp * il;
+    const V3<T> Nn{Tn.z * bn.y - Tn.y * bn.z, Tn.x * bn.z - Tn.z * bn.x, Tn.y * bn.x - Tn.x * bn.y};  // b x T
+    const V3<T> d = x - pt;
+    const V3<T> xs{dot(Nn, d), d.x * bn.x + d.y * bn.y + d.z * bn.z, dot(Tn, d)};
+    T a[3], e[2];
+    for (int i = 0; i < 3; ++i) a[i] = pr.a0[i] + tk * (pr.a1[i] - pr.a0[i]);
+    for (int i = 0; i < 2; ++i) e[i] = pr.e0[i] + tk * (pr.e1[i] - pr.e0[i]);
+    neg[size_t(k)] = -psq_sdf(pr, xs, a, e, prm);
+  }
+  return -lse(neg, prm.tau_cup);
+}
+
+template <class T> T prim_sdf(const Prim& pr, const V3<T>& x, const Params& prm) {
+  if (pr.kind == 1) return xpsq_sdf(pr, x, prm);
+  const V3<T> d{x.x - pr.c[0], x.y - pr.c[1], x.z - pr.c[2]};
+  const V3<T> xs{pr.R[0] * d.x + pr.R[3] * d.y + pr.R[6] * d.z, pr.R[1] * d.x + pr.R[4] * d.y + pr.R[7] * d.z,
+                 pr.R[2] * d.x + pr.R[5] * d.y + pr.R[8] * d.z};  // R^T d
+  const T a[3] = {T(pr.a0[0]), T(pr.a0[1]), T(pr.a0[2])}, e[2] = {T(pr.e0[0]), T(pr.e0[1])};
+  return psq_sdf(pr, xs, a, e, prm);
+}
+
+// The object's SDF from its primitives (Sec. III-A.2): folded in order, each
+// joining the result so far by smooth union (-LSE(-phi, -phi_i), tau_cup),
+// subtraction (LSE(phi, -phi_i), tau_cap) or intersection (LSE(phi, phi_i), tau_cap).
+template <class T> T prims_sdf(const Object& o, const V3<T>& x, const Params& prm) {
+  T phi = prim_sdf(o.prims[0], x, prm);
+  for (size_t i = 1; i < o.prims.size(); ++i) {
+    const T v = prim_sdf(o.prims[i], x, prm);
+    const int op = o.prims[i].op;
+    if (op == 0) phi = -lse(std::vector<T>{-phi, -v}, prm.tau_cup);
+    else if (op == 1) phi = lse(std::vector<T>{phi, -v}, prm.tau_cap);
+    else phi = lse(std::vector<T>{phi, v}, prm.tau_cap);
+  }
+  return phi;
 }
 
 
@@ -603,7 +773,10 @@ template <class T> void spline_eval(const Spline& sp, const V3<T>& x, T& phi, V3
 // separately fitted normal spline, Sec. III-B.2).
 template <class T> T object_phi(const Object& o, const V3<T>& x, const Params& prm) {
   T phi;
-  if (o.has_spline) {
+  if (o.has_prims) {
+    phi = prims_sdf(o, x, prm);
+    probe(phi, true);
+  } else if (o.has_spline) {
     V3<T> n;
     spline_eval(o.spl, x, phi, n);
     probe(phi, true);
@@ -614,7 +787,19 @@ template <class T> T object_phi(const Object& o, const V3<T>& x, const Params& p
   return phi;
 }
 template <class T> void object_phi_normal(const Object& o, const V3<T>& x, const Params& prm, T& phi, V3<T>& n) {
-  if (o.has_spline) {
+  if (o.has_prims) {
+    // (primitives: the normalised gradient, by forward differentiation in x)
+    using G = Dual<T, 3>;
+    const V3<G> xg{G(x.x, 0), G(x.y, 0), G(x.z, 0)};
+    V3<G> xs = xg;
+    xs.x.d[0] = T(1.0); xs.y.d[1] = T(1.0); xs.z.d[2] = T(1.0);
+    const G r = prims_sdf(o, xs, prm);
+    phi = r.v;
+    V3<T> g{r.d[0], r.d[1], r.d[2]};
+    probe(phi, true);
+    probe3(g, false);
+    n = normal_of(g, prm);
+  } else if (o.has_spline) {
     spline_eval(o.spl, x, phi, n);
     probe(phi, true);
     probe3(n, false);
@@ -1055,6 +1240,54 @@ void orc_object_set_tris(int32_t h, const int64_t* tri_off, const double* tris) 
 
 // S1: fits the object's spline SDF (then its voxel grid follows the spline).
 void orc_build_spline(int32_t h, const Params* prm) { build_spline(*g_objects.at(size_t(h)), *prm); }
+
+// The object's SDF side becomes its primitives (Sec. III-A), n records of 32
+// doubles: [0] kind (0 PSQ, 1 XPSQ), [1] op (0 union, 1 subtraction,
+// 2 intersection with the primitives before it), [2..4] PSQ centre / XPSQ p1,
+// [5..7] p2, [8..10] p3, [11..14] PSQ rotation as a unit quaternion (w, x, y, z),
+// [15..17] scales a at t = 0, [18..19] exponents (eps1, eps2) at t = 0,
+// [20..22] a at t = 1, [23..24] exponents at t = 1; half-spaces planes[4 plane_off[i]
+// .. 4 plane_off[i + 1]) in the PSQ frame.  Its pieces remain the mesh side.
+void orc_object_set_prims(int32_t h, int32_t n, const double* rec, const int64_t* plane_off, const double* planes) {
+  Object& o = *g_objects.at(size_t(h));
+  o.prims.assign(size_t(n), Prim{});
+  for (int32_t i = 0; i < n; ++i) {
+    const double* r = rec + 32 * i;
+    Prim& q = o.prims[size_t(i)];
+    q.kind = int(r[0]);
+    q.op = int(r[1]);
+    for (int k = 0; k < 3; ++k) q.c[k] = r[2 + k];
+    for (int k = 0; k < 9; ++k) q.p[k] = r[2 + k];
+    const M3<double> R = quat_to_R(r + 11);
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) q.R[3 * a + b] = R.m[a][b];
+    for (int k = 0; k < 3; ++k) { q.a0[k] = r[15 + k]; q.a1[k] = r[20 + k]; }
+    for (int k = 0; k < 2; ++k) { q.e0[k] = r[18 + k]; q.e1[k] = r[23 + k]; }
+    q.planes.assign(planes + 4 * plane_off[i], planes + 4 * plane_off[i + 1]);
+  }
+  o.has_prims = n > 0;
+}
+
+// The primitive SDF phi and its gradient (n x 3) at n object-frame points.
+void orc_prims_eval(int32_t h, const Params* prm, int64_t n, const double* x, double* phi, double* grad) {
+  const Object& o = obj(h);
+  typedef Dual<double, 3> D3;
+  for (int64_t i = 0; i < n; ++i) {
+    V3<D3> xd{D3(x[3 * i]), D3(x[3 * i + 1]), D3(x[3 * i + 2])};
+    xd.x.d[0] = 1; xd.y.d[1] = 1; xd.z.d[2] = 1;
+    const D3 r = prims_sdf(o, xd, *prm);
+    phi[i] = r.v;
+    if (grad)
+      for (int a = 0; a < 3; ++a) grad[3 * i + a] = r.d[a];
+  }
+}
+
+// The three projection parameters t* (Sec. III-A.5) of primitive `k` (an XPSQ)
+// at n object-frame points (n x 3).
+void orc_xpsq_roots(int32_t h, int32_t k, const Params* prm, int64_t n, const double* x, double* t) {
+  const Prim& pr = obj(h).prims.at(size_t(k));
+  for (int64_t i = 0; i < n; ++i) xpsq_roots(pr, cvt<double>(x + 3 * i), *prm, t + 3 * i);
+}
 
 // meta: n, origin (3), spacing (3); coeffs [4][(n+3)^3] may be null.
 void orc_spline(int32_t h, double* meta, double* coeffs) {
