@@ -460,10 +460,12 @@ def step_leg(api, W, config, pairs, budget_gb, args, steps, warmup, golden=None,
         shape = tp.autotune(tq, tc, tg, dir_d[:ns].contiguous(), torch.empty_like(tg), stream)
         shape_f = tp.autotune(tq, tc, tg, stream=stream)
         plan.launch_shape = (shape_f, shape)
+        plan.wg_waves = tp.wg_waves
         del tp, tq, tc, tg
         tuned_on = ns
     how = ("autotuned on %d pair-queries" % tuned_on) if tuned_on else "set by --launch-shape"
-    log("launch shape (%s): %d workgroups per CU (dual sweeps), %d (float sweeps)" % (how, shape, shape_f))
+    log("launch shape (%s): %d workgroups per CU of %d waves (dual sweeps), %d of %d (float sweeps)"
+        % (how, shape, plan.wg_waves[1], shape_f, plan.wg_waves[0]))
     long_steps = config == "c4"  # seconds per step: report each one
     for k in range(warmup):
         step()
@@ -491,6 +493,7 @@ def step_leg(api, W, config, pairs, budget_gb, args, steps, warmup, golden=None,
     step_out = (out.clone(), grad.clone(), hv.clone())
     res = dict(w=w, ctx=ctx, hs=hs, plan=plan, qd=qd, cot=cot, direc=direc, cot_d=cot_d, dir_d=dir_d,
                out=out, grad=grad, hv=hv, ms=ms, wall=wall, shape=shape, shape_f=shape_f, tuned_on=tuned_on,
+               wg_waves=plan.wg_waves,
                step=step, timed=timed, stream=stream, step_out=step_out)
     # the step's outputs now are those of every timed step (deterministic launches)
     if golden is not None:
@@ -498,11 +501,22 @@ def step_leg(api, W, config, pairs, budget_gb, args, steps, warmup, golden=None,
         rows = np.concatenate([np.arange(plan.group_off[i], plan.group_off[i + 1]) for i in sel])
         goff_s = np.array(golden["group_off"], np.int64)
         Ls = np.repeat(np.array(golden["scene_scale"]), np.diff(goff_s))
+        g_gpu = out.cpu().numpy().T.astype(np.float64)[rows]
+        gr_gpu = grad.cpu().numpy()[sel].astype(np.float64)
+        hv_gpu = hv.cpu().numpy()[sel].astype(np.float64)
         res["parity"] = dict(queries=len(sel), source="tests/golden/c4_oracle.json (FP64 oracle)",
-                             **parity_of(out.cpu().numpy().T.astype(np.float64)[rows],
-                                         grad.cpu().numpy()[sel].astype(np.float64),
-                                         hv.cpu().numpy()[sel].astype(np.float64), np.array(golden["records"]),
+                             **parity_of(g_gpu, gr_gpu, hv_gpu, np.array(golden["records"]),
                                          np.array(golden["grad"]), np.array(golden["hv"]), Ls))
+        # the acceptance bounds of the parity tests: 1e-4 relative (floor 1e-3 |cot| max(1, L_s)),
+        # or 4 times the oracle's FP32 spread where a query is ill-conditioned at FP32
+        cq = np.sqrt(np.add.reduceat((cot_s.astype(np.float64) ** 2).sum(1), goff_s[:-1]))
+        floor = 1e-3 * cq * np.maximum(1.0, np.array(golden["scene_scale"]))
+        for name, got, key in (("grad", gr_gpu, "grad"), ("hvp", hv_gpu, "hv")):
+            ref = np.array(golden[key])
+            allowed = np.maximum(1e-4 * np.maximum(np.linalg.norm(ref, axis=1), floor),
+                                 4.0 * np.array(golden["spread_" + key]))
+            res["parity"]["max_%s_err_over_allowed" % name] = float(
+                (np.linalg.norm(got - ref, axis=1) / allowed).max())
         log("parity against the stored oracle values: %s" % res["parity"])
     if quick:
         return res
@@ -576,6 +590,7 @@ def step_leg(api, W, config, pairs, budget_gb, args, steps, warmup, golden=None,
         for i in range(ns):
             p1 = ctx.plan(hs[w.qa[i:i + 1]], hs[w.qb[i:i + 1]])
             p1.launch_shape = plan.launch_shape
+            p1.wg_waves = plan.wg_waves
             q1 = p1.device_queries(w.poses[i:i + 1])
             g0, g1 = plan.group_off[i], plan.group_off[i + 1]
             c1 = cot_d[:, g0:g1].contiguous()
@@ -692,6 +707,7 @@ def main():
         hs_t = ctx_t.build_objects(w.objects)
         plan_t = ctx_t.plan(hs_t[w.qa], hs_t[w.qb])
         plan_t.launch_shape = plan.launch_shape
+        plan_t.wg_waves = plan.wg_waves
         qd_t = plan_t.device_queries(w.poses)
         o_t, g_t, h_t = torch.empty_like(r["out"]), torch.empty_like(r["grad"]), torch.empty_like(r["hv"])
         t_ms = r["timed"](lambda: plan_t.step(qd_t, r["cot_d"], r["dir_d"], out=o_t, grad=g_t, hv=h_t,
@@ -715,6 +731,7 @@ def main():
         split_ms=r["split"], separate_calls_ms_per_step=round(r["sep_ms"], 3) if r["sep_ms"] else None,
         graph_replay_ms_per_step=round(r["graph_ms"], 3),
         launch_shape={"workgroups_per_cu": r["shape"], "workgroups_per_cu_float": r["shape_f"],
+                      "waves_per_workgroup": r["wg_waves"][1], "waves_per_workgroup_float": r["wg_waves"][0],
                       "tile": "one wave of 64 contacts", "tuned_on_pair_queries": r["tuned_on"]},
         forward_gradient_step_ms=round(r["fg_ms"], 3), forward_gradient_value=round(w.n / (r["fg_ms"] * 1e-3), 1),
         forward_ms=round(r["fw_ms"], 3), forward_value=round(w.n / (r["fw_ms"] * 1e-3), 1),

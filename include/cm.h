@@ -181,7 +181,31 @@ cm_status cm_object_spline(cm_context* ctx, cm_object obj, float* coef, float* m
 /* n >= 1 (an empty batch is CM_E_INVALID); the context must own a device. */
 cm_status cm_plan_create(cm_context* ctx, const cm_query* host_queries, int32_t n, cm_plan** out);
 cm_status cm_plan_destroy(cm_plan* plan);
-/* Totals: groups G, contacts C (vertices + edges of both sides), queries n. */
+/* A plan of fixed capacity whose batch can be replaced (batching of the
+ * persistent launch over changing sets of pair-queries, Sec. IV-C): device
+ * memory laid out for up to max_queries pair-queries, max_groups groups (sum
+ * over queries of both objects' piece counts) and max_contacts contacts (sum of
+ * both objects' vertices and edges), holding an empty batch until
+ * cm_plan_refill.  Every kernel of a pass reads the batch's counts and the
+ * object table from the plan's device memory, so a graph captured on such a
+ * plan (cm_graph_create) replays whatever batch the plan holds when it is
+ * launched.  Records and cotangents of a reserved plan are SoA rows of stride
+ * max_groups (cm_groups rows of a [12][max_groups] array), gradients and
+ * directions [max_queries][12]; the first G (n) of each row are the batch's.
+ * CM_E_INVALID for non-positive capacities; CM_E_OOM if the memory is not there. */
+cm_status cm_plan_reserve(cm_context* ctx, int32_t max_queries, int64_t max_groups, int64_t max_contacts,
+                          cm_plan** out);
+/* Plans the batch host_queries[0..n) (n may be 0) into a reserved plan and
+ * enqueues the upload of its tables on `stream`: passes enqueued on the same
+ * stream before this call see the previous batch, those after it this one.
+ * Waits (host) only for the previous refill's uploads.  CM_E_INVALID if the
+ * plan was not reserved or the batch exceeds a capacity (the plan keeps its
+ * previous batch); CM_E_NOTFOUND for an unknown object. */
+cm_status cm_plan_refill(cm_context* ctx, cm_plan* plan, const cm_query* host_queries, int32_t n, void* stream);
+/* Capacities of a reserved plan; for other plans the batch's own sizes. */
+cm_status cm_plan_capacity(const cm_plan* plan, int32_t* max_queries, int64_t* max_groups, int64_t* max_contacts);
+/* Totals of the batch the plan holds: groups G, contacts C (vertices + edges
+ * of both sides), queries n. */
 cm_status cm_plan_info(const cm_plan* plan, int64_t* n_groups, int64_t* n_contacts, int32_t* n_queries);
 /* group_off[n + 1], contact_off[n + 1] (host).  Either may be NULL. */
 cm_status cm_plan_offsets(const cm_plan* plan, int64_t* group_off, int64_t* contact_off);
@@ -315,7 +339,8 @@ cm_status cm_contacts_step(cm_context* ctx, cm_plan* plan, const cm_query* q_dev
  * cm_contacts_step with these device buffers (same arguments and rules) into
  * a graph; cm_graph_launch replays it on `stream`.  The kernels read every
  * count on the device, so a replay computes the step for whatever poses the
- * query buffer holds at that time; buffers and plan must outlive the graph,
+ * query buffer holds at that time, and, on a reserved plan, for whatever batch
+ * the last cm_plan_refill enqueued before it; buffers and plan must outlive the graph,
  * and replays of one plan must not overlap.  Timing events are not recorded
  * into the graph.  For callers whose step launch overhead matters (small
  * batches, serving loops). */
@@ -325,23 +350,31 @@ cm_status cm_graph_create(cm_context* ctx, cm_plan* plan, const cm_query* q_dev,
 cm_status cm_graph_launch(cm_graph* graph, void* stream);
 cm_status cm_graph_destroy(cm_graph* graph);
 
-/* Launch-shape autotuner: times cm_contacts_step (records not written) with
- * 2, 4, 6, 8, 12 and 16 persistent workgroups per CU on `stream`
- * (synchronous) and keeps the fastest for the plan's later launches of the
- * same kind: with dir the sweeps in dual numbers (H v), without dir the float
- * sweeps (forward, gradient); *best (nullable) receives it.  The tile shape
- * itself is one wave of 64 contacts. */
+/* Launch-shape autotuner (batching of the persistent launch): times
+ * cm_contacts_step (records not written) on `stream` (synchronous) with 2, 4,
+ * 6, 8, 12 and 16 persistent workgroups of 4 waves per CU, then at the fastest
+ * count of resident waves per CU with workgroups of 2 and of 1 wave, and keeps
+ * the fastest (workgroups per CU, waves per workgroup) for the plan's later
+ * launches of the same kind: with dir the sweeps in dual numbers (H v),
+ * without dir the float sweeps (forward, gradient); *best (nullable) receives
+ * the workgroups per CU (cm_plan_wg_waves the workgroup size).  A tile is one
+ * wave's 64 contacts; results do not depend on the shape. */
 cm_status cm_plan_autotune(cm_context* ctx, cm_plan* plan, const cm_query* q_dev, cm_groups cot, float* grad,
                            const float* dir, float* hv, void* stream, int32_t* best);
 
 /* Launch shape of a plan: persistent workgroups per CU for the float sweeps
  * (forward, gradient) and for the sweeps in dual numbers (H v).  The setter
- * takes values in [1, 32] (else CM_E_INVALID, shape unchanged) and lets a shape
+ * takes values in [1, 64] (else CM_E_INVALID, shape unchanged) and lets a shape
  * tuned on a representative sub-batch (cm_plan_autotune on a smaller plan of
  * the same workload) be applied to a large plan; results do not depend on it.
  * The getter's outputs are nullable. */
 cm_status cm_plan_set_launch_shape(cm_plan* plan, int32_t float_per_cu, int32_t dual_per_cu);
 cm_status cm_plan_launch_shape(const cm_plan* plan, int32_t* float_per_cu, int32_t* dual_per_cu);
+/* Waves per workgroup of the narrow-phase sweeps (float, dual): 1, 2 or 4
+ * (default 4; else CM_E_INVALID, unchanged); results do not depend on it.
+ * The getter's outputs are nullable. */
+cm_status cm_plan_set_wg_waves(cm_plan* plan, int32_t float_waves, int32_t dual_waves);
+cm_status cm_plan_wg_waves(const cm_plan* plan, int32_t* float_waves, int32_t* dual_waves);
 
 /* Serving statistics: [0] submitted, [1] completed, [2] batches, [3] queued,
  * [4] in flight, [5] peak device bytes held by the serving slots' buffers (the

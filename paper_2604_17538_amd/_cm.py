@@ -81,6 +81,9 @@ cm_object_grid = _sig("cm_object_grid", I32, [P, U32, P, P])
 cm_object_spline = _sig("cm_object_spline", I32, [P, U32, P, P])
 cm_plan_create = _sig("cm_plan_create", I32, [P, P, I32, PP])
 cm_plan_destroy = _sig("cm_plan_destroy", I32, [P])
+cm_plan_reserve = _sig("cm_plan_reserve", I32, [P, I32, I64, I64, PP])
+cm_plan_refill = _sig("cm_plan_refill", I32, [P, P, P, I32, P])
+cm_plan_capacity = _sig("cm_plan_capacity", I32, [P, ctypes.POINTER(I32), ctypes.POINTER(I64), ctypes.POINTER(I64)])
 cm_plan_info = _sig("cm_plan_info", I32, [P, ctypes.POINTER(I64), ctypes.POINTER(I64), ctypes.POINTER(I32)])
 cm_plan_offsets = _sig("cm_plan_offsets", I32, [P, P, P])
 cm_plan_stats = _sig("cm_plan_stats", I32, [P, P])
@@ -100,6 +103,8 @@ cm_graph_destroy = _sig("cm_graph_destroy", I32, [P])
 cm_plan_autotune = _sig("cm_plan_autotune", I32, [P, P, P, cm_groups, P, P, P, P, ctypes.POINTER(I32)])
 cm_plan_set_launch_shape = _sig("cm_plan_set_launch_shape", I32, [P, I32, I32])
 cm_plan_launch_shape = _sig("cm_plan_launch_shape", I32, [P, ctypes.POINTER(I32), ctypes.POINTER(I32)])
+cm_plan_set_wg_waves = _sig("cm_plan_set_wg_waves", I32, [P, I32, I32])
+cm_plan_wg_waves = _sig("cm_plan_wg_waves", I32, [P, ctypes.POINTER(I32), ctypes.POINTER(I32)])
 cm_submit = _sig("cm_submit", I32, [P, ctypes.POINTER(cm_request), ctypes.POINTER(U64)])
 cm_poll = _sig("cm_poll", I32, [P, U64, ctypes.POINTER(I32), ctypes.POINTER(I32)])
 cm_wait = _sig("cm_wait", I32, [P, U64, I32, ctypes.POINTER(I32)])
@@ -108,10 +113,10 @@ cm_serve_latencies = _sig("cm_serve_latencies", I32, [P, P, I64, ctypes.POINTER(
 
 EXPORTED = ["cm_default_params", "cm_init", "cm_shutdown", "cm_last_error", "cm_build_pieces", "cm_build_objects",
             "cm_build_pieces_raw", "cm_release_object", "cm_object_info", "cm_object_export", "cm_object_grid", "cm_object_spline",
-            "cm_plan_create", "cm_plan_destroy", "cm_plan_info", "cm_plan_offsets", "cm_plan_stats", "cm_plan_work",
+            "cm_plan_create", "cm_plan_destroy", "cm_plan_reserve", "cm_plan_refill", "cm_plan_capacity", "cm_plan_info", "cm_plan_offsets", "cm_plan_stats", "cm_plan_work",
             "cm_plan_set_timing", "cm_plan_timing",
             "cm_contacts_fwd", "cm_contacts_fwd_noalloc", "cm_contacts_bwd", "cm_hvp", "cm_contacts_jvp", "cm_project_points",
             "cm_contacts_step", "cm_graph_create", "cm_graph_launch",
-            "cm_graph_destroy", "cm_plan_autotune", "cm_plan_set_launch_shape", "cm_plan_launch_shape",
+            "cm_graph_destroy", "cm_plan_autotune", "cm_plan_set_launch_shape", "cm_plan_launch_shape", "cm_plan_set_wg_waves", "cm_plan_wg_waves",
             "cm_submit", "cm_poll", "cm_wait", "cm_serve_stats",
             "cm_serve_latencies"]

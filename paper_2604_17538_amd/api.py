@@ -196,12 +196,46 @@ class Plan:
         hq = make_queries(self.qa, self.qb, np.tile([1, 0, 0, 0, 0, 0, 0] * 2, (len(self.qa), 1)))
         self._h = ctypes.c_void_p()
         ctx._check(_cm.cm_plan_create(ctx.handle, _ptr(hq), len(hq), ctypes.byref(self._h)), "cm_plan_create")
+        self._info()
+
+    @classmethod
+    def reserve(cls, ctx: Context, max_queries: int, max_groups: int, max_contacts: int) -> "Plan":
+        """A plan of fixed capacity holding an empty batch (cm_plan_reserve);
+        refill() replaces its batch.  Records and cotangents are [12, max_groups],
+        gradients and directions [max_queries, 12]; the first G (n) rows are the
+        batch's."""
+        self = cls.__new__(cls)
+        self.ctx = ctx
+        self.qa = np.zeros(0, np.uint32)
+        self.qb = np.zeros(0, np.uint32)
+        self._h = ctypes.c_void_p()
+        ctx._check(_cm.cm_plan_reserve(ctx.handle, int(max_queries), int(max_groups), int(max_contacts),
+                                       ctypes.byref(self._h)), "cm_plan_reserve")
+        self._info()
+        return self
+
+    def refill(self, qa, qb, stream=None):
+        """Replace the batch of a reserved plan (cm_plan_refill, enqueued on `stream`)."""
+        qa = np.asarray(qa, np.uint32)
+        qb = np.asarray(qb, np.uint32)
+        hq = make_queries(qa, qb, np.tile([1, 0, 0, 0, 0, 0, 0] * 2, (len(qa), 1)))
+        self.ctx._check(_cm.cm_plan_refill(self.ctx.handle, self._h, _ptr(hq), len(hq), _stream_ptr(stream)),
+                        "cm_plan_refill")
+        self.qa, self.qb = qa, qb
+        self._info()
+
+    def _info(self):
         G, C, n = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32()
         _cm.cm_plan_info(self._h, ctypes.byref(G), ctypes.byref(C), ctypes.byref(n))
         self.G, self.C, self.n = G.value, C.value, n.value
         self.group_off = np.zeros(self.n + 1, np.int64)
         self.contact_off = np.zeros(self.n + 1, np.int64)
         _cm.cm_plan_offsets(self._h, _ptr(self.group_off), _ptr(self.contact_off))
+        mq, mg, mc = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int64()
+        _cm.cm_plan_capacity(self._h, ctypes.byref(mq), ctypes.byref(mg), ctypes.byref(mc))
+        # rows of the record (group) and per-query arrays the kernels address:
+        # the capacity of a reserved plan, else the batch's own sizes
+        self.rows_G, self.rows_n, self.cap_C = mg.value, mq.value, mc.value
 
     @property
     def handle(self):
@@ -224,11 +258,20 @@ class Plan:
         hq = make_queries(self.qa, self.qb, poses)
         return torch.from_numpy(hq.view(np.uint8).reshape(-1, 64).copy()).to(device)
 
+    def write_queries(self, q_buf, poses):
+        """Write the batch's device queries into the first n rows of q_buf
+        (torch uint8 [rows, 64], rows >= n: e.g. a reserved plan's rows_n, the
+        buffer a graph was captured with)."""
+        torch = _torch()
+        hq = make_queries(self.qa, self.qb, poses)
+        q_buf[: self.n].copy_(torch.from_numpy(hq.view(np.uint8).reshape(-1, 64).copy()))
+        return q_buf
+
     def forward(self, q_dev, out=None, debug: bool = False, stream=None):
         """Group records [12, G] (rows p, n, d, q, W, logZ) and optional per-contact [13, C]."""
         torch = _torch()
         if out is None:
-            out = torch.empty((12, self.G), dtype=torch.float32, device=q_dev.device)
+            out = torch.empty((12, self.rows_G), dtype=torch.float32, device=q_dev.device)
         dbg = torch.empty((13, self.C), dtype=torch.float32, device=q_dev.device) if debug else None
         st = _cm.cm_contacts_fwd(self.ctx.handle, self._h, ctypes.c_void_p(q_dev.data_ptr()), groups_struct(out),
                                  ctypes.c_void_p(dbg.data_ptr()) if dbg is not None else None,
@@ -261,7 +304,7 @@ class Plan:
     def backward(self, q_dev, cot, grad=None, stream=None):
         torch = _torch()
         if grad is None:
-            grad = torch.empty((self.n, 12), dtype=torch.float32, device=q_dev.device)
+            grad = torch.empty((self.rows_n, 12), dtype=torch.float32, device=q_dev.device)
         st = _cm.cm_contacts_bwd(self.ctx.handle, self._h, ctypes.c_void_p(q_dev.data_ptr()), groups_struct(cot),
                                  ctypes.c_void_p(grad.data_ptr()), _stream_ptr(stream))
         self.ctx._check(st, "cm_contacts_bwd")
@@ -272,11 +315,11 @@ class Plan:
         from one forward sweep and one adjoint (cm_contacts_step)."""
         torch = _torch()
         if records and out is None:
-            out = torch.empty((12, self.G), dtype=torch.float32, device=q_dev.device)
+            out = torch.empty((12, self.rows_G), dtype=torch.float32, device=q_dev.device)
         if grad is None:
-            grad = torch.empty((self.n, 12), dtype=torch.float32, device=q_dev.device)
+            grad = torch.empty((self.rows_n, 12), dtype=torch.float32, device=q_dev.device)
         if direction is not None and hv is None:
-            hv = torch.empty((self.n, 12), dtype=torch.float32, device=q_dev.device)
+            hv = torch.empty((self.rows_n, 12), dtype=torch.float32, device=q_dev.device)
         st = _cm.cm_contacts_step(self.ctx.handle, self._h, ctypes.c_void_p(q_dev.data_ptr()),
                                   groups_struct(out) if records else _cm.cm_groups(), groups_struct(cot),
                                   ctypes.c_void_p(grad.data_ptr()),
@@ -320,10 +363,21 @@ class Plan:
         self.ctx._check(_cm.cm_plan_set_launch_shape(self._h, int(shape[0]), int(shape[1])),
                         "cm_plan_set_launch_shape")
 
+    @property
+    def wg_waves(self) -> tuple:
+        """(float sweeps, dual sweeps) waves per workgroup of the narrow phase."""
+        f, d = ctypes.c_int32(), ctypes.c_int32()
+        self.ctx._check(_cm.cm_plan_wg_waves(self._h, ctypes.byref(f), ctypes.byref(d)), "cm_plan_wg_waves")
+        return int(f.value), int(d.value)
+
+    @wg_waves.setter
+    def wg_waves(self, waves):
+        self.ctx._check(_cm.cm_plan_set_wg_waves(self._h, int(waves[0]), int(waves[1])), "cm_plan_set_wg_waves")
+
     def hvp(self, q_dev, cot, direction, hv=None, grad=None, stream=None):
         torch = _torch()
         if hv is None:
-            hv = torch.empty((self.n, 12), dtype=torch.float32, device=q_dev.device)
+            hv = torch.empty((self.rows_n, 12), dtype=torch.float32, device=q_dev.device)
         st = _cm.cm_hvp(self.ctx.handle, self._h, ctypes.c_void_p(q_dev.data_ptr()), groups_struct(cot),
                         ctypes.c_void_p(direction.data_ptr()), ctypes.c_void_p(hv.data_ptr()),
                         ctypes.c_void_p(grad.data_ptr()) if grad is not None else None, _stream_ptr(stream))
@@ -335,9 +389,9 @@ class Plan:
         (cm_contacts_jvp)."""
         torch = _torch()
         if out is None:
-            out = torch.empty((12, self.G), dtype=torch.float32, device=q_dev.device)
+            out = torch.empty((12, self.rows_G), dtype=torch.float32, device=q_dev.device)
         if out_t is None:
-            out_t = torch.empty((12, self.G), dtype=torch.float32, device=q_dev.device)
+            out_t = torch.empty((12, self.rows_G), dtype=torch.float32, device=q_dev.device)
         st = _cm.cm_contacts_jvp(self.ctx.handle, self._h, ctypes.c_void_p(q_dev.data_ptr()), groups_struct(out),
                                  groups_struct(out_t), ctypes.c_void_p(direction.data_ptr()), _stream_ptr(stream))
         self.ctx._check(st, "cm_contacts_jvp")

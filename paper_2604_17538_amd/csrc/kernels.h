@@ -27,7 +27,20 @@ constexpr int kTapeFixed = 10;
 constexpr int kTapeStep = 8;
 inline int tape_values(int st_iters) { return kTapeFixed + kTapeStep * st_iters; }
 
+// The batch a plan holds, read by every kernel of a pass from device memory:
+// the counts bound the loops, the object table is the one the entries index.
+// A pass captured into a graph therefore replays whatever batch the plan holds
+// when it is launched (up to the plan's capacity); the counts passed by value
+// beside it are capacities (grid sizes, and the row stride of the SoA records).
+struct DevCounts {
+  int64_t E, R, G, n;     // entries, runs, groups, pair-queries
+  const ObjDesc* objs;
+  int64_t pad[3];
+};
+static_assert(sizeof(DevCounts) == 64, "DevCounts layout");
+
 struct FwdArgs {
+  const DevCounts* dc;
   const Entry* ents;
   int64_t n_ent;
   const QueryDev* Q;
@@ -58,6 +71,8 @@ struct FwdArgs {
   int32_t n_cu;
   int32_t blocks_per_cu;       // persistent workgroups per CU, float sweeps
   int32_t blocks_per_cu_dual;  // the same in dual numbers
+  int32_t wg_waves;            // waves per workgroup of the narrow sweeps (1, 2 or 4), float
+  int32_t wg_waves_dual;       // the same in dual numbers
   // adjoint / HVP
   OutPtrs cot;          // cotangent group records
   float* gscratch;      // [G][kGStride] per-piece adjoint seeds
@@ -80,6 +95,7 @@ struct FwdArgs {
 enum { kTBroad = 0, kTNarrowFwd = 1, kTNarrowTan = 2, kTNarrowAdj = 3, kTNarrowDualAdj = 4, kTimed = 5 };
 
 struct NarrowArgs {
+  const DevCounts* dc;
   const Entry* ents;
   int64_t n_ent;
   const int64_t* tile_off;   // [R + 1]
@@ -108,7 +124,8 @@ struct NarrowArgs {
 };
 
 struct FinArgs {
-  int64_t G;
+  const DevCounts* dc;
+  int64_t G;            // capacity: the row stride of the SoA records
   const I2* gent;
   const int64_t* tile_off;   // [R + 1] tiles of the runs
   const int64_t* part_off;   // [E + 1] blend partials of the entries

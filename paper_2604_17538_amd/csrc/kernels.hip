@@ -57,12 +57,14 @@ __global__ __launch_bounds__(256) void k_grid_build(const ObjDesc* __restrict__ 
 // phi(p_c) - r >= d_max, an edge when min(lb_1, lb_2) - l >= d_max), and the
 // count and world-frame point sum of filtered contacts, which enter the blend
 // with (d_max, 0, 0) in closed form.
-__global__ __launch_bounds__(256) void k_broad(const Entry* __restrict__ ents, int64_t n_ent,
-                                               const QueryDev* __restrict__ Q, const ObjDesc* __restrict__ objs,
-                                               DevParams P, uint64_t* __restrict__ bits, int32_t* __restrict__ nsurv,
+__global__ __launch_bounds__(256) void k_broad(const DevCounts* __restrict__ dc, const Entry* __restrict__ ents,
+                                               const QueryDev* __restrict__ Q, DevParams P,
+                                               uint64_t* __restrict__ bits, int32_t* __restrict__ nsurv,
                                                int32_t* __restrict__ wpre, F4* __restrict__ filt,
                                                float* __restrict__ dbg, int64_t C) {
   const int l = lane();
+  const int64_t n_ent = dc->E;
+  const ObjDesc* __restrict__ objs = dc->objs;
   const int64_t wave = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
   const int64_t nwaves = (int64_t(gridDim.x) * blockDim.x) >> 6;
   for (int64_t e = wave; e < n_ent; e += nwaves) {
@@ -155,9 +157,10 @@ CM_DEV int64_t block_excl_scan(int64_t v, int64_t* sm /*[4]*/, int64_t* total) {
   return off + x - v;
 }
 
-__global__ __launch_bounds__(256) void k_scan_blocks(const int32_t* __restrict__ in, int64_t n,
+__global__ __launch_bounds__(256) void k_scan_blocks(const int32_t* __restrict__ in, const int64_t* __restrict__ np,
                                                      int64_t* __restrict__ bsum) {
   __shared__ int64_t sm[4];
+  const int64_t n = *np;
   const int64_t base = int64_t(blockIdx.x) * kScanBlock + int64_t(threadIdx.x) * kScanItems;
   int64_t s = 0;
 #pragma unroll
@@ -168,8 +171,9 @@ __global__ __launch_bounds__(256) void k_scan_blocks(const int32_t* __restrict__
 }
 
 __global__ __launch_bounds__(256) void k_scan_top(int64_t* __restrict__ bsum, int64_t nb, int64_t* __restrict__ out,
-                                                  int64_t n) {
+                                                  const int64_t* __restrict__ np) {
   __shared__ int64_t sm[4];
+  const int64_t n = *np;
   int64_t carry = 0;
   for (int64_t b0 = 0; b0 < nb; b0 += blockDim.x) {
     const int64_t i = b0 + threadIdx.x;
@@ -182,9 +186,10 @@ __global__ __launch_bounds__(256) void k_scan_top(int64_t* __restrict__ bsum, in
   if (threadIdx.x == 0) out[n] = carry;
 }
 
-__global__ __launch_bounds__(256) void k_scan_apply(const int32_t* __restrict__ in, int64_t n,
+__global__ __launch_bounds__(256) void k_scan_apply(const int32_t* __restrict__ in, const int64_t* __restrict__ np,
                                                     const int64_t* __restrict__ boff, int64_t* __restrict__ out) {
   __shared__ int64_t sm[4];
+  const int64_t n = *np;
   const int64_t base = int64_t(blockIdx.x) * kScanBlock + int64_t(threadIdx.x) * kScanItems;
   int64_t v[kScanItems], s = 0;
 #pragma unroll
@@ -201,19 +206,20 @@ __global__ __launch_bounds__(256) void k_scan_apply(const int32_t* __restrict__ 
 // ------------------------------------------------------------- run tiles --
 // A run is the entries of one (query, direction, kind): every piece of the
 // mesh side.  Its survivors, in entry order, fill consecutive tiles of 64.
-__global__ void k_run_tiles(const int64_t* __restrict__ run_off, const int64_t* __restrict__ surv_off, int64_t R,
-                            int32_t* __restrict__ ntr) {
+__global__ void k_run_tiles(const int64_t* __restrict__ run_off, const int64_t* __restrict__ surv_off,
+                            const DevCounts* __restrict__ dc, int32_t* __restrict__ ntr) {
   const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (r >= R) return;
+  if (r >= dc->R) return;
   const int64_t n = surv_off[run_off[r + 1]] - surv_off[run_off[r]];
   ntr[r] = int32_t((n + kWave - 1) / kWave);
 }
 
 // Blend partials of an entry: one per tile its survivors reach.
 __global__ void k_entry_parts(const int64_t* __restrict__ run_off, const int32_t* __restrict__ ent_run,
-                              const int64_t* __restrict__ surv_off, int64_t E, int32_t* __restrict__ npart) {
+                              const int64_t* __restrict__ surv_off, const DevCounts* __restrict__ dc,
+                              int32_t* __restrict__ npart) {
   const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (e >= E) return;
+  if (e >= dc->E) return;
   const int64_t rs = surv_off[run_off[ent_run[e]]];
   const int64_t a = surv_off[e] - rs, b = surv_off[e + 1] - rs;
   npart[e] = b > a ? int32_t((b - 1) / kWave - a / kWave + 1) : 0;
@@ -296,27 +302,32 @@ void launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL(k_fill_u32, dim3(unsigned(std::max<int64_t>(cdiv(n, 256), 1))), dim3(256), 0, s, p, v, n);
 }
 
-// out[0..n) = exclusive scan of in, out[n] = total.
-static void launch_scan(const int32_t* in, int64_t n, int64_t* out, int64_t* bsum, hipStream_t s) {
-  const int64_t nb = std::max<int64_t>(cdiv(n, kScanBlock), 1);
-  hipLaunchKernelGGL(k_scan_blocks, dim3(unsigned(nb)), dim3(256), 0, s, in, n, bsum);
-  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(256), 0, s, bsum, nb, out, n);
-  hipLaunchKernelGGL(k_scan_apply, dim3(unsigned(nb)), dim3(256), 0, s, in, n, bsum, out);
+// device address of count i of a DevCounts (0: E, 1: R, 2: G, 3: n)
+static const int64_t* dc_count(const DevCounts* dc, int i) { return reinterpret_cast<const int64_t*>(dc) + i; }
+
+// out[0..n) = exclusive scan of in, out[n] = total; n read on the device
+// (*np), the grid sized for the capacity n_cap >= n.
+static void launch_scan(const int32_t* in, int64_t n_cap, const int64_t* np, int64_t* out, int64_t* bsum,
+                        hipStream_t s) {
+  const int64_t nb = std::max<int64_t>(cdiv(n_cap, kScanBlock), 1);
+  hipLaunchKernelGGL(k_scan_blocks, dim3(unsigned(nb)), dim3(256), 0, s, in, np, bsum);
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(256), 0, s, bsum, nb, out, np);
+  hipLaunchKernelGGL(k_scan_apply, dim3(unsigned(nb)), dim3(256), 0, s, in, np, bsum, out);
 }
 
 void launch_front(const FwdArgs& a, hipStream_t s) {
   const int64_t nb_broad = std::min<int64_t>(cdiv(a.n_ent, 4), int64_t(a.n_cu) * 16);
   if (a.ev) (void)hipEventRecord(a.ev[2 * kTBroad], s);
-  hipLaunchKernelGGL(k_broad, dim3(unsigned(std::max<int64_t>(nb_broad, 1))), dim3(256), 0, s, a.ents, a.n_ent, a.Q,
-                     a.objs, a.P, a.bits, a.nsurv, a.wpre, a.filt, a.dbg, a.C);
+  hipLaunchKernelGGL(k_broad, dim3(unsigned(std::max<int64_t>(nb_broad, 1))), dim3(256), 0, s, a.dc, a.ents, a.Q,
+                     a.P, a.bits, a.nsurv, a.wpre, a.filt, a.dbg, a.C);
   if (a.ev) (void)hipEventRecord(a.ev[2 * kTBroad + 1], s);
-  launch_scan(a.nsurv, a.n_ent, a.surv_off, a.bsum, s);
+  launch_scan(a.nsurv, a.n_ent, dc_count(a.dc, 0), a.surv_off, a.bsum, s);
   hipLaunchKernelGGL(k_run_tiles, dim3(unsigned(std::max<int64_t>(cdiv(a.n_run, 256), 1))), dim3(256), 0, s, a.run_off,
-                     a.surv_off, a.n_run, a.ntr);
-  launch_scan(a.ntr, a.n_run, a.tile_off, a.bsum, s);
+                     a.surv_off, a.dc, a.ntr);
+  launch_scan(a.ntr, a.n_run, dc_count(a.dc, 1), a.tile_off, a.bsum, s);
   hipLaunchKernelGGL(k_entry_parts, dim3(unsigned(std::max<int64_t>(cdiv(a.n_ent, 256), 1))), dim3(256), 0, s,
-                     a.run_off, a.ent_run, a.surv_off, a.n_ent, a.npart);
-  launch_scan(a.npart, a.n_ent, a.part_off, a.bsum, s);
+                     a.run_off, a.ent_run, a.surv_off, a.dc, a.npart);
+  launch_scan(a.npart, a.n_ent, dc_count(a.dc, 0), a.part_off, a.bsum, s);
 }
 
 }  // namespace cm

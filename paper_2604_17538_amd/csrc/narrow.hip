@@ -492,7 +492,9 @@ template <class T, bool ADJ, bool TAPE, int REP>
 __global__ __launch_bounds__(256) void k_narrow(NarrowArgs a) {
   static_assert(REP == kRepPlanes || !TAPE, "spline SDFs recompute instead of taping");
   const int l = lane();
-  const int64_t total = a.tile_off[a.n_run];
+  const int64_t n_run = a.dc->R;
+  const ObjDesc* __restrict__ objs = a.dc->objs;
+  const int64_t total = a.tile_off[n_run];
   const int64_t t_end = (ADJ && TAPE) ? min(total, a.tape_tiles) : total;
   const int64_t t_begin = (ADJ && !TAPE) ? a.t_begin : 0;
   const int64_t rs = a.tape_tiles * kWave;
@@ -506,7 +508,7 @@ __global__ __launch_bounds__(256) void k_narrow(NarrowArgs a) {
     const int64_t t = t_begin + int64_t(uint32_t(uni(int(t0))));
     if (t >= t_end) break;
     // the tile: 64 consecutive survivors of a run (one query, direction, kind)
-    const int64_t r = last_le(a.tile_off, 0, a.n_run, t);
+    const int64_t r = last_le(a.tile_off, 0, n_run, t);
     const int64_t j = t - a.tile_off[r];
     const int64_t eb = a.run_off[r], ee = a.run_off[r + 1];
     const int64_t sb = a.surv_off[eb];
@@ -519,8 +521,8 @@ __global__ __launch_bounds__(256) void k_narrow(NarrowArgs a) {
     const int c = entry_survivor(a.bits, a.wpre, E, int(sb + rk - a.surv_off[e]));
     const Entry E0 = ldc(a.ents + eb);  // query, direction, kind, objects: uniform over the run
     const QueryDev q = ldc(a.Q + E0.query);
-    const ObjDesc M = ldc(a.objs + E0.mesh_obj);
-    const ObjDesc S = ldc(a.objs + E0.sdf_obj);
+    const ObjDesc M = ldc(objs + E0.mesh_obj);
+    const ObjDesc S = ldc(objs + E0.sdf_obj);
     const PieceDesc& pd = M.pieces[E.piece];
     const int ci = E0.kind == 0 ? pd.vert_begin + c : pd.edge_begin + c;
     const float* d12 = (nT<T>() == 2) ? a.dir + 12 * int64_t(E0.query) : nullptr;
@@ -678,7 +680,7 @@ template <class T> CM_DEV BlendT<T> group_blend(const FinArgs& a, int64_t g) {
 template <class T, int WHAT>
 __global__ __launch_bounds__(256) void k_finalize(FinArgs a) {
   const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (g >= a.G) return;
+  if (g >= a.dc->G) return;
   const BlendT<T> b = group_blend<T>(a, g);
   const T iz = cst<T>(1.f) / b.Z;
   const V3<T> m = b.n * iz;
@@ -746,10 +748,10 @@ __global__ void k_dbg_weights(float* __restrict__ dbg, int64_t C, const float* _
 // L(exp([w]x) R, t + v) at zero.
 template <class T>
 __global__ __launch_bounds__(256) void k_reduce(FinArgs a, const float* __restrict__ bpartials,
-                                                const int64_t* __restrict__ group_off, int32_t n,
+                                                const int64_t* __restrict__ group_off,
                                                 float* __restrict__ grad, float* __restrict__ hv) {
   const int64_t qi = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (qi >= n) return;
+  if (qi >= a.dc->n) return;
   T acc[12];
   for (int i = 0; i < 12; ++i) acc[i] = cst<T>(0.f);
   const DevParams& P = a.P;
@@ -800,22 +802,24 @@ static inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 // Timing events bracket a group of launches: `first` records the start,
 // `last` the stop.
 template <class T, bool ADJ, bool TAPE>
-static void narrow_launch(const NarrowArgs& na, int grid, hipStream_t s, hipEvent_t* ev, bool first = true,
+static void narrow_launch(const NarrowArgs& na, int grid, int waves, hipStream_t s, hipEvent_t* ev, bool first = true,
                           bool last = true) {
+  const dim3 block(unsigned(kWave * std::min(std::max(waves, 1), 4)));  // (the kernels' bound: 256 threads)
   launch_fill_u32(na.counter, 0u, 1, s);
   const int slot = nT<T>() == 1 ? (ADJ ? kTNarrowAdj : kTNarrowFwd) : (ADJ ? kTNarrowDualAdj : kTNarrowTan);
   if (ev && first) (void)hipEventRecord(ev[2 * slot], s);
   if (na.rep == kRepSpline) {
-    if constexpr (!TAPE) hipLaunchKernelGGL((k_narrow<T, ADJ, false, kRepSpline>), dim3(unsigned(grid)), dim3(256), 0,
-                                            s, na);
+    if constexpr (!TAPE) hipLaunchKernelGGL((k_narrow<T, ADJ, false, kRepSpline>), dim3(unsigned(grid)), block, 0, s,
+                                            na);
   } else {
-    hipLaunchKernelGGL((k_narrow<T, ADJ, TAPE, kRepPlanes>), dim3(unsigned(grid)), dim3(256), 0, s, na);
+    hipLaunchKernelGGL((k_narrow<T, ADJ, TAPE, kRepPlanes>), dim3(unsigned(grid)), block, 0, s, na);
   }
   if (ev && last) (void)hipEventRecord(ev[2 * slot + 1], s);
 }
 
 static NarrowArgs narrow_args(const FwdArgs& a, float* partials, const float* dir, float* dbg) {
   NarrowArgs na{};
+  na.dc = a.dc;
   na.ents = a.ents; na.n_ent = a.n_ent; na.tile_off = a.tile_off; na.bits = a.bits; na.Q = a.Q; na.objs = a.objs;
   na.run_off = a.run_off; na.surv_off = a.surv_off; na.part_off = a.part_off; na.wpre = a.wpre; na.n_run = a.n_run;
   na.P = a.P; na.counter = a.counter; na.partials = partials; na.gscratch = a.gscratch; na.dir = dir;
@@ -827,6 +831,7 @@ static NarrowArgs narrow_args(const FwdArgs& a, float* partials, const float* di
 }
 static FinArgs fin_args(const FwdArgs& a, const float* partials, const float* dir) {
   FinArgs fa{};
+  fa.dc = a.dc;
   fa.G = a.G; fa.gent = a.gent; fa.tile_off = a.tile_off; fa.filt = a.filt; fa.partials = partials;
   fa.part_off = a.part_off; fa.q_runs = a.q_runs;
   fa.ents = a.ents; fa.Q = a.Q; fa.P = a.P; fa.out = a.out; fa.out_t = a.out_t; fa.cot = a.cot;
@@ -841,7 +846,7 @@ hipError_t launch_forward(const FwdArgs& a, hipStream_t s) {
   if (a.work) launch_fill_u32(reinterpret_cast<uint32_t*>(a.work), 0u, 4, s);
   launch_front(a, s);
   const int grid = a.n_cu * a.blocks_per_cu;
-  narrow_launch<float, false, false>(narrow_args(a, a.partials, nullptr, a.dbg), grid, s, a.ev);
+  narrow_launch<float, false, false>(narrow_args(a, a.partials, nullptr, a.dbg), grid, a.wg_waves, s, a.ev);
   hipLaunchKernelGGL((k_finalize<float, 0>), dim3(unsigned(cdiv(a.G, 256))), dim3(256), 0, s,
                      fin_args(a, a.partials, nullptr));
   if (a.dbg != nullptr)
@@ -857,10 +862,11 @@ template <class T> static hipError_t adjoint_impl(const FwdArgs& a, hipStream_t 
   if (a.work) launch_fill_u32(reinterpret_cast<uint32_t*>(a.work), 0u, 4, s);
   launch_front(a, s);
   const int grid = a.n_cu * (nT<T>() == 2 ? a.blocks_per_cu_dual : a.blocks_per_cu);
+  const int waves = nT<T>() == 2 ? a.wg_waves_dual : a.wg_waves;
   const float* dir = a.dir;
   const bool tape = a.tape != nullptr && a.tape_tiles > 0;
-  if (tape) narrow_launch<T, false, true>(narrow_args(a, a.partials, dir, nullptr), grid, s, a.ev);
-  else narrow_launch<T, false, false>(narrow_args(a, a.partials, dir, nullptr), grid, s, a.ev);
+  if (tape) narrow_launch<T, false, true>(narrow_args(a, a.partials, dir, nullptr), grid, waves, s, a.ev);
+  else narrow_launch<T, false, false>(narrow_args(a, a.partials, dir, nullptr), grid, waves, s, a.ev);
   if (records)
     hipLaunchKernelGGL((k_finalize<T, 2>), dim3(unsigned(cdiv(a.G, 256))), dim3(256), 0, s,
                        fin_args(a, a.partials, dir));
@@ -868,11 +874,11 @@ template <class T> static hipError_t adjoint_impl(const FwdArgs& a, hipStream_t 
     hipLaunchKernelGGL((k_finalize<T, 1>), dim3(unsigned(cdiv(a.G, 256))), dim3(256), 0, s,
                        fin_args(a, a.partials, dir));
   NarrowArgs nb = narrow_args(a, a.bpartials, dir, nullptr);
-  if (tape) narrow_launch<T, true, true>(nb, grid, s, a.ev, true, false);
+  if (tape) narrow_launch<T, true, true>(nb, grid, waves, s, a.ev, true, false);
   nb.t_begin = tape ? a.tape_tiles : 0;  // tiles past the tape, if any
-  narrow_launch<T, true, false>(nb, grid, s, a.ev, !tape, true);
+  narrow_launch<T, true, false>(nb, grid, waves, s, a.ev, !tape, true);
   hipLaunchKernelGGL((k_reduce<T>), dim3(unsigned(cdiv(a.n, 256))), dim3(256), 0, s, fin_args(a, a.partials, dir),
-                     a.bpartials, a.group_off, a.n, a.grad, a.hv);
+                     a.bpartials, a.group_off, a.grad, a.hv);
   return hipGetLastError();
 }
 
@@ -881,7 +887,7 @@ hipError_t launch_jvp(const FwdArgs& a, hipStream_t s) {
   if (a.work) launch_fill_u32(reinterpret_cast<uint32_t*>(a.work), 0u, 4, s);
   launch_front(a, s);
   const int grid = a.n_cu * a.blocks_per_cu_dual;
-  narrow_launch<df, false, false>(narrow_args(a, a.partials, a.dir, nullptr), grid, s, a.ev);
+  narrow_launch<df, false, false>(narrow_args(a, a.partials, a.dir, nullptr), grid, a.wg_waves_dual, s, a.ev);
   hipLaunchKernelGGL((k_finalize<df, 3>), dim3(unsigned(cdiv(a.G, 256))), dim3(256), 0, s,
                      fin_args(a, a.partials, a.dir));
   return hipGetLastError();

@@ -46,21 +46,22 @@ static void* static_scratch_ptr(int device) {
 // Bytes of launch scratch a forward pass over the plan needs; with base set,
 // points the launch arguments at their parts of it.
 static size_t forward_scratch(const cm_plan* pl, char* b, FwdArgs* a) {
-  const int64_t W = std::max<int64_t>(pl->W, 1);
+  const PlanSizes z = layout_sizes(pl);  // the batch's sizes, or a reserved plan's capacity
+  const int64_t W = std::max<int64_t>(z.W, 1);
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t r = off; off = align_up(off + bytes, 256); return r; };
   const size_t o_bits = take(8 * size_t(W));
-  const size_t o_nsurv = take(4 * size_t(pl->E));
+  const size_t o_nsurv = take(4 * size_t(z.E));
   const size_t o_wpre = take(4 * size_t(W));
-  const size_t o_soff = take(8 * size_t(pl->E + 1));
-  const size_t o_ntr = take(4 * size_t(pl->R));
-  const size_t o_npart = take(4 * size_t(pl->E));
-  const size_t o_poff = take(8 * size_t(pl->E + 1));
-  const size_t o_filt = take(16 * size_t(pl->E));
-  const size_t o_toff = take(8 * size_t(pl->R + 1));
-  const size_t o_bsum = take(8 * size_t(pl->nb + 1));
+  const size_t o_soff = take(8 * size_t(z.E + 1));
+  const size_t o_ntr = take(4 * size_t(z.R));
+  const size_t o_npart = take(4 * size_t(z.E));
+  const size_t o_poff = take(8 * size_t(z.E + 1));
+  const size_t o_filt = take(16 * size_t(z.E));
+  const size_t o_toff = take(8 * size_t(z.R + 1));
+  const size_t o_bsum = take(8 * size_t(z.nb + 1));
   const size_t o_cnt = take(256);
-  const size_t o_part = take(4 * size_t(kStride) * size_t(W + pl->E));
+  const size_t o_part = take(4 * size_t(kStride) * size_t(W + z.E));
   if (b != nullptr) {
     a->bits = reinterpret_cast<uint64_t*>(b + o_bits);
     a->nsurv = reinterpret_cast<int32_t*>(b + o_nsurv);

@@ -295,7 +295,7 @@ static void cross_edges(ObjHost& o) {
 static void finish_host(ObjHost& o, bool assign_crossing) {
   if (assign_crossing) cross_edges(o);
   else o.xedges.assign(o.pieces.size(), {});
-  o.n_planes = o.n_verts = o.n_edges = 0;
+  o.n_planes = o.n_verts = o.n_edges = o.n_words = 0;
   o.radius = 0;
   o.centres.assign(3 * o.pieces.size(), 0.0);
   o.counts.assign(2 * o.pieces.size(), 0);
@@ -307,6 +307,7 @@ static void finish_host(ObjHost& o, bool assign_crossing) {
     o.n_planes += int64_t(g.n_planes());
     o.n_verts += int64_t(g.n_verts());
     o.n_edges += int64_t(g.n_edges()) + nx;
+    o.n_words += (o.counts[2 * k] + kWave - 1) / kWave + (o.counts[2 * k + 1] + kWave - 1) / kWave;
     double c[3] = {0, 0, 0};
     for (size_t i = 0; i < g.n_verts(); ++i) {
       for (int a = 0; a < 3; ++a) c[a] += g.verts[3 * i + size_t(a)];
@@ -402,7 +403,7 @@ static cm_status register_objects(cm_context* ctx, std::vector<ObjHost>& built, 
     for (auto& t : th) t.join();
   }
   if (ctx->device < 0) {
-    std::lock_guard<std::mutex> lk(ctx->mu);
+    std::unique_lock<std::shared_mutex> lk(ctx->reg_mu);
     for (size_t i = 0; i < n; ++i) {
       built[i].alive = true;
       out[i] = cm_object(ctx->objs.size());
@@ -412,14 +413,13 @@ static cm_status register_objects(cm_context* ctx, std::vector<ObjHost>& built, 
   }
   std::vector<int32_t> ids(n);
   {
-    std::lock_guard<std::mutex> lk(ctx->mu);
+    std::unique_lock<std::shared_mutex> lk(ctx->reg_mu);
     for (size_t i = 0; i < n; ++i) {
       ObjHost& o = built[i];
       o.dmem = ctx->arena->alloc(packs[i].bytes.size(), &o.chunk);
       if (!o.dmem) {
-        ctx->err = "device allocation of object geometry failed";
         for (size_t k = 0; k < i; ++k) ctx->arena->release(built[k].chunk);
-        return CM_E_OOM;
+        return fail(ctx, CM_E_OOM, "device allocation of object geometry failed");
       }
       o.desc = make_desc(packs[i], static_cast<char*>(o.dmem));
       o.alive = true;
@@ -427,7 +427,7 @@ static cm_status register_objects(cm_context* ctx, std::vector<ObjHost>& built, 
     for (size_t i = 0; i < n; ++i) {
       hipError_t e = hipMemcpyAsync(built[i].dmem, packs[i].bytes.data(), packs[i].bytes.size(),
                                     hipMemcpyHostToDevice, ctx->build_stream);
-      if (e != hipSuccess) { ctx->err = hipGetErrorString(e); return CM_E_HIP; }
+      if (e != hipSuccess) return hip_fail(ctx, e, "object upload");
     }
     for (size_t i = 0; i < n; ++i) {
       ids[i] = int32_t(ctx->objs.size());
@@ -439,7 +439,7 @@ static cm_status register_objects(cm_context* ctx, std::vector<ObjHost>& built, 
     if (need > ctx->d_objs_cap) {
       size_t cap = std::max<size_t>(need, 2 * ctx->d_objs_cap + 64);
       ObjDesc* nd = nullptr;
-      if (hipMalloc(&nd, cap * sizeof(ObjDesc)) != hipSuccess) { ctx->err = "object table allocation failed"; return CM_E_OOM; }
+      if (hipMalloc(&nd, cap * sizeof(ObjDesc)) != hipSuccess) return fail(ctx, CM_E_OOM, "object table allocation failed");
       // the old table is kept until shutdown: kernels in flight, captured
       // graphs and a serving batch being launched may still hold its address
       // (its descriptors stay valid for the objects it lists)
@@ -450,14 +450,14 @@ static cm_status register_objects(cm_context* ctx, std::vector<ObjHost>& built, 
       for (size_t i = 0; i < need; ++i) all[i] = ctx->objs[i].desc;
       hipError_t e = hipMemcpyAsync(ctx->d_objs, all.data(), need * sizeof(ObjDesc), hipMemcpyHostToDevice,
                                     ctx->build_stream);
-      if (e != hipSuccess) { ctx->err = hipGetErrorString(e); return CM_E_HIP; }
+      if (e != hipSuccess) return hip_fail(ctx, e, "object table upload");
       (void)hipStreamSynchronize(ctx->build_stream);
     } else {
       std::vector<ObjDesc> fresh(n);
       for (size_t i = 0; i < n; ++i) fresh[i] = ctx->objs[size_t(ids[i])].desc;
       hipError_t e = hipMemcpyAsync(ctx->d_objs + ids[0], fresh.data(), n * sizeof(ObjDesc), hipMemcpyHostToDevice,
                                     ctx->build_stream);
-      if (e != hipSuccess) { ctx->err = hipGetErrorString(e); return CM_E_HIP; }
+      if (e != hipSuccess) return hip_fail(ctx, e, "object table upload");
       (void)hipStreamSynchronize(ctx->build_stream);
     }
   }
@@ -619,9 +619,9 @@ cm_status cm_build_pieces_raw(cm_context* ctx, int32_t n_pieces, const int64_t* 
 
 cm_status cm_release_object(cm_context* ctx, cm_object obj) {
   if (!ctx) return CM_E_INVALID;
-  std::lock_guard<std::mutex> lk(ctx->mu);
+  std::unique_lock<std::shared_mutex> lk(ctx->reg_mu);
   ObjHost* o = get_obj(ctx, obj);
-  if (!o) { ctx->err = "unknown object"; return CM_E_NOTFOUND; }
+  if (!o) return fail(ctx, CM_E_NOTFOUND, "unknown object");
   if (o->dmem) {
     (void)hipDeviceSynchronize();
     ctx->arena->release(o->chunk);
@@ -633,9 +633,9 @@ cm_status cm_release_object(cm_context* ctx, cm_object obj) {
 cm_status cm_object_info(cm_context* ctx, cm_object obj, int32_t* n_pieces, int64_t* n_planes, int64_t* n_verts,
                          int64_t* n_edges) {
   if (!ctx) return CM_E_INVALID;
-  std::lock_guard<std::mutex> lk(ctx->mu);
+  std::shared_lock<std::shared_mutex> lk(ctx->reg_mu);
   ObjHost* o = get_obj(ctx, obj);
-  if (!o) { ctx->err = "unknown object"; return CM_E_NOTFOUND; }
+  if (!o) return fail(ctx, CM_E_NOTFOUND, "unknown object");
   if (n_pieces) *n_pieces = int32_t(o->pieces.size());
   if (n_planes) *n_planes = o->n_planes;
   if (n_verts) *n_verts = o->n_verts;
@@ -646,9 +646,9 @@ cm_status cm_object_info(cm_context* ctx, cm_object obj, int32_t* n_pieces, int6
 cm_status cm_object_export(cm_context* ctx, cm_object obj, int64_t* plane_off, double* planes, int64_t* vert_off,
                            double* verts, int64_t* edge_off, int32_t* edges) {
   if (!ctx) return CM_E_INVALID;
-  std::lock_guard<std::mutex> lk(ctx->mu);
+  std::shared_lock<std::shared_mutex> lk(ctx->reg_mu);
   ObjHost* o = get_obj(ctx, obj);
-  if (!o) { ctx->err = "unknown object"; return CM_E_NOTFOUND; }
+  if (!o) return fail(ctx, CM_E_NOTFOUND, "unknown object");
   int64_t pb = 0, vb = 0, eb = 0;
   for (size_t k = 0; k < o->pieces.size(); ++k) {
     const PieceGeom& g = o->pieces[k];
@@ -671,9 +671,9 @@ cm_status cm_object_spline(cm_context* ctx, cm_object obj, float* coef, float* m
   if (!ctx || !meta) return fail(ctx, CM_E_INVALID, "null argument");
   ObjHost* o;
   {
-    std::lock_guard<std::mutex> lk(ctx->mu);
+    std::shared_lock<std::shared_mutex> lk(ctx->reg_mu);
     o = get_obj(ctx, obj);
-    if (!o) { ctx->err = "unknown object"; return CM_E_NOTFOUND; }
+    if (!o) return fail(ctx, CM_E_NOTFOUND, "unknown object");
   }
   if (ctx->prm.sdf_kind != 1 || ctx->device < 0) return fail(ctx, CM_E_INVALID, "not a spline object on a device");
   const int n = o->desc.gn;
@@ -690,10 +690,10 @@ cm_status cm_object_grid(cm_context* ctx, cm_object obj, float* G, float* meta) 
   if (!ctx) return CM_E_INVALID;
   ObjDesc d;
   {
-    std::lock_guard<std::mutex> lk(ctx->mu);
+    std::shared_lock<std::shared_mutex> lk(ctx->reg_mu);
     ObjHost* o = get_obj(ctx, obj);
-    if (!o) { ctx->err = "unknown object"; return CM_E_NOTFOUND; }
-    if (ctx->device < 0) { ctx->err = "host-only context has no grid"; return CM_E_INVALID; }
+    if (!o) return fail(ctx, CM_E_NOTFOUND, "unknown object");
+    if (ctx->device < 0) return fail(ctx, CM_E_INVALID, "host-only context has no grid");
     d = o->desc;
   }
   if (meta) {
@@ -716,8 +716,30 @@ static double sdf_terms(const cm_context* ctx, const ObjHost& o) {
   return ctx->prm.sdf_kind == 1 ? 64.0 : double(o.n_planes);
 }
 
+// Sizes of the plan of a batch, from the objects' counts alone (no tables).
+cm_status plan_sizes(cm_context* ctx, const cm_query* hq, int32_t n, PlanSizes* z) {
+  *z = PlanSizes{};
+  z->n = n;
+  {
+    std::shared_lock<std::shared_mutex> lk(ctx->reg_mu);
+    for (int32_t i = 0; i < n; ++i) {
+      const ObjHost* A = get_obj(ctx, hq[i].a);
+      const ObjHost* B = get_obj(ctx, hq[i].b);
+      if (!A || !B) return fail(ctx, CM_E_NOTFOUND, "query names an unknown object");
+      z->G += int64_t(A->pieces.size() + B->pieces.size());
+      z->C += A->n_verts + A->n_edges + B->n_verts + B->n_edges;
+      z->W += A->n_words + B->n_words;
+    }
+  }
+  z->E = 2 * z->G;
+  z->R = 4 * int64_t(n);
+  z->nb = (std::max(z->E, z->R) + 1023) / 1024;
+  return CM_OK;
+}
+
 // Host tables of a plan (entries sorted by estimated cost, group -> entries)
-// and the size of its device scratch.  Takes ctx->mu.
+// and the size of its device scratch.  Reads the object registry under a
+// shared lock: batches are planned concurrently.
 cm_status plan_host(cm_context* ctx, const cm_query* hq, int32_t n, cm_plan* pl, size_t* dev_bytes) {
   pl->ctx = ctx;
   pl->n = n;
@@ -736,7 +758,7 @@ cm_status plan_host(cm_context* ctx, const cm_query* hq, int32_t n, cm_plan* pl,
   cost.clear();
   const int K2 = 2 * ctx->prm.st_iters + 1;
   {
-    std::lock_guard<std::mutex> lk(ctx->mu);
+    std::shared_lock<std::shared_mutex> lk(ctx->reg_mu);
     size_t n_ent = 0;  // 2 entries (vertices, edges) per piece of either side
     for (int32_t i = 0; i < n; ++i) {
       const ObjHost* A = get_obj(ctx, hq[i].a);
@@ -748,7 +770,7 @@ cm_status plan_host(cm_context* ctx, const cm_query* hq, int32_t n, cm_plan* pl,
     for (int32_t i = 0; i < n; ++i) {
       const ObjHost* A = get_obj(ctx, hq[i].a);
       const ObjHost* B = get_obj(ctx, hq[i].b);
-      if (!A || !B) { ctx->err = "query names an unknown object"; return CM_E_NOTFOUND; }
+      if (!A || !B) return fail(ctx, CM_E_NOTFOUND, "query names an unknown object");
       pl->qa[size_t(i)] = int32_t(hq[i].a);
       pl->qb[size_t(i)] = int32_t(hq[i].b);
       const int64_t ga = int64_t(A->pieces.size()), gb = int64_t(B->pieces.size());
@@ -786,7 +808,7 @@ cm_status plan_host(cm_context* ctx, const cm_query* hq, int32_t n, cm_plan* pl,
   }
   pl->G = pl->group_off[size_t(n)];
   pl->C = pl->contact_off[size_t(n)];
-  if (pl->G >= (int64_t(1) << 31)) { std::lock_guard<std::mutex> lk(ctx->mu); ctx->err = "too many groups"; return CM_E_INVALID; }
+  if (pl->G >= (int64_t(1) << 31)) return fail(ctx, CM_E_INVALID, "too many groups");
   // runs: the entries of one (query, direction, kind), i.e. every piece of the
   // mesh side, whose survivors share tiles; costliest runs first, so their tiles
   // head the work queue, pieces in order within a run
@@ -844,33 +866,42 @@ cm_status plan_host(cm_context* ctx, const cm_query* hq, int32_t n, cm_plan* pl,
   return CM_OK;
 }
 
-// Carves the plan's device scratch out of `base` (nullptr: only sizes it).
+PlanSizes layout_sizes(const cm_plan* pl) {
+  if (pl->reserved) return pl->cap;
+  PlanSizes z;
+  z.n = pl->n; z.G = pl->G; z.C = pl->C; z.E = pl->E; z.W = pl->W; z.nb = pl->nb; z.R = pl->R;
+  return z;
+}
+
+// Carves the plan's device scratch out of `base` (nullptr: only sizes it),
+// for the batch's sizes or, reserved, for the capacity.
 size_t plan_layout(cm_plan* pl, char* b) {
-  const int64_t W = std::max<int64_t>(pl->W, 1);
+  const PlanSizes z = layout_sizes(pl);
+  const int64_t W = std::max<int64_t>(z.W, 1);
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t r = off; off = align_up(off + bytes, 256); return r; };
-  const size_t o_ents = take(sizeof(Entry) * size_t(pl->E));
-  const size_t o_gent = take(sizeof(I2) * size_t(pl->G));
+  const size_t o_ents = take(sizeof(Entry) * size_t(z.E));
+  const size_t o_gent = take(sizeof(I2) * size_t(z.G));
   const size_t o_bits = take(8 * size_t(W));
-  const size_t o_nsurv = take(4 * size_t(pl->E));
+  const size_t o_nsurv = take(4 * size_t(z.E));
   const size_t o_wpre = take(4 * size_t(W));
-  const size_t o_soff = take(8 * size_t(pl->E + 1));
-  const size_t o_roff = take(8 * size_t(pl->R + 1));
-  const size_t o_erun = take(4 * size_t(pl->E));
-  const size_t o_qrun = take(4 * size_t(pl->R));
-  const size_t o_ntr = take(4 * size_t(pl->R));
-  const size_t o_npart = take(4 * size_t(pl->E));
-  const size_t o_poff = take(8 * size_t(pl->E + 1));
-  const size_t o_filt = take(16 * size_t(pl->E));
-  const size_t o_toff = take(8 * size_t(pl->R + 1));
-  const size_t o_bsum = take(8 * size_t(pl->nb + 1));
+  const size_t o_soff = take(8 * size_t(z.E + 1));
+  const size_t o_roff = take(8 * size_t(z.R + 1));
+  const size_t o_erun = take(4 * size_t(z.E));
+  const size_t o_qrun = take(4 * size_t(z.R));
+  const size_t o_ntr = take(4 * size_t(z.R));
+  const size_t o_npart = take(4 * size_t(z.E));
+  const size_t o_poff = take(8 * size_t(z.E + 1));
+  const size_t o_filt = take(16 * size_t(z.E));
+  const size_t o_toff = take(8 * size_t(z.R + 1));
+  const size_t o_bsum = take(8 * size_t(z.nb + 1));
   const size_t o_cnt = take(256);
   // blend partials: one per (entry, tile its survivors reach): at most W + E
-  const size_t o_part = take(4 * size_t(kStride) * size_t(W + pl->E));
-  const size_t o_gs = take(4 * size_t(kGStride) * size_t(pl->G));
+  const size_t o_part = take(4 * size_t(kStride) * size_t(W + z.E));
+  const size_t o_gs = take(4 * size_t(kGStride) * size_t(z.G));
   const size_t o_bp = take(4 * size_t(kStride) * size_t(W));
-  const size_t o_goff = take(8 * size_t(pl->n + 1));
-  const size_t o_gt = take(4 * 12 * size_t(pl->n));
+  const size_t o_goff = take(8 * size_t(z.n + 1));
+  const size_t o_gt = take(4 * 12 * size_t(z.n));
   // the adjoint tape (dual values), for a quarter of the bitmask words as tiles
   // plus the partly filled last tile of each run: the broad phase leaves far
   // fewer tiles than words (a few per cent of the contacts survive), and sizing
@@ -880,7 +911,7 @@ size_t plan_layout(cm_plan* pl, char* b) {
   const int st = pl->ctx->prm.st_iters;
   const int64_t tape_slot_bytes = int64_t(std::max(pl->tape_kind, 1) * 4 * tape_values(st));
   const int64_t budget_tiles = int64_t(pl->ctx->budget / 4) / (tape_slot_bytes * kWave);
-  const int64_t want_tiles = std::min<int64_t>(W, W / 4 + pl->R);
+  const int64_t want_tiles = std::min<int64_t>(W, W / 4 + z.R);
   // (spline SDFs keep no tape: an evaluation is 64 gathers, cheap to repeat)
   pl->tape_tiles = (st <= kMaxTraceAdj && pl->tape_kind > 0 && pl->ctx->prm.sdf_kind == 0)
                        ? std::min<int64_t>(want_tiles, budget_tiles) : 0;
@@ -903,6 +934,7 @@ size_t plan_layout(cm_plan* pl, char* b) {
     pl->d_bsum = reinterpret_cast<int64_t*>(b + o_bsum);
     pl->d_counter = reinterpret_cast<uint32_t*>(b + o_cnt);
     pl->d_work = reinterpret_cast<unsigned long long*>(b + o_cnt + 8);
+    pl->d_dc = reinterpret_cast<DevCounts*>(b + o_cnt + 64);
     pl->d_partials = reinterpret_cast<float*>(b + o_part);
     pl->d_gscratch = reinterpret_cast<float*>(b + o_gs);
     pl->d_bpartials = reinterpret_cast<float*>(b + o_bp);
@@ -917,12 +949,27 @@ size_t plan_layout(cm_plan* pl, char* b) {
 // when given; the host tables live in the plan until it is destroyed).
 cm_status plan_bind(cm_plan* pl, void* dmem, hipStream_t s) {
   plan_layout(pl, static_cast<char*>(dmem));
-  hipError_t e1 = hipMemcpyAsync(pl->d_ents, pl->ents.data(), sizeof(Entry) * size_t(pl->E), hipMemcpyHostToDevice, s);
-  hipError_t e2 = hipMemcpyAsync(pl->d_gent, pl->gent.data(), sizeof(I2) * size_t(pl->G), hipMemcpyHostToDevice, s);
-  hipError_t e3 = hipMemcpyAsync(pl->d_group_off, pl->group_off.data(), 8 * size_t(pl->n + 1), hipMemcpyHostToDevice, s);
-  hipError_t e4 = hipMemcpyAsync(pl->d_run_off, pl->run_off.data(), 8 * size_t(pl->R + 1), hipMemcpyHostToDevice, s);
-  hipError_t e5 = hipMemcpyAsync(pl->d_ent_run, pl->ent_run.data(), 4 * size_t(pl->E), hipMemcpyHostToDevice, s);
-  hipError_t e6 = hipMemcpyAsync(pl->d_q_runs, pl->q_runs.data(), 4 * size_t(pl->R), hipMemcpyHostToDevice, s);
+  pl->h_dc = DevCounts{};
+  pl->h_dc.E = pl->E;
+  pl->h_dc.R = pl->R;
+  pl->h_dc.G = pl->G;
+  pl->h_dc.n = pl->n;
+  {
+    std::shared_lock<std::shared_mutex> lk(pl->ctx->reg_mu);  // the table may be replaced by a concurrent build
+    pl->h_dc.objs = pl->ctx->d_objs;
+  }
+  if (hipMemcpyAsync(pl->d_dc, &pl->h_dc, sizeof(DevCounts), hipMemcpyHostToDevice, s) != hipSuccess)
+    return fail(pl->ctx, CM_E_HIP, "plan upload failed");
+  // (an empty batch of a reserved plan uploads its counts and offsets only)
+  auto up = [&](void* dst, const void* src, size_t bytes) {
+    return bytes ? hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s) : hipSuccess;
+  };
+  hipError_t e1 = up(pl->d_ents, pl->ents.data(), sizeof(Entry) * size_t(pl->E));
+  hipError_t e2 = up(pl->d_gent, pl->gent.data(), sizeof(I2) * size_t(pl->G));
+  hipError_t e3 = up(pl->d_group_off, pl->group_off.data(), 8 * size_t(pl->n + 1));
+  hipError_t e4 = pl->R ? up(pl->d_run_off, pl->run_off.data(), 8 * size_t(pl->R + 1)) : hipSuccess;
+  hipError_t e5 = up(pl->d_ent_run, pl->ent_run.data(), 4 * size_t(pl->E));
+  hipError_t e6 = up(pl->d_q_runs, pl->q_runs.data(), 4 * size_t(pl->R));
   if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess || e4 != hipSuccess || e5 != hipSuccess ||
       e6 != hipSuccess)
     return fail(pl->ctx, CM_E_HIP, "plan upload failed");
@@ -954,12 +1001,97 @@ cm_status cm_plan_create(cm_context* ctx, const cm_query* hq, int32_t n, cm_plan
   return CM_OK;
 }
 
+cm_status cm_plan_reserve(cm_context* ctx, int32_t max_queries, int64_t max_groups, int64_t max_contacts,
+                          cm_plan** out) {
+  if (!ctx || !out || max_queries <= 0 || max_groups <= 0 || max_contacts < 0)
+    return fail(ctx, CM_E_INVALID, "bad arguments");
+  *out = nullptr;
+  if (ctx->device < 0) return fail(ctx, CM_E_INVALID, "host-only context cannot run queries");
+  if (max_groups > (int64_t(1) << 30) || max_contacts > (int64_t(1) << 40))
+    return fail(ctx, CM_E_INVALID, "capacity beyond the entry index range");
+  auto* pl = new cm_plan;
+  pl->ctx = ctx;
+  pl->reserved = true;
+  PlanSizes& c = pl->cap;
+  c.n = max_queries;
+  c.G = max_groups;
+  c.C = max_contacts;
+  c.E = 2 * max_groups;                     // a vertex and an edge entry per group
+  c.R = 4 * int64_t(max_queries);           // (direction, kind) runs per query
+  c.W = (max_contacts + kWave - 1) / kWave + c.E;  // an entry's words: at most count / 64 + 1
+  c.nb = (std::max(c.E, c.R) + 1023) / 1024;
+  pl->group_off.assign(1, 0);  // the empty batch
+  pl->contact_off.assign(1, 0);
+  const size_t bytes = plan_layout(pl, nullptr);
+  if (hipMalloc(&pl->dmem, bytes) != hipSuccess) { delete pl; return fail(ctx, CM_E_OOM, "plan allocation failed"); }
+  pl->owns_mem = true;
+  cm_status st = plan_bind(pl, pl->dmem, nullptr);  // an empty batch
+  if (st == CM_OK && (hipDeviceSynchronize() != hipSuccess || hipEventCreateWithFlags(&pl->uploaded, hipEventDisableTiming) != hipSuccess))
+    st = fail(ctx, CM_E_HIP, "plan set-up failed");
+  if (st != CM_OK) {
+    (void)hipFree(pl->dmem);
+    delete pl;
+    return st;
+  }
+  *out = pl;
+  return CM_OK;
+}
+
+cm_status cm_plan_refill(cm_context* ctx, cm_plan* pl, const cm_query* hq, int32_t n, void* stream) {
+  if (!ctx || !pl || pl->ctx != ctx || n < 0 || (n > 0 && !hq)) return fail(ctx, CM_E_INVALID, "bad arguments");
+  if (!pl->reserved) return fail(ctx, CM_E_INVALID, "cm_plan_refill needs a plan made by cm_plan_reserve");
+  // the previous refill's uploads read the host tables about to be replaced
+  if (hipEventSynchronize(pl->uploaded) != hipSuccess) return fail(ctx, CM_E_HIP, "waiting for the last refill");
+  cm_plan tmp;
+  tmp.tape_kind = pl->tape_kind;
+  if (n > 0) {
+    size_t bytes = 0;
+    const cm_status st = plan_host(ctx, hq, n, &tmp, &bytes);
+    if (st != CM_OK) return st;
+  } else {
+    tmp.ctx = ctx;
+    tmp.group_off.assign(1, 0);
+    tmp.contact_off.assign(1, 0);
+  }
+  const PlanSizes& c = pl->cap;
+  if (tmp.n > c.n || tmp.G > c.G || tmp.C > c.C)
+    return fail(ctx, CM_E_INVALID,
+                "batch of " + std::to_string(tmp.n) + " queries, " + std::to_string(tmp.G) + " groups, " +
+                    std::to_string(tmp.C) + " contacts exceeds the plan's capacity (" + std::to_string(c.n) + ", " +
+                    std::to_string(c.G) + ", " + std::to_string(c.C) + ")");
+  pl->n = tmp.n; pl->G = tmp.G; pl->C = tmp.C; pl->E = tmp.E; pl->W = tmp.W; pl->R = tmp.R; pl->nb = tmp.nb;
+  pl->group_off.swap(tmp.group_off);
+  pl->contact_off.swap(tmp.contact_off);
+  pl->ents.swap(tmp.ents);
+  pl->run_off.swap(tmp.run_off);
+  pl->ent_run.swap(tmp.ent_run);
+  pl->q_runs.swap(tmp.q_runs);
+  pl->gent.swap(tmp.gent);
+  pl->qa.swap(tmp.qa);
+  pl->qb.swap(tmp.qb);
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  const cm_status st = plan_bind(pl, pl->dmem, s);
+  if (st != CM_OK) return st;
+  if (hipEventRecord(pl->uploaded, s) != hipSuccess) return fail(ctx, CM_E_HIP, "refill event");
+  return CM_OK;
+}
+
+cm_status cm_plan_capacity(const cm_plan* pl, int32_t* max_queries, int64_t* max_groups, int64_t* max_contacts) {
+  if (!pl) return CM_E_INVALID;
+  const PlanSizes z = layout_sizes(pl);
+  if (max_queries) *max_queries = z.n;
+  if (max_groups) *max_groups = z.G;
+  if (max_contacts) *max_contacts = z.C;
+  return CM_OK;
+}
+
 cm_status cm_plan_destroy(cm_plan* pl) {
   if (!pl) return CM_E_INVALID;
   if (pl->dmem && pl->owns_mem) {
     (void)hipDeviceSynchronize();
     (void)hipFree(pl->dmem);
   }
+  if (pl->uploaded) (void)hipEventDestroy(pl->uploaded);
   for (auto& e : pl->ev)
     if (e) (void)hipEventDestroy(e);
   delete pl;
@@ -1045,11 +1177,13 @@ cm_status cm_plan_stats(const cm_plan* pl, int64_t* st) {  // 8 entries
 namespace cm {
 FwdArgs fwd_args(cm_context* ctx, cm_plan* pl, const cm_query* q, const cm_groups& out, float* dbg) {
   FwdArgs a{};
+  const PlanSizes z = layout_sizes(pl);  // grids and record strides: the capacity
+  a.dc = pl->d_dc;
   a.ents = pl->d_ents;
-  a.n_ent = pl->E;
+  a.n_ent = z.E;
   a.Q = reinterpret_cast<const QueryDev*>(q);
   {
-    std::lock_guard<std::mutex> lk(ctx->mu);  // the table may be replaced by a concurrent build
+    std::shared_lock<std::shared_mutex> lk(ctx->reg_mu);  // the table may be replaced by a concurrent build
     a.objs = ctx->d_objs;
   }
   a.P = ctx->dp;
@@ -1063,24 +1197,26 @@ FwdArgs fwd_args(cm_context* ctx, cm_plan* pl, const cm_query* q, const cm_group
   a.ntr = pl->d_ntr;
   a.npart = pl->d_npart;
   a.part_off = pl->d_part_off;
-  a.n_run = pl->R;
+  a.n_run = z.R;
   a.filt = pl->d_filt;
   a.bsum = pl->d_bsum;
   a.tile_off = pl->d_tile_off;
   a.counter = pl->d_counter;
   a.partials = pl->d_partials;
   a.gent = pl->d_gent;
-  a.G = pl->G;
+  a.G = z.G;
   a.out = OutPtrs{out.p, out.n, out.d, out.q, out.W, out.logZ};
   a.dbg = dbg;
   a.C = pl->C;
   a.n_cu = ctx->n_cu;
   a.blocks_per_cu = pl->blocks_per_cu;
   a.blocks_per_cu_dual = pl->blocks_per_cu_dual;
+  a.wg_waves = pl->wg_waves;
+  a.wg_waves_dual = pl->wg_waves_dual;
   a.gscratch = pl->d_gscratch;
   a.bpartials = pl->d_bpartials;
   a.group_off = pl->d_group_off;
-  a.n = pl->n;
+  a.n = z.n;
   a.ev = pl->timing ? pl->ev : nullptr;
   a.work = pl->d_work;
   a.tape = pl->d_tape;
@@ -1155,7 +1291,7 @@ cm_status cm_project_points(cm_context* ctx, cm_plan* pl, const cm_query* q, con
   if (!ctx || !pl || pl->ctx != ctx || !q || !p_in || !p_out) return fail(ctx, CM_E_INVALID, "bad arguments");
   const ObjDesc* objs;
   {
-    std::lock_guard<std::mutex> lk(ctx->mu);
+    std::shared_lock<std::shared_mutex> lk(ctx->reg_mu);
     objs = ctx->d_objs;
   }
   hipError_t e = launch_project(reinterpret_cast<const QueryDev*>(q), objs, pl->d_group_off, pl->n, ctx->dp, p_in,

@@ -10,6 +10,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <shared_mutex>
 #include <string>
 #include <thread>
 #include <vector>
@@ -51,6 +52,7 @@ struct ObjHost {
   // (edge assignment of Sec. IV-D.1; empty unless cm_params.edge_assign)
   std::vector<std::vector<int32_t>> xedges;
   int64_t n_planes = 0, n_verts = 0, n_edges = 0;
+  int64_t n_words = 0;  // survivor bitmask words of its entries (per piece and kind: count / 64 rounded up)
   double radius = 0;
   void* dmem = nullptr;
   int chunk = -1;
@@ -68,8 +70,12 @@ struct cm_context {
   cm::DevParams dp{};
   int n_cu = 0;
   size_t budget = 0;
-  std::mutex mu;             // registry + error string
+  std::mutex mu;             // error string, serving start
   std::string err;
+  // the object registry (objs, d_objs, d_objs_cap, old_tables): shared by
+  // planners and launches, exclusive for registration and release; taken
+  // before mu when both are held
+  std::shared_mutex reg_mu;
   std::vector<cm::ObjHost> objs;
   cm::ObjDesc* d_objs = nullptr;  // device table
   size_t d_objs_cap = 0;
@@ -79,10 +85,24 @@ struct cm_context {
   cm::Serving* serving = nullptr;
 };
 
+namespace cm {
+// Sizes a plan's device memory is laid out for: the batch's own, or the
+// capacity of a reserved plan (cm_plan_reserve), whose batch can be replaced.
+struct PlanSizes {
+  int32_t n = 0;
+  int64_t G = 0, C = 0, E = 0, W = 0, nb = 0, R = 0;
+};
+}  // namespace cm
+
 struct cm_plan {
   cm_context* ctx = nullptr;
   int32_t n = 0;
   int64_t G = 0, C = 0, E = 0, W = 0, nb = 0, R = 0;
+  bool reserved = false;             // laid out for `cap`; cm_plan_refill replaces the batch
+  cm::PlanSizes cap;
+  cm::DevCounts h_dc{};              // the batch's counts and object table, uploaded with the tables
+  cm::DevCounts* d_dc = nullptr;
+  hipEvent_t uploaded = nullptr;     // reserved plans: the last refill's uploads are done
   std::vector<int64_t> group_off, contact_off;
   std::vector<cm::Entry> ents;       // host copy (device order: runs in cost order)
   std::vector<int64_t> run_off;      // [R + 1] entry ranges of the runs (query, direction, kind)
@@ -121,6 +141,8 @@ struct cm_plan {
   int32_t tape_kind = 2;
   int32_t blocks_per_cu = 8;       // persistent workgroups per CU, float sweeps (cm_plan_autotune)
   int32_t blocks_per_cu_dual = 8;  // the same for the sweeps in dual numbers
+  int32_t wg_waves = 4;            // waves per workgroup of the narrow sweeps, float
+  int32_t wg_waves_dual = 4;       // the same in dual numbers
   bool timing = false;
   uint32_t timed_mask = 0;  // timing slots launched by the last pass
   hipEvent_t ev[2 * cm::kTimed] = {};
@@ -131,7 +153,9 @@ cm_status fail(cm_context* ctx, cm_status st, const std::string& msg);
 cm_status hip_fail(cm_context* ctx, hipError_t e, const char* where);
 ObjHost* get_obj(cm_context* ctx, cm_object h);
 cm_status plan_host(cm_context* ctx, const cm_query* hq, int32_t n, cm_plan* pl, size_t* dev_bytes);
+cm_status plan_sizes(cm_context* ctx, const cm_query* hq, int32_t n, PlanSizes* z);
 size_t plan_layout(cm_plan* pl, char* base);
+PlanSizes layout_sizes(const cm_plan* pl);
 cm_status plan_bind(cm_plan* pl, void* dmem, hipStream_t s);
 FwdArgs fwd_args(cm_context* ctx, cm_plan* pl, const cm_query* q, const cm_groups& out, float* dbg);
 hipError_t static_scratch_setup(int device);  // noalloc.hip

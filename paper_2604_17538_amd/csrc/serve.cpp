@@ -3,7 +3,8 @@
 // cm_submit copies a request (host queries, optional cotangents) into the
 // pending queue.  A scheduler thread, started on the first submit, keeps up to
 // kSlots batches in flight on their own streams: whenever a slot is free it
-// admits pending requests in arrival order while the device memory the slots
+// admits pending requests in arrival order (sized at submit from the objects'
+// counts) while the device memory the slots
 // hold stays within the context's budget (each request's plan scratch and
 // buffers estimated as the plan lays them out; a slot's buffer is sized to its
 // batch, and idle slots give theirs back when a batch needs the room), packs
@@ -11,7 +12,9 @@
 // requests and the gradient pass (one forward sweep that also writes the
 // records, and the adjoint) over those that asked for a gradient, and copies
 // the results back into pinned staging.  Batches on
-// different streams overlap; the next batch is formed while others run.
+// different streams overlap; each slot's batch is planned and launched by the
+// slot's own worker thread (planners share the object registry under a
+// reader lock), so batches are planned concurrently while others run.
 // Completion is detected with events; results are scattered to the callers'
 // buffers and the tickets are marked done.  A query's results depend only on
 // that query (fixed-order reductions), so they are the same alone and mixed.
@@ -58,7 +61,10 @@ struct Slot {
   size_t dcap = 0;
   char* pinned = nullptr;
   size_t pcap = 0;
-  bool busy = false;
+  bool busy = false;     // admitted requests: being planned or on the device
+  bool running = false;  // launched: the scheduler polls its event
+  std::thread worker;    // plans and launches the slot's batches
+  std::condition_variable wcv;
   std::vector<Req*> reqs;
   std::unique_ptr<cm_plan> pf, pg;  // forward plan (forward-only requests), adjoint plan (gradient requests)
   size_t bytes = 0;
@@ -81,6 +87,7 @@ struct Serving {
   size_t inflight = 0;            // estimated bytes of the admitted requests
   size_t held = 0, peak_held = 0;  // device bytes the slots' buffers hold (never above the budget)
   bool stop = false;
+  bool quit_workers = false;
   cm_ticket next = 1;
   int64_t n_submitted = 0, n_completed = 0, n_batches = 0, n_queries = 0;
   std::vector<double> latencies;  // seconds from submit to results written, in completion order
@@ -94,11 +101,25 @@ namespace {
 // forward request joins the forward plan (no tape); a gradient request joins
 // the adjoint plan (a tape of float values), whose forward sweep also writes
 // its records, and brings cotangents and a gradient buffer.
-size_t request_bytes(cm_plan& pl, bool grad) {
-  pl.tape_kind = grad ? 1 : 0;
-  size_t b = plan_layout(&pl, nullptr) + 64 * size_t(pl.n) + 48 * size_t(pl.G);  // plan, queries, records
-  if (grad) b += 48 * size_t(pl.G) + 48 * size_t(pl.n);                        // cotangents, gradient
+size_t request_bytes(cm_context* ctx, const PlanSizes& z, bool grad) {
+  cm_plan probe;  // laid out for the request's sizes (no tables are built)
+  probe.ctx = ctx;
+  probe.reserved = true;
+  probe.cap = z;
+  probe.tape_kind = grad ? 1 : 0;
+  size_t b = plan_layout(&probe, nullptr) + 64 * size_t(z.n) + 48 * size_t(z.G);  // plan, queries, records
+  if (grad) b += 48 * size_t(z.G) + 48 * size_t(z.n);                             // cotangents, gradient
   return b + kSlackPerRequest;
+}
+
+// Device bytes slot t holds, or, once admitted, will hold for its batch (its
+// worker sizes the buffer after admission).  Called with S->mu held.
+size_t claim(const Slot& t) { return t.busy ? std::max(t.dcap, align_up(t.bytes, kDevGranule)) : t.dcap; }
+size_t claims_except(const Serving* S, const Slot* s) {
+  size_t c = 0;
+  for (const Slot& t : S->slots)
+    if (&t != s) c += claim(t);
+  return c;
 }
 
 // Frees the buffers of idle slots other than `keep` (their last batch has
@@ -115,14 +136,14 @@ void release_idle(Serving* S, const Slot* keep) {
 }
 
 // Sizes the slot's device buffer for a batch of `bytes` (exactly, in MiB
-// granules; a larger buffer is kept) so that the slots together never hold
-// more than the budget.
+// granules; a larger buffer is kept) so that what the slots hold and have
+// been admitted to hold never exceeds the budget.
 bool ensure_device(Serving* S, Slot& s, size_t bytes) {
   if (s.dcap >= bytes) return true;
   const size_t want = align_up(bytes, kDevGranule);
   std::lock_guard<std::mutex> lk(S->mu);
-  if (S->held - s.dcap + want > S->ctx->budget) release_idle(S, &s);
-  if (S->held - s.dcap + want > S->ctx->budget) return false;
+  if (claims_except(S, &s) + want > S->ctx->budget) release_idle(S, &s);
+  if (claims_except(S, &s) + want > S->ctx->budget) return false;
   if (s.dmem) {
     (void)hipStreamSynchronize(s.stream);
     (void)hipFree(s.dmem);
@@ -264,6 +285,43 @@ void scatter(Slot& s) {
   }
 }
 
+// Marks the slot's requests done with `st` and frees the slot.  Called with S->mu held.
+void finish_slot(Serving* S, Slot& s, cm_status st, double t_done, bool record) {
+  for (Req* r : s.reqs) {
+    S->finished[r->id] = st;
+    S->live.erase(r->id);
+    S->n_completed++;
+    if (record) {
+      S->n_queries += int64_t(r->q.size());
+      if (S->latencies.size() < (size_t(1) << 24)) S->latencies.push_back(t_done - r->t_submit);
+    }
+    delete r;
+  }
+  s.reqs.clear();
+  S->inflight -= s.bytes;
+  s.bytes = 0;
+  s.busy = false;
+  s.running = false;
+  S->done_cv.notify_all();
+}
+
+// A slot's worker: plans and launches each batch the scheduler admits into
+// the slot, then hands it back for completion polling.
+void worker(Serving* S, Slot* s) {
+  (void)hipSetDevice(S->ctx->device);
+  std::unique_lock<std::mutex> lk(S->mu);
+  for (;;) {
+    s->wcv.wait(lk, [&] { return (s->busy && !s->running) || S->quit_workers; });
+    if (!(s->busy && !s->running)) break;
+    lk.unlock();
+    const cm_status st = launch_batch(S, S->ctx, *s);
+    lk.lock();
+    if (st == CM_OK) s->running = true;
+    else finish_slot(S, *s, st, 0.0, false);
+    S->cv.notify_all();
+  }
+}
+
 void scheduler(Serving* S) {
   cm_context* ctx = S->ctx;
   (void)hipSetDevice(ctx->device);
@@ -272,7 +330,7 @@ void scheduler(Serving* S) {
     bool progressed = false;
     // completions
     for (Slot& s : S->slots) {
-      if (!s.busy) continue;
+      if (!s.running) continue;
       hipError_t q = hipEventQuery(s.done);
       if (q == hipErrorNotReady) continue;
       const cm_status st = q == hipSuccess ? CM_OK : CM_E_HIP;
@@ -280,20 +338,8 @@ void scheduler(Serving* S) {
       if (st == CM_OK) scatter(s);
       const double t_done = now_s();
       lk.lock();
-      for (Req* r : s.reqs) {
-        S->finished[r->id] = st;
-        S->live.erase(r->id);
-        S->n_completed++;
-        S->n_queries += int64_t(r->q.size());
-        if (S->latencies.size() < (size_t(1) << 24)) S->latencies.push_back(t_done - r->t_submit);
-        delete r;
-      }
-      s.reqs.clear();
-      S->inflight -= s.bytes;
-      s.bytes = 0;
-      s.busy = false;
+      finish_slot(S, s, st, t_done, true);
       progressed = true;
-      S->done_cv.notify_all();
     }
     // admission into free slots: a batch may use the budget less what the
     // other slots hold (idle slots give their buffers back when it is short)
@@ -303,11 +349,16 @@ void scheduler(Serving* S) {
       int64_t nq = 0;
       while (!S->pending.empty()) {
         Req* r = S->pending.front();
-        const size_t room = ctx->budget - (S->held - s.dcap);
-        bool fits = bytes + r->bytes <= room;
+        // what the other slots hold or were admitted to hold (batches still
+        // being planned by their workers included)
+        auto room = [&]() {
+          const size_t o = claims_except(S, &s);
+          return ctx->budget > o ? ctx->budget - o : size_t(0);
+        };
+        bool fits = align_up(bytes + r->bytes, kDevGranule) <= room();
         if (!fits && s.reqs.empty()) {
           release_idle(S, &s);
-          fits = r->bytes <= ctx->budget - (S->held - s.dcap);
+          fits = align_up(r->bytes, kDevGranule) <= room();
         }
         if (!s.reqs.empty() && (!fits || nq + int64_t(r->q.size()) > kMaxBatchQueries)) break;
         if (s.reqs.empty() && !fits) break;  // wait for busy slots to finish
@@ -321,22 +372,7 @@ void scheduler(Serving* S) {
       s.bytes = bytes;
       S->inflight += bytes;
       S->n_batches++;
-      lk.unlock();
-      const cm_status st = launch_batch(S, ctx, s);
-      lk.lock();
-      if (st != CM_OK) {
-        for (Req* r : s.reqs) {
-          S->finished[r->id] = st;
-          S->live.erase(r->id);
-          S->n_completed++;
-          delete r;
-        }
-        s.reqs.clear();
-        S->inflight -= s.bytes;
-        s.bytes = 0;
-        s.busy = false;
-        S->done_cv.notify_all();
-      }
+      s.wcv.notify_one();  // the slot's worker plans and launches it
       progressed = true;
     }
     bool any_busy = false;
@@ -359,6 +395,7 @@ Serving* start(cm_context* ctx) {
       return nullptr;
     }
   }
+  for (Slot& s : S->slots) s.worker = std::thread(worker, S, &s);
   S->th = std::thread(scheduler, S);
   return S;
 }
@@ -380,7 +417,15 @@ void serving_stop(cm_context* ctx) {
     S->pending.clear();
   }
   S->cv.notify_all();
-  S->th.join();
+  S->th.join();  // (returns once no slot is busy: the workers are waiting)
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->quit_workers = true;
+  }
+  for (Slot& s : S->slots) {
+    s.wcv.notify_all();
+    if (s.worker.joinable()) s.worker.join();
+  }
   for (Slot& s : S->slots) {
     if (s.dmem) (void)hipFree(s.dmem);
     if (s.pinned) (void)hipHostFree(s.pinned);
@@ -416,12 +461,11 @@ cm_status cm_submit(cm_context* ctx, const cm_request* req, cm_ticket* ticket) {
   r->out_grad = req->out_grad;
   r->t_submit = now_s();
   {
-    cm_plan probe;
-    size_t b = 0;
-    cm_status st = plan_host(ctx, r->q.data(), req->n, &probe, &b);
+    PlanSizes z;
+    cm_status st = plan_sizes(ctx, r->q.data(), req->n, &z);
     if (st != CM_OK) { delete r; return st; }
-    r->G = probe.G;
-    r->bytes = request_bytes(probe, r->grad);
+    r->G = z.G;
+    r->bytes = request_bytes(ctx, z, r->grad);
   }
   if (r->bytes > ctx->budget) { delete r; return fail(ctx, CM_E_OOM, "request exceeds the memory budget on its own"); }
   if (r->grad) r->cot.assign(req->cotangent, req->cotangent + 12 * r->G);
