@@ -87,6 +87,11 @@ typedef struct {
                            paper's two alternatives, Sec. III):
                            0: smooth union of smooth intersections of the pieces'
                               hull half-spaces (Sec. III-A.2/3);
+                           2: primitives (Sec. III-A), set per object by
+                              cm_object_set_prims (its pieces stay the mesh side):
+                              PSQs and XPSQs folded by smooth union, subtraction and
+                              intersection.  No broad-phase bound (every contact is
+                              evaluated) and no adjoint tape;
                            1: cubic spline (Sec. III-B): the ground-truth SDF and
                               normal of the pieces (closest point on their hulls,
                               phi = min over pieces) sampled at the (grid_res + 1)^3
@@ -105,6 +110,9 @@ typedef struct {
                            positive length, > 1e-9 of the object's scale, inside that
                            piece's hull), after the piece's own edges.  Vertices stay
                            with their own piece.  cm_object_export lists own edges. */
+  float tau_t;          /* primitives: soft clip of the spline parameter t to (0, 1) */
+  float tau_disc;       /* primitives: softplus and sigmoid of the projection cubic's
+                           discriminant (both dimensionless) */
 } cm_params;
 
 /* A pair-query: objects and poses (body -> world). 64 bytes. */
@@ -123,7 +131,8 @@ typedef struct {
 /* Constants scaled with a length L_ref (metres): tau = 0.01 L_ref (all four
  * smoothing temperatures), tau_blend = 0.02 L_ref, d_max = 0.05 L_ref,
  * eps_t = 0.025 L_ref, eps_n = 1e-6, K = 3, 32^3 grid with margin
- * 0.1 L_ref + 1.0 * radius, Hilbert serialization, broad phase on, edge_bound 0. */
+ * 0.1 L_ref + 1.0 * radius, Hilbert serialization, broad phase on, edge_bound 0,
+ * tau_t = 0.01, tau_disc = 1e-3. */
 cm_status cm_default_params(float L_ref, cm_params* out);
 
 /* Creates a context on HIP device `device` (-1: host-only context that builds
@@ -173,6 +182,31 @@ cm_status cm_object_grid(cm_context* ctx, cm_object obj, float* G, float* meta);
  * (i (n+3) + j) (n+3) + k; may be NULL) and meta = n, box origin (3), cell
  * size (3).  Its grid (cm_object_grid) holds the per-cell lower bounds. */
 cm_status cm_object_spline(cm_context* ctx, cm_object obj, float* coef, float* meta);
+
+/* The SDF side of an object of a primitive context (sdf_kind 2) as n
+ * primitives (Sec. III-A), records of 32 doubles (host):
+ *   [0] kind: 0 PSQ (a superquadric intersected with half-spaces, at a fixed
+ *       pose), 1 XPSQ (a PSQ swept along the quadratic spline
+ *       p(t) = (1-t)^2 p1 + 2t(1-t) p2 + t^2 p3, t in [0, 1]);
+ *   [1] op: how it joins the primitives before it: 0 smooth union (tau_cup),
+ *       1 smooth subtraction, 2 smooth intersection (tau_cap); ignored for the
+ *       first;
+ *   [2..4] PSQ centre / XPSQ p1, [5..7] p2, [8..10] p3 (object frame);
+ *   [11..14] PSQ rotation (unit quaternion w, x, y, z: PSQ frame -> object);
+ *   [15..17] superquadric scales a, [18..19] exponents (eps1, eps2), at t = 0
+ *       (PSQ: the superquadric); [20..22], [23..24] the same at t = 1 (XPSQ,
+ *       linear in t); [25..31] unused.
+ * The superquadric's SDF is its radial distance |x| (1 - f(x)^(-eps1/2)) (f the
+ * inside-outside function of Sec. III-A.1; exact for a sphere).  An XPSQ's PSQ
+ * frame is the spline's Frenet frame: x along the in-plane normal, y along
+ * the binormal (B x A, A = p1 - 2 p2 + p3, B = 2 (p2 - p1)), z along the
+ * tangent; its spline must be curved.  Half-spaces planes[4 plane_off[i] ..
+ * 4 plane_off[i + 1]) (n, h; n.x + h <= 0 inside; normalised here) in each PSQ
+ * frame, plane_off[0] = 0.  Replaces the object's earlier primitives
+ * (synchronous).  CM_E_INVALID for a bad record or a context of another
+ * sdf_kind; CM_E_NOTFOUND for an unknown object. */
+cm_status cm_object_set_prims(cm_context* ctx, cm_object obj, int32_t n, const double* rec, const int64_t* plane_off,
+                              const double* planes);
 
 /* A plan fixes the objects of a batch of n pair-queries (poses are read at run
  * time from the device query array) and owns the scratch of the batched

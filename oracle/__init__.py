@@ -298,7 +298,10 @@ def spline_operator(n: int) -> np.ndarray:
 def from_workload_object(o) -> Obj:
     """Oracle object from a generator object (point clouds or explicit pieces)."""
     if hasattr(o, "points"):
-        return from_points(o.offsets, o.points)
+        ob = from_points(o.offsets, o.points)
+        if getattr(o, "prim_rec", None) is not None:  # primitive objects: the SDF side (Sec. III-A)
+            ob.set_prims(o.prim_rec, o.prim_plane_off, o.prim_planes)
+        return ob
     return Obj(o.plane_off, o.planes, o.vert_off, o.verts, o.edge_off, o.edges)
 
 

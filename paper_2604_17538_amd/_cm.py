@@ -37,7 +37,8 @@ class cm_params(ctypes.Structure):
                 ("tau_cap", "tau_cup", "tau_st", "tau_clip", "tau_blend", "d_max", "eps_t", "eps_n",
                  "grid_margin", "grid_margin_rel")] + \
                [(n, ctypes.c_int32) for n in ("st_iters", "grid_res", "curve", "broad_phase", "edge_bound", "prune_pieces",
-                                              "sdf_kind", "edge_assign")]
+                                              "sdf_kind", "edge_assign")] + \
+               [(n, ctypes.c_float) for n in ("tau_t", "tau_disc")]
 
 
 class cm_groups(ctypes.Structure):
@@ -79,6 +80,7 @@ cm_object_info = _sig("cm_object_info", I32, [P, U32, ctypes.POINTER(I32), ctype
 cm_object_export = _sig("cm_object_export", I32, [P, U32, P, P, P, P, P, P])
 cm_object_grid = _sig("cm_object_grid", I32, [P, U32, P, P])
 cm_object_spline = _sig("cm_object_spline", I32, [P, U32, P, P])
+cm_object_set_prims = _sig("cm_object_set_prims", I32, [P, U32, I32, P, P, P])
 cm_plan_create = _sig("cm_plan_create", I32, [P, P, I32, PP])
 cm_plan_destroy = _sig("cm_plan_destroy", I32, [P])
 cm_plan_reserve = _sig("cm_plan_reserve", I32, [P, I32, I64, I64, PP])
@@ -112,7 +114,7 @@ cm_serve_stats = _sig("cm_serve_stats", I32, [P, P])
 cm_serve_latencies = _sig("cm_serve_latencies", I32, [P, P, I64, ctypes.POINTER(I64)])
 
 EXPORTED = ["cm_default_params", "cm_init", "cm_shutdown", "cm_last_error", "cm_build_pieces", "cm_build_objects",
-            "cm_build_pieces_raw", "cm_release_object", "cm_object_info", "cm_object_export", "cm_object_grid", "cm_object_spline",
+            "cm_build_pieces_raw", "cm_release_object", "cm_object_info", "cm_object_export", "cm_object_grid", "cm_object_spline", "cm_object_set_prims",
             "cm_plan_create", "cm_plan_destroy", "cm_plan_reserve", "cm_plan_refill", "cm_plan_capacity", "cm_plan_info", "cm_plan_offsets", "cm_plan_stats", "cm_plan_work",
             "cm_plan_set_timing", "cm_plan_timing",
             "cm_contacts_fwd", "cm_contacts_fwd_noalloc", "cm_contacts_bwd", "cm_hvp", "cm_contacts_jvp", "cm_project_points",

@@ -124,6 +124,11 @@ class Context:
         for i, o in enumerate(objects):
             if not hasattr(o, "points"):
                 out[i] = self.build_raw(o.plane_off, o.planes, o.vert_off, o.verts, o.edge_off, o.edges)
+        # primitive objects (contexts with sdf_kind = 2): their SDF side
+        if self.params.sdf_kind == 2:
+            for i, o in enumerate(objects):
+                if getattr(o, "prim_rec", None) is not None:
+                    self.object_set_prims(int(out[i]), o.prim_rec, o.prim_plane_off, o.prim_planes)
         return out
 
     def release(self, h: int):
@@ -160,6 +165,16 @@ class Context:
         C = np.zeros(((n + 3) ** 3, 4), np.float32)
         self._check(_cm.cm_object_spline(self._h, int(h), _ptr(C), _ptr(meta)), "cm_object_spline")
         return n, meta[1:4].astype(np.float64), meta[4:7].astype(np.float64), C.T.reshape(4, n + 3, n + 3, n + 3)
+
+    def object_set_prims(self, h: int, rec, plane_off, planes):
+        """The SDF side of object h as primitives (cm_object_set_prims; contexts
+        with sdf_kind = 2): rec [n, 32] records, half-spaces planes [*, 4] indexed
+        by plane_off [n + 1]."""
+        rec = np.ascontiguousarray(rec, np.float64).reshape(-1, 32)
+        off = np.ascontiguousarray(plane_off, np.int64)
+        pl = np.ascontiguousarray(planes, np.float64).reshape(-1, 4)
+        self._check(_cm.cm_object_set_prims(self._h, int(h), len(rec), _ptr(rec), _ptr(off), _ptr(pl)),
+                    "cm_object_set_prims")
 
     def plan(self, qa, qb) -> "Plan":
         return Plan(self, qa, qb)

@@ -13,12 +13,34 @@ constexpr int kMaxPieces = 4096;   // pieces per object (index fits 16 bits)
 constexpr int kSub = 16;           // support planes per piece (lower bound of its SDF)
 constexpr float kPruneTau = 20.f;  // a piece this many tau_cup above the union's minimum has weight < 2^-28
 
-// SDF representations of an object (the paper's two alternatives, Sec. III):
-// the smooth union of smooth intersections of half-spaces (one convex piece
-// each), or a cubic spline fitted to the ground-truth SDF with a separately
-// fitted normal spline.
+// SDF representations of an object (Sec. III): the smooth union of smooth
+// intersections of half-spaces (one convex piece each), a cubic spline fitted
+// to the ground-truth SDF with a separately fitted normal spline, or primitives
+// (PSQ / XPSQ, Sec. III-A) folded by smooth union, subtraction and intersection.
 constexpr int32_t kRepPlanes = 0;
 constexpr int32_t kRepSpline = 1;
+constexpr int32_t kRepPrims = 2;
+
+// One primitive of the primitive representation (Sec. III-A), FP32; the
+// derived XPSQ constants formed in FP64 and rounded once.
+struct PrimDev {
+  int32_t kind;         // 0 PSQ at a fixed pose, 1 XPSQ (PSQ swept along a quadratic spline)
+  int32_t op;           // joins the primitives before it by 0 union, 1 subtraction, 2 intersection
+  int32_t plane_begin;  // its half-spaces in the object's primitive planes
+  int32_t plane_count;
+  float c[3], pad0;     // PSQ centre; XPSQ p1
+  float p2[3], pad1;    // XPSQ p2, p3
+  float p3[3], pad2;
+  float Rt[9], pad3[3]; // PSQ: R^T row-major (object frame -> PSQ frame)
+  float a0[3], e0a;     // SQ scales and eps1 at t = 0 (PSQ: the SQ)
+  float a1[3], e1a;     // the same at t = 1
+  float e0b, e1b;       // eps2 at t = 0, t = 1
+  float a2, inv2AA;     // XPSQ cubic: a2 = 3 A.B / (2 |A|^2); 1 / (2 |A|^2)
+  float A[3], BB;       // A = p1 - 2 p2 + p3; |B|^2
+  float B[3], pad4;     // B = 2 (p2 - p1)
+  float bn[3], pad5;    // unit binormal along B x A
+};
+static_assert(sizeof(PrimDev) == 208, "PrimDev layout");
 
 // Per piece of a resident object (device).  Planes of the piece are stored
 // relative to `centre` and pre-scaled by kappa = log2(e) / tau_cap, so the
@@ -51,10 +73,12 @@ struct ObjDesc {
   float ginv[3];          // 1 / voxel size
   float gr;               // voxel circumradius
   int32_t gn;             // voxels per axis
-  int32_t rep;            // SDF representation: kRepPlanes or kRepSpline
+  int32_t rep;            // SDF representation: kRepPlanes, kRepSpline or kRepPrims
   // kRepPlanes: [n_pieces][kSub] support planes (scaled like planes), min(kSub,
   // plane_count) used.  kRepSpline: the spline coefficients, (gn + 3)^3 float4
-  // (phi, n_x, n_y, n_z) over the grid's box (its cells are the grid's voxels)
+  // (phi, n_x, n_y, n_z) over the grid's box (its cells are the grid's voxels).
+  // kRepPrims: gn PrimDev records, then their half-spaces (float4 (n, h) in each
+  // PSQ frame); such an object has no voxel grid
   const F4* sub;
 };
 static_assert(sizeof(ObjDesc) == 128, "ObjDesc layout");
@@ -102,7 +126,9 @@ struct DevParams {
   int32_t edge_bound;
   int32_t prune;       // skip pieces that cannot matter (see sdf_eval)
   float prune_margin;  // kPruneTau * tau_cup
-  int32_t pad[3];
+  float tau_t, inv_tau_t;        // primitives: soft clip of the spline parameter to (0, 1)
+  float tau_disc, inv_tau_disc;  // primitives: softplus / sigmoid of the cubic's discriminant
+  int32_t pad;
 };
 
 }  // namespace cm

@@ -150,6 +150,11 @@ template <class T> CM_DEV T sigmoidT(T z) {
   return cst<T>(1.f) / (e + 1.f);
 }
 CM_DEV float sigmoidT(float z) { return 1.f / (1.f + expf(-z)); }
+// dual: sigma' = sigma (1 - sigma) (no overflow of exp(-z) into the tangent)
+CM_DEV df sigmoidT(df z) {
+  const float s = sigmoidT(z.v);
+  return {s, s * (1.f - s) * z.t};
+}
 // s_+(x) = tau log(1 + exp(x / tau)) = max(x, 0) + tau log1p(exp(-|x| / tau))  (Sec. II)
 template <class T> CM_DEV T softplusT(T x, float tau, float inv_tau) {
   if (val(x) >= 0.f) return x + tau * log1pT(expT(-x * inv_tau));

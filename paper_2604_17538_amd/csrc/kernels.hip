@@ -10,6 +10,7 @@
 // piece) so a query's result does not depend on the rest of its batch.
 #include "devmath.h"
 #include "kernels.h"
+#include "prims.h"
 #include "wave.h"
 
 namespace cm {
@@ -86,13 +87,17 @@ __global__ __launch_bounds__(256) void k_broad(const DevCounts* __restrict__ dc,
       if (E.kind == 0) {
         const V3<float> v = vert(M, pd.vert_begin + cc);
         const V3<float> x = mulM(F.Rrel, v) + F.trel;
-        surv = !P.broad_phase || (S.rep == kRepSpline ? spline_lb(S, x) : grid_lb(S, x)) < P.d_max;
+        // (primitive SDFs carry no bound: every contact survives)
+        surv = !P.broad_phase || S.rep == kRepPrims ||
+               (S.rep == kRepSpline ? spline_lb(S, x) : grid_lb(S, x)) < P.d_max;
         prest = mulM(F.RM, v) + F.tM;
       } else {
         const I2 ed = M.edges[pd.edge_begin + cc];
         const V3<float> v0 = vert(M, ed.x), v1 = vert(M, ed.y);
         const V3<float> x0 = mulM(F.Rrel, v0) + F.trel, x1 = mulM(F.Rrel, v1) + F.trel;
-        if (P.broad_phase && S.rep == kRepSpline) {
+        if (S.rep == kRepPrims) {
+          surv = true;
+        } else if (P.broad_phase && S.rep == kRepSpline) {
           surv = spline_edge_lb(S, x0, x1) < P.d_max;
         } else if (P.broad_phase) {
           const V3<float> dv = x1 - x0;
@@ -258,6 +263,11 @@ __global__ __launch_bounds__(256) void k_project(const QueryDev* __restrict__ Q,
       spline_eval<false, true, false, float>(S, x, r);
       phi = r.phi;
       nS = r.n;
+    } else if (S.rep == kRepPrims) {
+      const Jt<float, 1> j = prims_eval<float, 1>(S, x, P);
+      phi = j.v;
+      const V3<float> g{j.g[0], j.g[1], j.g[2]};
+      nS = g * (1.f / sqrtf(dot(g, g) + P.eps_n2));
     } else {
       SdfRes<float> r;
       sdf_eval<1, 1, float>(S, P, &x, &r);

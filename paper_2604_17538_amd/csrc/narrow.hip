@@ -14,6 +14,7 @@
 // arithmetic operations.  Tiles past the tape recompute their forward pass.
 #include "devmath.h"
 #include "kernels.h"
+#include "prims.h"
 #include "wave.h"
 
 namespace cm {
@@ -44,12 +45,6 @@ template <class T> CM_DEV void tput3(float* tp, int64_t rs, int v, int64_t slot,
 }
 template <class T> CM_DEV V3<T> tget3(const float* tp, int64_t rs, int v, int64_t slot) {
   return {tget<T>(tp, rs, v, slot), tget<T>(tp, rs, v + 1, slot), tget<T>(tp, rs, v + 2, slot)};
-}
-
-// Stable dual sigmoid: sigma' = sigma (1 - sigma).
-CM_DEV df sigmoidT(df z) {
-  const float s = sigmoidT(z.v);
-  return {s, s * (1.f - s) * z.t};
 }
 
 template <class T> CM_DEV V3<T> mulMc(const M3<T>& R, V3<float> v) {
@@ -119,7 +114,7 @@ template <class T> struct CF {
 // The contact normal: for plane SDFs the normalised gradient (set here), for
 // spline SDFs the normal spline's value (set by the evaluation, Sec. III-B.2).
 template <class T, int REP> CM_DEV void finish_contact(CF<T>& c, const FrameT<T>& F, const DevParams& P) {
-  if (REP == kRepPlanes) {
+  if (REP != kRepSpline) {
     c.sg = sqrtT(dot(c.g, c.g) + P.eps_n2);
     c.nS = c.g * (cst<T>(1.f) / c.sg);
   }
@@ -143,8 +138,15 @@ template <class T, int REP> CM_DEV void finish_contact(CF<T>& c, const FrameT<T>
 // terms of work each.
 template <int REP, int NP, bool GRAD, class T>
 CM_DEV void sdf_points(const ObjDesc& S, const DevParams& P, const V3<T>* x, SdfRes<T>* r, uint64_t* work) {
-  if (REP == kRepPlanes) {
+  if constexpr (REP == kRepPlanes) {
     sdf_eval<NP, GRAD ? 1 : 0, T>(S, P, x, r, work);
+  } else if constexpr (REP == kRepPrims) {
+    for (int p = 0; p < NP; ++p) {
+      const Jt<T, GRAD ? 1 : 0> j = prims_eval<T, GRAD ? 1 : 0>(S, x[p], P);
+      r[p].phi = j.v;
+      if (GRAD) r[p].g = V3<T>{j.g[0], j.g[1], j.g[2]};
+    }
+    if (work) *work += uint64_t(64 * NP * S.gn);
   } else {
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
@@ -161,12 +163,18 @@ CM_DEV void sdf_points(const ObjDesc& S, const DevParams& P, const V3<T>* x, Sdf
 // Hessian of phi, or the gradient of phi and the normal spline's Jacobian).
 template <int REP, bool HIST, class T>
 CM_DEV void sdf_contact(const ObjDesc& S, const DevParams& P, const V3<T>& x, CF<T>& c, uint64_t* work) {
-  if (REP == kRepPlanes) {
+  if constexpr (REP == kRepPlanes) {
     SdfRes<T> r;
     sdf_eval<1, HIST ? 2 : 1, T>(S, P, &x, &r, work);
     c.phi = r.phi;
     c.g = r.g;
     if (HIST) c.H = r.H;
+  } else if constexpr (REP == kRepPrims) {
+    const Jt<T, HIST ? 2 : 1> j = prims_eval<T, HIST ? 2 : 1>(S, x, P);
+    c.phi = j.v;
+    c.g = V3<T>{j.g[0], j.g[1], j.g[2]};
+    if (HIST) c.H = Sym<T>{j.h[0], j.h[1], j.h[2], j.h[3], j.h[4], j.h[5]};
+    if (work) *work += uint64_t(64 * S.gn);
   } else {
     SplRes<T> q;
     spline_eval<HIST, true, HIST, T>(S, x, q);
@@ -490,7 +498,7 @@ CM_DEV void edge_adj(const CF<T>& c, const Trace<T>& tr, const FrameT<T>& F, con
 //   ADJ = true,  TAPE = false  adjoint of tiles [t_begin, total), recomputing
 template <class T, bool ADJ, bool TAPE, int REP>
 __global__ __launch_bounds__(256) void k_narrow(NarrowArgs a) {
-  static_assert(REP == kRepPlanes || !TAPE, "spline SDFs recompute instead of taping");
+  static_assert(REP == kRepPlanes || !TAPE, "spline and primitive SDFs recompute instead of taping");
   const int l = lane();
   const int64_t n_run = a.dc->R;
   const ObjDesc* __restrict__ objs = a.dc->objs;
@@ -810,6 +818,9 @@ static void narrow_launch(const NarrowArgs& na, int grid, int waves, hipStream_t
   if (ev && first) (void)hipEventRecord(ev[2 * slot], s);
   if (na.rep == kRepSpline) {
     if constexpr (!TAPE) hipLaunchKernelGGL((k_narrow<T, ADJ, false, kRepSpline>), dim3(unsigned(grid)), block, 0, s,
+                                            na);
+  } else if (na.rep == kRepPrims) {
+    if constexpr (!TAPE) hipLaunchKernelGGL((k_narrow<T, ADJ, false, kRepPrims>), dim3(unsigned(grid)), block, 0, s,
                                             na);
   } else {
     hipLaunchKernelGGL((k_narrow<T, ADJ, TAPE, kRepPlanes>), dim3(unsigned(grid)), block, 0, s, na);

@@ -42,7 +42,11 @@ bool valid_params(const cm_params& p, std::string* why) {
   if (p.curve < 0 || p.curve > 2) { *why = "curve must be 0, 1 or 2"; return false; }
   if (!(p.grid_margin >= 0.f) || !(p.grid_margin_rel >= 0.f)) { *why = "grid margins must be >= 0"; return false; }
   if (p.prune_pieces < 0 || p.prune_pieces > 1) { *why = "prune_pieces must be 0 or 1"; return false; }
-  if (p.sdf_kind < 0 || p.sdf_kind > 1) { *why = "sdf_kind must be 0 (planes) or 1 (spline)"; return false; }
+  if (p.sdf_kind < 0 || p.sdf_kind > 2) { *why = "sdf_kind must be 0 (planes), 1 (spline) or 2 (primitives)"; return false; }
+  if (p.sdf_kind == 2 && (!(p.tau_t > 0.f) || !(p.tau_disc > 0.f) || !std::isfinite(p.tau_t) || !std::isfinite(p.tau_disc))) {
+    *why = "tau_t and tau_disc must be positive";
+    return false;
+  }
   if (p.edge_assign < 0 || p.edge_assign > 1) { *why = "edge_assign must be 0 or 1"; return false; }
   return true;
 }
@@ -68,6 +72,10 @@ DevParams make_dev_params(const cm_params& p) {
   d.edge_bound = p.edge_bound;
   d.prune = p.prune_pieces;
   d.prune_margin = kPruneTau * p.tau_cup;
+  d.tau_t = p.tau_t;
+  d.inv_tau_t = p.tau_t > 0.f ? 1.f / p.tau_t : 0.f;
+  d.tau_disc = p.tau_disc;
+  d.inv_tau_disc = p.tau_disc > 0.f ? 1.f / p.tau_disc : 0.f;
   return d;
 }
 
@@ -141,7 +149,7 @@ static void pack_object(const ObjHost& o, const cm_params& prm, Packed* pk) {
   pk->off_vz = take(4 * size_t(pk->V));
   pk->off_edges = take(8 * size_t(pk->E));
   pk->off_grid = take(4 * size_t(gn) * gn * gn);
-  pk->rep = prm.sdf_kind == 1 ? kRepSpline : kRepPlanes;
+  pk->rep = prm.sdf_kind == 1 ? kRepSpline : (prm.sdf_kind == 2 ? kRepPrims : kRepPlanes);
   pk->off_coef = pk->rep == kRepSpline ? take(16 * size_t(gn + 3) * (gn + 3) * (gn + 3)) : 0;
   pk->bytes.assign(off, 0);
   F4* planes = reinterpret_cast<F4*>(pk->bytes.data() + pk->off_planes);
@@ -248,6 +256,7 @@ static ObjDesc make_desc(const Packed& pk, char* base) {
   d.gn = pk.gn;
   d.rep = pk.rep;
   if (pk.rep == kRepSpline) d.sub = reinterpret_cast<const F4*>(base + pk.off_coef);
+  if (pk.rep == kRepPrims) { d.sub = nullptr; d.gn = 0; }  // until cm_object_set_prims
   return d;
 }
 
@@ -505,6 +514,8 @@ cm_status cm_default_params(float L_ref, cm_params* out) {
   p.broad_phase = 1;
   p.edge_bound = 0;
   p.prune_pieces = 1;
+  p.tau_t = 0.01f;
+  p.tau_disc = 1e-3f;
   *out = p;
   return CM_OK;
 }
@@ -626,6 +637,7 @@ cm_status cm_release_object(cm_context* ctx, cm_object obj) {
     (void)hipDeviceSynchronize();
     ctx->arena->release(o->chunk);
   }
+  if (o->dprims) (void)hipFree(o->dprims);
   *o = ObjHost{};
   return CM_OK;
 }
@@ -686,6 +698,84 @@ cm_status cm_object_spline(cm_context* ctx, cm_object obj, float* coef, float* m
   return CM_OK;
 }
 
+cm_status cm_object_set_prims(cm_context* ctx, cm_object obj, int32_t n, const double* rec, const int64_t* plane_off,
+                              const double* planes) {
+  if (!ctx || n <= 0 || n > kMaxPieces || !rec || !plane_off || (plane_off[n] > 0 && !planes))
+    return fail(ctx, CM_E_INVALID, "bad arguments");
+  if (ctx->prm.sdf_kind != 2 || ctx->device < 0) return fail(ctx, CM_E_INVALID, "not a primitive context on a device");
+  if (plane_off[0] != 0) return fail(ctx, CM_E_INVALID, "plane_off[0] must be 0");
+  std::vector<PrimDev> pd(static_cast<size_t>(n));
+  for (int32_t i = 0; i < n; ++i) {
+    const double* r = rec + 32 * i;
+    PrimDev& q = pd[size_t(i)];
+    q = PrimDev{};
+    q.kind = int32_t(r[0]);
+    q.op = int32_t(r[1]);
+    if ((q.kind != 0 && q.kind != 1) || q.op < 0 || q.op > 2 || plane_off[i + 1] < plane_off[i])
+      return fail(ctx, CM_E_INVALID, "primitive kind must be 0 or 1, op 0..2, plane offsets ascending");
+    q.plane_begin = int32_t(plane_off[i]);
+    q.plane_count = int32_t(plane_off[i + 1] - plane_off[i]);
+    for (int k = 0; k < 3; ++k) {
+      q.c[k] = float(r[2 + k]); q.p2[k] = float(r[5 + k]); q.p3[k] = float(r[8 + k]);
+      q.a0[k] = float(r[15 + k]); q.a1[k] = float(r[20 + k]);
+      if (!(r[15 + k] > 0.0) || !(r[20 + k] > 0.0)) return fail(ctx, CM_E_INVALID, "superquadric scales must be positive");
+    }
+    q.e0a = float(r[18]); q.e0b = float(r[19]); q.e1a = float(r[23]); q.e1b = float(r[24]);
+    if (!(r[18] > 0.0) || !(r[19] > 0.0) || !(r[23] > 0.0) || !(r[24] > 0.0))
+      return fail(ctx, CM_E_INVALID, "superquadric exponents must be positive");
+    // PSQ rotation from its quaternion, in FP64, rounded once
+    const double qn = std::sqrt(r[11] * r[11] + r[12] * r[12] + r[13] * r[13] + r[14] * r[14]);
+    if (!(qn > 1e-12)) return fail(ctx, CM_E_INVALID, "degenerate quaternion");
+    const double w = r[11] / qn, x = r[12] / qn, y = r[13] / qn, z = r[14] / qn;
+    const double R[9] = {1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y),
+                         2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x),
+                         2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)};
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) q.Rt[3 * a + b] = float(R[3 * b + a]);
+    if (q.kind == 1) {  // XPSQ spline constants in FP64
+      double A[3], B[3];
+      for (int k = 0; k < 3; ++k) { A[k] = r[2 + k] - 2 * r[5 + k] + r[8 + k]; B[k] = 2 * (r[5 + k] - r[2 + k]); }
+      const double AA = A[0] * A[0] + A[1] * A[1] + A[2] * A[2], AB = A[0] * B[0] + A[1] * B[1] + A[2] * B[2];
+      const double bn[3] = {B[1] * A[2] - B[2] * A[1], B[2] * A[0] - B[0] * A[2], B[0] * A[1] - B[1] * A[0]};
+      const double bl = std::sqrt(bn[0] * bn[0] + bn[1] * bn[1] + bn[2] * bn[2]);
+      const double BBd = B[0] * B[0] + B[1] * B[1] + B[2] * B[2];
+      if (!(bl > 1e-9 * std::max(AA, BBd))) return fail(ctx, CM_E_INVALID, "an XPSQ spline must be curved (p2 off the line p1 p3)");
+      q.a2 = float(1.5 * AB / AA);
+      q.inv2AA = float(1.0 / (2.0 * AA));
+      q.BB = float(BBd);
+      for (int k = 0; k < 3; ++k) { q.A[k] = float(A[k]); q.B[k] = float(B[k]); q.bn[k] = float(bn[k] / bl); }
+    }
+  }
+  const int64_t P = plane_off[n];
+  std::vector<F4> pl(static_cast<size_t>(P));
+  for (int64_t j = 0; j < P; ++j) {
+    const double* v = planes + 4 * j;
+    const double l = std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+    if (!(l > 0)) return fail(ctx, CM_E_INVALID, "zero plane normal");
+    pl[size_t(j)] = F4{float(v[0] / l), float(v[1] / l), float(v[2] / l), float(v[3] / l)};
+  }
+  const size_t bytes = sizeof(PrimDev) * size_t(n) + sizeof(F4) * size_t(P);
+  void* mem = nullptr;
+  CM_HIP(ctx, hipMalloc(&mem, bytes));
+  hipError_t e = hipMemcpy(mem, pd.data(), sizeof(PrimDev) * size_t(n), hipMemcpyHostToDevice);
+  if (e == hipSuccess && P)
+    e = hipMemcpy(static_cast<char*>(mem) + sizeof(PrimDev) * size_t(n), pl.data(), sizeof(F4) * size_t(P),
+                  hipMemcpyHostToDevice);
+  if (e != hipSuccess) { (void)hipFree(mem); return hip_fail(ctx, e, "primitive upload"); }
+  std::unique_lock<std::shared_mutex> lk(ctx->reg_mu);
+  ObjHost* o = get_obj(ctx, obj);
+  if (!o) { (void)hipFree(mem); return fail(ctx, CM_E_NOTFOUND, "unknown object"); }
+  (void)hipDeviceSynchronize();  // (kernels in flight may read the old block)
+  if (o->dprims) (void)hipFree(o->dprims);
+  o->dprims = mem;
+  o->n_prims = n;
+  o->desc.sub = static_cast<const F4*>(mem);
+  o->desc.gn = n;
+  e = hipMemcpy(ctx->d_objs + obj, &o->desc, sizeof(ObjDesc), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(ctx, e, "object table update");
+  return CM_OK;
+}
+
 cm_status cm_object_grid(cm_context* ctx, cm_object obj, float* G, float* meta) {
   if (!ctx) return CM_E_INVALID;
   ObjDesc d;
@@ -694,6 +784,7 @@ cm_status cm_object_grid(cm_context* ctx, cm_object obj, float* G, float* meta) 
     ObjHost* o = get_obj(ctx, obj);
     if (!o) return fail(ctx, CM_E_NOTFOUND, "unknown object");
     if (ctx->device < 0) return fail(ctx, CM_E_INVALID, "host-only context has no grid");
+    if (ctx->prm.sdf_kind == 2) return fail(ctx, CM_E_INVALID, "primitive objects have no voxel grid");
     d = o->desc;
   }
   if (meta) {
@@ -713,6 +804,7 @@ namespace cm {
 // Terms of one SDF evaluation against an object: its planes, or the 64
 // coefficients of a spline evaluation.
 static double sdf_terms(const cm_context* ctx, const ObjHost& o) {
+  if (ctx->prm.sdf_kind == 2) return 64.0 * double(std::max(o.n_prims, 1));  // (a jet evaluation per primitive)
   return ctx->prm.sdf_kind == 1 ? 64.0 : double(o.n_planes);
 }
 
@@ -771,6 +863,8 @@ cm_status plan_host(cm_context* ctx, const cm_query* hq, int32_t n, cm_plan* pl,
       const ObjHost* A = get_obj(ctx, hq[i].a);
       const ObjHost* B = get_obj(ctx, hq[i].b);
       if (!A || !B) return fail(ctx, CM_E_NOTFOUND, "query names an unknown object");
+      if (ctx->prm.sdf_kind == 2 && (A->n_prims <= 0 || B->n_prims <= 0))
+        return fail(ctx, CM_E_INVALID, "an object of a primitive context has no primitives (cm_object_set_prims)");
       pl->qa[size_t(i)] = int32_t(hq[i].a);
       pl->qb[size_t(i)] = int32_t(hq[i].b);
       const int64_t ga = int64_t(A->pieces.size()), gb = int64_t(B->pieces.size());
@@ -1222,7 +1316,7 @@ FwdArgs fwd_args(cm_context* ctx, cm_plan* pl, const cm_query* q, const cm_group
   a.tape = pl->d_tape;
   a.tape_tiles = pl->d_tape ? pl->tape_tiles : 0;
   a.tape_nv = tape_values(ctx->prm.st_iters);
-  a.rep = ctx->prm.sdf_kind == 1 ? kRepSpline : kRepPlanes;
+  a.rep = ctx->prm.sdf_kind == 1 ? kRepSpline : (ctx->prm.sdf_kind == 2 ? kRepPrims : kRepPlanes);
   return a;
 }
 }  // namespace cm
@@ -1330,6 +1424,8 @@ cm_status cm_shutdown(cm_context* ctx) {
   serving_stop(ctx);
   if (ctx->device >= 0) (void)hipDeviceSynchronize();
   ctx->arena.reset();
+  for (const cm::ObjHost& o : ctx->objs)
+    if (o.dprims) (void)hipFree(o.dprims);
   if (ctx->d_objs) (void)hipFree(ctx->d_objs);
   for (cm::ObjDesc* t : ctx->old_tables) (void)hipFree(t);
   if (ctx->build_stream) (void)hipStreamDestroy(ctx->build_stream);

@@ -57,6 +57,8 @@ struct ObjHost {
   void* dmem = nullptr;
   int chunk = -1;
   ObjDesc desc{};
+  void* dprims = nullptr;  // primitive block (sdf_kind 2), its own allocation
+  int32_t n_prims = 0;
 };
 
 struct Serving;

@@ -265,3 +265,137 @@ def serving_trace(library: list, rate_hz: float, duration_s: float,
 def library_objects(n: int = 2048, seed: int = SEED_BASE + 3) -> list:
     rng = np.random.Generator(np.random.PCG64(seed + 7))
     return [_c2_object(rng) for _ in range(n)]
+
+
+# ------------------------------------------------------- primitive objects --
+# Objects whose SDF side is a list of primitives (Sec. III-A: superquadrics
+# intersected with half-spaces (PSQ), swept along quadratic splines (XPSQ),
+# folded by union / subtraction / intersection) and whose mesh side is convex
+# pieces: hulls of points drawn on the primitives' surfaces.  The records are the
+# 32-double layout of cm_object_set_prims; every value is FP32-representable.
+@dataclasses.dataclass
+class PrimObject(PointObject):
+    prim_rec: np.ndarray = None        # float64 [n, 32]
+    prim_plane_off: np.ndarray = None  # int64 [n + 1]
+    prim_planes: np.ndarray = None     # float64 [P, 4]
+
+
+def prim_record(kind, op=0, c=(0, 0, 0), p=None, quat=(1, 0, 0, 0), a0=(1, 1, 1), e0=(1, 1), a1=None, e1=None):
+    r = np.zeros(32)
+    r[0], r[1] = kind, op
+    if p is None:
+        r[2:5] = c
+    else:
+        r[2:11] = np.asarray(p, np.float64).ravel()
+    r[11:15] = quat
+    r[15:18], r[18:20] = a0, e0
+    r[20:23] = a0 if a1 is None else a1
+    r[23:25] = e0 if e1 is None else e1
+    return _f32(r)
+
+
+def _spow(v, k):
+    return np.sign(v) * np.abs(v) ** k
+
+
+def sq_surface_points(rng, n, a, e):
+    """Points of the superquadric f = 1 by its parametric form (angles uniform)."""
+    eta = rng.uniform(-np.pi / 2, np.pi / 2, n)
+    om = rng.uniform(-np.pi, np.pi, n)
+    return np.stack([a[0] * _spow(np.cos(eta), e[0]) * _spow(np.cos(om), e[1]),
+                     a[1] * _spow(np.cos(eta), e[0]) * _spow(np.sin(om), e[1]),
+                     a[2] * _spow(np.sin(eta), e[0])], 1)
+
+
+def _quat_R(q):
+    w, x, y, z = np.asarray(q, np.float64) / np.linalg.norm(q)
+    return np.array([[1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)],
+                     [2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)],
+                     [2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)]])
+
+
+def _sweep_points(rng, P, a0, e0, a1, e1, t_lo, t_hi, n):
+    """Points on the superquadrics placed along the spline P (3 control points)
+    between t_lo and t_hi, each in the spline's Frenet frame [N, b, T]."""
+    P = np.asarray(P, np.float64)
+    A, B = P[0] - 2 * P[1] + P[2], 2 * (P[1] - P[0])
+    b = np.cross(B, A)
+    b /= np.linalg.norm(b)
+    t = rng.uniform(t_lo, t_hi, n)
+    t[:2] = (t_lo, t_hi)
+    out = []
+    for tk in t:
+        T = 2 * A * tk + B
+        T /= np.linalg.norm(T)
+        N = np.cross(b, T)
+        a = np.asarray(a0) + tk * (np.asarray(a1) - np.asarray(a0))
+        e = np.asarray(e0) + tk * (np.asarray(e1) - np.asarray(e0))
+        s = sq_surface_points(rng, 6, a, e)
+        pt = (1 - tk) ** 2 * P[0] + 2 * tk * (1 - tk) * P[1] + tk ** 2 * P[2]
+        out.append(pt + s[:, :1] * N + s[:, 1:2] * b + s[:, 2:3] * T)
+    return np.concatenate(out, 0)
+
+
+def prim_object(rng, kind: int) -> PrimObject:
+    """One of four primitive objects, its sizes jittered by U[0.8, 1.2]:
+    0 cup (cylinder minus a raised cylinder, plus a handle: a rounded box swept
+    along a spline), 1 tube (a sphere swept along a random curved spline),
+    2 dome (an ellipsoid cut by a half-space), 3 rounded box (a superquadric of
+    exponents 0.3 at a random rotation)."""
+    j = lambda: rng.uniform(0.8, 1.2)
+    recs, planes, plane_off, pieces = [], [], [0], []
+    if kind == 0:
+        r, h, w = 0.05 * j(), 0.06 * j(), 0.007 * j()
+        recs.append(prim_record(0, 0, c=(0, 0, 0), a0=(r, r, h), e0=(0.1, 1.0)))
+        recs.append(prim_record(0, 1, c=(0, 0, 1.5 * w), a0=(r - w, r - w, h), e0=(0.1, 1.0)))
+        P = [(0.9 * r, 0, 0.55 * h), (1.9 * r, 0, 0.0), (0.9 * r, 0, -0.55 * h)]
+        ah = (w * 1.2, w * 1.6, w * 1.2)
+        recs.append(prim_record(1, 0, p=P, a0=ah, e0=(0.3, 0.3)))
+        plane_off += [0, 0, 0]
+        pieces.append(sq_surface_points(rng, 160, (r, r, h), (0.1, 1.0)))
+        for lo, hi in ((0.0, 0.5), (0.5, 1.0)):
+            pieces.append(_sweep_points(rng, P, ah, (0.3, 0.3), ah, (0.3, 0.3), lo, hi, 12))
+    elif kind == 1:
+        rad = 0.015 * j()
+        P = [(-0.06 * j(), 0, 0), (0.0, 0.05 * j(), 0.02 * rng.uniform(-1, 1)), (0.06 * j(), 0, 0.01 * rng.uniform(-1, 1))]
+        recs.append(prim_record(1, 0, p=P, a0=(rad, rad, rad), e0=(1.0, 1.0), a1=(0.7 * rad, 0.7 * rad, 0.7 * rad)))
+        plane_off.append(0)
+        a1 = (0.7 * rad,) * 3
+        for lo, hi in ((0.0, 1 / 3), (1 / 3, 2 / 3), (2 / 3, 1.0)):
+            pieces.append(_sweep_points(rng, P, (rad,) * 3, (1.0, 1.0), a1, (1.0, 1.0), lo, hi, 14))
+    elif kind == 2:
+        a = (0.05 * j(), 0.04 * j(), 0.05 * j())
+        cut = 0.3 * a[2]
+        recs.append(prim_record(0, 0, c=(0, 0, 0), a0=a, e0=(1.0, 1.0)))
+        planes.append((0.0, 0.0, 1.0, -cut))  # z <= cut
+        plane_off.append(1)
+        s = sq_surface_points(rng, 300, a, (1.0, 1.0))
+        s = s[s[:, 2] <= cut]
+        rr = np.sqrt(np.maximum(0.0, 1 - (cut / a[2]) ** 2))
+        th = rng.uniform(0, 2 * np.pi, 40)
+        disk = np.stack([a[0] * rr * np.cos(th), a[1] * rr * np.sin(th), np.full(40, cut)], 1)
+        pieces.append(np.concatenate([s, disk], 0))
+    else:
+        a = (0.04 * j(), 0.03 * j(), 0.02 * j())
+        q = _unit_gauss(rng, 1, 4)[0]
+        recs.append(prim_record(0, 0, c=(0, 0, 0), quat=q, a0=a, e0=(0.3, 0.3)))
+        plane_off.append(0)
+        pieces.append(sq_surface_points(rng, 200, a, (0.3, 0.3)) @ _quat_R(_f32(q)).T)
+    off = np.cumsum([0] + [len(p) for p in pieces]).astype(np.int64)
+    return PrimObject(off, _f32(np.concatenate(pieces, 0)), np.array(recs), np.array(plane_off, np.int64),
+                      _f32(np.array(planes, np.float64).reshape(-1, 4)))
+
+
+def config_prims(seed: int = SEED_BASE + 5, n_pairs: int = 256) -> Workload:
+    """Pairs of primitive objects (cup, tube, dome, rounded box, drawn uniformly),
+    posed as the other workloads but closer, t_B at (r_A + r_B) U[0.35, 0.75]:
+    the shapes are thin (handles, tubes), and at the usual distances few of
+    their pieces come within d_max."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    kinds = rng.integers(0, 4, size=2 * n_pairs)
+    objects = [prim_object(rng, int(k)) for k in kinds]
+    radii = np.array([o.radius() for o in objects])
+    qa = np.arange(0, 2 * n_pairs, 2, dtype=np.int32)
+    qb = qa + 1
+    poses = random_poses(rng, radii[qa], radii[qb], lo=0.35, hi=0.75)
+    return Workload("prims", objects, qa, qb, poses, 0.1, cot_seed=seed + 1000)
