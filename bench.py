@@ -51,7 +51,7 @@ OPS = {
 }
 
 
-DOMINANT = "k_narrow<df, false, true>"
+DOMINANT = "k_narrow<df, false, true, 0>"  # the forward sweep in dual numbers keeping the tape (plane SDFs)
 HERE_PROFILES = os.path.join(HERE, "profiles")
 KERNEL_FILES = ("common.h", "devmath.h", "kernels.h", "wave.h")  # headers the kernels include
 
@@ -375,6 +375,55 @@ def spline_leg(n_pairs=2048, reps=5):
     return out
 
 
+def prims_leg(n_pairs=4096, reps=5):
+    """The primitive representation (Sec. III-A: PSQs and XPSQs folded by
+    union / subtraction / intersection) on pairs of cup / tube / dome /
+    rounded-box objects: forward records and the step (records + gradient +
+    H v), evaluations per second of the primitive SDF (every contact survives:
+    primitives carry no broad-phase bound)."""
+    import torch
+    from paper_2604_17538_amd import api, workloads as W
+    w = W.config_prims(n_pairs=n_pairs)
+    stream = torch.cuda.current_stream()
+    ctx = api.Context(0, L_ref=w.L_ref, sdf_kind=2)
+    hs = ctx.build_objects(w.objects)
+    plan = ctx.plan(hs[w.qa], hs[w.qb])
+    qd = plan.device_queries(w.poses)
+    cot = torch.tensor(np.ascontiguousarray(W.cotangents(5, plan.G).T, np.float32)).cuda()
+    direc = torch.tensor(W.directions(5, w.n).astype(np.float32)).cuda()
+    o = plan.forward(qd, stream=stream)
+    res = {"workload": "prims: %d pair-queries of primitive objects (cup, tube, dome, rounded box)" % w.n,
+           "contacts": plan.C, "groups": plan.G}
+    for what, fn in (("forward", lambda: plan.forward(qd, out=o, stream=stream)),
+                     ("step", lambda: plan.step(qd, cot, direc, stream=stream))):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(reps):
+            fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / reps
+        res[what + "_ms"] = round(ms, 3)
+        res[what + "_value"] = round(w.n / (ms * 1e-3), 1)
+    plan.set_timing(True)
+    plan.forward(qd, out=o, stream=stream)
+    torch.cuda.synchronize()
+    k_ms = plan.timing()["narrow_fwd"]
+    plan.set_timing(False)
+    st = plan.stats()
+    # evaluations of the object SDF by the forward sweep: a vertex once, an edge 2K + 1 times
+    K2 = 2 * ctx.params.st_iters + 1
+    evals = st["surv_verts"] + K2 * st["surv_edges"]
+    res.update(narrow_fwd_ms=round(k_ms, 3), sdf_evaluations=int(evals),
+               sdf_evaluations_per_s=round(evals / (k_ms * 1e-3), 1))
+    log("prims leg %s" % res)
+    del plan, ctx
+    torch.cuda.empty_cache()
+    return res
+
+
 def golden_c4():
     """Stored FP64 oracle values of sampled queries of the large workload."""
     path = os.path.join(HERE, "tests", "golden", "c4_oracle.json")
@@ -641,6 +690,7 @@ def main():
     ap.add_argument("--sweep", action="store_true",
                     help="only the broad-phase sweep (broad + narrow vs narrow only over d_max); prints its own JSON line")
     ap.add_argument("--no-spline", action="store_true", help="skip the spline-representation leg")
+    ap.add_argument("--no-prims", action="store_true", help="skip the primitive-representation leg")
     ap.add_argument("--curve-study", action="store_true",
                     help="only the serialization study (no curve / Morton / Hilbert); prints its own JSON line")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -757,6 +807,9 @@ def main():
     spline = None
     if not args.no_spline:
         spline = spline_leg()
+    prims = None
+    if not args.no_prims:
+        prims = prims_leg()
 
     serving = None
     if not args.no_serving:
@@ -803,7 +856,7 @@ def main():
     }
     line.update(line_extra)
     line.update({"roofline": roofline, "cpu_baseline": cpu, "plain_launch": plain, "parity": parity,
-                 "secondary": secondary, "spline": spline, "serving": serving})
+                 "secondary": secondary, "spline": spline, "prims": prims, "serving": serving})
     if plain:
         line["vs_plain_launch"] = round(value / plain["value"], 2)
     print(json.dumps(line), flush=True)
