@@ -284,9 +284,11 @@ template <> CM_DEV df mkT<df>(float v, float t) { return df{v, t}; }
 //
 // Pieces that cannot matter at any of the wave's points are skipped (when
 // P.prune): a piece's SDF is at least the max over its support subset of
-// planes, and the union's minimum is at most min_k (|x - c_k| + ub_off_k).  A
-// piece whose lower bound exceeds that by prune_margin = 20 tau_cup has union
-// weight below e^-20 < 2^-28 relative to the sum, under FP32 resolution.
+// planes, and the union's minimum is at most min_k (|x - c_k| + ub_off_k) and at
+// most the least piece SDF evaluated so far (the running minimum M).  A piece
+// whose lower bound exceeds the smaller of the two by prune_margin = 20 tau_cup
+// has union weight below e^-20 < 2^-28 relative to the sum, under FP32
+// resolution.
 //
 // The Hessian is (1/tau_cap) sum_k u_k Cov_k(n) - (1/tau_cup) Cov_u(g_k), two
 // weighted covariances.  Expanded as E[n n^T] - g g^T they cancel terms of size
@@ -324,17 +326,26 @@ CM_DEV void sdf_eval(const ObjDesc& o, const DevParams& P, const V3<T>* x, SdfRe
   float mub[NP];  // upper bound of the union's minimum
 #pragma unroll
   for (int p = 0; p < NP; ++p) mub[p] = __builtin_inff();
+  // with pruning, the piece of the least upper bound at the wave's first point
+  // is evaluated first, so that the running minimum M bounds the others early
+  int k_first = 0;
   if (P.prune) {
+    int kb = 0;
     for (int k = 0; k < K; ++k) {
       const PieceDesc pd = ldc(o.pieces + k);
 #pragma unroll
       for (int p = 0; p < NP; ++p) {
         const V3<float> d = val3(x[p]) - V3<float>{pd.cx, pd.cy, pd.cz};
-        mub[p] = fminf(mub[p], sqrtf(dot(d, d)) + pd.ub_off);
+        const float u = sqrtf(dot(d, d)) + pd.ub_off;
+        if (p == 0 && u < mub[0]) kb = k;
+        mub[p] = fminf(mub[p], u);
       }
     }
+    k_first = __builtin_amdgcn_readfirstlane(kb);
   }
-  for (int k = 0; k < K; ++k) {
+  // order: k_first, then 0 .. K - 1 without it
+  for (int kk = 0; kk < K; ++kk) {
+    const int k = kk == 0 ? k_first : (kk <= k_first ? kk - 1 : kk);
     const PieceDesc pd = ldc(o.pieces + k);
     const int pb = min(max(pd.plane_begin, 0), o.n_planes);
     const F4* pl = o.planes + pb;
@@ -389,7 +400,7 @@ CM_DEV void sdf_eval(const ObjDesc& o, const DevParams& P, const V3<T>* x, SdfRe
       if (P.prune) {
         bool need = false;
 #pragma unroll
-        for (int p = 0; p < NP; ++p) need = need || m[p] * P.icap < mub[p] + P.prune_margin;
+        for (int p = 0; p < NP; ++p) need = need || m[p] * P.icap < fminf(mub[p], M[p]) + P.prune_margin;
         if (!__any(need)) continue;  // no lane of the wave needs this piece
       }
     }
