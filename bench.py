@@ -494,6 +494,8 @@ def step_leg(api, W, config, pairs, budget_gb, args, steps, warmup, golden=None,
     if args.launch_shape:
         shape_f, shape = (int(v) for v in args.launch_shape.split(","))
         plan.launch_shape = (shape_f, shape)
+        if args.wg_waves:
+            plan.wg_waves = tuple(int(v) for v in args.wg_waves.split(","))
         tuned_on = 0
     elif w.n <= args.tune_sample:
         shape = plan.autotune(qd, cot_d, grad, dir_d, hv, stream)
@@ -566,6 +568,10 @@ def step_leg(api, W, config, pairs, budget_gb, args, steps, warmup, golden=None,
                                  4.0 * np.array(golden["spread_" + key]))
             res["parity"]["max_%s_err_over_allowed" % name] = float(
                 (np.linalg.norm(got - ref, axis=1) / allowed).max())
+        # positions within 1e-5 L_s, derivatives within their bounds: the headline's accuracy condition
+        res["parity"]["within_bounds"] = bool(res["parity"]["max_pos_err_over_Ls"] <= 1e-5 and
+                                              res["parity"]["max_grad_err_over_allowed"] <= 1.0 and
+                                              res["parity"]["max_hvp_err_over_allowed"] <= 1.0)
         log("parity against the stored oracle values: %s" % res["parity"])
     if quick:
         return res
@@ -685,6 +691,8 @@ def main():
     ap.add_argument("--no-tight", action="store_true", help="skip the step with the tighter edge bound")
     ap.add_argument("--launch-shape", default=None,
                     help="F,D: fixed persistent workgroups per CU for the float and dual sweeps (no autotuning)")
+    ap.add_argument("--wg-waves", default=None,
+                    help="F,D: waves per workgroup for the float and dual sweeps (with --launch-shape)")
     ap.add_argument("--tune-sample", type=int, default=16384,
                     help="autotune on a plan of the first N pair-queries when the batch is larger")
     ap.add_argument("--sweep", action="store_true",
