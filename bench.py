@@ -82,7 +82,7 @@ def measured_traffic(config, pairs):
     except OSError:
         return None
     tag = "kernel sources sha256[:16]"
-    h = [l.split(":", 1)[1].strip() for l in lines if l.startswith(tag)]
+    h = [l.rsplit(":", 1)[1].strip() for l in lines if l.startswith(tag)]
     if not h or h[0] != kernel_source_hash():
         return None
     for l in lines:
