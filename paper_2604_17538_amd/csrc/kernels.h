@@ -15,6 +15,8 @@ struct OutPtrs {
 };
 
 constexpr int kStride = 32;   // floats per tile partial
+constexpr int kQueues = 8;    // narrow-phase work queues: one per XCD of the MI355X
+constexpr int kChunk = 16;    // consecutive tiles dealt to one queue at a time
 constexpr int kGStride = 64;  // floats per per-group adjoint record (24 values, dual: 48)
 constexpr int kMaxTraceAdj = 4;  // sphere-trace steps supported by the adjoint
 
@@ -60,7 +62,7 @@ struct FwdArgs {
   F4* filt;
   int64_t* bsum;
   int64_t* tile_off;    // [R + 1] tile offsets of the runs
-  uint32_t* counter;
+  uint32_t* counter;    // [kQueues] work-queue counters
   float* partials;
   const I2* gent;       // per group: (vertex entry, edge entry)
   int64_t G;
@@ -108,7 +110,7 @@ struct NarrowArgs {
   const QueryDev* Q;
   const ObjDesc* objs;
   DevParams P;
-  uint32_t* counter;
+  uint32_t* counter;    // [kQueues] work-queue counters
   float* partials;        // output partials
   const float* gscratch;  // per-piece adjoint seeds (adjoint pass)
   const float* dir;       // HVP direction (dual passes)

@@ -509,12 +509,23 @@ __global__ __launch_bounds__(256) void k_narrow(NarrowArgs a) {
   const DevParams& P = a.P;
   constexpr bool HIST = ADJ || TAPE;  // Hessian and trace history
   uint64_t work[2] = {0, 0};          // point-plane evaluations per lane by contact kind (wave-uniform)
-  // each pop returns a distinct tile, so a wave pops at most total + 1 times
-  for (int64_t it = 0; it <= total; ++it) {
-    uint32_t t0 = 0;
-    if (l == 0) t0 = atomicAdd(a.counter, 1u);
-    const int64_t t = t_begin + int64_t(uint32_t(uni(int(t0))));
-    if (t >= t_end) break;
+  // One queue per XCD (workgroups are dispatched to the XCDs in turn): the
+  // sweep's tiles, in queue order, form chunks of kChunk consecutive tiles
+  // dealt to the queues in turn, so the tiles of a run (one query direction,
+  // one SDF object) are mostly taken by waves of one XCD and its L2 serves the
+  // object's planes to all of them.  Queue xq holds chunks xq, xq + kQueues, ...
+  const int xq = int(blockIdx.x) & (kQueues - 1);
+  const int64_t n_t = t_end > t_begin ? t_end - t_begin : 0;
+  const int64_t n_ch = (n_t + kChunk - 1) / kChunk;
+  const int64_t n_pop = n_ch > xq ? ((n_ch - 1 - xq) / kQueues + 1) * kChunk : 0;
+  // each pop returns a distinct index of the queue, so a wave pops at most n_pop + 1 times
+  for (int64_t it = 0; it <= n_pop; ++it) {
+    uint32_t i0 = 0;
+    if (l == 0) i0 = atomicAdd(a.counter + xq, 1u);
+    const int64_t i = int64_t(uint32_t(uni(int(i0))));
+    if (i >= n_pop) break;
+    const int64_t t = t_begin + ((i / kChunk) * kQueues + xq) * kChunk + (i % kChunk);
+    if (t >= t_end) continue;  // past the last tile (in the sweep's last chunk)
     // the tile: 64 consecutive survivors of a run (one query, direction, kind)
     const int64_t r = last_le(a.tile_off, 0, n_run, t);
     const int64_t j = t - a.tile_off[r];
@@ -813,7 +824,7 @@ template <class T, bool ADJ, bool TAPE>
 static void narrow_launch(const NarrowArgs& na, int grid, int waves, hipStream_t s, hipEvent_t* ev, bool first = true,
                           bool last = true) {
   const dim3 block(unsigned(kWave * std::min(std::max(waves, 1), 4)));  // (the kernels' bound: 256 threads)
-  launch_fill_u32(na.counter, 0u, 1, s);
+  launch_fill_u32(na.counter, 0u, kQueues, s);
   const int slot = nT<T>() == 1 ? (ADJ ? kTNarrowAdj : kTNarrowFwd) : (ADJ ? kTNarrowDualAdj : kTNarrowTan);
   if (ev && first) (void)hipEventRecord(ev[2 * slot], s);
   if (na.rep == kRepSpline) {

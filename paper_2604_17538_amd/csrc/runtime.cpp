@@ -1026,9 +1026,10 @@ size_t plan_layout(cm_plan* pl, char* b) {
     pl->d_filt = reinterpret_cast<F4*>(b + o_filt);
     pl->d_tile_off = reinterpret_cast<int64_t*>(b + o_toff);
     pl->d_bsum = reinterpret_cast<int64_t*>(b + o_bsum);
-    pl->d_counter = reinterpret_cast<uint32_t*>(b + o_cnt);
-    pl->d_work = reinterpret_cast<unsigned long long*>(b + o_cnt + 8);
+    pl->d_counter = reinterpret_cast<uint32_t*>(b + o_cnt);  // [kQueues]
+    pl->d_work = reinterpret_cast<unsigned long long*>(b + o_cnt + 32);
     pl->d_dc = reinterpret_cast<DevCounts*>(b + o_cnt + 64);
+    static_assert(4 * kQueues <= 32, "queue counters overlap the work counters");
     pl->d_partials = reinterpret_cast<float*>(b + o_part);
     pl->d_gscratch = reinterpret_cast<float*>(b + o_gs);
     pl->d_bpartials = reinterpret_cast<float*>(b + o_bp);
