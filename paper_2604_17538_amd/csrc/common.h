@@ -11,6 +11,7 @@ constexpr int kWave = 64;          // CDNA wavefront width
 constexpr int kPartial = 16;       // floats per tile partial (forward blend state)
 constexpr int kMaxPieces = 4096;   // pieces per object (index fits 16 bits)
 constexpr int kSub = 16;           // support planes per piece (lower bound of its SDF)
+constexpr int kGrp = 16;           // planes per plane group (a cone of normals bounds their values)
 constexpr float kPruneTau = 20.f;  // a piece this many tau_cup above the union's minimum has weight < 2^-28
 
 // SDF representations of an object (Sec. III): the smooth union of smooth
@@ -54,7 +55,8 @@ struct PieceDesc {
   int32_t edge_begin;     // object-level edge index
   int32_t edge_count;
   float ub_off;           // tau_cap ln(plane_count) - (distance from the centre to the nearest plane)
-  int32_t pad[2];
+  int32_t grp_begin;      // object-level index of the piece's first plane group
+  int32_t pad;
 };
 static_assert(sizeof(PieceDesc) == 48, "PieceDesc layout");
 
@@ -75,7 +77,10 @@ struct ObjDesc {
   int32_t gn;             // voxels per axis
   int32_t rep;            // SDF representation: kRepPlanes, kRepSpline or kRepPrims
   // kRepPlanes: [n_pieces][kSub] support planes (scaled like planes), min(kSub,
-  // plane_count) used.  kRepSpline: the spline coefficients, (gn + 3)^3 float4
+  // plane_count) used, then two float4 per plane group (groups of kGrp
+  // consecutive planes of a piece, the last one of a piece possibly partial):
+  // (axis, largest scaled offset), (cos, kappa cos, kappa sin of the cone's
+  // half-angle).  kRepSpline: the spline coefficients, (gn + 3)^3 float4
   // (phi, n_x, n_y, n_z) over the grid's box (its cells are the grid's voxels).
   // kRepPrims: gn PrimDev records, then their half-spaces (float4 (n, h) in each
   // PSQ frame); such an object has no voxel grid

@@ -404,8 +404,57 @@ CM_DEV void sdf_eval(const ObjDesc& o, const DevParams& P, const V3<T>* x, SdfRe
         if (!__any(need)) continue;  // no lane of the wave needs this piece
       }
     }
-    // point-plane evaluations performed by the wave (per lane)
-    if (work) *work += uint64_t(np * NP);
+    // Plane groups (kGrp consecutive planes whose normals lie in a cone of axis
+    // a and half-angle th): at v = x - c every plane of the group has
+    //   a_j = kappa (n_j . v + h_j) <= kappa C(v) + e,
+    //   C(v) = |v| if angle(a, v) <= th, else cos th (a . v) + sin th |v x a|,
+    // e the group's largest scaled offset.  With P.prune, a group whose bound
+    // lies more than gmarg below the running max at every point of the wave is
+    // skipped: gmarg = 20 log2 e + log2(np), so the skipped planes together
+    // weigh less than e^-20 < 2^-28 of the max plane's term.  Groups are visited
+    // in index order through a 64-bit mask per 64 groups.
+    const int ng = (np + kGrp - 1) / kGrp;
+    const F4* gr = o.sub + int64_t(kSub) * o.n_pieces + 2 * int64_t(pd.grp_begin);
+    const float gmarg = kPruneTau * kLog2e + lg2(float(max(np, 1)));
+    auto gmask = [&](int c0) -> uint64_t {
+      const int c1 = min(ng, c0 + 64);
+      if (!P.prune) return c1 - c0 >= 64 ? ~0ull : (1ull << (c1 - c0)) - 1ull;
+      float vr[NP], thr[NP];
+#pragma unroll
+      for (int p = 0; p < NP; ++p) {
+        vr[p] = sqrtf(dot(xl0[p], xl0[p]));
+        thr[p] = m[p] - gmarg;
+      }
+      uint64_t mk = 0;
+      for (int g = c0; g < c1; ++g) {
+        const F4 A = ldc(gr + 2 * g), B = ldc(gr + 2 * g + 1);
+        bool nd = false;
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+          const float t = fmaf(A.x, xl0[p].x, fmaf(A.y, xl0[p].y, A.z * xl0[p].z));
+          const float w = sqrtf(fmaxf(fmaf(-t, t, vr[p] * vr[p]), 0.f));
+          const float ub = (t >= vr[p] * B.x ? vr[p] * P.kcap : fmaf(B.y, t, B.z * w)) + A.w;
+          nd = nd || ub >= thr[p];
+        }
+        if (__any(nd)) mk |= 1ull << (g - c0);
+      }
+      return mk;
+    };
+    // cursor over the blocks of 4 planes of the kept groups of one chunk of 64
+    // groups (mask cur_mk of chunk cur_c0): j = first plane of the next block,
+    // -1 past the chunk's last one
+    int cur_c0 = 0, cur_j = -1;
+    uint64_t cur_mk = 0;
+    auto cur_group = [&]() {
+      if (cur_mk == 0) { cur_j = -1; return; }
+      cur_j = (cur_c0 + int(__builtin_ctzll(cur_mk))) * kGrp;
+      cur_mk &= cur_mk - 1ull;
+    };
+    auto cur_next = [&]() {
+      if (cur_j < 0) return;
+      const int j = cur_j + 4;
+      if ((j & (kGrp - 1)) != 0 && j < np) cur_j = j; else cur_group();
+    };
     // pass 1: shift = max_j a_j (value only; LSE is shift-invariant)
     if (np > kSub) {
       // blocks of 4 in ping-pong pairs as in the second pass; the clamped
@@ -428,16 +477,27 @@ CM_DEV void sdf_eval(const ObjDesc& o, const DevParams& P, const V3<T>* x, SdfRe
           }
         }
       };
-      F4 qa = blk_plane(pl, 0, np), qb = blk_plane(pl, 4, np);
-      int j = 0;
-      for (; j + 8 <= np; j += 8) {
-        blk(qa, j);
-        qa = blk_plane(pl, j + 8, np);
-        blk(qb, j + 4);
-        qb = blk_plane(pl, j + 12, np);
+      for (cur_c0 = 0; cur_c0 < ng; cur_c0 += 64) {
+        cur_mk = gmask(cur_c0);
+        cur_group();
+        int ja = cur_j;
+        F4 qa = blk_plane(pl, max(ja, 0), np);
+        cur_next();
+        int jb = cur_j;
+        F4 qb = blk_plane(pl, max(jb, 0), np);
+        cur_next();
+        while (ja >= 0) {
+          blk(qa, ja);
+          ja = cur_j;
+          qa = blk_plane(pl, max(ja, 0), np);
+          cur_next();
+          if (jb < 0) break;
+          blk(qb, jb);
+          jb = cur_j;
+          qb = blk_plane(pl, max(jb, 0), np);
+          cur_next();
+        }
       }
-      if (j < np) blk(qa, j);
-      if (j + 4 < np) blk(qb, j + 4);
     }
     V3<float> ref[NP];  // PREC: kappa n of the max plane (first of equal ones)
 #pragma unroll
@@ -489,12 +549,15 @@ CM_DEV void sdf_eval(const ObjDesc& o, const DevParams& P, const V3<T>* x, SdfRe
       }
     };
     if (np > 0) {
-      // Two blocks per iteration with ping-pong buffers for the lane's plane
-      // (matrix-core operand, vector load) and the block's planes (SGPRs, scalar
-      // loads), each refilled one block ahead: no buffer is copied across the
-      // loop, so every load has a whole block of work to complete.  Indices past
-      // the piece are clamped to its last plane (never used).
-      auto blk = [&](const F4& ql, const F4* sq, int j0, int cnt) {
+      // Blocks of the kept groups in ping-pong pairs of buffers for the lane's
+      // plane (matrix-core operand, vector load) and the block's planes (SGPRs,
+      // scalar loads), each refilled two blocks ahead: no buffer is copied
+      // across the loop, so every load has a whole block of work to complete.
+      // Indices past the piece are clamped to its last plane (never used).
+      int n2 = 0;  // planes evaluated
+      auto blk = [&](const F4& ql, const F4* sq, int j0) {
+        const int cnt = min(np - j0, 4);
+        n2 += cnt;
         f4v av[NP], at[NP];
         blk_vals_t<NP, DUAL>(ql, xl0, nm, xt, av, at);
 #pragma unroll
@@ -506,19 +569,30 @@ CM_DEV void sdf_eval(const ObjDesc& o, const DevParams& P, const V3<T>* x, SdfRe
 #pragma unroll
         for (int i = 0; i < 4; ++i) sq[i] = ldc(pl + min(j0 + i, np - 1));
       };
-      F4 qa, qb, sa[4], sb[4];
-      fill(qa, sa, 0);
-      fill(qb, sb, 4);
-      int j = 0;
-      for (; j + 8 <= np; j += 8) {
-        blk(qa, sa, j, 4);
-        fill(qa, sa, j + 8);
-        blk(qb, sb, j + 4, 4);
-        fill(qb, sb, j + 12);
+      for (cur_c0 = 0; cur_c0 < ng; cur_c0 += 64) {
+        cur_mk = gmask(cur_c0);
+        cur_group();
+        F4 qa, qb, sa[4], sb[4];
+        int ja = cur_j;
+        fill(qa, sa, max(ja, 0));
+        cur_next();
+        int jb = cur_j;
+        fill(qb, sb, max(jb, 0));
+        cur_next();
+        while (ja >= 0) {
+          blk(qa, sa, ja);
+          ja = cur_j;
+          fill(qa, sa, max(ja, 0));
+          cur_next();
+          if (jb < 0) break;
+          blk(qb, sb, jb);
+          jb = cur_j;
+          fill(qb, sb, max(jb, 0));
+          cur_next();
+        }
       }
-      // at most 7 planes left: block j in (qa, sa), block j + 4 in (qb, sb)
-      if (j < np) blk(qa, sa, j, min(np - j, 4));
-      if (j + 4 < np) blk(qb, sb, j + 4, np - j - 4);
+      // point-plane evaluations performed by the wave (per lane)
+      if (work) *work += uint64_t(n2 * NP);
     }
     // combine the piece into the running smooth union
 #pragma unroll

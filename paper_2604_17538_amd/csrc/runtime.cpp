@@ -132,6 +132,58 @@ struct Packed {
   int32_t rep;
 };
 
+// Order of a piece's planes in which each run of kGrp consecutive planes has
+// nearby normals: recursive halving of the normal set along the coordinate of
+// largest spread, the first half a whole number of groups, so that only the
+// piece's last group can be partial.
+static void group_order(const std::vector<double>& planes, std::vector<int32_t>& idx, size_t b, size_t e) {
+  const size_t n = e - b;
+  if (n <= size_t(kGrp)) return;
+  double lo[3] = {2, 2, 2}, hi[3] = {-2, -2, -2};
+  for (size_t i = b; i < e; ++i)
+    for (int a = 0; a < 3; ++a) {
+      lo[a] = std::min(lo[a], planes[4 * size_t(idx[i]) + size_t(a)]);
+      hi[a] = std::max(hi[a], planes[4 * size_t(idx[i]) + size_t(a)]);
+    }
+  int ax = 0;
+  for (int a = 1; a < 3; ++a)
+    if (hi[a] - lo[a] > hi[ax] - lo[ax]) ax = a;
+  const size_t half = size_t(kGrp) * (((n + size_t(kGrp) - 1) / size_t(kGrp)) / 2);
+  std::nth_element(idx.begin() + std::ptrdiff_t(b), idx.begin() + std::ptrdiff_t(b + half),
+                   idx.begin() + std::ptrdiff_t(e), [&](int32_t u, int32_t v) {
+                     const double pu = planes[4 * size_t(u) + size_t(ax)], pv = planes[4 * size_t(v) + size_t(ax)];
+                     return pu < pv || (pu == pv && u < v);
+                   });
+  group_order(planes, idx, b, b + half);
+  group_order(planes, idx, b + half, e);
+}
+
+// Cone record of the scaled planes q[0 .. n-1] of one group: axis a, the
+// largest offset e, and the cone's half-angle as (cos, kappa cos, kappa sin),
+// rounded outwards, so that kappa n.v + kappa h <= kappa C(v) + e for every
+// plane of the group, C(v) = max over unit n within the cone of n.v.
+static void group_cone(const std::vector<double>& planes, const int32_t* idx, size_t n, double kap,
+                       const double* hl, F4* rec) {
+  double a[3] = {0, 0, 0};
+  for (size_t i = 0; i < n; ++i)
+    for (int c = 0; c < 3; ++c) a[c] += planes[4 * size_t(idx[i]) + size_t(c)];
+  double an = std::sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]);
+  if (!(an > 1e-12)) {  // normals that cancel: the whole sphere
+    a[0] = 1; a[1] = 0; a[2] = 0; an = 1;
+  }
+  for (int c = 0; c < 3; ++c) a[c] /= an;
+  double cmin = 1, emax = -1e300;
+  for (size_t i = 0; i < n; ++i) {
+    const double* q = &planes[4 * size_t(idx[i])];
+    cmin = std::min(cmin, a[0] * q[0] + a[1] * q[1] + a[2] * q[2]);
+    emax = std::max(emax, kap * hl[i]);
+  }
+  cmin = std::max(-1.0, cmin - 1e-6);
+  const double smax = std::min(1.0, std::sqrt(std::max(0.0, 1 - cmin * cmin)) + 1e-6);
+  rec[0] = F4{float(a[0]), float(a[1]), float(a[2]), float(emax + 1e-6 * std::fabs(emax) + 1e-6)};
+  rec[1] = F4{float(cmin), float(kap * cmin), float(kap * smax), 0.f};
+}
+
 static void pack_object(const ObjHost& o, const cm_params& prm, Packed* pk) {
   const double kap = kLog2eD / double(prm.tau_cap);
   pk->K = int32_t(o.pieces.size());
@@ -142,7 +194,9 @@ static void pack_object(const ObjHost& o, const cm_params& prm, Packed* pk) {
   size_t off = 0;
   auto take = [&](size_t b) { size_t r = off; off = align_up(off + b, 256); return r; };
   pk->off_planes = take(16 * size_t(pk->P));
-  pk->off_sub = take(16 * size_t(kSub) * size_t(pk->K));
+  size_t n_grp = 0;  // plane groups of all pieces
+  for (const PieceGeom& g : o.pieces) n_grp += (g.n_planes() + size_t(kGrp) - 1) / size_t(kGrp);
+  pk->off_sub = take(16 * size_t(kSub) * size_t(pk->K) + 32 * n_grp);
   pk->off_pieces = take(sizeof(PieceDesc) * size_t(pk->K));
   pk->off_vx = take(4 * size_t(pk->V));
   pk->off_vy = take(4 * size_t(pk->V));
@@ -159,7 +213,8 @@ static void pack_object(const ObjHost& o, const cm_params& prm, Packed* pk) {
   float* vy = reinterpret_cast<float*>(pk->bytes.data() + pk->off_vy);
   float* vz = reinterpret_cast<float*>(pk->bytes.data() + pk->off_vz);
   I2* edges = reinterpret_cast<I2*>(pk->bytes.data() + pk->off_edges);
-  int32_t pb = 0, vb = 0, eb = 0;
+  F4* grp = sub + size_t(kSub) * size_t(pk->K);
+  int32_t pb = 0, vb = 0, eb = 0, gb = 0;
   std::vector<int32_t> vbase(size_t(pk->K) + 1, 0);  // object-level first vertex of each piece
   for (int32_t k = 0; k < pk->K; ++k) vbase[size_t(k) + 1] = vbase[size_t(k)] + int32_t(o.pieces[size_t(k)].n_verts());
   double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
@@ -176,11 +231,22 @@ static void pack_object(const ObjHost& o, const cm_params& prm, Packed* pk) {
     // the centre as stored in FP32 is the one the kernels subtract
     const double cf[3] = {double(d.cx), double(d.cy), double(d.cz)};
     double rin = 1e300;
-    for (size_t j = 0; j < g.n_planes(); ++j) {
-      const double* q = &g.planes[4 * j];
+    // planes in groups of kGrp with nearby normals, each with its cone record
+    std::vector<int32_t> idx(g.n_planes());
+    for (size_t j = 0; j < idx.size(); ++j) idx[j] = int32_t(j);
+    group_order(g.planes, idx, 0, idx.size());
+    std::vector<double> hls(idx.size());
+    for (size_t j = 0; j < idx.size(); ++j) {
+      const double* q = &g.planes[4 * size_t(idx[j])];
       const double hl = q[3] + q[0] * cf[0] + q[1] * cf[1] + q[2] * cf[2];
       planes[pb + int32_t(j)] = F4{float(kap * q[0]), float(kap * q[1]), float(kap * q[2]), float(kap * hl)};
+      hls[j] = hl;
       rin = std::min(rin, -hl);
+    }
+    d.grp_begin = gb;
+    for (size_t j = 0; j < idx.size(); j += size_t(kGrp), ++gb) {
+      const size_t n = std::min(size_t(kGrp), idx.size() - j);
+      group_cone(g.planes, &idx[j], n, kap, &hls[j], grp + 2 * size_t(gb));
     }
     // upper bound of the piece SDF: phi_k(x) <= |x - c| - rin + tau_cap ln P
     d.ub_off = float(double(prm.tau_cap) * std::log(double(g.n_planes())) - rin);
@@ -191,8 +257,10 @@ static void pack_object(const ObjHost& o, const cm_params& prm, Packed* pk) {
       std::vector<double> best(P, -2.0);
       size_t j = 0;
       for (int m = 0; m < kSub && m < int(P); ++m) {
-        sub[size_t(kSub) * size_t(k) + size_t(m)] = planes[pb + int32_t(j)];
         const double* a = &g.planes[4 * j];
+        const double hl = a[3] + a[0] * cf[0] + a[1] * cf[1] + a[2] * cf[2];
+        sub[size_t(kSub) * size_t(k) + size_t(m)] =
+            F4{float(kap * a[0]), float(kap * a[1]), float(kap * a[2]), float(kap * hl)};
         size_t nxt = 0;
         double lo = 3.0;
         for (size_t i = 0; i < P; ++i) {
