@@ -271,6 +271,34 @@ CM_DEV void blk_vals_t(const F4& ql, const V3<float>* x0, const f4v* nm, const V
     }
   }
 }
+// Order-preserving bits of a float (as unsigned: a < b iff bits(a) < bits(b)
+// for non-NaN a, b); never all ones for a float.
+CM_DEV uint32_t ord_bits(float f) {
+  const uint32_t b = __float_as_uint(f);
+  return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+// Least value over the wave (every lane active): within rows of 16 lanes by
+// DPP exchanges (quad swaps, half-row and row mirrors), then over the 4 rows.
+CM_DEV uint32_t dpp_min(uint32_t v, int ctrl) {
+  switch (ctrl) {  // (the DPP control must be a constant)
+    case 0: return min(v, uint32_t(__builtin_amdgcn_mov_dpp(int(v), 0xB1, 0xf, 0xf, false)));   // quad [1,0,3,2]
+    case 1: return min(v, uint32_t(__builtin_amdgcn_mov_dpp(int(v), 0x4E, 0xf, 0xf, false)));   // quad [2,3,0,1]
+    case 2: return min(v, uint32_t(__builtin_amdgcn_mov_dpp(int(v), 0x141, 0xf, 0xf, false)));  // row half mirror
+    default: return min(v, uint32_t(__builtin_amdgcn_mov_dpp(int(v), 0x140, 0xf, 0xf, false))); // row mirror
+  }
+}
+CM_DEV uint32_t wave_umin(uint32_t v) {
+  v = dpp_min(v, 0);
+  v = dpp_min(v, 1);
+  v = dpp_min(v, 2);
+  v = dpp_min(v, 3);
+  const uint32_t a = uint32_t(__builtin_amdgcn_readlane(int(v), 0));
+  const uint32_t b = uint32_t(__builtin_amdgcn_readlane(int(v), 16));
+  const uint32_t c = uint32_t(__builtin_amdgcn_readlane(int(v), 32));
+  const uint32_t d = uint32_t(__builtin_amdgcn_readlane(int(v), 48));
+  return min(min(a, b), min(c, d));
+}
+
 template <class T> CM_DEV T mkT(float v, float t);
 template <> CM_DEV float mkT<float>(float v, float) { return v; }
 template <> CM_DEV df mkT<df>(float v, float t) { return df{v, t}; }
@@ -326,26 +354,38 @@ CM_DEV void sdf_eval(const ObjDesc& o, const DevParams& P, const V3<T>* x, SdfRe
   float mub[NP];  // upper bound of the union's minimum
 #pragma unroll
   for (int p = 0; p < NP; ++p) mub[p] = __builtin_inff();
-  // with pruning, the piece of the least upper bound at the wave's first point
-  // is evaluated first, so that the running minimum M bounds the others early
-  int k_first = 0;
+  // With pruning, the first 64 pieces are visited in increasing order of their
+  // least upper bound over the wave's points (|x - c_k| + ub_off_k), so that the
+  // running minimum M is tight early; the others follow in index order.  Lane k
+  // of `key` holds piece k's bound as order-preserving bits, all ones once the
+  // piece is taken (or for no piece).
+  const int lane = int(threadIdx.x) & (kWave - 1);
+  uint32_t key = ~0u;
   if (P.prune) {
-    int kb = 0;
     for (int k = 0; k < K; ++k) {
       const PieceDesc pd = ldc(o.pieces + k);
+      float umin = __builtin_inff();
 #pragma unroll
       for (int p = 0; p < NP; ++p) {
         const V3<float> d = val3(x[p]) - V3<float>{pd.cx, pd.cy, pd.cz};
         const float u = sqrtf(dot(d, d)) + pd.ub_off;
-        if (p == 0 && u < mub[0]) kb = k;
         mub[p] = fminf(mub[p], u);
+        umin = fminf(umin, u);
+      }
+      if (k < kWave) {
+        const uint32_t w = wave_umin(ord_bits(umin));
+        key = lane == k ? w : key;
       }
     }
-    k_first = __builtin_amdgcn_readfirstlane(kb);
   }
-  // order: k_first, then 0 .. K - 1 without it
+  const int K64 = P.prune ? min(K, kWave) : 0;
   for (int kk = 0; kk < K; ++kk) {
-    const int k = kk == 0 ? k_first : (kk <= k_first ? kk - 1 : kk);
+    int k = kk;
+    if (kk < K64) {  // the untaken piece of least bound (lowest index on ties)
+      const uint32_t w = wave_umin(key);
+      k = int(__builtin_ctzll(__ballot(key == w)));
+      key = lane == k ? ~0u : key;
+    }
     const PieceDesc pd = ldc(o.pieces + k);
     const int pb = min(max(pd.plane_begin, 0), o.n_planes);
     const F4* pl = o.planes + pb;
