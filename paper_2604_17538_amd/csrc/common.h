@@ -48,8 +48,8 @@ static_assert(sizeof(PrimDev) == 208, "PrimDev layout");
 // piece's log-sum-exp runs in base 2 with the temperature folded in.
 struct PieceDesc {
   float cx, cy, cz;       // centre (mean of the piece's vertices), object frame
-  int32_t plane_begin;    // object-level plane index
-  int32_t plane_count;
+  int32_t plane_begin;    // object-level plane index (a multiple of kGrp)
+  int32_t plane_count;    // planes of the piece; the array holds them padded to whole groups
   int32_t vert_begin;     // object-level vertex index
   int32_t vert_count;
   int32_t edge_begin;     // object-level edge index
@@ -62,7 +62,8 @@ static_assert(sizeof(PieceDesc) == 48, "PieceDesc layout");
 
 // A resident object (device).  All arrays are SoA in one allocation.
 struct ObjDesc {
-  const F4* planes;       // [P] (kappa n, kappa h_local), h_local relative to the piece centre
+  const F4* planes;       // [P] (kappa n, kappa h_local), h_local relative to the piece centre;
+                          // each piece padded to whole groups of kGrp with (0, 0, 0, -1e30)
   const PieceDesc* pieces;
   const float* vx;        // [V] object frame
   const float* vy;

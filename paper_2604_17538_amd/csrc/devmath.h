@@ -237,6 +237,13 @@ CM_DEV F4 blk_plane(const F4* q, int j, int n) {
   __builtin_memcpy(&r, &w, 16);
   return r;
 }
+// this lane's plane of the block q[j .. j + 3] of a piece stored in whole groups
+CM_DEV F4 grp_plane(const F4* q, int j) {
+  const v4i w = ((gv4p)q)[j + (int(threadIdx.x) & 3)];
+  F4 r;
+  __builtin_memcpy(&r, &w, 16);
+  return r;
+}
 // plane values of a block at NP points: value and (dual scalars) tangent
 template <int NP, class T>
 CM_DEV void blk_vals(const F4& ql, const V3<T>* xl, f4v* av, f4v* at) {
@@ -445,7 +452,8 @@ CM_DEV void sdf_eval(const ObjDesc& o, const DevParams& P, const V3<T>* x, SdfRe
       }
     }
     // Plane groups (kGrp consecutive planes whose normals lie in a cone of axis
-    // a and half-angle th): at v = x - c every plane of the group has
+    // a and half-angle th; a piece's planes are stored padded to whole groups
+    // with inert planes): at v = x - c every plane of the group has
     //   a_j = kappa (n_j . v + h_j) <= kappa C(v) + e,
     //   C(v) = |v| if angle(a, v) <= th, else cos th (a . v) + sin th |v x a|,
     // e the group's largest scaled offset.  With P.prune, a group whose bound
@@ -453,7 +461,7 @@ CM_DEV void sdf_eval(const ObjDesc& o, const DevParams& P, const V3<T>* x, SdfRe
     // skipped: gmarg = 20 log2 e + log2(np), so the skipped planes together
     // weigh less than e^-20 < 2^-28 of the max plane's term.  Groups are visited
     // in index order through a 64-bit mask per 64 groups.
-    const int ng = (np + kGrp - 1) / kGrp;
+    const int ng = min((np + kGrp - 1) / kGrp, (o.n_planes - pb) / kGrp);  // (never past the array)
     const F4* gr = o.sub + int64_t(kSub) * o.n_pieces + 2 * int64_t(pd.grp_begin);
     const float gmarg = kPruneTau * kLog2e + lg2(float(max(np, 1)));
     auto gmask = [&](int c0) -> uint64_t {
@@ -480,25 +488,18 @@ CM_DEV void sdf_eval(const ObjDesc& o, const DevParams& P, const V3<T>* x, SdfRe
       }
       return mk;
     };
-    // cursor over the blocks of 4 planes of the kept groups of one chunk of 64
-    // groups (mask cur_mk of chunk cur_c0): j = first plane of the next block,
-    // -1 past the chunk's last one
-    int cur_c0 = 0, cur_j = -1;
-    uint64_t cur_mk = 0;
-    auto cur_group = [&]() {
-      if (cur_mk == 0) { cur_j = -1; return; }
-      cur_j = (cur_c0 + int(__builtin_ctzll(cur_mk))) * kGrp;
-      cur_mk &= cur_mk - 1ull;
-    };
-    auto cur_next = [&]() {
-      if (cur_j < 0) return;
-      const int j = cur_j + 4;
-      if ((j & (kGrp - 1)) != 0 && j < np) cur_j = j; else cur_group();
+    // the lowest kept group of the chunk at c0 (its bit cleared), -1 if none
+    auto take = [&](uint64_t& mk, int c0) -> int {
+      if (mk == 0) return -1;
+      const int g = c0 + int(__builtin_ctzll(mk));
+      mk &= mk - 1ull;
+      return g;
     };
     // pass 1: shift = max_j a_j (value only; LSE is shift-invariant)
     if (np > kSub) {
-      // blocks of 4 in ping-pong pairs as in the second pass; the clamped
-      // repeats of the last plane come after it and never raise the max
+      // the 4 blocks of each kept group, the lane plane in ping-pong buffers
+      // refilled two blocks ahead (the next kept group's first two blocks during
+      // this group's last two); padding planes never raise the max
       auto blk = [&](const F4& ql, int j0) {
         f4v av[NP], at[NP];
         blk_vals<NP, float>(ql, xl0, av, at);
@@ -517,25 +518,23 @@ CM_DEV void sdf_eval(const ObjDesc& o, const DevParams& P, const V3<T>* x, SdfRe
           }
         }
       };
-      for (cur_c0 = 0; cur_c0 < ng; cur_c0 += 64) {
-        cur_mk = gmask(cur_c0);
-        cur_group();
-        int ja = cur_j;
-        F4 qa = blk_plane(pl, max(ja, 0), np);
-        cur_next();
-        int jb = cur_j;
-        F4 qb = blk_plane(pl, max(jb, 0), np);
-        cur_next();
-        while (ja >= 0) {
-          blk(qa, ja);
-          ja = cur_j;
-          qa = blk_plane(pl, max(ja, 0), np);
-          cur_next();
-          if (jb < 0) break;
-          blk(qb, jb);
-          jb = cur_j;
-          qb = blk_plane(pl, max(jb, 0), np);
-          cur_next();
+      for (int c0 = 0; c0 < ng; c0 += 64) {
+        uint64_t mk = gmask(c0);
+        int g = take(mk, c0);
+        const int j1 = max(g, 0) * kGrp;
+        F4 qa = grp_plane(pl, j1), qb = grp_plane(pl, j1 + 4);
+        while (g >= 0) {
+          const int gn = take(mk, c0);
+          const int j = g * kGrp, jn = (gn >= 0 ? gn : g) * kGrp;
+          blk(qa, j);
+          qa = grp_plane(pl, j + 8);
+          blk(qb, j + 4);
+          qb = grp_plane(pl, j + 12);
+          blk(qa, j + 8);
+          qa = grp_plane(pl, jn);
+          blk(qb, j + 12);
+          qb = grp_plane(pl, jn + 4);
+          g = gn;
         }
       }
     }
@@ -589,46 +588,44 @@ CM_DEV void sdf_eval(const ObjDesc& o, const DevParams& P, const V3<T>* x, SdfRe
       }
     };
     if (np > 0) {
-      // Blocks of the kept groups in ping-pong pairs of buffers for the lane's
-      // plane (matrix-core operand, vector load) and the block's planes (SGPRs,
-      // scalar loads), each refilled two blocks ahead: no buffer is copied
-      // across the loop, so every load has a whole block of work to complete.
-      // Indices past the piece are clamped to its last plane (never used).
-      int n2 = 0;  // planes evaluated
-      auto blk = [&](const F4& ql, const F4* sq, int j0) {
-        const int cnt = min(np - j0, 4);
-        n2 += cnt;
+      // The 4 blocks of each kept group, in ping-pong pairs of buffers for the
+      // lane's plane (matrix-core operand, vector load) and the block's planes
+      // (SGPRs, scalar loads), each refilled two blocks ahead (the next kept
+      // group's first two blocks during this group's last two): no buffer is
+      // copied across the loop, so every load has a whole block of work to
+      // complete.  Padding planes add exact zeros.
+      int n2 = 0;  // planes of the piece evaluated
+      auto blk = [&](const F4& ql, const F4* sq) {
         f4v av[NP], at[NP];
         blk_vals_t<NP, DUAL>(ql, xl0, nm, xt, av, at);
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-          if (i < cnt) term(sq[i], av, at, i);
+        for (int i = 0; i < 4; ++i) term(sq[i], av, at, i);
       };
       auto fill = [&](F4& ql, F4* sq, int j0) {
-        ql = blk_plane(pl, j0, np);
+        ql = grp_plane(pl, j0);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) sq[i] = ldc(pl + min(j0 + i, np - 1));
+        for (int i = 0; i < 4; ++i) sq[i] = ldc(pl + j0 + i);
       };
-      for (cur_c0 = 0; cur_c0 < ng; cur_c0 += 64) {
-        cur_mk = gmask(cur_c0);
-        cur_group();
+      for (int c0 = 0; c0 < ng; c0 += 64) {
+        uint64_t mk = gmask(c0);
+        int g = take(mk, c0);
+        const int j1 = max(g, 0) * kGrp;
         F4 qa, qb, sa[4], sb[4];
-        int ja = cur_j;
-        fill(qa, sa, max(ja, 0));
-        cur_next();
-        int jb = cur_j;
-        fill(qb, sb, max(jb, 0));
-        cur_next();
-        while (ja >= 0) {
-          blk(qa, sa, ja);
-          ja = cur_j;
-          fill(qa, sa, max(ja, 0));
-          cur_next();
-          if (jb < 0) break;
-          blk(qb, sb, jb);
-          jb = cur_j;
-          fill(qb, sb, max(jb, 0));
-          cur_next();
+        fill(qa, sa, j1);
+        fill(qb, sb, j1 + 4);
+        while (g >= 0) {
+          const int gn = take(mk, c0);
+          const int j = g * kGrp, jn = (gn >= 0 ? gn : g) * kGrp;
+          n2 += min(kGrp, np - j);
+          blk(qa, sa);
+          fill(qa, sa, j + 8);
+          blk(qb, sb);
+          fill(qb, sb, j + 12);
+          blk(qa, sa);
+          fill(qa, sa, jn);
+          blk(qb, sb);
+          fill(qb, sb, jn + 4);
+          g = gn;
         }
       }
       // point-plane evaluations performed by the wave (per lane)

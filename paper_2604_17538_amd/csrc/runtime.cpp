@@ -187,15 +187,17 @@ static void group_cone(const std::vector<double>& planes, const int32_t* idx, si
 static void pack_object(const ObjHost& o, const cm_params& prm, Packed* pk) {
   const double kap = kLog2eD / double(prm.tau_cap);
   pk->K = int32_t(o.pieces.size());
-  pk->P = int32_t(o.n_planes);
+  // every piece's planes fill whole groups of kGrp: the last group is padded
+  // with inert planes (n = 0, h = -1e30: value -1e30, weight 0, never the max)
+  size_t n_grp = 0;  // plane groups of all pieces
+  for (const PieceGeom& g : o.pieces) n_grp += (g.n_planes() + size_t(kGrp) - 1) / size_t(kGrp);
+  pk->P = int32_t(n_grp * size_t(kGrp));
   pk->V = int32_t(o.n_verts);
   pk->E = int32_t(o.n_edges);
   const int gn = prm.grid_res;
   size_t off = 0;
   auto take = [&](size_t b) { size_t r = off; off = align_up(off + b, 256); return r; };
   pk->off_planes = take(16 * size_t(pk->P));
-  size_t n_grp = 0;  // plane groups of all pieces
-  for (const PieceGeom& g : o.pieces) n_grp += (g.n_planes() + size_t(kGrp) - 1) / size_t(kGrp);
   pk->off_sub = take(16 * size_t(kSub) * size_t(pk->K) + 32 * n_grp);
   pk->off_pieces = take(sizeof(PieceDesc) * size_t(pk->K));
   pk->off_vx = take(4 * size_t(pk->V));
@@ -248,6 +250,8 @@ static void pack_object(const ObjHost& o, const cm_params& prm, Packed* pk) {
       const size_t n = std::min(size_t(kGrp), idx.size() - j);
       group_cone(g.planes, &idx[j], n, kap, &hls[j], grp + 2 * size_t(gb));
     }
+    const size_t padded = size_t(kGrp) * ((idx.size() + size_t(kGrp) - 1) / size_t(kGrp));
+    for (size_t j = idx.size(); j < padded; ++j) planes[pb + int32_t(j)] = F4{0.f, 0.f, 0.f, -1e30f};
     // upper bound of the piece SDF: phi_k(x) <= |x - c| - rin + tau_cap ln P
     d.ub_off = float(double(prm.tau_cap) * std::log(double(g.n_planes())) - rin);
     // support subset: farthest-point sampling of the normals; the max plane
@@ -289,7 +293,8 @@ static void pack_object(const ObjHost& o, const cm_params& prm, Packed* pk) {
       const int32_t vk = vbase[size_t(xe[2 * x])];
       edges[eb + int32_t(g.n_edges() + x)] = I2{vk + gk.edges[2 * e], vk + gk.edges[2 * e + 1]};
     }
-    pb += d.plane_count; vb += d.vert_count; eb += d.edge_count;
+    pb += int32_t(kGrp) * ((d.plane_count + int32_t(kGrp) - 1) / int32_t(kGrp));
+    vb += d.vert_count; eb += d.edge_count;
   }
   // voxel grid over the vertex AABB grown by margin + margin_rel * radius
   const double margin = double(prm.grid_margin) + double(prm.grid_margin_rel) * o.radius;
