@@ -397,7 +397,6 @@ CM_DEV void sdf_eval(const ObjDesc& o, const DevParams& P, const V3<T>* x, SdfRe
     const int pb = min(max(pd.plane_begin, 0), o.n_planes);
     const F4* pl = o.planes + pb;
     const int np = min(max(pd.plane_count, 0), o.n_planes - pb);  // never past the object's planes
-    const int ns = min(np, kSub);
     const F4* sp = o.sub + int64_t(kSub) * k;
     V3<T> xl[NP];
     float m[NP];
@@ -414,42 +413,46 @@ CM_DEV void sdf_eval(const ObjDesc& o, const DevParams& P, const V3<T>* x, SdfRe
     }
     // the support subset: a lower bound of the piece SDF, and for a piece of
     // at most kSub planes (the subset is all of them) already the LSE shift
-    if (P.prune || np <= kSub) {
-      if (work && P.prune) *work += uint64_t(ns * NP);  // the bound
-      // (a block's repeats of the last plane never raise the max: equal values)
-      if (ns > 0) {
-        // at most kSub / 4 blocks: every block's lane plane is loaded first
-        F4 qv[kSub / 4];
+    // a piece matters at a lane while its lower bound m / kappa (the largest
+    // plane value found so far) is below lim = min(mub, M) + prune_margin
+    float lim[NP];
 #pragma unroll
-        for (int b = 0; b < kSub / 4; ++b) qv[b] = blk_plane(sp, 4 * b, ns);
+    for (int p = 0; p < NP; ++p) lim[p] = fminf(mub[p], M[p]) + P.prune_margin;
+    auto needed = [&]() {
+      bool need = false;
+#pragma unroll
+      for (int p = 0; p < NP; ++p) need = need || m[p] * P.icap < lim[p];
+      return __any(need);
+    };
+    if (P.prune || np <= kSub) {
+      if (work && P.prune) *work += uint64_t(kSub * NP);  // the bound
+      // the kSub planes of the subset (a piece of fewer planes repeats its
+      // first, and repeats never raise the max: equal values)
+      if (np > 0) {
+        F4 qv[kSub / 4];  // every block's lane plane is loaded first
+#pragma unroll
+        for (int b = 0; b < kSub / 4; ++b) qv[b] = grp_plane(sp, 4 * b);
 #pragma unroll
         for (int b = 0; b < kSub / 4; ++b) {
-          if (4 * b < ns) {
-            f4v av[NP], at[NP];
-            blk_vals<NP, float>(qv[b], xl0, av, at);
+          f4v av[NP], at[NP];
+          blk_vals<NP, float>(qv[b], xl0, av, at);
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
+          for (int i = 0; i < 4; ++i) {
 #pragma unroll
-              for (int p = 0; p < NP; ++p) {
-                const float a = av[p][i];
-                if (PREC) {
-                  const bool up = a > m[p];
-                  m[p] = up ? a : m[p];
-                  jm[p] = up ? -1 - (4 * b + i) : jm[p];
-                } else {
-                  m[p] = fmaxf(m[p], a);
-                }
+            for (int p = 0; p < NP; ++p) {
+              const float a = av[p][i];
+              if (PREC) {
+                const bool up = a > m[p];
+                m[p] = up ? a : m[p];
+                jm[p] = up ? -1 - (4 * b + i) : jm[p];
+              } else {
+                m[p] = fmaxf(m[p], a);
               }
             }
           }
         }
       }
-      if (P.prune) {
-        bool need = false;
-#pragma unroll
-        for (int p = 0; p < NP; ++p) need = need || m[p] * P.icap < fminf(mub[p], M[p]) + P.prune_margin;
-        if (!__any(need)) continue;  // no lane of the wave needs this piece
-      }
+      if (P.prune && !needed()) continue;  // no lane of the wave needs this piece
     }
     // Plane groups (kGrp consecutive planes whose normals lie in a cone of axis
     // a and half-angle th; a piece's planes are stored padded to whole groups
@@ -518,7 +521,11 @@ CM_DEV void sdf_eval(const ObjDesc& o, const DevParams& P, const V3<T>* x, SdfRe
           }
         }
       };
-      for (int c0 = 0; c0 < ng; c0 += 64) {
+      // with pruning, the largest plane value found so far is a tighter lower
+      // bound of the piece SDF than the subset's: the pass stops, and the piece
+      // is skipped, once it shows that no lane needs the piece
+      bool skip = false;
+      for (int c0 = 0; c0 < ng && !skip; c0 += 64) {
         uint64_t mk = gmask(c0);
         int g = take(mk, c0);
         const int j1 = max(g, 0) * kGrp;
@@ -535,15 +542,17 @@ CM_DEV void sdf_eval(const ObjDesc& o, const DevParams& P, const V3<T>* x, SdfRe
           blk(qb, j + 12);
           qb = grp_plane(pl, jn + 4);
           g = gn;
+          if (P.prune && !needed()) { skip = true; break; }
         }
       }
+      if (skip) continue;
     }
     V3<float> ref[NP];  // PREC: kappa n of the max plane (first of equal ones)
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
       ref[p] = {0.f, 0.f, 0.f};
       if (PREC && np > 0) {
-        const F4 q = jm[p] >= 0 ? pl[min(jm[p], np - 1)] : sp[min(-1 - jm[p], ns - 1)];
+        const F4 q = jm[p] >= 0 ? pl[min(jm[p], np - 1)] : sp[min(-1 - jm[p], kSub - 1)];
         ref[p] = {q.x, q.y, q.z};
       }
     }

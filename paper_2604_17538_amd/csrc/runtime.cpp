@@ -274,6 +274,9 @@ static void pack_object(const ObjHost& o, const cm_params& prm, Packed* pk) {
         }
         j = nxt;
       }
+      // a piece of fewer planes repeats its first one (the max is unchanged)
+      for (int m = int(std::min<size_t>(P, size_t(kSub))); m < kSub && P > 0; ++m)
+        sub[size_t(kSub) * size_t(k) + size_t(m)] = sub[size_t(kSub) * size_t(k)];
     }
     for (size_t i = 0; i < g.n_verts(); ++i) {
       vx[vb + int32_t(i)] = float(g.verts[3 * i]);
