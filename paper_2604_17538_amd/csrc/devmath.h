@@ -467,9 +467,12 @@ CM_DEV void sdf_eval(const ObjDesc& o, const DevParams& P, const V3<T>* x, SdfRe
     const int ng = min((np + kGrp - 1) / kGrp, (o.n_planes - pb) / kGrp);  // (never past the array)
     const F4* gr = o.sub + int64_t(kSub) * o.n_pieces + 2 * int64_t(pd.grp_begin);
     const float gmarg = kPruneTau * kLog2e + lg2(float(max(np, 1)));
-    auto gmask = [&](int c0) -> uint64_t {
+    // (best: when given, the kept group of the highest bound at lane 0's first point)
+    auto gmask = [&](int c0, int* best) -> uint64_t {
       const int c1 = min(ng, c0 + 64);
+      if (best) *best = -1;
       if (!P.prune) return c1 - c0 >= 64 ? ~0ull : (1ull << (c1 - c0)) - 1ull;
+      uint32_t bu = 0u;
       float vr[NP], thr[NP];
 #pragma unroll
       for (int p = 0; p < NP; ++p) {
@@ -480,14 +483,22 @@ CM_DEV void sdf_eval(const ObjDesc& o, const DevParams& P, const V3<T>* x, SdfRe
       for (int g = c0; g < c1; ++g) {
         const F4 A = ldc(gr + 2 * g), B = ldc(gr + 2 * g + 1);
         bool nd = false;
+        float ub0 = 0.f;
 #pragma unroll
         for (int p = 0; p < NP; ++p) {
           const float t = fmaf(A.x, xl0[p].x, fmaf(A.y, xl0[p].y, A.z * xl0[p].z));
           const float w = sqrtf(fmaxf(fmaf(-t, t, vr[p] * vr[p]), 0.f));
           const float ub = (t >= vr[p] * B.x ? vr[p] * P.kcap : fmaf(B.y, t, B.z * w)) + A.w;
           nd = nd || ub >= thr[p];
+          if (p == 0) ub0 = ub;
         }
-        if (__any(nd)) mk |= 1ull << (g - c0);
+        if (__any(nd)) {
+          mk |= 1ull << (g - c0);
+          if (best) {
+            const uint32_t u = uint32_t(__builtin_amdgcn_readfirstlane(int(ord_bits(ub0))));
+            if (*best < 0 || u > bu) { bu = u; *best = g; }
+          }
+        }
       }
       return mk;
     };
@@ -526,8 +537,10 @@ CM_DEV void sdf_eval(const ObjDesc& o, const DevParams& P, const V3<T>* x, SdfRe
       // is skipped, once it shows that no lane needs the piece
       bool skip = false;
       for (int c0 = 0; c0 < ng && !skip; c0 += 64) {
-        uint64_t mk = gmask(c0);
-        int g = take(mk, c0);
+        // the group most likely to hold the max first, then the others in order
+        int g = -1;
+        uint64_t mk = gmask(c0, &g);
+        if (g >= 0) mk &= ~(1ull << (g - c0)); else g = take(mk, c0);  // (no best without pruning)
         const int j1 = max(g, 0) * kGrp;
         F4 qa = grp_plane(pl, j1), qb = grp_plane(pl, j1 + 4);
         while (g >= 0) {
@@ -616,7 +629,7 @@ CM_DEV void sdf_eval(const ObjDesc& o, const DevParams& P, const V3<T>* x, SdfRe
         for (int i = 0; i < 4; ++i) sq[i] = ldc(pl + j0 + i);
       };
       for (int c0 = 0; c0 < ng; c0 += 64) {
-        uint64_t mk = gmask(c0);
+        uint64_t mk = gmask(c0, nullptr);
         int g = take(mk, c0);
         const int j1 = max(g, 0) * kGrp;
         F4 qa, qb, sa[4], sb[4];
