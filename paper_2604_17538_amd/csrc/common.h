@@ -12,6 +12,7 @@ constexpr int kPartial = 16;       // floats per tile partial (forward blend sta
 constexpr int kMaxPieces = 4096;   // pieces per object (index fits 16 bits)
 constexpr int kSub = 16;           // support planes per piece (lower bound of its SDF)
 constexpr int kGrp = 16;           // planes per plane group (a cone of normals bounds their values)
+static_assert(kGrp % 8 == 0, "plane groups are whole pairs of blocks of 4");
 constexpr float kPruneTau = 20.f;  // a piece this many tau_cup above the union's minimum has weight < 2^-28
 
 // SDF representations of an object (Sec. III): the smooth union of smooth

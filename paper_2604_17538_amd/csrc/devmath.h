@@ -455,13 +455,14 @@ CM_DEV void sdf_eval(const ObjDesc& o, const DevParams& P, const V3<T>* x, SdfRe
       if (P.prune && !needed()) continue;  // no lane of the wave needs this piece
     }
     // Plane groups (kGrp consecutive planes whose normals lie in a cone of axis
-    // a and half-angle th; a piece's planes are stored padded to whole groups
-    // with inert planes): at v = x - c every plane of the group has
-    //   a_j = kappa (n_j . v + h_j) <= kappa C(v) + e,
-    //   C(v) = |v| if angle(a, v) <= th, else cos th (a . v) + sin th |v x a|,
-    // e the group's largest scaled offset.  With P.prune, a group whose bound
-    // lies more than gmarg below the running max at every point of the wave is
-    // skipped: gmarg = 20 log2 e + log2(np), so the skipped planes together
+    // a and half-angle th <= 90 degrees; a piece's planes are stored padded to
+    // whole groups with inert planes): at v = x - c every plane of the group has
+    //   a_j = kappa (n_j . v + h_j) <= kappa (cos th (a . v) + sin th |v|) + e,
+    // e the group's largest scaled offset (the max of n . v over the cone is
+    // |v| cos(max(phi - th, 0)), phi = angle(a, v), which the right side bounds
+    // for every phi when th <= 90 degrees: no square root or select per test).
+    // With P.prune, a group whose bound lies more than gmarg below the running
+    // max at every point of the wave is skipped: gmarg = 20 log2 e + log2(np), so the skipped planes together
     // weigh less than e^-20 < 2^-28 of the max plane's term.  Groups are visited
     // in index order through a 64-bit mask per 64 groups.
     const int ng = min((np + kGrp - 1) / kGrp, (o.n_planes - pb) / kGrp);  // (never past the array)
@@ -487,8 +488,7 @@ CM_DEV void sdf_eval(const ObjDesc& o, const DevParams& P, const V3<T>* x, SdfRe
 #pragma unroll
         for (int p = 0; p < NP; ++p) {
           const float t = fmaf(A.x, xl0[p].x, fmaf(A.y, xl0[p].y, A.z * xl0[p].z));
-          const float w = sqrtf(fmaxf(fmaf(-t, t, vr[p] * vr[p]), 0.f));
-          const float ub = (t >= vr[p] * B.x ? vr[p] * P.kcap : fmaf(B.y, t, B.z * w)) + A.w;
+          const float ub = fmaf(B.y, t, fmaf(B.z, vr[p], A.w));
           nd = nd || ub >= thr[p];
           if (p == 0) ub0 = ub;
         }
@@ -546,14 +546,14 @@ CM_DEV void sdf_eval(const ObjDesc& o, const DevParams& P, const V3<T>* x, SdfRe
         while (g >= 0) {
           const int gn = take(mk, c0);
           const int j = g * kGrp, jn = (gn >= 0 ? gn : g) * kGrp;
-          blk(qa, j);
-          qa = grp_plane(pl, j + 8);
-          blk(qb, j + 4);
-          qb = grp_plane(pl, j + 12);
-          blk(qa, j + 8);
-          qa = grp_plane(pl, jn);
-          blk(qb, j + 12);
-          qb = grp_plane(pl, jn + 4);
+#pragma unroll
+          for (int b = 0; b < kGrp; b += 8) {
+            const bool last = b + 8 >= kGrp;
+            blk(qa, j + b);
+            qa = grp_plane(pl, last ? jn : j + b + 8);
+            blk(qb, j + b + 4);
+            qb = grp_plane(pl, last ? jn + 4 : j + b + 12);
+          }
           g = gn;
           if (P.prune && !needed()) { skip = true; break; }
         }
@@ -639,14 +639,14 @@ CM_DEV void sdf_eval(const ObjDesc& o, const DevParams& P, const V3<T>* x, SdfRe
           const int gn = take(mk, c0);
           const int j = g * kGrp, jn = (gn >= 0 ? gn : g) * kGrp;
           n2 += min(kGrp, np - j);
-          blk(qa, sa);
-          fill(qa, sa, j + 8);
-          blk(qb, sb);
-          fill(qb, sb, j + 12);
-          blk(qa, sa);
-          fill(qa, sa, jn);
-          blk(qb, sb);
-          fill(qb, sb, jn + 4);
+#pragma unroll
+          for (int b = 0; b < kGrp; b += 8) {
+            const bool last = b + 8 >= kGrp;
+            blk(qa, sa);
+            fill(qa, sa, last ? jn : j + b + 8);
+            blk(qb, sb);
+            fill(qb, sb, last ? jn + 4 : j + b + 12);
+          }
           g = gn;
         }
       }

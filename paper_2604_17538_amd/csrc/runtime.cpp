@@ -159,9 +159,9 @@ static void group_order(const std::vector<double>& planes, std::vector<int32_t>&
 }
 
 // Cone record of the scaled planes q[0 .. n-1] of one group: axis a, the
-// largest offset e, and the cone's half-angle as (cos, kappa cos, kappa sin),
-// rounded outwards, so that kappa n.v + kappa h <= kappa C(v) + e for every
-// plane of the group, C(v) = max over unit n within the cone of n.v.
+// largest offset e, and the cone's half-angle (at most 90 degrees) as (cos,
+// kappa cos, kappa sin), rounded outwards, so that for every plane of the group
+// kappa n.v + kappa h <= kappa (cos (a.v) + sin |v|) + e.
 static void group_cone(const std::vector<double>& planes, const int32_t* idx, size_t n, double kap,
                        const double* hl, F4* rec) {
   double a[3] = {0, 0, 0};
@@ -178,7 +178,7 @@ static void group_cone(const std::vector<double>& planes, const int32_t* idx, si
     cmin = std::min(cmin, a[0] * q[0] + a[1] * q[1] + a[2] * q[2]);
     emax = std::max(emax, kap * hl[i]);
   }
-  cmin = std::max(-1.0, cmin - 1e-6);
+  cmin = std::max(0.0, cmin - 1e-6);  // (a half-angle above 90 degrees counts as 90: the bound still holds)
   const double smax = std::min(1.0, std::sqrt(std::max(0.0, 1 - cmin * cmin)) + 1e-6);
   rec[0] = F4{float(a[0]), float(a[1]), float(a[2]), float(emax + 1e-6 * std::fabs(emax) + 1e-6)};
   rec[1] = F4{float(cmin), float(kap * cmin), float(kap * smax), 0.f};
