@@ -462,9 +462,10 @@ CM_DEV void sdf_eval(const ObjDesc& o, const DevParams& P, const V3<T>* x, SdfRe
     // |v| cos(max(phi - th, 0)), phi = angle(a, v), which the right side bounds
     // for every phi when th <= 90 degrees: no square root or select per test).
     // With P.prune, a group whose bound lies more than gmarg below the running
-    // max at every point of the wave is skipped: gmarg = 20 log2 e + log2(np), so the skipped planes together
-    // weigh less than e^-20 < 2^-28 of the max plane's term.  Groups are visited
-    // in index order through a 64-bit mask per 64 groups.
+    // max at every point of the wave is skipped: gmarg = 20 log2 e + log2(np),
+    // so the skipped planes together weigh less than e^-20 < 2^-28 of the max
+    // plane's term.  Groups are visited in index order through a 64-bit mask
+    // per 64 groups.
     const int ng = min((np + kGrp - 1) / kGrp, (o.n_planes - pb) / kGrp);  // (never past the array)
     const F4* gr = o.sub + int64_t(kSub) * o.n_pieces + 2 * int64_t(pd.grp_begin);
     const float gmarg = kPruneTau * kLog2e + lg2(float(max(np, 1)));
