@@ -12,6 +12,8 @@
 // point and at the sphere-trace iterates) on a tape for the tiles the plan's
 // memory holds; the adjoint rebuilds the rest of each contact with a few
 // arithmetic operations.  Tiles past the tape recompute their forward pass.
+#include <atomic>
+
 #include "devmath.h"
 #include "kernels.h"
 #include "prims.h"
@@ -818,12 +820,36 @@ __global__ __launch_bounds__(256) void k_reduce(FinArgs a, const float* __restri
 // ------------------------------------------------------------- launchers --
 static inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+// Workgroups of `waves` waves of one narrow-phase kernel that a CU keeps
+// resident (the occupancy query, cached per kernel and workgroup size; 0 if it
+// fails).
+template <class T, bool ADJ, bool TAPE, int REP> static int resident_per_cu(int waves) {
+  static std::atomic<int> cache[5];  // by waves per workgroup, 1 .. 4; -1: the query failed
+  int n = cache[waves].load(std::memory_order_relaxed);
+  if (n == 0) {
+    int r = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&r, reinterpret_cast<const void*>(&k_narrow<T, ADJ, TAPE, REP>),
+                                                     kWave * waves, 0) != hipSuccess || r <= 0)
+      r = -1;
+    cache[waves].store(r, std::memory_order_relaxed);
+    n = r;
+  }
+  return std::max(n, 0);
+}
+
 // Timing events bracket a group of launches: `first` records the start,
-// `last` the stop.
+// `last` the stop.  A persistent sweep never launches fewer workgroups than
+// the CUs keep resident: the launch shape is tuned on one sweep of a step and
+// shared with sweeps that may fit more waves.
 template <class T, bool ADJ, bool TAPE>
-static void narrow_launch(const NarrowArgs& na, int grid, int waves, hipStream_t s, hipEvent_t* ev, bool first = true,
-                          bool last = true) {
-  const dim3 block(unsigned(kWave * std::min(std::max(waves, 1), 4)));  // (the kernels' bound: 256 threads)
+static void narrow_launch(const NarrowArgs& na, int n_cu, int per_cu, int waves, hipStream_t s, hipEvent_t* ev,
+                          bool first = true, bool last = true) {
+  waves = std::min(std::max(waves, 1), 4);  // (the kernels' bound: 256 threads)
+  const dim3 block(unsigned(kWave * waves));
+  const int res = na.rep == kRepSpline ? resident_per_cu<T, ADJ, false, kRepSpline>(waves)
+                  : na.rep == kRepPrims ? resident_per_cu<T, ADJ, false, kRepPrims>(waves)
+                                        : resident_per_cu<T, ADJ, TAPE, kRepPlanes>(waves);
+  const int grid = n_cu * std::max(per_cu, res);
   launch_fill_u32(na.counter, 0u, kQueues, s);
   const int slot = nT<T>() == 1 ? (ADJ ? kTNarrowAdj : kTNarrowFwd) : (ADJ ? kTNarrowDualAdj : kTNarrowTan);
   if (ev && first) (void)hipEventRecord(ev[2 * slot], s);
@@ -867,8 +893,8 @@ hipError_t launch_forward(const FwdArgs& a, hipStream_t s) {
   (void)hipGetLastError();
   if (a.work) launch_fill_u32(reinterpret_cast<uint32_t*>(a.work), 0u, 4, s);
   launch_front(a, s);
-  const int grid = a.n_cu * a.blocks_per_cu;
-  narrow_launch<float, false, false>(narrow_args(a, a.partials, nullptr, a.dbg), grid, a.wg_waves, s, a.ev);
+  narrow_launch<float, false, false>(narrow_args(a, a.partials, nullptr, a.dbg), a.n_cu, a.blocks_per_cu, a.wg_waves, s,
+                                     a.ev);
   hipLaunchKernelGGL((k_finalize<float, 0>), dim3(unsigned(cdiv(a.G, 256))), dim3(256), 0, s,
                      fin_args(a, a.partials, nullptr));
   if (a.dbg != nullptr)
@@ -883,12 +909,12 @@ template <class T> static hipError_t adjoint_impl(const FwdArgs& a, hipStream_t 
   (void)hipGetLastError();
   if (a.work) launch_fill_u32(reinterpret_cast<uint32_t*>(a.work), 0u, 4, s);
   launch_front(a, s);
-  const int grid = a.n_cu * (nT<T>() == 2 ? a.blocks_per_cu_dual : a.blocks_per_cu);
+  const int per_cu = nT<T>() == 2 ? a.blocks_per_cu_dual : a.blocks_per_cu;
   const int waves = nT<T>() == 2 ? a.wg_waves_dual : a.wg_waves;
   const float* dir = a.dir;
   const bool tape = a.tape != nullptr && a.tape_tiles > 0;
-  if (tape) narrow_launch<T, false, true>(narrow_args(a, a.partials, dir, nullptr), grid, waves, s, a.ev);
-  else narrow_launch<T, false, false>(narrow_args(a, a.partials, dir, nullptr), grid, waves, s, a.ev);
+  if (tape) narrow_launch<T, false, true>(narrow_args(a, a.partials, dir, nullptr), a.n_cu, per_cu, waves, s, a.ev);
+  else narrow_launch<T, false, false>(narrow_args(a, a.partials, dir, nullptr), a.n_cu, per_cu, waves, s, a.ev);
   if (records)
     hipLaunchKernelGGL((k_finalize<T, 2>), dim3(unsigned(cdiv(a.G, 256))), dim3(256), 0, s,
                        fin_args(a, a.partials, dir));
@@ -896,9 +922,9 @@ template <class T> static hipError_t adjoint_impl(const FwdArgs& a, hipStream_t 
     hipLaunchKernelGGL((k_finalize<T, 1>), dim3(unsigned(cdiv(a.G, 256))), dim3(256), 0, s,
                        fin_args(a, a.partials, dir));
   NarrowArgs nb = narrow_args(a, a.bpartials, dir, nullptr);
-  if (tape) narrow_launch<T, true, true>(nb, grid, waves, s, a.ev, true, false);
+  if (tape) narrow_launch<T, true, true>(nb, a.n_cu, per_cu, waves, s, a.ev, true, false);
   nb.t_begin = tape ? a.tape_tiles : 0;  // tiles past the tape, if any
-  narrow_launch<T, true, false>(nb, grid, waves, s, a.ev, !tape, true);
+  narrow_launch<T, true, false>(nb, a.n_cu, per_cu, waves, s, a.ev, !tape, true);
   hipLaunchKernelGGL((k_reduce<T>), dim3(unsigned(cdiv(a.n, 256))), dim3(256), 0, s, fin_args(a, a.partials, dir),
                      a.bpartials, a.group_off, a.grad, a.hv);
   return hipGetLastError();
@@ -908,8 +934,8 @@ hipError_t launch_jvp(const FwdArgs& a, hipStream_t s) {
   (void)hipGetLastError();
   if (a.work) launch_fill_u32(reinterpret_cast<uint32_t*>(a.work), 0u, 4, s);
   launch_front(a, s);
-  const int grid = a.n_cu * a.blocks_per_cu_dual;
-  narrow_launch<df, false, false>(narrow_args(a, a.partials, a.dir, nullptr), grid, a.wg_waves_dual, s, a.ev);
+  narrow_launch<df, false, false>(narrow_args(a, a.partials, a.dir, nullptr), a.n_cu, a.blocks_per_cu_dual,
+                                  a.wg_waves_dual, s, a.ev);
   hipLaunchKernelGGL((k_finalize<df, 3>), dim3(unsigned(cdiv(a.G, 256))), dim3(256), 0, s,
                      fin_args(a, a.partials, a.dir));
   return hipGetLastError();
