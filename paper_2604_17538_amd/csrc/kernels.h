@@ -175,5 +175,9 @@ hipError_t launch_backward(const FwdArgs& a, hipStream_t s, bool records = false
 hipError_t launch_hvp(const FwdArgs& a, hipStream_t s, bool records = false);
 // records and their tangents along dir (one forward sweep in dual numbers)
 hipError_t launch_jvp(const FwdArgs& a, hipStream_t s);
+// Fills the resident-workgroup cache of every narrow-phase kernel (called once
+// per context before any launch, so no occupancy query runs inside a graph
+// capture).
+void warm_narrow_occupancy();
 
 }  // namespace cm

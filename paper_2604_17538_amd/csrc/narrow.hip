@@ -837,6 +837,27 @@ template <class T, bool ADJ, bool TAPE, int REP> static int resident_per_cu(int 
   return std::max(n, 0);
 }
 
+void warm_narrow_occupancy() {
+  for (int w : {1, 2, 4}) {
+    (void)resident_per_cu<float, false, false, kRepPlanes>(w);
+    (void)resident_per_cu<float, false, true, kRepPlanes>(w);
+    (void)resident_per_cu<float, true, true, kRepPlanes>(w);
+    (void)resident_per_cu<float, true, false, kRepPlanes>(w);
+    (void)resident_per_cu<df, false, false, kRepPlanes>(w);
+    (void)resident_per_cu<df, false, true, kRepPlanes>(w);
+    (void)resident_per_cu<df, true, true, kRepPlanes>(w);
+    (void)resident_per_cu<df, true, false, kRepPlanes>(w);
+    (void)resident_per_cu<float, false, false, kRepSpline>(w);
+    (void)resident_per_cu<float, true, false, kRepSpline>(w);
+    (void)resident_per_cu<df, false, false, kRepSpline>(w);
+    (void)resident_per_cu<df, true, false, kRepSpline>(w);
+    (void)resident_per_cu<float, false, false, kRepPrims>(w);
+    (void)resident_per_cu<float, true, false, kRepPrims>(w);
+    (void)resident_per_cu<df, false, false, kRepPrims>(w);
+    (void)resident_per_cu<df, true, false, kRepPrims>(w);
+  }
+}
+
 // Timing events bracket a group of launches: `first` records the start,
 // `last` the stop.  A persistent sweep never launches fewer workgroups than
 // the CUs keep resident: the launch shape is tuned on one sweep of a step and

@@ -613,6 +613,7 @@ cm_status cm_init(int32_t device, const cm_params* params, size_t mem_budget_byt
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) != hipSuccess) { delete ctx; return CM_E_HIP; }
     ctx->n_cu = prop.multiProcessorCount;
+    warm_narrow_occupancy();
     // device address of the fixed launch scratch of cm_contacts_fwd_noalloc
     if (static_scratch_setup(device) != hipSuccess) { delete ctx; return CM_E_HIP; }
     if (hipStreamCreateWithFlags(&ctx->build_stream, hipStreamNonBlocking) != hipSuccess) { delete ctx; return CM_E_HIP; }
