@@ -512,9 +512,9 @@ CM_DEV void sdf_eval(const ObjDesc& o, const DevParams& P, const V3<T>* x, SdfRe
     };
     // pass 1: shift = max_j a_j (value only; LSE is shift-invariant)
     if (np > kSub) {
-      // the 4 blocks of each kept group, the lane plane in ping-pong buffers
-      // refilled two blocks ahead (the next kept group's first two blocks during
-      // this group's last two); padding planes never raise the max
+      // the 4 blocks of each kept group, the lane plane in 4 buffers each
+      // refilled with the next kept group's block as soon as it is used;
+      // padding planes never raise the max
       auto blk = [&](const F4& ql, int j0) {
         f4v av[NP], at[NP];
         blk_vals<NP, float>(ql, xl0, av, at);
@@ -543,18 +543,18 @@ CM_DEV void sdf_eval(const ObjDesc& o, const DevParams& P, const V3<T>* x, SdfRe
         uint64_t mk = gmask(c0, &g);
         if (g >= 0) mk &= ~(1ull << (g - c0)); else g = take(mk, c0);  // (no best without pruning)
         const int j1 = max(g, 0) * kGrp;
-        F4 qa = grp_plane(pl, j1), qb = grp_plane(pl, j1 + 4);
+        F4 q0 = grp_plane(pl, j1), q1 = grp_plane(pl, j1 + 4), q2 = grp_plane(pl, j1 + 8), q3 = grp_plane(pl, j1 + 12);
         while (g >= 0) {
           const int gn = take(mk, c0);
           const int j = g * kGrp, jn = (gn >= 0 ? gn : g) * kGrp;
-#pragma unroll
-          for (int b = 0; b < kGrp; b += 8) {
-            const bool last = b + 8 >= kGrp;
-            blk(qa, j + b);
-            qa = grp_plane(pl, last ? jn : j + b + 8);
-            blk(qb, j + b + 4);
-            qb = grp_plane(pl, last ? jn + 4 : j + b + 12);
-          }
+          blk(q0, j);
+          q0 = grp_plane(pl, jn);
+          blk(q1, j + 4);
+          q1 = grp_plane(pl, jn + 4);
+          blk(q2, j + 8);
+          q2 = grp_plane(pl, jn + 8);
+          blk(q3, j + 12);
+          q3 = grp_plane(pl, jn + 12);
           g = gn;
           if (P.prune && !needed()) { skip = true; break; }
         }
@@ -611,12 +611,12 @@ CM_DEV void sdf_eval(const ObjDesc& o, const DevParams& P, const V3<T>* x, SdfRe
       }
     };
     if (np > 0) {
-      // The 4 blocks of each kept group, in ping-pong pairs of buffers for the
-      // lane's plane (matrix-core operand, vector load) and the block's planes
-      // (SGPRs, scalar loads), each refilled two blocks ahead (the next kept
-      // group's first two blocks during this group's last two): no buffer is
-      // copied across the loop, so every load has a whole block of work to
-      // complete.  Padding planes add exact zeros.
+      // The 4 blocks of each kept group: the lane's plane (matrix-core operand,
+      // vector load) in 4 buffers, each refilled with the next kept group's
+      // block as soon as it is used (a whole group ahead), and the block's
+      // planes (SGPRs, scalar loads) in a ping-pong pair refilled two blocks
+      // ahead: no buffer is copied across the loop, so every load has blocks of
+      // work to complete behind it.  Padding planes add exact zeros.
       int n2 = 0;  // planes of the piece evaluated
       auto blk = [&](const F4& ql, const F4* sq) {
         f4v av[NP], at[NP];
@@ -624,30 +624,35 @@ CM_DEV void sdf_eval(const ObjDesc& o, const DevParams& P, const V3<T>* x, SdfRe
 #pragma unroll
         for (int i = 0; i < 4; ++i) term(sq[i], av, at, i);
       };
-      auto fill = [&](F4& ql, F4* sq, int j0) {
-        ql = grp_plane(pl, j0);
+      auto sfill = [&](F4* sq, int j0) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) sq[i] = ldc(pl + j0 + i);
       };
+      static_assert(kGrp == 16, "four lane-plane buffers: one group");
       for (int c0 = 0; c0 < ng; c0 += 64) {
         uint64_t mk = gmask(c0, nullptr);
         int g = take(mk, c0);
         const int j1 = max(g, 0) * kGrp;
-        F4 qa, qb, sa[4], sb[4];
-        fill(qa, sa, j1);
-        fill(qb, sb, j1 + 4);
+        F4 q0 = grp_plane(pl, j1), q1 = grp_plane(pl, j1 + 4), q2 = grp_plane(pl, j1 + 8), q3 = grp_plane(pl, j1 + 12);
+        F4 sa[4], sb[4];
+        sfill(sa, j1);
+        sfill(sb, j1 + 4);
         while (g >= 0) {
           const int gn = take(mk, c0);
           const int j = g * kGrp, jn = (gn >= 0 ? gn : g) * kGrp;
           n2 += min(kGrp, np - j);
-#pragma unroll
-          for (int b = 0; b < kGrp; b += 8) {
-            const bool last = b + 8 >= kGrp;
-            blk(qa, sa);
-            fill(qa, sa, last ? jn : j + b + 8);
-            blk(qb, sb);
-            fill(qb, sb, last ? jn + 4 : j + b + 12);
-          }
+          blk(q0, sa);
+          q0 = grp_plane(pl, jn);
+          sfill(sa, j + 8);
+          blk(q1, sb);
+          q1 = grp_plane(pl, jn + 4);
+          sfill(sb, j + 12);
+          blk(q2, sa);
+          q2 = grp_plane(pl, jn + 8);
+          sfill(sa, jn);
+          blk(q3, sb);
+          q3 = grp_plane(pl, jn + 12);
+          sfill(sb, jn + 4);
           g = gn;
         }
       }
