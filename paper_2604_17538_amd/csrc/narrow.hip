@@ -498,8 +498,14 @@ CM_DEV void edge_adj(const CF<T>& c, const Trace<T>& tr, const FrameT<T>& F, con
 //                              tape records of tiles [0, tape_tiles)
 //   ADJ = true,  TAPE = true   adjoint of tiles [0, tape_tiles) from the tape
 //   ADJ = true,  TAPE = false  adjoint of tiles [t_begin, total), recomputing
+// Waves per SIMD the compiler must leave room for: 4 for the forward plane
+// sweep in floats (records only), no constraint for the others.
+template <class T, bool ADJ, bool TAPE, int REP> struct NarrowWaves {
+  static constexpr int value = (nT<T>() == 1 && !ADJ && !TAPE && REP == kRepPlanes) ? 4 : 1;
+};
 template <class T, bool ADJ, bool TAPE, int REP>
-__global__ __launch_bounds__(256) void k_narrow(NarrowArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NarrowWaves<T, ADJ, TAPE, REP>::value))) void
+k_narrow(NarrowArgs a) {
   static_assert(REP == kRepPlanes || !TAPE, "spline and primitive SDFs recompute instead of taping");
   const int l = lane();
   const int64_t n_run = a.dc->R;
