@@ -499,9 +499,10 @@ CM_DEV void edge_adj(const CF<T>& c, const Trace<T>& tr, const FrameT<T>& F, con
 //   ADJ = true,  TAPE = true   adjoint of tiles [0, tape_tiles) from the tape
 //   ADJ = true,  TAPE = false  adjoint of tiles [t_begin, total), recomputing
 // Waves per SIMD the compiler must leave room for: 4 for the forward plane
-// sweep in floats (records only), no constraint for the others.
+// sweep in floats (records only), 3 for the float forward sweep keeping the
+// tape (gradient without H v), no constraint for the others.
 template <class T, bool ADJ, bool TAPE, int REP> struct NarrowWaves {
-  static constexpr int value = (nT<T>() == 1 && !ADJ && !TAPE && REP == kRepPlanes) ? 4 : 1;
+  static constexpr int value = (nT<T>() == 1 && !ADJ && REP == kRepPlanes) ? (TAPE ? 3 : 4) : 1;
 };
 template <class T, bool ADJ, bool TAPE, int REP>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NarrowWaves<T, ADJ, TAPE, REP>::value))) void
